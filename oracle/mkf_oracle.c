@@ -1,0 +1,752 @@
+/*
+ * mkf_oracle.c -- TEST INFRASTRUCTURE ONLY: a plain FP64 CPU reference of
+ * Kalman-filter track finding and fitting (arXiv:1811.04141).  Used only by
+ * the tests, the smoke check and the benchmark's CPU-baseline leg; the GPU
+ * library never links it.
+ *
+ * The paper gives the method in words only (no equations, no listings):
+ *   - the Kalman filter it builds on (Introduction, ref. Fruhwirth);
+ *   - propagation and KF equations for both barrel cylinders and endcap
+ *     disks (Introduction, the paragraph on realistic geometries);
+ *   - a layer description and a per-region layer plan followed by track
+ *     finding (Section 2.1);
+ *   - multiple scattering from material and a constant field (Section 2.1);
+ *   - the "clone engine": score all hit extensions of all candidates by
+ *     chi2 first, keep the best ones, and only then run the Kalman updates
+ *     (Introduction);
+ *   - seeds and hits supplied from outside (Section 2.2).
+ * Every formula below is therefore the textbook definition it names.  The
+ * readings chosen where the paper is silent are listed in the design notes
+ * and repeated next to the code that takes them.
+ */
+#include "mkf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ---------------------------------------------------------------- util */
+
+static double wrap_phi(double a) {
+  /* map to (-pi, pi] */
+  a = fmod(a, 2.0 * M_PI);
+  if (a <= -M_PI) a += 2.0 * M_PI;
+  if (a > M_PI) a -= 2.0 * M_PI;
+  return a;
+}
+
+static double sinc(double h) { return h == 0.0 ? 1.0 : sin(h) / h; }
+
+/* d sinc / dh; the closed form cancels for small h, so a Taylor series is
+ * used there (terms through h^7). */
+static double dsinc(double h) {
+  if (fabs(h) < 1e-2) {
+    double h2 = h * h;
+    return h * (-1.0 / 3.0 + h2 * (1.0 / 30.0 + h2 * (-1.0 / 840.0 + h2 / 45360.0)));
+  }
+  return (h * cos(h) - sin(h)) / (h * h);
+}
+
+static void matmul6(const double *A, const double *B, double *C) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 6; ++k) s += A[i * 6 + k] * B[k * 6 + j];
+      C[i * 6 + j] = s;
+    }
+}
+
+static void transpose6(const double *A, double *At) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) At[j * 6 + i] = A[i * 6 + j];
+}
+
+static void symmetrize6(double *C) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = i + 1; j < 6; ++j) {
+      double s = 0.5 * (C[i * 6 + j] + C[j * 6 + i]);
+      C[i * 6 + j] = s;
+      C[j * 6 + i] = s;
+    }
+}
+
+/* ------------------------------------------------------ helix transport */
+
+/* Motion of a charge in a uniform field B along +z (Lorentz force
+ * F = q v x B): the transverse projection is a circle with signed
+ * curvature omega = -kappa * B * (q/pT) (a positive charge turns clockwise
+ * seen from +z), and z advances by l * cot(theta).  With h = omega*l/2 the
+ * chord is l*sinc(h) long and points along phi + h. */
+void orc_transport(const double p[6], double l, double bz, double kappa,
+                   double out[6]) {
+  double w = -kappa * bz * p[3];
+  double h = 0.5 * w * l;
+  double L = l * sinc(h);
+  double psi = p[4] + h;
+  out[0] = p[0] + L * cos(psi);
+  out[1] = p[1] + L * sin(psi);
+  out[2] = p[2] + l * cos(p[5]) / sin(p[5]);
+  out[3] = p[3];
+  out[4] = wrap_phi(p[4] + w * l);
+  out[5] = p[5];
+}
+
+/* ------------------------------------------------- crossing a cylinder */
+
+/* Exact crossing of the helix with the cylinder r = R.
+ *
+ * With a = x cos(phi) + y sin(phi), c = y cos(phi) - x sin(phi) and
+ * g0 = x^2 + y^2 - R^2, the squared radius after a transverse path l is
+ *   r(l)^2 - R^2 = g0 + L^2 + 2 L (a cos h + c sin h),  L = 2 sin(h)/omega.
+ * Multiplying by 1/cos^2(h) and substituting tau = (2/omega) tan(h) gives
+ * the quadratic
+ *   (1 + c omega + g0 omega^2 / 4) tau^2 + 2 a tau + g0 = 0,
+ * whose real roots are exactly the crossings with |omega l| < pi (the
+ * first half turn each way), and l = (2/omega) atan(omega tau / 2).
+ * Both maps are monotonic, so the smallest admissible root in tau is the
+ * smallest in l.  For omega -> 0 the quadratic becomes the straight
+ * line / circle equation, so the form is well conditioned at high pT. */
+static double tau_to_l(double tau, double w) {
+  double zz = 0.5 * w * tau;
+  double f = fabs(zz) < 1e-8 ? 1.0 - zz * zz / 3.0 : atan(zz) / zz;
+  return tau * f;
+}
+
+int orc_path_to_barrel(const double p[6], double R, double bz, double kappa,
+                       double l_min, double *l_out) {
+  double w = -kappa * bz * p[3];
+  double cphi = cos(p[4]), sphi = sin(p[4]);
+  double a = p[0] * cphi + p[1] * sphi;
+  double c = p[1] * cphi - p[0] * sphi;
+  double g0 = p[0] * p[0] + p[1] * p[1] - R * R;
+  double alpha = 1.0 + c * w + 0.25 * g0 * w * w;
+  double roots[2];
+  int nr = 0;
+  if (alpha == 0.0) {
+    if (a != 0.0) roots[nr++] = -g0 / (2.0 * a);
+  } else {
+    double disc = a * a - alpha * g0;
+    if (disc < 0.0) return ORC_NO_CROSSING;
+    double sq = sqrt(disc);
+    double qq = -(a + copysign(sq, a));
+    if (qq != 0.0) {
+      roots[nr++] = qq / alpha;
+      roots[nr++] = g0 / qq;
+    } else {
+      roots[nr++] = 0.0;
+    }
+  }
+  double best = INFINITY;
+  for (int i = 0; i < nr; ++i) {
+    double l = tau_to_l(roots[i], w);
+    if (l > l_min && l < best) best = l;
+  }
+  if (!(best < INFINITY)) return ORC_NO_CROSSING;
+  *l_out = best;
+  return ORC_OK;
+}
+
+/* Disk z = Z: z advances linearly, so l = (Z - z) tan(theta); it must be
+ * beyond l_min and within the first half turn. */
+int orc_path_to_disk(const double p[6], double Z, double bz, double kappa,
+                     double l_min, double *l_out) {
+  double ct = cos(p[5]);
+  if (ct == 0.0) return ORC_NO_CROSSING;
+  double l = (Z - p[2]) * sin(p[5]) / ct;
+  double w = -kappa * bz * p[3];
+  if (!(l > l_min) || fabs(w) * l >= M_PI) return ORC_NO_CROSSING;
+  *l_out = l;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------- full propagation */
+
+/* Propagation to a layer with the surface-constrained Jacobian.
+ *
+ * D = d p'/d p0 at fixed l follows from the transport above.  The path
+ * itself depends on p0 through the surface condition g(p') = 0 (barrel:
+ * g = x'^2 + y'^2 - R^2, disk: g = z' - Z), so with n = dg/dp' and
+ * t = dp'/dl = (cos phi', sin phi', cot theta, 0, omega, 0):
+ *   dl/dp0 = -(n^T D)/(n^T t),  F = D + t (dl/dp0)^T = (I - t n^T/(n^T t)) D.
+ * C' = F C F^T then has n as a null direction (rank 5): the state is
+ * constrained to the surface. */
+int orc_propagate(const double p[6], const double C[36], const orc_layer *Lr,
+                  double bz, double kappa, double l_min, double edge_margin,
+                  int check_extent, double p_out[6], double C_out[36],
+                  double F_out[36], double *l_out) {
+  double l;
+  int st = Lr->kind == 0
+               ? orc_path_to_barrel(p, Lr->pos, bz, kappa, l_min, &l)
+               : orc_path_to_disk(p, Lr->pos, bz, kappa, l_min, &l);
+  if (st != ORC_OK) return st;
+  double pp[6];
+  orc_transport(p, l, bz, kappa, pp);
+  if (check_extent) {
+    double q = Lr->kind == 0 ? pp[2] : hypot(pp[0], pp[1]);
+    if (q < Lr->ext_lo - edge_margin || q > Lr->ext_hi + edge_margin)
+      return ORC_OUT_OF_EXTENT;
+  }
+  if (l_out) *l_out = l;
+  memcpy(p_out, pp, sizeof(pp));
+  if (!F_out && !C_out) return ORC_OK;
+
+  double dw = -kappa * bz; /* d omega / d(q/pT) */
+  double w = dw * p[3];
+  double h = 0.5 * w * l;
+  double L = l * sinc(h);
+  double psi = p[4] + h;
+  double dLdw = l * dsinc(h) * 0.5 * l;
+  double st5 = sin(p[5]);
+  double D[36];
+  memset(D, 0, sizeof(D));
+  for (int i = 0; i < 6; ++i) D[i * 6 + i] = 1.0;
+  D[0 * 6 + 3] = (dLdw * cos(psi) - L * sin(psi) * 0.5 * l) * dw;
+  D[0 * 6 + 4] = -L * sin(psi);
+  D[1 * 6 + 3] = (dLdw * sin(psi) + L * cos(psi) * 0.5 * l) * dw;
+  D[1 * 6 + 4] = L * cos(psi);
+  D[2 * 6 + 5] = -l / (st5 * st5);
+  D[4 * 6 + 3] = l * dw;
+
+  double t[6] = {cos(pp[4]), sin(pp[4]), cos(pp[5]) / sin(pp[5]), 0.0, w, 0.0};
+  double n[6] = {0, 0, 0, 0, 0, 0};
+  if (Lr->kind == 0) {
+    n[0] = 2.0 * pp[0];
+    n[1] = 2.0 * pp[1];
+  } else {
+    n[2] = 1.0;
+  }
+  double nt = 0.0;
+  for (int i = 0; i < 6; ++i) nt += n[i] * t[i];
+  double nD[6];
+  for (int j = 0; j < 6; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < 6; ++i) s += n[i] * D[i * 6 + j];
+    nD[j] = s;
+  }
+  double F[36];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) F[i * 6 + j] = D[i * 6 + j] - t[i] * nD[j] / nt;
+  if (F_out) memcpy(F_out, F, sizeof(F));
+  if (C && C_out) {
+    double FC[36], Ft[36];
+    matmul6(F, C, FC);
+    transpose6(F, Ft);
+    matmul6(FC, Ft, C_out);
+    symmetrize6(C_out);
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------ multiple scattering */
+
+/* Two independent deflections of the momentum direction, each with
+ * standard deviation sigma, perpendicular to the momentum, |p| unchanged:
+ * theta moves by d_theta, phi by d_alpha / sin(theta), and since
+ * pT = |p| sin(theta), q/pT moves by -(q/pT) cot(theta) d_theta. */
+void orc_add_ms(const double p[6], double sigma, double C[36]) {
+  if (sigma == 0.0) return;
+  double s2 = sigma * sigma;
+  double st = sin(p[5]), cot = cos(p[5]) / st;
+  double a = p[3] * cot;
+  C[3 * 6 + 3] += a * a * s2;
+  C[3 * 6 + 5] += -a * s2;
+  C[5 * 6 + 3] += -a * s2;
+  C[4 * 6 + 4] += s2 / (st * st);
+  C[5 * 6 + 5] += s2;
+}
+
+/* ------------------------------------------------------- measurement */
+
+/* Local 2-D frame at the predicted point: t = (-y', x')/r' along the
+ * layer's azimuth, rh = (x', y')/r' radial.  Barrel: u = t.(xh - x'),
+ * v = zh - z'.  Disk: u = t.(xh - x'), v = rh.(xh - x').  A barrel hit in
+ * the opposite half of the cylinder (x'.xh <= 0) would alias to a small u,
+ * so it is not compatible (reading). */
+int orc_measure(const double p[6], int kind, const double hit[3], double r[2],
+                double H[12]) {
+  double rr = hypot(p[0], p[1]);
+  double tx = -p[1] / rr, ty = p[0] / rr;
+  double rx = p[0] / rr, ry = p[1] / rr;
+  double dx = hit[0] - p[0], dy = hit[1] - p[1], dz = hit[2] - p[2];
+  memset(H, 0, 12 * sizeof(double));
+  H[0] = tx;
+  H[1] = ty;
+  r[0] = tx * dx + ty * dy;
+  if (kind == 0) {
+    if (p[0] * hit[0] + p[1] * hit[1] <= 0.0) return 0;
+    r[1] = dz;
+    H[6 + 2] = 1.0;
+  } else {
+    r[1] = rx * dx + ry * dy;
+    H[6 + 0] = rx;
+    H[6 + 1] = ry;
+  }
+  return 1;
+}
+
+static void residual_cov(const double C[36], int m, const double *H,
+                         const double *V, double *S, double *PHt) {
+  /* PHt = C H^T (6 x m), S = H C H^T + V (m x m) */
+  for (int i = 0; i < 6; ++i)
+    for (int a = 0; a < m; ++a) {
+      double s = 0.0;
+      for (int k = 0; k < 6; ++k) s += C[i * 6 + k] * H[a * 6 + k];
+      PHt[i * m + a] = s;
+    }
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b) {
+      double s = V[a * m + b];
+      for (int k = 0; k < 6; ++k) s += H[a * 6 + k] * PHt[k * m + b];
+      S[a * m + b] = s;
+    }
+}
+
+static void inv_small(int m, const double *S, double *Si) {
+  if (m == 1) {
+    Si[0] = 1.0 / S[0];
+  } else {
+    double det = S[0] * S[3] - S[1] * S[2];
+    Si[0] = S[3] / det;
+    Si[1] = -S[1] / det;
+    Si[2] = -S[2] / det;
+    Si[3] = S[0] / det;
+  }
+}
+
+int orc_chi2(const double p[6], const double C[36], int kind,
+             const double hit[3], double var_u, double var_v, double *chi2) {
+  double r[2], H[12], S[4], Si[4], PHt[12];
+  if (!orc_measure(p, kind, hit, r, H)) return 0;
+  double V[4] = {var_u, 0.0, 0.0, var_v};
+  residual_cov(C, 2, H, V, S, PHt);
+  inv_small(2, S, Si);
+  *chi2 = r[0] * (Si[0] * r[0] + Si[1] * r[1]) + r[1] * (Si[2] * r[0] + Si[3] * r[1]);
+  return 1;
+}
+
+/* ---------------------------------------------------- Kalman update */
+
+/* Textbook gain-form Kalman update (Fruhwirth 1987, the filter the paper
+ * builds on): S = H C H^T + V, K = C H^T S^-1, p += K r,
+ * C -= K S K^T (= K (C H^T)^T), symmetrised; chi2 = r^T S^-1 r.
+ * The Joseph form (I - KH) C (I - KH)^T + K V K^T is equal in exact
+ * arithmetic and is kept as a cross-check. */
+void orc_kf_update(double p[6], double C[36], int m, const double *H,
+                   const double *r, const double *V, int joseph,
+                   double *chi2) {
+  double S[4], Si[4], PHt[12], K[12];
+  residual_cov(C, m, H, V, S, PHt);
+  inv_small(m, S, Si);
+  for (int i = 0; i < 6; ++i)
+    for (int a = 0; a < m; ++a) {
+      double s = 0.0;
+      for (int b = 0; b < m; ++b) s += PHt[i * m + b] * Si[b * m + a];
+      K[i * m + a] = s;
+    }
+  double c2 = 0.0;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b) c2 += r[a] * Si[a * m + b] * r[b];
+  if (chi2) *chi2 = c2;
+  for (int i = 0; i < 6; ++i)
+    for (int a = 0; a < m; ++a) p[i] += K[i * m + a] * r[a];
+  if (!joseph) {
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double s = 0.0;
+        for (int a = 0; a < m; ++a) s += K[i * m + a] * PHt[j * m + a];
+        C[i * 6 + j] -= s;
+      }
+  } else {
+    double A[36], AC[36], At[36], Cn[36];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double s = (i == j) ? 1.0 : 0.0;
+        for (int a = 0; a < m; ++a) s -= K[i * m + a] * H[a * 6 + j];
+        A[i * 6 + j] = s;
+      }
+    matmul6(A, C, AC);
+    transpose6(A, At);
+    matmul6(AC, At, Cn);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double s = 0.0;
+        for (int a = 0; a < m; ++a)
+          for (int b = 0; b < m; ++b) s += K[i * m + a] * V[a * m + b] * K[j * m + b];
+        Cn[i * 6 + j] += s;
+      }
+    memcpy(C, Cn, sizeof(Cn));
+  }
+  symmetrize6(C);
+}
+
+int orc_update_hit(double p[6], double C[36], int kind, const double hit[3],
+                   double var_u, double var_v, double *chi2) {
+  double r[2], H[12];
+  if (!orc_measure(p, kind, hit, r, H)) return 0;
+  double V[4] = {var_u, 0.0, 0.0, var_v};
+  orc_kf_update(p, C, 2, H, r, V, 0, chi2);
+  p[4] = wrap_phi(p[4]);
+  return 1;
+}
+
+/* ------------------------------------------------------------ seeding */
+
+static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
+  double q = Lr->kind == 0 ? pp[2] : hypot(pp[0], pp[1]);
+  return fmin(fabs(q - (Lr->ext_lo - m)), fabs(q - (Lr->ext_hi + m)));
+}
+
+/* Seed from three hits (seeds are supplied from outside, Section 2.2):
+ * the circle through the three transverse points gives the centre and the
+ * radius rho; the turning sense gives the charge; pT = kappa |B| rho; phi
+ * is the tangent at the first hit in the direction of motion; cot(theta)
+ * is the z rise over the transverse arc from the first to the third hit.
+ * The state starts at the first hit with a wide diagonal prior and is filtered
+ * through the three hits (propagate, scatter, update), ending on the third
+ * seed layer.  The layer plan (the paper's per-region list of layers to
+ * traverse, Section 2.1) is read per seed: every non-seed layer the seed
+ * helix crosses inside its widened extent in the remaining half turn,
+ * ordered by path length. */
+int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
+             const double h[9], const double hv[6], const int32_t hl[3],
+             double pos_tol, orc_seed_out *out) {
+  memset(out, 0, sizeof(*out));
+  double x1 = h[0], y1 = h[1], z1 = h[2];
+  double x2 = h[3], y2 = h[4];
+  double x3 = h[6], y3 = h[7], z3 = h[8];
+  double ax = x2 - x1, ay = y2 - y1, bx = x3 - x1, by = y3 - y1;
+  double d = 2.0 * (ax * by - ay * bx);
+  if (d == 0.0 || cfg->bz == 0.0) return 0;
+  double a2 = ax * ax + ay * ay, b2 = bx * bx + by * by;
+  double ux = (by * a2 - ay * b2) / d;
+  double uy = (ax * b2 - bx * a2) / d;
+  double cx = x1 + ux, cy = y1 + uy;
+  double rho = hypot(ux, uy);
+  double turn = (x2 - x1) * (y3 - y2) - (y2 - y1) * (x3 - x2);
+  int ccw = turn > 0.0; /* omega > 0 */
+  double pt = cfg->kappa * fabs(cfg->bz) * rho;
+  /* omega = -kappa B ipt > 0  <=>  B * ipt < 0 */
+  double ipt = (ccw ? -1.0 : 1.0) * (cfg->bz > 0 ? 1.0 : -1.0) / pt;
+  double r1x = x1 - cx, r1y = y1 - cy;
+  double dirx = ccw ? -r1y : r1y, diry = ccw ? r1x : -r1x;
+  double phi1 = atan2(diry, dirx);
+  double r3x = x3 - cx, r3y = y3 - cy;
+  double dpsi = atan2(r1x * r3y - r1y * r3x, r1x * r3x + r1y * r3y);
+  double s13 = rho * fabs(dpsi);
+  double theta = atan2(s13, z3 - z1);
+
+  double p[6] = {x1, y1, z1, ipt, phi1, theta};
+  double C[36];
+  memset(C, 0, sizeof(C));
+  for (int i = 0; i < 6; ++i) C[i * 6 + i] = cfg->init_var[i];
+
+  for (int k = 0; k < 3; ++k) {
+    const orc_layer *Lr = &layers[hl[k]];
+    if (k > 0) {
+      double pp[6], Cp[36];
+      if (orc_propagate(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp,
+                        Cp, NULL, NULL) != ORC_OK)
+        return 0;
+      memcpy(p, pp, sizeof(pp));
+      memcpy(C, Cp, sizeof(Cp));
+    }
+    orc_add_ms(p, cfg->ms_sigma, C);
+    double c2;
+    if (!orc_update_hit(p, C, Lr->kind, &h[3 * k], hv[2 * k], hv[2 * k + 1], &c2))
+      return 0;
+  }
+  memcpy(out->par, p, sizeof(p));
+  memcpy(out->cov, C, sizeof(C));
+
+  int n = 0;
+  for (int i = 0; i < n_layers; ++i) {
+    if (i == hl[0] || i == hl[1] || i == hl[2]) continue;
+    double pp[6], l;
+    int st = orc_propagate(p, NULL, &layers[i], cfg->bz, cfg->kappa, cfg->l_min,
+                           cfg->edge_margin, 1, pp, NULL, NULL, &l);
+    if (st == ORC_NO_CROSSING) continue;
+    if (st == ORC_OUT_OF_EXTENT) {
+      double l2;
+      /* near the widened edge the FP32 decision may flip */
+      int s2 = layers[i].kind == 0
+                   ? orc_path_to_barrel(p, layers[i].pos, cfg->bz, cfg->kappa, cfg->l_min, &l2)
+                   : orc_path_to_disk(p, layers[i].pos, cfg->bz, cfg->kappa, cfg->l_min, &l2);
+      if (s2 == ORC_OK) {
+        double p2[6];
+        orc_transport(p, l2, cfg->bz, cfg->kappa, p2);
+        if (edge_distance(&layers[i], p2, cfg->edge_margin) <= pos_tol) out->plan_fragile = 1;
+      }
+      continue;
+    }
+    if (edge_distance(&layers[i], pp, cfg->edge_margin) <= pos_tol) out->plan_fragile = 1;
+    if (n >= ORC_MAX_PLAN) break;
+    /* insertion by path length, ties by layer index */
+    int j = n;
+    while (j > 0 && out->plan_l[j - 1] > l) {
+      out->plan_l[j] = out->plan_l[j - 1];
+      out->plan[j] = out->plan[j - 1];
+      --j;
+    }
+    out->plan_l[j] = l;
+    out->plan[j] = i;
+    ++n;
+  }
+  out->plan_len = n;
+  out->ok = 1;
+  return 1;
+}
+
+/* ------------------------------------------------------- clone engine */
+
+typedef struct {
+  double p[6], C[36];
+  int32_t n_hits, n_miss;
+  double chi2;
+  int32_t hist[ORC_MAX_PLAN];
+} cand_t;
+
+enum { EXT_HIT = 0, EXT_MISS = 1, EXT_SKIP = 2 };
+
+typedef struct {
+  int32_t n_hits;   /* after the extension */
+  double chi2_sum;  /* after the extension */
+  int32_t parent;   /* parent rank */
+  int32_t order;    /* hit index; misses and skips after every hit */
+  int32_t type;
+  int32_t hit;
+  double chi2;
+} ext_t;
+
+/* Ranking key (reading of "best extensions based on chi2", Introduction):
+ * more hits first, then smaller accumulated chi2, then parent rank, then
+ * hit index with miss/skip last.  Total and deterministic. */
+static int ext_cmp(const void *A, const void *B) {
+  const ext_t *a = (const ext_t *)A, *b = (const ext_t *)B;
+  if (a->n_hits != b->n_hits) return a->n_hits > b->n_hits ? -1 : 1;
+  if (a->chi2_sum != b->chi2_sum) return a->chi2_sum < b->chi2_sum ? -1 : 1;
+  if (a->parent != b->parent) return a->parent < b->parent ? -1 : 1;
+  if (a->order != b->order) return a->order < b->order ? -1 : 1;
+  return 0;
+}
+
+static double tol_of(const orc_tol *t, double v) { return t->chi2_rel * fabs(v) + t->chi2_abs; }
+
+static void mark(int32_t *fragile, int32_t step) {
+  if (*fragile < 0 || step < *fragile) *fragile = step;
+}
+
+static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                     int32_t n_layers, const int32_t *lay_off, const int32_t *lay_idx,
+                     const float *x, const float *y, const float *z, const float *vu,
+                     const float *vv, const int32_t *layer, const int32_t *sh,
+                     orc_track *out) {
+  memset(out, 0, sizeof(*out));
+  out->fragile_step = -1;
+  double h[9], hv[6];
+  int32_t hl[3];
+  for (int k = 0; k < 3; ++k) {
+    int32_t i = sh[k];
+    h[3 * k] = x[i];
+    h[3 * k + 1] = y[i];
+    h[3 * k + 2] = z[i];
+    hv[2 * k] = vu[i];
+    hv[2 * k + 1] = vv[i];
+    hl[k] = layer[i];
+  }
+  orc_seed_out so;
+  if (!orc_seed(cfg, layers, n_layers, h, hv, hl, tol->pos_tol, &so)) return;
+  out->seed_ok = 1;
+  out->plan_len = so.plan_len;
+  memcpy(out->plan, so.plan, sizeof(so.plan));
+  if (so.plan_fragile) out->fragile_step = 0;
+
+  int nc = cfg->n_cand;
+  cand_t *cands = (cand_t *)calloc((size_t)nc, sizeof(cand_t));
+  cand_t *next = (cand_t *)calloc((size_t)nc, sizeof(cand_t));
+  cand_t *fin = (cand_t *)calloc((size_t)(ORC_MAX_PLAN + 1) * nc, sizeof(cand_t));
+  double *pp = (double *)malloc(sizeof(double) * 6 * nc);
+  double *Cp = (double *)malloc(sizeof(double) * 36 * nc);
+  int n_fin = 0;
+  int n = 1;
+  memcpy(cands[0].p, so.par, sizeof(so.par));
+  memcpy(cands[0].C, so.cov, sizeof(so.cov));
+  cands[0].n_hits = 3;
+  cands[0].n_miss = 0;
+  cands[0].chi2 = 0.0;
+  for (int k = 0; k < ORC_MAX_PLAN; ++k) cands[0].hist[k] = ORC_HIT_NONE;
+
+  for (int s = 0; s < so.plan_len; ++s) {
+    const orc_layer *Lr = &layers[so.plan[s]];
+    int32_t L = so.plan[s];
+    int32_t nh = lay_off[L + 1] - lay_off[L];
+    ext_t *ext = (ext_t *)malloc(sizeof(ext_t) * (size_t)n * (size_t)(nh + 1));
+    int ne = 0;
+    out->n_steps += n;
+    for (int c = 0; c < n; ++c) {
+      int ne0 = ne;
+      double *pc = &pp[6 * c], *Cc = &Cp[36 * c];
+      double l;
+      int st = orc_propagate(cands[c].p, cands[c].C, Lr, cfg->bz, cfg->kappa, cfg->l_min,
+                             cfg->edge_margin, 1, pc, Cc, NULL, &l);
+      if (st == ORC_OK && edge_distance(Lr, pc, cfg->edge_margin) <= tol->pos_tol) mark(&out->fragile_step, s);
+      if (st == ORC_OUT_OF_EXTENT) {
+        double l2, p2[6];
+        int s2 = Lr->kind == 0
+                     ? orc_path_to_barrel(cands[c].p, Lr->pos, cfg->bz, cfg->kappa, cfg->l_min, &l2)
+                     : orc_path_to_disk(cands[c].p, Lr->pos, cfg->bz, cfg->kappa, cfg->l_min, &l2);
+        if (s2 == ORC_OK) {
+          orc_transport(cands[c].p, l2, cfg->bz, cfg->kappa, p2);
+          if (edge_distance(Lr, p2, cfg->edge_margin) <= tol->pos_tol) mark(&out->fragile_step, s);
+        }
+      }
+      if (st != ORC_OK) {
+        ext_t e = {cands[c].n_hits, cands[c].chi2, c, 0x7fffffff, EXT_SKIP, ORC_HIT_SKIP, 0.0};
+        ext[ne++] = e;
+        continue;
+      }
+      orc_add_ms(pc, cfg->ms_sigma, Cc);
+      for (int k = lay_off[L]; k < lay_off[L + 1]; ++k) {
+        int32_t hi = lay_idx[k];
+        double hh[3] = {x[hi], y[hi], z[hi]};
+        double c2;
+        if (!orc_chi2(pc, Cc, Lr->kind, hh, vu[hi], vv[hi], &c2)) continue;
+        if (fabs(c2 - cfg->chi2_cut) <= tol_of(tol, cfg->chi2_cut)) mark(&out->fragile_step, s);
+        if (c2 < cfg->chi2_cut) {
+          ext_t e = {cands[c].n_hits + 1, cands[c].chi2 + c2, c, hi, EXT_HIT, hi, c2};
+          ext[ne++] = e;
+        }
+      }
+      if (cands[c].n_miss < cfg->max_holes) {
+        ext_t e = {cands[c].n_hits, cands[c].chi2, c, 0x7fffffff, EXT_MISS, ORC_HIT_MISS, 0.0};
+        ext[ne++] = e;
+      }
+      if (ne == ne0) fin[n_fin++] = cands[c]; /* no extension: retired */
+    }
+    qsort(ext, (size_t)ne, sizeof(ext_t), ext_cmp);
+    int keep = ne < nc ? ne : nc;
+    if (ne > nc && ext[nc - 1].n_hits == ext[nc].n_hits &&
+        fabs(ext[nc - 1].chi2_sum - ext[nc].chi2_sum) <=
+            tol_of(tol, fmax(ext[nc - 1].chi2_sum, ext[nc].chi2_sum)))
+      mark(&out->fragile_step, s);
+    for (int r = 0; r < keep; ++r) {
+      const ext_t *e = &ext[r];
+      cand_t *dst = &next[r];
+      const cand_t *par = &cands[e->parent];
+      *dst = *par;
+      if (e->type == EXT_SKIP) {
+        dst->hist[s] = ORC_HIT_SKIP;
+      } else {
+        memcpy(dst->p, &pp[6 * e->parent], 6 * sizeof(double));
+        memcpy(dst->C, &Cp[36 * e->parent], 36 * sizeof(double));
+        if (e->type == EXT_MISS) {
+          dst->n_miss += 1;
+          dst->hist[s] = ORC_HIT_MISS;
+        } else {
+          double hh[3] = {x[e->hit], y[e->hit], z[e->hit]};
+          double c2;
+          orc_update_hit(dst->p, dst->C, Lr->kind, hh, vu[e->hit], vv[e->hit], &c2);
+          dst->n_hits += 1;
+          dst->chi2 = e->chi2_sum;
+          dst->hist[s] = e->hit;
+        }
+      }
+    }
+    free(ext);
+    cand_t *tmp = cands;
+    cands = next;
+    next = tmp;
+    n = keep;
+  }
+
+  /* best over final candidates (by rank) then retired ones (in order) */
+  const cand_t *bc = NULL, *sc = NULL;
+  for (int i = 0; i < n + n_fin; ++i) {
+    const cand_t *c = i < n ? &cands[i] : &fin[i - n];
+    if (!bc || c->n_hits > bc->n_hits || (c->n_hits == bc->n_hits && c->chi2 < bc->chi2)) {
+      sc = bc;
+      bc = c;
+    } else if (!sc || c->n_hits > sc->n_hits || (c->n_hits == sc->n_hits && c->chi2 < sc->chi2)) {
+      sc = c;
+    }
+  }
+  if (bc) {
+    if (sc && sc->n_hits == bc->n_hits && fabs(sc->chi2 - bc->chi2) <= tol_of(tol, fmax(sc->chi2, bc->chi2)))
+      mark(&out->fragile_step, so.plan_len);
+    out->n_hits = bc->n_hits;
+    out->n_miss = bc->n_miss;
+    out->chi2 = bc->chi2;
+    memcpy(out->par, bc->p, sizeof(bc->p));
+    memcpy(out->cov, bc->C, sizeof(bc->C));
+    memcpy(out->hit, bc->hist, sizeof(bc->hist));
+  }
+  free(cands);
+  free(next);
+  free(fin);
+  free(pp);
+  free(Cp);
+}
+
+int orc_find_event(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                   int32_t n_layers, int32_t n_hits, const float *x, const float *y,
+                   const float *z, const float *var_u, const float *var_v,
+                   const int32_t *layer, int32_t n_seeds, const int32_t *seed_hits,
+                   orc_track *out) {
+  if (cfg->n_cand < 1) return -1;
+  /* hits of each layer in original order (the brute-force scan below
+   * visits every hit of the layer) */
+  int32_t *off = (int32_t *)calloc((size_t)n_layers + 1, sizeof(int32_t));
+  int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_hits > 0 ? n_hits : 1));
+  for (int32_t i = 0; i < n_hits; ++i) {
+    if (layer[i] < 0 || layer[i] >= n_layers) {
+      free(off);
+      free(idx);
+      return -1;
+    }
+    off[layer[i] + 1]++;
+  }
+  for (int32_t L = 0; L < n_layers; ++L) off[L + 1] += off[L];
+  int32_t *fill = (int32_t *)calloc((size_t)n_layers, sizeof(int32_t));
+  for (int32_t i = 0; i < n_hits; ++i) idx[off[layer[i]] + fill[layer[i]]++] = i;
+  for (int32_t s = 0; s < n_seeds; ++s)
+    find_one(cfg, tol, layers, n_layers, off, idx, x, y, z, var_u, var_v, layer,
+             &seed_hits[3 * s], &out[s]);
+  free(off);
+  free(idx);
+  free(fill);
+  return 0;
+}
+
+/* ------------------------------------------------------------- fitting */
+
+/* Kalman fit through a known hit sequence (the paper's vectorized fitting,
+ * Introduction): for every hit, propagate to its surface, add the
+ * scattering noise, update. */
+int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36], int32_t n,
+                  const int32_t *kinds, const double *pos, const double *hits,
+                  const double *var_u, const double *var_v, double p_out[6],
+                  double C_out[36], double *chi2_sum) {
+  double p[6], C[36];
+  memcpy(p, p0, sizeof(p));
+  memcpy(C, C0, sizeof(C));
+  double sum = 0.0;
+  for (int32_t k = 0; k < n; ++k) {
+    orc_layer Lr = {kinds[k], pos[k], 0.0, 0.0};
+    double pp[6], Cp[36];
+    if (orc_propagate(p, C, &Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL) != ORC_OK)
+      return -(k + 1);
+    orc_add_ms(pp, cfg->ms_sigma, Cp);
+    double c2;
+    if (!orc_update_hit(pp, Cp, kinds[k], &hits[3 * k], var_u[k], var_v[k], &c2)) return -(k + 1);
+    sum += c2;
+    memcpy(p, pp, sizeof(p));
+    memcpy(C, Cp, sizeof(C));
+  }
+  memcpy(p_out, p, sizeof(p));
+  memcpy(C_out, C, sizeof(C));
+  *chi2_sum = sum;
+  return 0;
+}

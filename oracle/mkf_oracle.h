@@ -1,0 +1,167 @@
+/*
+ * mkf_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU reference of the Kalman-filter track finding and
+ * fitting hot path of "Parallelized and Vectorized Tracking Using Kalman
+ * Filters with CMS Detector Geometry and Events" (arXiv:1811.04141).
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg use
+ * it.  It shares no code, header or constant with the GPU library.
+ *
+ * The paper prints no equations.  Each function names the passage it
+ * follows and the textbook definition used where the paper is silent.
+ *
+ * Units: cm, GeV/c, tesla, radians.
+ * State p = (x, y, z, q/pT, phi, theta): a point on the track, the signed
+ * inverse transverse momentum, the momentum azimuth and the polar angle.
+ * Covariances are full 6x6 row-major double arrays here (the oracle does
+ * not pack triangles).
+ */
+#ifndef MKF_ORACLE_H
+#define MKF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Curvature constant c * 1e-9: transverse radius rho = pT / (k |q| B). */
+#define ORC_KAPPA 0.299792458e-2
+
+#define ORC_MAX_PLAN 32
+
+/* Outcome of a propagation. */
+#define ORC_OK 0
+#define ORC_NO_CROSSING 1   /* no root in the first half turn beyond l_min */
+#define ORC_OUT_OF_EXTENT 2 /* crossing outside the widened layer extent */
+
+/* History codes in a track's per-plan-layer hit list. */
+#define ORC_HIT_MISS (-1)
+#define ORC_HIT_SKIP (-2)
+#define ORC_HIT_NONE (-3) /* the candidate retired before this layer */
+
+typedef struct {
+  int32_t kind;  /* 0 barrel cylinder, 1 endcap disk */
+  double pos;    /* radius R (barrel) or signed z position Z (disk) */
+  double ext_lo; /* barrel: lowest z; disk: inner radius */
+  double ext_hi; /* barrel: highest z; disk: outer radius */
+} orc_layer;
+
+typedef struct {
+  double bz;          /* field along +z, tesla */
+  double kappa;       /* curvature constant (normally ORC_KAPPA) */
+  double chi2_cut;    /* accept a hit if chi2 < chi2_cut (2 dof) */
+  double ms_sigma;    /* multiple-scattering angle per crossed layer, rad */
+  double edge_margin; /* extent widening for plan and crossing tests, cm */
+  double l_min;       /* smallest admissible transverse path, cm */
+  int32_t n_cand;     /* candidates kept per seed */
+  int32_t max_holes;  /* misses allowed per candidate */
+  double init_var[6]; /* diagonal seed prior variances */
+} orc_cfg;
+
+/* ---- single-state primitives (exposed for the tests) ---------------- */
+
+/* Exact helix transport by transverse path length l. */
+void orc_transport(const double p[6], double l, double bz, double kappa,
+                   double out[6]);
+
+/* Path length to a surface: smallest l > l_min inside the first half
+ * turn.  Returns ORC_OK or ORC_NO_CROSSING. */
+int orc_path_to_barrel(const double p[6], double R, double bz, double kappa,
+                       double l_min, double *l);
+int orc_path_to_disk(const double p[6], double Z, double bz, double kappa,
+                     double l_min, double *l);
+
+/* Full propagation to a layer: state, surface-constrained Jacobian F
+ * (6x6, may be NULL), transported covariance F C F^T (may be NULL when C is
+ * NULL).  check_extent = 0 skips the extent test (used by the fit).
+ * Multiple scattering is NOT added here. */
+int orc_propagate(const double p[6], const double C[36], const orc_layer *L,
+                  double bz, double kappa, double l_min, double edge_margin,
+                  int check_extent, double p_out[6], double C_out[36],
+                  double F_out[36], double *l_out);
+
+/* Multiple-scattering noise for state p with angle sigma, added to C. */
+void orc_add_ms(const double p[6], double sigma, double C[36]);
+
+/* Local measurement of a hit at the predicted state: residual r[2],
+ * projection H (2x6) and hit variances.  Returns 0 if the hit lies in the
+ * wrong hemisphere (barrel only), 1 otherwise. */
+int orc_measure(const double p[6], int kind, const double hit[3],
+                double r[2], double H[12]);
+
+/* chi2 = r^T (H C H^T + V)^-1 r.  Returns 0 if incompatible (hemisphere). */
+int orc_chi2(const double p[6], const double C[36], int kind,
+             const double hit[3], double var_u, double var_v, double *chi2);
+
+/* General linear Kalman update with an m-dimensional measurement
+ * (m <= 2): K = C H^T S^-1, p += K r, C -= K S K^T (symmetrised).
+ * joseph != 0 uses (I-KH) C (I-KH)^T + K V K^T instead.  chi2 out. */
+void orc_kf_update(double p[6], double C[36], int m, const double *H,
+                   const double *r, const double *V, int joseph,
+                   double *chi2);
+
+/* Hit update at a layer: measure + orc_kf_update + wrap phi. */
+int orc_update_hit(double p[6], double C[36], int kind, const double hit[3],
+                   double var_u, double var_v, double *chi2);
+
+/* ---- seeding, plan, find, fit --------------------------------------- */
+
+typedef struct {
+  int32_t ok;          /* 1 if seeding succeeded */
+  double par[6];       /* seed state on the third seed layer */
+  double cov[36];
+  int32_t plan_len;
+  int32_t plan[ORC_MAX_PLAN];
+  double plan_l[ORC_MAX_PLAN];
+  int32_t plan_fragile; /* a crossing lies within tol of a widened edge */
+} orc_seed_out;
+
+/* h: 3 hits x (x,y,z); hv: 3 hits x (var_u, var_v); hl: their layers.
+ * pos_tol: distance to a widened edge below which the plan is flagged. */
+int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
+             const double h[9], const double hv[6], const int32_t hl[3],
+             double pos_tol, orc_seed_out *out);
+
+typedef struct {
+  int32_t seed_ok;
+  int32_t n_hits, n_miss, plan_len;
+  int32_t plan[ORC_MAX_PLAN];
+  int32_t hit[ORC_MAX_PLAN];
+  double par[6];
+  double cov[36];
+  double chi2;
+  /* parity bookkeeping: first plan step (0-based) at which a decision was
+   * within tolerance of a cut or a tie, plan_len if the final choice was,
+   * -1 if no decision was fragile. */
+  int32_t fragile_step;
+  int64_t n_steps; /* candidate-layer steps taken for this seed */
+} orc_track;
+
+typedef struct {
+  double chi2_rel, chi2_abs; /* chi2 tolerance: rel * chi2 + abs */
+  double pos_tol;            /* cm, for extent-edge decisions */
+} orc_tol;
+
+/* Clone-engine track finding for n_seeds seeds of one event.  Hits are
+ * the event's hits (FP32 inputs, original order).  seed_hits holds 3
+ * event-local hit indices per seed. */
+int orc_find_event(const orc_cfg *cfg, const orc_tol *tol,
+                   const orc_layer *layers, int32_t n_layers, int32_t n_hits,
+                   const float *x, const float *y, const float *z,
+                   const float *var_u, const float *var_v,
+                   const int32_t *layer, int32_t n_seeds,
+                   const int32_t *seed_hits, orc_track *out);
+
+/* Kalman fit of one track through n hits on given surfaces (no search,
+ * no extent test).  kinds/pos describe each hit's surface. */
+int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36],
+                  int32_t n, const int32_t *kinds, const double *pos,
+                  const double *hits /* n x 3 */, const double *var_u,
+                  const double *var_v, double p_out[6], double C_out[36],
+                  double *chi2_sum);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

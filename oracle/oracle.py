@@ -1,0 +1,252 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the FP64 CPU oracle
+(mkf_oracle.c).  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg import this module; the GPU library never does.
+"""
+import ctypes as C
+import os
+import subprocess
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mkf_oracle.c")
+HDR = os.path.join(HERE, "mkf_oracle.h")
+LIB = os.path.join(HERE, "libmkf_oracle.so")
+
+MAX_PLAN = 32
+OK, NO_CROSSING, OUT_OF_EXTENT = 0, 1, 2
+HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math)."""
+    stale = (not os.path.exists(LIB) or
+             os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(HDR)))
+    if force or stale:
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Layer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pos", C.c_double), ("ext_lo", C.c_double),
+                ("ext_hi", C.c_double)]
+
+
+class Cfg(C.Structure):
+    _fields_ = [("bz", C.c_double), ("kappa", C.c_double), ("chi2_cut", C.c_double),
+                ("ms_sigma", C.c_double), ("edge_margin", C.c_double), ("l_min", C.c_double),
+                ("n_cand", C.c_int32), ("max_holes", C.c_int32), ("init_var", C.c_double * 6)]
+
+
+class SeedOut(C.Structure):
+    _fields_ = [("ok", C.c_int32), ("par", C.c_double * 6), ("cov", C.c_double * 36),
+                ("plan_len", C.c_int32), ("plan", C.c_int32 * MAX_PLAN),
+                ("plan_l", C.c_double * MAX_PLAN), ("plan_fragile", C.c_int32)]
+
+
+class Track(C.Structure):
+    _fields_ = [("seed_ok", C.c_int32), ("n_hits", C.c_int32), ("n_miss", C.c_int32),
+                ("plan_len", C.c_int32), ("plan", C.c_int32 * MAX_PLAN),
+                ("hit", C.c_int32 * MAX_PLAN), ("par", C.c_double * 6),
+                ("cov", C.c_double * 36), ("chi2", C.c_double),
+                ("fragile_step", C.c_int32), ("n_steps", C.c_int64)]
+
+
+class Tol(C.Structure):
+    _fields_ = [("chi2_rel", C.c_double), ("chi2_abs", C.c_double), ("pos_tol", C.c_double)]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_F = C.POINTER(C.c_float)
+_I = C.POINTER(C.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        L = _lib
+        L.orc_transport.argtypes = [_D, C.c_double, C.c_double, C.c_double, _D]
+        L.orc_path_to_barrel.argtypes = [_D, C.c_double, C.c_double, C.c_double, C.c_double, _D]
+        L.orc_path_to_disk.argtypes = L.orc_path_to_barrel.argtypes
+        L.orc_propagate.argtypes = [_D, _D, C.POINTER(Layer), C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int, _D, _D, _D, _D]
+        L.orc_add_ms.argtypes = [_D, C.c_double, _D]
+        L.orc_measure.argtypes = [_D, C.c_int, _D, _D, _D]
+        L.orc_chi2.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, _D]
+        L.orc_kf_update.argtypes = [_D, _D, C.c_int, _D, _D, _D, C.c_int, _D]
+        L.orc_update_hit.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, _D]
+        L.orc_seed.argtypes = [C.POINTER(Cfg), C.POINTER(Layer), C.c_int32, _D, _D, _I,
+                               C.c_double, C.POINTER(SeedOut)]
+        L.orc_find_event.argtypes = [C.POINTER(Cfg), C.POINTER(Tol), C.POINTER(Layer), C.c_int32,
+                                     C.c_int32, _F, _F, _F, _F, _F, _I, C.c_int32, _I,
+                                     C.POINTER(Track)]
+        L.orc_fit_track.argtypes = [C.POINTER(Cfg), _D, _D, C.c_int32, _I, _D, _D, _D, _D, _D,
+                                    _D, _D]
+    return _lib
+
+
+def _d(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None:
+        assert a.size == n, (a.shape, n)
+    return a
+
+
+def _p(a, t=_D):
+    return a.ctypes.data_as(t)
+
+
+def make_layers(layers) -> "C.Array":
+    arr = (Layer * len(layers))()
+    for i, l in enumerate(layers):
+        arr[i] = Layer(int(l.kind), float(l.pos), float(l.ext_lo), float(l.ext_hi))
+    return arr
+
+
+def make_cfg(fc) -> Cfg:
+    c = Cfg()
+    c.bz, c.kappa, c.chi2_cut = fc.bz, fc.kappa, fc.chi2_cut
+    c.ms_sigma, c.edge_margin, c.l_min = fc.ms_sigma, fc.edge_margin, fc.l_min
+    c.n_cand, c.max_holes = fc.n_cand, fc.max_holes
+    for i in range(6):
+        c.init_var[i] = fc.init_var[i]
+    return c
+
+
+# ------------------------------------------------------------ primitives
+
+def transport(p, l, bz, kappa):
+    p = _d(p, 6)
+    out = np.zeros(6)
+    lib().orc_transport(_p(p), l, bz, kappa, _p(out))
+    return out
+
+
+def path_to_barrel(p, R, bz, kappa, l_min=1e-4):
+    p = _d(p, 6)
+    l = np.zeros(1)
+    st = lib().orc_path_to_barrel(_p(p), R, bz, kappa, l_min, _p(l))
+    return float(l[0]) if st == OK else None
+
+
+def path_to_disk(p, Z, bz, kappa, l_min=1e-4):
+    p = _d(p, 6)
+    l = np.zeros(1)
+    st = lib().orc_path_to_disk(_p(p), Z, bz, kappa, l_min, _p(l))
+    return float(l[0]) if st == OK else None
+
+
+def propagate(p, Cm, layer, bz, kappa, l_min=1e-4, edge_margin=0.0, check_extent=True):
+    """Returns (status, p', C', F, l)."""
+    p = _d(p, 6)
+    Cm = _d(Cm, 36) if Cm is not None else None
+    lay = Layer(int(layer.kind), float(layer.pos), float(layer.ext_lo), float(layer.ext_hi))
+    po, Co, Fo, lo = np.zeros(6), np.zeros(36), np.zeros(36), np.zeros(1)
+    st = lib().orc_propagate(_p(p), _p(Cm) if Cm is not None else None, C.byref(lay), bz, kappa,
+                             l_min, edge_margin, int(check_extent), _p(po),
+                             _p(Co) if Cm is not None else None, _p(Fo), _p(lo))
+    return st, po, Co.reshape(6, 6), Fo.reshape(6, 6), float(lo[0])
+
+
+def add_ms(p, sigma, Cm):
+    p = _d(p, 6)
+    out = _d(Cm, 36).copy()
+    lib().orc_add_ms(_p(p), sigma, _p(out))
+    return out.reshape(6, 6)
+
+
+def measure(p, kind, hit):
+    p, hit = _d(p, 6), _d(hit, 3)
+    r, H = np.zeros(2), np.zeros(12)
+    ok = lib().orc_measure(_p(p), int(kind), _p(hit), _p(r), _p(H))
+    return bool(ok), r, H.reshape(2, 6)
+
+
+def chi2(p, Cm, kind, hit, var_u, var_v):
+    p, Cm, hit = _d(p, 6), _d(Cm, 36), _d(hit, 3)
+    out = np.zeros(1)
+    ok = lib().orc_chi2(_p(p), _p(Cm), int(kind), _p(hit), var_u, var_v, _p(out))
+    return float(out[0]) if ok else None
+
+
+def kf_update(p, Cm, H, r, V, joseph=False):
+    p = _d(p, 6).copy()
+    Cm = _d(Cm, 36).copy()
+    H = _d(H)
+    m = H.size // 6
+    r, V = _d(r, m), _d(V, m * m)
+    c2 = np.zeros(1)
+    lib().orc_kf_update(_p(p), _p(Cm), m, _p(H), _p(r), _p(V), int(joseph), _p(c2))
+    return p, Cm.reshape(6, 6), float(c2[0])
+
+
+def update_hit(p, Cm, kind, hit, var_u, var_v):
+    p = _d(p, 6).copy()
+    Cm = _d(Cm, 36).copy()
+    hit = _d(hit, 3)
+    c2 = np.zeros(1)
+    ok = lib().orc_update_hit(_p(p), _p(Cm), int(kind), _p(hit), var_u, var_v, _p(c2))
+    return bool(ok), p, Cm.reshape(6, 6), float(c2[0])
+
+
+def seed(fc, layers, h, hv, hl, pos_tol=0.0):
+    cfg = make_cfg(fc)
+    lay = make_layers(layers)
+    h, hv = _d(h, 9), _d(hv, 6)
+    hl = np.ascontiguousarray(hl, np.int32)
+    out = SeedOut()
+    lib().orc_seed(C.byref(cfg), lay, len(layers), _p(h), _p(hv), _p(hl, _I), pos_tol,
+                   C.byref(out))
+    n = out.plan_len
+    return {"ok": bool(out.ok), "par": np.array(out.par[:]),
+            "cov": np.array(out.cov[:]).reshape(6, 6), "plan": np.array(out.plan[:n], np.int32),
+            "plan_l": np.array(out.plan_l[:n]), "plan_fragile": bool(out.plan_fragile)}
+
+
+DEFAULT_TOL = (1e-3, 1e-2, 1e-3)  # chi2 rel, chi2 abs, cm
+
+
+def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL):
+    """Clone-engine finding for the seeds of one event (all seeds if None).
+    Returns a list of dicts, one per seed."""
+    cfg = make_cfg(fc)
+    lay = make_layers(layers)
+    t = Tol(*tol)
+    seeds = ev.seeds if seeds is None else seeds
+    seeds = np.ascontiguousarray(seeds, np.int32).reshape(-1, 3)
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z, ev.var_u, ev.var_v)]
+    layer = np.ascontiguousarray(ev.layer, np.int32)
+    out = (Track * max(1, seeds.shape[0]))()
+    rc = lib().orc_find_event(C.byref(cfg), C.byref(t), lay, len(layers), int(layer.shape[0]),
+                              *[_p(a, _F) for a in arrs], _p(layer, _I), int(seeds.shape[0]),
+                              _p(seeds, _I), out)
+    if rc != 0:
+        raise ValueError("oracle find failed")
+    res = []
+    for i in range(seeds.shape[0]):
+        o = out[i]
+        n = o.plan_len
+        res.append({"seed_ok": bool(o.seed_ok), "n_hits": o.n_hits, "n_miss": o.n_miss,
+                    "plan": np.array(o.plan[:n], np.int32), "hit": np.array(o.hit[:n], np.int32),
+                    "par": np.array(o.par[:]), "cov": np.array(o.cov[:]).reshape(6, 6),
+                    "chi2": o.chi2, "fragile_step": o.fragile_step, "n_steps": o.n_steps})
+    return res
+
+
+def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v):
+    cfg = make_cfg(fc)
+    p0, C0 = _d(p0, 6), _d(C0, 36)
+    kinds = np.ascontiguousarray(kinds, np.int32)
+    n = kinds.shape[0]
+    pos, hits = _d(pos, n), _d(hits, 3 * n)
+    var_u, var_v = _d(var_u, n), _d(var_v, n)
+    po, Co, c2 = np.zeros(6), np.zeros(36), np.zeros(1)
+    rc = lib().orc_fit_track(C.byref(cfg), _p(p0), _p(C0), n, _p(kinds, _I), _p(pos), _p(hits),
+                             _p(var_u), _p(var_v), _p(po), _p(Co), _p(c2))
+    return rc, po, Co.reshape(6, 6), float(c2[0])

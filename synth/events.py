@@ -1,0 +1,317 @@
+"""Seeded synthetic event generator (input side only).
+
+It simulates charged particles in a uniform solenoid field crossing the
+layers of a workload geometry, records smeared hits, adds noise hits and
+forms truth-matched seeds from each track's first three hits.  It describes
+the truth and carries no part of the filter (no covariance, no chi2, no
+Kalman update, no hit selection); its trajectory code is a separate
+centre-and-angle description of the circle, independent of the oracle's and
+the GPU library's propagation.
+
+Random numbers come from numpy's Philox counter-based generator, keyed by
+(workload master seed, event index), so every event is reproducible on its
+own.
+"""
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+from .workloads import BARREL, DISK, KAPPA, SIGMA_R, SIGMA_RPHI, SIGMA_Z, Workload
+
+
+def event_rng(master_seed: int, event: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=(int(master_seed) << 32) | int(event)))
+
+
+@dataclass
+class Event:
+    x: np.ndarray        # float32 hit coordinates
+    y: np.ndarray
+    z: np.ndarray
+    var_u: np.ndarray    # float32 hit variances in the local frame
+    var_v: np.ndarray
+    layer: np.ndarray    # int32
+    track: np.ndarray    # int32 truth track id, -1 for noise
+    seeds: np.ndarray    # (n_seeds, 3) int32 event-local hit indices
+    seed_track: np.ndarray  # int32 truth track of each seed
+    # truth per recorded hit (float64): state after the layer at that hit
+    # (position on the surface, q/pT, phi, theta after the scattering kick)
+    truth_state: np.ndarray  # (n_hits, 6); NaN rows for noise
+    track_hits: List[np.ndarray]  # per track: event-local hit indices in order
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.x.shape[0])
+
+
+def _wrap(a):
+    return (a + np.pi) % (2.0 * np.pi) - np.pi
+
+
+def _next_crossings(cx, cy, rho, sgn, x, y, z, cot, budget, kinds, poss, eps):
+    """Transverse path length to the next crossing of every surface.
+
+    The track is the circle of centre (cx, cy) and radius rho travelled with
+    sense sgn (+1 anticlockwise); z rises by cot per unit transverse path.
+    Returns an (n_tracks, n_surfaces) array, inf where there is no crossing
+    within `budget` (the remaining transverse path of the half turn)."""
+    n = x.shape[0]
+    out = np.full((n, len(kinds)), np.inf)
+    beta0 = np.arctan2(y - cy, x - cx)
+    d = np.hypot(cx, cy)
+    dhat_x, dhat_y = cx / d, cy / d
+    for j, (kind, pos) in enumerate(zip(kinds, poss)):
+        if kind == BARREL:
+            R = pos
+            # intersection of circle(centre, rho) with circle(origin, R):
+            # the chord midpoint lies at distance a from the origin along
+            # the centre direction, the chord half-length is hh
+            a = (R * R - rho * rho + d * d) / (2.0 * d)
+            hh2 = R * R - a * a
+            ok = hh2 >= 0.0
+            hh = np.sqrt(np.where(ok, hh2, 0.0))
+            best = np.full(n, np.inf)
+            for s in (1.0, -1.0):
+                px = a * dhat_x - s * hh * dhat_y
+                py = a * dhat_y + s * hh * dhat_x
+                beta = np.arctan2(py - cy, px - cx)
+                dturn = np.mod(sgn * (beta - beta0), 2.0 * np.pi)
+                l = dturn * rho
+                good = ok & (l > eps) & (l < budget)
+                best = np.where(good & (l < best), l, best)
+            out[:, j] = best
+        else:
+            Z = pos
+            with np.errstate(divide="ignore", invalid="ignore"):
+                l = (Z - z) / cot
+            good = np.isfinite(l) & (l > eps) & (l < budget)
+            out[:, j] = np.where(good, l, np.inf)
+    return out
+
+
+def simulate_tracks(rng, n, layers, bz, recipe, pt=None, eta=None, phi=None, q=None,
+                    vertex=None, max_iter=64):
+    """Simulate n tracks; returns per-crossing records (track, layer, true
+    position, state after the layer) in crossing order, plus the initial
+    parameters."""
+    if q is None:
+        q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    if pt is None:
+        pt = np.exp(rng.uniform(np.log(recipe.pt_lo), np.log(recipe.pt_hi), n))
+    if eta is None:
+        eta = rng.uniform(-recipe.eta_max, recipe.eta_max, n)
+    if phi is None:
+        phi = rng.uniform(-np.pi, np.pi, n)
+    if vertex is None:
+        vx = rng.normal(0.0, recipe.sigma_vxy, n)
+        vy = rng.normal(0.0, recipe.sigma_vxy, n)
+        vz = rng.normal(0.0, recipe.sigma_vz, n)
+    else:
+        vx, vy, vz = vertex
+    theta = 2.0 * np.arctan(np.exp(-eta))
+    init = np.stack([vx, vy, vz, q / pt, phi, theta], axis=1)
+
+    kinds = [l.kind for l in layers]
+    poss = [l.pos for l in layers]
+    x, y, z = vx.copy(), vy.copy(), vz.copy()
+    ph, th, ptc = phi.copy(), theta.copy(), pt.copy()
+    turned = np.zeros(n)          # transverse turning angle so far
+    alive = np.ones(n, bool)
+    eps = 1e-6
+    recs = []
+    for _ in range(max_iter):
+        idx = np.nonzero(alive)[0]
+        if idx.size == 0:
+            break
+        omega = -KAPPA * bz * q[idx] / ptc[idx]      # signed curvature
+        rho = 1.0 / np.abs(omega)
+        sgn = np.sign(omega)
+        # centre: a quarter turn from the direction, toward the turning side
+        cx = x[idx] - np.sin(ph[idx]) / omega
+        cy = y[idx] + np.cos(ph[idx]) / omega
+        cot = np.cos(th[idx]) / np.sin(th[idx])
+        budget = (np.pi - turned[idx]) * rho
+        L = _next_crossings(cx, cy, rho, sgn, x[idx], y[idx], z[idx], cot, budget,
+                            kinds, poss, eps)
+        j = np.argmin(L, axis=1)
+        l = L[np.arange(idx.size), j]
+        done = ~np.isfinite(l)
+        alive[idx[done]] = False
+        keep = ~done
+        idx, j, l = idx[keep], j[keep], l[keep]
+        omega, cx, cy, cot, rho = omega[keep], cx[keep], cy[keep], cot[keep], rho[keep]
+        if idx.size == 0:
+            break
+        beta0 = np.arctan2(y[idx] - cy, x[idx] - cx)
+        beta = beta0 + omega * l
+        nx = cx + rho * np.cos(beta)
+        ny = cy + rho * np.sin(beta)
+        nz = z[idx] + l * cot
+        # the layer's tangent-plane definition puts a barrel crossing on r = R
+        # and a disk crossing on z = Z exactly
+        is_b = np.array([kinds[k] == BARREL for k in j])
+        posj = np.array([poss[k] for k in j])
+        rr = np.hypot(nx, ny)
+        nx = np.where(is_b, nx * posj / rr, nx)
+        ny = np.where(is_b, ny * posj / rr, ny)
+        nz = np.where(is_b, nz, posj)
+        x[idx], y[idx], z[idx] = nx, ny, nz
+        ph[idx] = _wrap(ph[idx] + omega * l)
+        turned[idx] += np.abs(omega) * l
+        lo = np.array([layers[k].ext_lo for k in j])
+        hi = np.array([layers[k].ext_hi for k in j])
+        qv = np.where(is_b, nz, np.hypot(nx, ny))
+        inside = (qv >= lo) & (qv <= hi)
+        sel = np.nonzero(inside)[0]
+        if sel.size:
+            t = idx[sel]
+            # scattering on the crossed layer, after the hit is made
+            if recipe.ms_sigma > 0.0:
+                dth = rng.normal(0.0, recipe.ms_sigma, t.size)
+                dal = rng.normal(0.0, recipe.ms_sigma, t.size)
+                p_tot = ptc[t] / np.sin(th[t])
+                ph[t] = _wrap(ph[t] + dal / np.sin(th[t]))
+                th[t] = th[t] + dth
+                ptc[t] = p_tot * np.sin(th[t])
+            state = np.stack([x[t], y[t], z[t], q[t] / ptc[t], ph[t], th[t]], axis=1)
+            recs.append((t, j[sel], state))
+    if recs:
+        trk = np.concatenate([r[0] for r in recs])
+        lay = np.concatenate([r[1] for r in recs]).astype(np.int32)
+        st = np.concatenate([r[2] for r in recs])
+    else:
+        trk = np.zeros(0, np.int64)
+        lay = np.zeros(0, np.int32)
+        st = np.zeros((0, 6))
+    return init, trk, lay, st
+
+
+def _smear(rng, layers, lay, st):
+    """Smeared hit positions on their layer surfaces and their variances."""
+    n = lay.shape[0]
+    kind = np.array([layers[k].kind for k in lay]) if n else np.zeros(0, int)
+    posv = np.array([layers[k].pos for k in lay]) if n else np.zeros(0)
+    x, y, z = st[:, 0], st[:, 1], st[:, 2]
+    r = np.hypot(x, y)
+    phi = np.arctan2(y, x)
+    e_u = rng.normal(0.0, SIGMA_RPHI, n)
+    e_v = rng.normal(0.0, 1.0, n)
+    is_b = kind == BARREL
+    # barrel: along the cylinder in r-phi, and in z
+    rb = np.where(is_b, posv, r + e_v * SIGMA_R)
+    phib = phi + e_u / np.where(is_b, posv, r)
+    hx = rb * np.cos(phib)
+    hy = rb * np.sin(phib)
+    hz = np.where(is_b, z + e_v * SIGMA_Z, posv)
+    vu = np.full(n, SIGMA_RPHI ** 2)
+    vv = np.where(is_b, SIGMA_Z ** 2, SIGMA_R ** 2)
+    return hx, hy, hz, vu, vv
+
+
+def _noise(rng, layers, counts, frac):
+    xs, ys, zs, vus, vvs, ls = [], [], [], [], [], []
+    for k, layer in enumerate(layers):
+        m = int(round(frac * counts[k]))
+        if m == 0:
+            continue
+        phi = rng.uniform(-np.pi, np.pi, m)
+        if layer.kind == BARREL:
+            r = np.full(m, layer.pos)
+            z = rng.uniform(layer.ext_lo, layer.ext_hi, m)
+            vv = np.full(m, SIGMA_Z ** 2)
+        else:
+            r = np.sqrt(rng.uniform(layer.ext_lo ** 2, layer.ext_hi ** 2, m))
+            z = np.full(m, layer.pos)
+            vv = np.full(m, SIGMA_R ** 2)
+        xs.append(r * np.cos(phi))
+        ys.append(r * np.sin(phi))
+        zs.append(z)
+        vus.append(np.full(m, SIGMA_RPHI ** 2))
+        vvs.append(vv)
+        ls.append(np.full(m, k, np.int32))
+    if not xs:
+        e = np.zeros(0)
+        return e, e, e, e, e, np.zeros(0, np.int32)
+    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(zs),
+            np.concatenate(vus), np.concatenate(vvs), np.concatenate(ls))
+
+
+def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None) -> Event:
+    rng = event_rng(w.master_seed, event)
+    lo, hi = w.n_tracks
+    if n_tracks is None:
+        n_tracks = lo if lo == hi else int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+    init, trk, lay, st = simulate_tracks(rng, n_tracks, w.layers, w.find.bz, w.recipe)
+    # 2% (or as configured) independent loss of hits
+    if w.recipe.hit_ineff > 0.0:
+        keep = rng.random(trk.shape[0]) >= w.recipe.hit_ineff
+        trk, lay, st = trk[keep], lay[keep], st[keep]
+    hx, hy, hz, vu, vv = _smear(rng, w.layers, lay, st)
+    counts = np.bincount(lay, minlength=len(w.layers))
+    nx, ny, nz, nvu, nvv, nl = _noise(rng, w.layers, counts, w.recipe.noise_frac)
+    X = np.concatenate([hx, nx]).astype(np.float32)
+    Y = np.concatenate([hy, ny]).astype(np.float32)
+    Zc = np.concatenate([hz, nz]).astype(np.float32)
+    VU = np.concatenate([vu, nvu]).astype(np.float32)
+    VV = np.concatenate([vv, nvv]).astype(np.float32)
+    LAY = np.concatenate([lay, nl]).astype(np.int32)
+    TRK = np.concatenate([trk, np.full(nl.shape[0], -1)]).astype(np.int32)
+    TS = np.concatenate([st, np.full((nl.shape[0], 6), np.nan)])
+    # hits in random order: nothing may depend on the input order
+    perm = rng.permutation(X.shape[0])
+    X, Y, Zc, VU, VV, LAY, TRK, TS = (a[perm] for a in (X, Y, Zc, VU, VV, LAY, TRK, TS))
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.shape[0])
+    # per-track hit lists in crossing order (records were made in order)
+    n_true = trk.shape[0]
+    new_idx = inv[:n_true]
+    order = np.argsort(trk, kind="stable")
+    bounds = np.searchsorted(trk[order], np.arange(n_tracks + 1))
+    track_hits = [new_idx[order[bounds[t]:bounds[t + 1]]].astype(np.int32)
+                  for t in range(n_tracks)]
+    seeds, seed_track = [], []
+    for t, h in enumerate(track_hits):
+        if h.shape[0] >= 3:
+            seeds.append(h[:3])
+            seed_track.append(t)
+    seeds = np.array(seeds, np.int32).reshape(-1, 3)
+    return Event(X, Y, Zc, VU, VV, LAY, TRK, seeds, np.array(seed_track, np.int32),
+                 TS, track_hits)
+
+
+@dataclass
+class EventBatch:
+    """Several events concatenated: hits of event e are
+    [ev_off[e], ev_off[e+1]); seeds carry their event and event-local
+    hit indices."""
+    ev_off: np.ndarray      # int64 (n_events + 1)
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    var_u: np.ndarray
+    var_v: np.ndarray
+    layer: np.ndarray
+    seed_event: np.ndarray  # int32
+    seed_hits: np.ndarray   # (n_seeds, 3) int32, event-local
+    events: List[Event]
+
+    @property
+    def n_events(self) -> int:
+        return len(self.events)
+
+
+def make_batch(events: List[Event]) -> EventBatch:
+    off = np.zeros(len(events) + 1, np.int64)
+    off[1:] = np.cumsum([e.n_hits for e in events])
+    cat = lambda f: np.concatenate([getattr(e, f) for e in events])
+    se = np.concatenate([np.full(e.seeds.shape[0], i, np.int32) for i, e in enumerate(events)])
+    sh = np.concatenate([e.seeds for e in events]).astype(np.int32).reshape(-1, 3)
+    return EventBatch(off, cat("x"), cat("y"), cat("z"), cat("var_u"), cat("var_v"),
+                      cat("layer"), se, sh, events)
+
+
+def generate(w: Workload, events=None) -> EventBatch:
+    if events is None:
+        events = range(w.n_events)
+    return make_batch([generate_event(w, e) for e in events])

@@ -1,0 +1,140 @@
+"""Detector geometries, event recipes and method settings of the synthetic
+workloads.  Plain values only: both the GPU library and the CPU oracle
+receive them as arguments; nothing here computes any part of the method.
+
+The paper's sample (simulated ttbar events with 70 pile-up collisions in the
+CMS-2017 geometry, Section 3) is not available, so seeded synthetic events of
+the shapes below stand in for it.
+"""
+from dataclasses import dataclass, field, replace
+from typing import List, Tuple
+
+import numpy as np
+
+KAPPA = 0.299792458e-2  # GeV / (T cm): rho = pT / (KAPPA |q| B)
+
+BARREL, DISK = 0, 1
+
+
+@dataclass(frozen=True)
+class Layer:
+    kind: int          # BARREL or DISK
+    pos: float         # radius (barrel) or signed z (disk), cm
+    ext_lo: float      # barrel: lowest z; disk: inner radius
+    ext_hi: float      # barrel: highest z; disk: outer radius
+    var_u_max: float   # largest hit variance along u on this layer, cm^2
+    var_v_max: float   # largest hit variance along v on this layer, cm^2
+    n_phi_bins: int = 256
+    n_q_bins: int = 16
+
+
+BARREL_RADII = (4.0, 7.0, 11.0, 16.0, 25.0, 34.0, 43.0, 52.0, 61.0, 70.0)
+DISK_Z = tuple(120.0 + 20.0 * i for i in range(9))
+
+SIGMA_RPHI = 0.003   # cm, barrel and disk
+SIGMA_Z = 0.01       # cm, barrel
+SIGMA_R = 0.01       # cm, disk (the workload leaves it open; same as z)
+
+
+def barrel_layers(half_len: float = 100.0) -> List[Layer]:
+    return [Layer(BARREL, r, -half_len, half_len, SIGMA_RPHI ** 2, SIGMA_Z ** 2)
+            for r in BARREL_RADII]
+
+
+def disk_layers(r_min: float = 20.0, r_max: float = 110.0) -> List[Layer]:
+    plus = [Layer(DISK, z, r_min, r_max, SIGMA_RPHI ** 2, SIGMA_R ** 2) for z in DISK_Z]
+    minus = [Layer(DISK, -z, r_min, r_max, SIGMA_RPHI ** 2, SIGMA_R ** 2) for z in DISK_Z]
+    return plus + minus
+
+
+@dataclass(frozen=True)
+class FindConfig:
+    """Settings of the method (all readings of the paper's unstated
+    values)."""
+    bz: float = 3.8
+    kappa: float = KAPPA
+    chi2_cut: float = 30.0
+    n_cand: int = 6
+    max_holes: int = 3
+    ms_sigma: float = 0.001
+    edge_margin: float = 2.0
+    l_min: float = 1e-4
+    # diagonal seed prior: x, y, z (cm^2), q/pT ((c/GeV)^2), phi, theta (rad^2).
+    # It must be wide against what the three seed hits measure, since it is
+    # centred on the triplet estimate itself and would otherwise count the
+    # same data twice.
+    init_var: Tuple[float, ...] = (1.0, 1.0, 1.0, 1.0, 0.01, 0.01)
+
+
+@dataclass(frozen=True)
+class EventRecipe:
+    pt_lo: float = 0.5
+    pt_hi: float = 10.0
+    eta_max: float = 0.8
+    sigma_vxy: float = 0.01
+    sigma_vz: float = 5.0
+    ms_sigma: float = 0.0
+    hit_ineff: float = 0.0
+    noise_frac: float = 0.0
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    layers: Tuple[Layer, ...]
+    recipe: EventRecipe
+    find: FindConfig
+    n_events: int
+    n_tracks: Tuple[int, int]   # (lo, hi); lo == hi means fixed, else log-uniform
+    master_seed: int
+
+
+def small_barrel() -> Workload:
+    """1 event, 200 tracks, 10 cylinders, no material, no noise."""
+    return Workload(
+        name="barrel10_1x200",
+        layers=tuple(barrel_layers()),
+        recipe=EventRecipe(),
+        find=FindConfig(ms_sigma=0.0),
+        n_events=1, n_tracks=(200, 200), master_seed=0x5EED0001)
+
+
+def barrel_endcap(n_events: int = 100, n_tracks: int = 5000) -> Workload:
+    """Barrel + 2x9 disks; 100 events x 5,000 tracks; scattering,
+    inefficiency and noise."""
+    return Workload(
+        name=f"barrel10_disk18_{n_events}x{n_tracks}",
+        layers=tuple(barrel_layers() + disk_layers()),
+        recipe=EventRecipe(pt_lo=0.3, pt_hi=10.0, eta_max=2.4, ms_sigma=0.001,
+                           hit_ineff=0.02, noise_frac=0.3),
+        find=FindConfig(),
+        n_events=n_events, n_tracks=(n_tracks, n_tracks), master_seed=0x5EED0002)
+
+
+def batched_uneven(n_events: int = 512) -> Workload:
+    """Many events of uneven size: track counts log-uniform in 500-20,000."""
+    w = barrel_endcap()
+    return replace(w, name=f"barrel10_disk18_{n_events}x500-20000",
+                   n_events=n_events, n_tracks=(500, 20000), master_seed=0x5EED0003)
+
+
+def dense(n_events: int = 4) -> Workload:
+    """Dense finding events: 25,000 tracks with 50% noise."""
+    w = barrel_endcap()
+    return replace(w, name=f"barrel10_disk18_{n_events}x25000_noise50",
+                   recipe=replace(w.recipe, noise_frac=0.5),
+                   n_events=n_events, n_tracks=(25000, 25000), master_seed=0x5EED0005)
+
+
+def layer_arrays(layers) -> dict:
+    """Columns of a layer list, for marshalling."""
+    return {
+        "kind": np.array([l.kind for l in layers], np.int32),
+        "pos": np.array([l.pos for l in layers], np.float64),
+        "ext_lo": np.array([l.ext_lo for l in layers], np.float64),
+        "ext_hi": np.array([l.ext_hi for l in layers], np.float64),
+        "var_u_max": np.array([l.var_u_max for l in layers], np.float64),
+        "var_v_max": np.array([l.var_v_max for l in layers], np.float64),
+        "n_phi_bins": np.array([l.n_phi_bins for l in layers], np.int32),
+        "n_q_bins": np.array([l.n_q_bins for l in layers], np.int32),
+    }
