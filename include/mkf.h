@@ -1,0 +1,201 @@
+/*
+ * mkf.h -- C ABI of the MI355X (gfx950) Kalman-filter track finding and
+ * fitting library.
+ *
+ * The method is the one of "Parallelized and Vectorized Tracking Using
+ * Kalman Filters with CMS Detector Geometry and Events" (arXiv:1811.04141):
+ * for every track candidate and every layer of its layer plan, propagate
+ * the helix state and its covariance to the layer (barrel cylinder by
+ * radius, endcap disk by z), look up nearby hits in a binned layer index,
+ * score every candidate-hit pair by chi2, keep the best extensions per seed,
+ * and only then apply the Kalman update (the "clone engine", Introduction).
+ *
+ * Conventions
+ *  - Units: cm, GeV/c, tesla, radians.  State p = (x, y, z, q/pT, phi,
+ *    theta); covariance: 21 floats, upper triangle of the 6x6 matrix,
+ *    row-major: (0,0) (0,1) .. (0,5) (1,1) .. (1,5) (2,2) .. (5,5).
+ *  - Every call returns an mkf_status; no call aborts or throws.  On error
+ *    mkf_last_error() describes it.
+ *  - Memory: arguments marked "host" are read or written by the CPU before
+ *    the call returns; arguments marked "device" are HIP device pointers
+ *    read or written on the context's stream (the call returns after the
+ *    work is queued unless stated otherwise).  Inputs are copied into the
+ *    context: the caller may free or reuse them when the call returns.
+ *  - All device work of a context is ordered on the stream given at
+ *    creation.  One context per host thread; contexts do not share state.
+ *  - Call order: create -> load_geometry -> load_hits -> seed -> find ->
+ *    get_tracks.  Out-of-order calls return MKF_E_ORDER.
+ */
+#ifndef MKF_H
+#define MKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MKF_OK = 0,
+  MKF_E_ARG = -1,      /* a NULL, negative, non-finite or out-of-range input */
+  MKF_E_ORDER = -2,    /* call made before the data it needs was loaded */
+  MKF_E_CAPACITY = -3, /* output too small or a size limit exceeded */
+  MKF_E_HIP = -4,      /* a HIP runtime call failed */
+  MKF_E_GEOMETRY = -5, /* invalid layer description */
+  MKF_E_NUMERIC = -6
+} mkf_status;
+
+enum { MKF_BARREL = 0, MKF_DISK = 1 };
+enum { MKF_MEM_HOST = 0, MKF_MEM_DEVICE = 1 };
+
+#define MKF_MAX_LAYERS 32
+#define MKF_MAX_PLAN 32
+#define MKF_MAX_CAND 8
+
+/* Find forms (mkf_config.flags). */
+#define MKF_F_BATCHED 1u  /* one persistent launch over all seeds and layers */
+#define MKF_F_GRAPH 2u    /* replay the find as a captured HIP graph */
+
+/* History codes in mkf_track.hit. */
+#define MKF_HIT_MISS (-1) /* layer crossed, no hit taken */
+#define MKF_HIT_SKIP (-2) /* layer not crossed by the candidate */
+#define MKF_HIT_NONE (-3) /* candidate had already stopped */
+
+/* One layer of the detector description (the paper's per-layer record of
+ * dimensions, type and hit-search parameters, Section 2.1). */
+typedef struct {
+  int32_t kind;      /* MKF_BARREL (cylinder r = pos) or MKF_DISK (plane z = pos) */
+  float pos;         /* radius (barrel) or signed z (disk), cm */
+  float ext_lo;      /* barrel: lowest z; disk: inner radius, cm */
+  float ext_hi;      /* barrel: highest z; disk: outer radius, cm */
+  float var_u_max;   /* bound on the layer's hit variances along u, v (cm^2); */
+  float var_v_max;   /*   search windows are sized with them               */
+  int32_t n_phi_bins; /* hit index bins in phi (1..4096) */
+  int32_t n_q_bins;   /* hit index bins in z (barrel) or r (disk) (1..1024) */
+} mkf_layer;
+
+/* Method settings.  The paper states none of these values; the defaults
+ * used by the workloads are in the design notes. */
+typedef struct {
+  float bz;          /* uniform field along +z, T (constant field, Section 2.1) */
+  float kappa;       /* curvature constant: rho = pT / (kappa |q| B) */
+  float chi2_cut;    /* a hit extends a candidate if chi2 < chi2_cut (2 dof) */
+  float ms_sigma;    /* multiple-scattering angle per crossed layer, rad */
+  float edge_margin; /* widening of layer extents for plan and crossing tests */
+  float l_min;       /* smallest admissible transverse path, cm */
+  int32_t n_cand;    /* candidates kept per seed, 1..MKF_MAX_CAND */
+  int32_t max_holes; /* misses allowed per candidate */
+  float init_var[6]; /* diagonal prior of the seed fit */
+  uint32_t flags;    /* MKF_F_* */
+} mkf_config;
+
+/* One found track: the best candidate of a seed. */
+typedef struct {
+  int32_t seed_id;  /* index of the seed in the mkf_seed call */
+  int32_t status;   /* 1 found, 0 seed fit failed */
+  int32_t n_hits;   /* including the 3 seed hits */
+  int32_t n_miss;
+  int32_t plan_len;
+  float chi2;       /* sum over the hits added by the find */
+  float par[6];
+  float cov[21];
+  int8_t plan[MKF_MAX_PLAN]; /* layer ids of the layer plan */
+  int32_t hit[MKF_MAX_PLAN]; /* event-local hit index per plan layer, or MKF_HIT_* */
+} mkf_track;
+
+typedef struct {
+  int64_t n_seeds;
+  int64_t n_seeds_ok;      /* seeds whose triplet fit succeeded */
+  int64_t n_steps;         /* candidate-layer steps of the last find */
+  int32_t max_plan_len;
+  int32_t n_launches;      /* kernel launches of the last find */
+  float find_ms;           /* device time of the last find (HIP events) */
+  float index_ms;          /* device time of the last hit-index build */
+  float seed_ms;           /* device time of the last seeding */
+  float main_ms;           /* device time of the last find's layer-step kernels
+                              (all step launches, or the one persistent launch) */
+  int32_t main_launches;   /* number of those launches */
+} mkf_stats;
+
+typedef struct mkf_ctx mkf_ctx;
+
+/* Create a context.  cfg is copied.  stream: a hipStream_t (NULL = the
+ * default stream), e.g. torch.cuda.current_stream().cuda_stream. */
+mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out);
+
+/* Release all device memory of ctx.  NULL is accepted. */
+void mkf_destroy(mkf_ctx *ctx);
+
+/* Text of the last error on ctx (never NULL; valid until the next call on
+ * ctx).  For ctx == NULL: the last error of mkf_create. */
+const char *mkf_last_error(const mkf_ctx *ctx);
+
+/* Detector description (Section 2.1): n_layers records, host memory.
+ * Replaces any previous geometry and invalidates loaded hits. */
+mkf_status mkf_load_geometry(mkf_ctx *ctx, const mkf_layer *layers, int32_t n_layers);
+
+/* Hits of n_events events (hits and seeds are supplied from outside,
+ * Section 2.2).  Event e owns hits [ev_off[e], ev_off[e+1]) of the arrays;
+ * ev_off (host, n_events + 1 entries, ev_off[0] = 0).  x, y, z: position,
+ * var_u, var_v: variances in the layer's local frame (barrel: r-phi and z;
+ * disk: r-phi and r), layer: layer id.  mem says whether the six arrays are
+ * host or device memory.  Builds the binned hit index (untimed
+ * pre-processing).  Invalidates seeds. */
+mkf_status mkf_load_hits(mkf_ctx *ctx, int32_t n_events, const int64_t *ev_off,
+                         const float *x, const float *y, const float *z,
+                         const float *var_u, const float *var_v,
+                         const int32_t *layer, int32_t mem);
+
+/* Seeds: n_seeds triplets; seed_event[i] is the event of seed i and
+ * seed_hits[3 i .. 3 i + 2] its event-local hit indices, innermost first.
+ * Both arrays host or device per mem.  Fits each triplet and builds its
+ * layer plan (untimed pre-processing). */
+mkf_status mkf_seed(mkf_ctx *ctx, int64_t n_seeds, const int32_t *seed_event,
+                    const int32_t *seed_hits, int32_t mem);
+
+/* Seed states after the triplet fit (host outputs, each may be NULL):
+ * par [n_seeds][6], cov [n_seeds][21], ok [n_seeds], plan_len [n_seeds],
+ * plan [n_seeds][MKF_MAX_PLAN] (layer ids).  Blocks until done. */
+mkf_status mkf_get_seed_states(mkf_ctx *ctx, float *par, float *cov, int32_t *ok,
+                               int32_t *plan_len, int8_t *plan);
+
+/* Clone-engine track finding over all seeds (the timed hot path). */
+mkf_status mkf_find(mkf_ctx *ctx);
+
+/* Copy the found tracks (one per seed, in seed order) to host memory.
+ * Writes min(capacity, n_seeds) records; *n_total = n_seeds; returns
+ * MKF_E_CAPACITY if capacity < n_seeds.  Blocks until done. */
+mkf_status mkf_get_tracks(mkf_ctx *ctx, mkf_track *out, int64_t capacity, int64_t *n_total);
+
+/* Propagate n states to layers of the loaded geometry (unit access to the
+ * propagation of the hot path, no scattering, extent widened by
+ * edge_margin).  Device pointers: par [n][6], cov [n][21], layer [n];
+ * outputs out_par [n][6], out_cov [n][21], out_l [n] (transverse path),
+ * out_status [n] (0 ok, 1 no crossing, 2 outside the widened extent, 3 bad
+ * layer id). */
+mkf_status mkf_propagate(mkf_ctx *ctx, int64_t n, const float *par, const float *cov,
+                         const int32_t *layer, float *out_par, float *out_cov,
+                         float *out_l, int32_t *out_status);
+
+/* Kalman fit without search (the paper's vectorized fitting,
+ * Introduction): n_tracks tracks, each through up to n_steps hits on its
+ * own surfaces.  Device pointers, step-major so that consecutive tracks
+ * are adjacent: kind/pos/x/y/z/var_u/var_v [n_steps][n_tracks]; len
+ * [n_tracks] (hits used, <= n_steps); init_par [n_tracks][6], init_cov
+ * [n_tracks][21]; outputs out_par, out_cov, out_chi2 [n_tracks],
+ * out_status [n_tracks] (0 ok, k > 0: propagation to hit k-1 failed).
+ * Scattering uses cfg.ms_sigma; no extent test. */
+mkf_status mkf_fit(mkf_ctx *ctx, int64_t n_tracks, int32_t n_steps, const int8_t *kind,
+                   const float *pos, const float *x, const float *y, const float *z,
+                   const float *var_u, const float *var_v, const int32_t *len,
+                   const float *init_par, const float *init_cov, float *out_par,
+                   float *out_cov, float *out_chi2, int32_t *out_status);
+
+/* Counters and timings of the last calls. */
+mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

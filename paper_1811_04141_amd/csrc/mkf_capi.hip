@@ -1,0 +1,638 @@
+// mkf_capi.hip -- host runtime behind the C ABI declared in include/mkf.h:
+// argument validation, device buffers owned by the context, stream
+// ordering, and the drivers of the two find forms.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mkf.h"
+#include "mkf_kernels.hpp"
+
+using namespace mkf;
+
+namespace {
+
+// grow-only device buffer
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && ptr) return hipSuccess;
+    if (ptr) {
+      hipError_t e = hipFree(ptr);
+      if (e != hipSuccess) return e;
+      ptr = nullptr;
+      bytes = 0;
+    }
+    size_t alloc = n ? n : 256;
+    hipError_t e = hipMalloc(&ptr, alloc);
+    if (e == hipSuccess) bytes = alloc;
+    return e;
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+enum Stage { kCreated = 0, kGeometry = 1, kHits = 2, kSeeds = 3, kFound = 4 };
+
+}  // namespace
+
+struct mkf_ctx {
+  mkf_config cfg{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int stage = kCreated;
+
+  int n_layers = 0;
+  DevLayer layers[kMaxLayers]{};
+  int bins_per_event = 0;
+  DevBuf d_layers;
+
+  // hits
+  int n_events = 0;
+  int64_t n_hits = 0;
+  std::vector<int64_t> ev_off;
+  DevBuf d_ev_off, d_x, d_y, d_z, d_vu, d_vv, d_layer;
+  DevBuf d_hit_bin, d_counts, d_fill, d_bin_start, d_scan_tmp, d_sorted, d_bad;
+
+  // seeds
+  int64_t n_seeds = 0;
+  DevBuf d_seed_event, d_seed_hits, d_seed_state, d_seed_ok, d_plan_len, d_plan, d_plan_l;
+  DevBuf d_order;
+  std::vector<int64_t> active_at_step;  // seeds (in processing order) with plan_len > step
+  int max_plan_len = 0;
+  int64_t n_seeds_ok = 0;
+
+  // find
+  DevBuf d_cand, d_fin_key, d_fin_rec, d_fin_meta, d_bp, d_tracks, d_steps, d_tiles;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_m0 = nullptr, ev_m1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_launches = 0;
+  mkf_stats stats{};
+  int persistent_blocks = 0;
+
+  // fit scratch (host-side inputs are staged here)
+  ~mkf_ctx() {
+    DevBuf *all[] = {&d_layers, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
+                     &d_hit_bin, &d_counts, &d_fill, &d_bin_start, &d_scan_tmp, &d_sorted,
+                     &d_bad, &d_seed_event, &d_seed_hits, &d_seed_state, &d_seed_ok,
+                     &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_cand, &d_fin_key,
+                     &d_fin_rec, &d_fin_meta, &d_bp, &d_tracks, &d_steps, &d_tiles};
+    for (DevBuf *b : all) b->release();
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    if (ev_m0) (void)hipEventDestroy(ev_m0);
+    if (ev_m1) (void)hipEventDestroy(ev_m1);
+  }
+};
+
+namespace {
+
+std::string g_create_error = "no error";
+
+mkf_status fail(mkf_ctx *c, mkf_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_error = buf;
+  return st;
+}
+
+#define HIP_TRY(c, expr)                                                                 \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail((c), MKF_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+DevCfg dev_cfg(const mkf_config &c) {
+  DevCfg d{};
+  d.mkb = -c.kappa * c.bz;
+  d.chi2_cut = c.chi2_cut;
+  d.ms_var = c.ms_sigma * c.ms_sigma;
+  d.edge_margin = c.edge_margin;
+  d.l_min = c.l_min;
+  d.n_cand = c.n_cand;
+  d.max_holes = c.max_holes;
+  for (int i = 0; i < 6; ++i) d.init_var[i] = c.init_var[i];
+  return d;
+}
+
+FindParams params(mkf_ctx *c) {
+  FindParams P{};
+  P.layers = c->d_layers.as<DevLayer>();
+  P.n_layers = c->n_layers;
+  P.cfg = dev_cfg(c->cfg);
+  P.n_events = c->n_events;
+  P.ev_off = c->d_ev_off.as<int64_t>();
+  P.hx = c->d_x.as<float>();
+  P.hy = c->d_y.as<float>();
+  P.hz = c->d_z.as<float>();
+  P.hvu = c->d_vu.as<float>();
+  P.hvv = c->d_vv.as<float>();
+  P.hlayer = c->d_layer.as<int>();
+  P.sorted = c->d_sorted.as<HitRec>();
+  P.bin_start = c->d_bin_start.as<int>();
+  P.bins_per_event = c->bins_per_event;
+  P.n_seeds = c->n_seeds;
+  P.seed_event = c->d_seed_event.as<int>();
+  P.seed_state = c->d_seed_state.as<float>();
+  P.seed_ok = c->d_seed_ok.as<int>();
+  P.plan_len = c->d_plan_len.as<int>();
+  P.plan = c->d_plan.as<int8_t>();
+  P.order = c->d_order.as<int>();
+  P.cand = c->d_cand.as<float>();
+  P.fin_key = c->d_fin_key.as<unsigned long long>();
+  P.fin_rec = c->d_fin_rec.as<float>();
+  P.fin_meta = c->d_fin_meta.as<int>();
+  P.bp = c->d_bp.as<int>();
+  P.tile_counter = c->d_tiles.as<int>();
+  P.n_tiles = (int)((c->n_seeds + 7) / 8);
+  P.tracks = c->d_tracks.as<mkf_track>();
+  P.n_steps = c->d_steps.as<unsigned long long>();
+  return P;
+}
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+void drop_graph(mkf_ctx *c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+// copy a caller array (host or device) into a context buffer
+mkf_status stage_in(mkf_ctx *c, DevBuf &dst, const void *src, size_t bytes, int mem) {
+  HIP_TRY(c, dst.ensure(bytes));
+  if (bytes == 0) return MKF_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst.ptr, src, bytes,
+                            mem == MKF_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                  : hipMemcpyHostToDevice,
+                            c->stream));
+  return MKF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
+  if (!out) return fail(nullptr, MKF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, MKF_E_ARG, "cfg is NULL");
+  if (!(cfg->n_cand >= 1 && cfg->n_cand <= MKF_MAX_CAND))
+    return fail(nullptr, MKF_E_ARG, "n_cand must be in 1..%d", MKF_MAX_CAND);
+  if (cfg->max_holes < 0 || cfg->max_holes > 32)
+    return fail(nullptr, MKF_E_ARG, "max_holes must be in 0..32");
+  const float fv[] = {cfg->bz, cfg->kappa, cfg->chi2_cut, cfg->ms_sigma, cfg->edge_margin,
+                      cfg->l_min};
+  for (float v : fv)
+    if (!finite_f(v)) return fail(nullptr, MKF_E_ARG, "non-finite setting");
+  if (!(cfg->chi2_cut > 0.f) || cfg->ms_sigma < 0.f || cfg->edge_margin < 0.f ||
+      !(cfg->l_min > 0.f) || !(cfg->kappa > 0.f))
+    return fail(nullptr, MKF_E_ARG, "chi2_cut, kappa, l_min must be > 0; ms_sigma, edge_margin >= 0");
+  for (int i = 0; i < 6; ++i)
+    if (!(cfg->init_var[i] > 0.f) || !finite_f(cfg->init_var[i]))
+      return fail(nullptr, MKF_E_ARG, "init_var must be finite and > 0");
+  mkf_ctx *c = new (std::nothrow) mkf_ctx();
+  if (!c) return fail(nullptr, MKF_E_CAPACITY, "out of host memory");
+  c->cfg = *cfg;
+  c->stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipEventCreate(&c->ev_a);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_b);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_m0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev_m1);
+  if (e == hipSuccess) e = c->d_steps.ensure(sizeof(unsigned long long));
+  if (e == hipSuccess) e = c->d_tiles.ensure(sizeof(int));
+  if (e == hipSuccess) e = c->d_bad.ensure(sizeof(int));
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, MKF_E_HIP, "HIP setup failed: %s", hipGetErrorString(e));
+  }
+  int dev = 0, n_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  c->persistent_blocks = std::max(1, n_cu) * 8;
+  c->err = "no error";
+  *out = c;
+  return MKF_OK;
+}
+
+void mkf_destroy(mkf_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+const char *mkf_last_error(const mkf_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_layers) {
+  if (!c) return MKF_E_ARG;
+  if (!layers || n_layers <= 0 || n_layers > MKF_MAX_LAYERS)
+    return fail(c, MKF_E_ARG, "need 1..%d layers", MKF_MAX_LAYERS);
+  int base = 0;
+  DevLayer dl[kMaxLayers]{};
+  for (int i = 0; i < n_layers; ++i) {
+    const mkf_layer &L = layers[i];
+    if (L.kind != MKF_BARREL && L.kind != MKF_DISK)
+      return fail(c, MKF_E_GEOMETRY, "layer %d: bad kind %d", i, L.kind);
+    if (!finite_f(L.pos) || !finite_f(L.ext_lo) || !finite_f(L.ext_hi) ||
+        !(L.ext_lo < L.ext_hi))
+      return fail(c, MKF_E_GEOMETRY, "layer %d: bad position or extent", i);
+    if (L.kind == MKF_BARREL && !(L.pos > 0.f))
+      return fail(c, MKF_E_GEOMETRY, "layer %d: barrel radius must be > 0", i);
+    if (L.kind == MKF_DISK && !(L.ext_lo >= 0.f))
+      return fail(c, MKF_E_GEOMETRY, "layer %d: disk inner radius must be >= 0", i);
+    if (!(L.var_u_max > 0.f) || !(L.var_v_max > 0.f) || !finite_f(L.var_u_max) ||
+        !finite_f(L.var_v_max))
+      return fail(c, MKF_E_GEOMETRY, "layer %d: variance bounds must be > 0", i);
+    if (L.n_phi_bins < 1 || L.n_phi_bins > 4096 || L.n_q_bins < 1 || L.n_q_bins > 1024)
+      return fail(c, MKF_E_GEOMETRY, "layer %d: bin counts out of range", i);
+    DevLayer &d = dl[i];
+    d.kind = L.kind;
+    d.pos = L.pos;
+    d.lo = L.ext_lo;
+    d.hi = L.ext_hi;
+    d.vu_max = L.var_u_max;
+    d.vv_max = L.var_v_max;
+    d.nphi = L.n_phi_bins;
+    d.nq = L.n_q_bins;
+    d.bin_base = base;
+    d.q_lo = L.ext_lo;
+    d.q_scale = (float)L.n_q_bins / (L.ext_hi - L.ext_lo);
+    d.phi_scale = (float)L.n_phi_bins / kTwoPi;
+    base += L.n_phi_bins * L.n_q_bins;
+  }
+  HIP_TRY(c, c->d_layers.ensure(sizeof(DevLayer) * kMaxLayers));
+  HIP_TRY(c, hipMemcpyAsync(c->d_layers.ptr, dl, sizeof(dl), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(c->layers, dl, sizeof(dl));
+  c->n_layers = n_layers;
+  c->bins_per_event = base;
+  c->stage = kGeometry;
+  return MKF_OK;
+}
+
+mkf_status mkf_load_hits(mkf_ctx *c, int32_t n_events, const int64_t *ev_off, const float *x,
+                         const float *y, const float *z, const float *var_u,
+                         const float *var_v, const int32_t *layer, int32_t mem) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kGeometry) return fail(c, MKF_E_ORDER, "load_geometry first");
+  if (n_events < 0 || !ev_off) return fail(c, MKF_E_ARG, "bad event offsets");
+  if (mem != MKF_MEM_HOST && mem != MKF_MEM_DEVICE) return fail(c, MKF_E_ARG, "bad mem");
+  if (ev_off[0] != 0) return fail(c, MKF_E_ARG, "ev_off[0] must be 0");
+  for (int e = 0; e < n_events; ++e) {
+    const int64_t n = ev_off[e + 1] - ev_off[e];
+    if (n < 0) return fail(c, MKF_E_ARG, "event offsets must not decrease");
+    if (n >= (int64_t)0x7FFFFF) return fail(c, MKF_E_CAPACITY, "event %d has too many hits", e);
+  }
+  const int64_t n_hits = ev_off[n_events];
+  if (n_hits > 0 && (!x || !y || !z || !var_u || !var_v || !layer))
+    return fail(c, MKF_E_ARG, "hit array is NULL");
+  if (n_hits >= ((int64_t)1 << 31)) return fail(c, MKF_E_CAPACITY, "too many hits");
+  const int64_t total_bins = (int64_t)n_events * c->bins_per_event;
+  if (total_bins >= ((int64_t)1 << 31) - 1)
+    return fail(c, MKF_E_CAPACITY, "events x bins exceed the index size");
+  if (mem == MKF_MEM_HOST) {
+    for (int64_t i = 0; i < n_hits; ++i) {
+      if (!finite_f(x[i]) || !finite_f(y[i]) || !finite_f(z[i]) || !finite_f(var_u[i]) ||
+          !finite_f(var_v[i]) || !(var_u[i] > 0.f) || !(var_v[i] > 0.f))
+        return fail(c, MKF_E_ARG, "hit %lld: non-finite value or variance <= 0", (long long)i);
+      if (layer[i] < 0 || layer[i] >= c->n_layers)
+        return fail(c, MKF_E_ARG, "hit %lld: layer %d out of range", (long long)i, layer[i]);
+    }
+  }
+  c->stage = kGeometry;
+  drop_graph(c);
+  const size_t fb = sizeof(float) * (size_t)n_hits;
+  mkf_status st;
+  if ((st = stage_in(c, c->d_ev_off, ev_off, sizeof(int64_t) * (n_events + 1), MKF_MEM_HOST))) return st;
+  if ((st = stage_in(c, c->d_x, x, fb, mem))) return st;
+  if ((st = stage_in(c, c->d_y, y, fb, mem))) return st;
+  if ((st = stage_in(c, c->d_z, z, fb, mem))) return st;
+  if ((st = stage_in(c, c->d_vu, var_u, fb, mem))) return st;
+  if ((st = stage_in(c, c->d_vv, var_v, fb, mem))) return st;
+  if ((st = stage_in(c, c->d_layer, layer, sizeof(int) * (size_t)n_hits, mem))) return st;
+  if (mem == MKF_MEM_DEVICE && n_hits > 0) {
+    HIP_TRY(c, hipMemsetAsync(c->d_bad.ptr, 0, sizeof(int), c->stream));
+    launch_validate_hits(c->stream, n_hits, c->d_x.as<float>(), c->d_y.as<float>(),
+                         c->d_z.as<float>(), c->d_vu.as<float>(), c->d_vv.as<float>(),
+                         c->d_layer.as<int>(), c->n_layers, c->d_bad.as<int>());
+    int bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, c->d_bad.ptr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, MKF_E_ARG, "hits: non-finite value, variance <= 0 or bad layer");
+  }
+  c->n_events = n_events;
+  c->n_hits = n_hits;
+  c->ev_off.assign(ev_off, ev_off + n_events + 1);
+
+  // binned index: count, scan, scatter
+  HIP_TRY(c, c->d_hit_bin.ensure(sizeof(int) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, c->d_counts.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
+  HIP_TRY(c, c->d_fill.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
+  HIP_TRY(c, c->d_bin_start.ensure(sizeof(int) * (size_t)(total_bins + 1)));
+  HIP_TRY(c, c->d_scan_tmp.ensure(sizeof(int) * (size_t)(4 * (total_bins / 2048 + 4) + 64)));
+  HIP_TRY(c, c->d_sorted.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
+  launch_fill_i32(c->stream, c->d_counts.as<int>(), total_bins, 0);
+  launch_fill_i32(c->stream, c->d_fill.as<int>(), total_bins, 0);
+  FindParams P = params(c);
+  launch_hit_bins(c->stream, P, n_hits, c->d_layer.as<int>(), c->d_hit_bin.as<int>(),
+                  c->d_counts.as<int>());
+  launch_scan(c->stream, c->d_counts.as<int>(), c->d_bin_start.as<int>(), total_bins,
+              c->d_scan_tmp.as<int>(), nullptr);
+  launch_scatter(c->stream, P, n_hits, c->d_hit_bin.as<int>(), c->d_fill.as<int>(),
+                 c->d_sorted.as<HitRec>());
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev_b));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+  c->stats.index_ms = ms;
+  c->stage = kHits;
+  c->n_seeds = 0;
+  return MKF_OK;
+}
+
+mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
+                    const int32_t *seed_hits, int32_t mem) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kHits) return fail(c, MKF_E_ORDER, "load_hits first");
+  if (n_seeds < 0 || n_seeds >= ((int64_t)1 << 28)) return fail(c, MKF_E_ARG, "bad seed count");
+  if (n_seeds > 0 && (!seed_event || !seed_hits)) return fail(c, MKF_E_ARG, "seed array is NULL");
+  if (mem != MKF_MEM_HOST && mem != MKF_MEM_DEVICE) return fail(c, MKF_E_ARG, "bad mem");
+  std::vector<int32_t> h_ev, h_hits;
+  const int32_t *sev = seed_event, *sh = seed_hits;
+  if (mem == MKF_MEM_DEVICE && n_seeds > 0) {
+    // seeds are small: validate on the host
+    h_ev.resize(n_seeds);
+    h_hits.resize(3 * n_seeds);
+    HIP_TRY(c, hipMemcpyAsync(h_ev.data(), seed_event, 4 * n_seeds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(h_hits.data(), seed_hits, 12 * n_seeds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    sev = h_ev.data();
+    sh = h_hits.data();
+  }
+  for (int64_t i = 0; i < n_seeds; ++i) {
+    if (sev[i] < 0 || sev[i] >= c->n_events)
+      return fail(c, MKF_E_ARG, "seed %lld: event %d out of range", (long long)i, sev[i]);
+    const int64_t nh = c->ev_off[sev[i] + 1] - c->ev_off[sev[i]];
+    for (int k = 0; k < 3; ++k)
+      if (sh[3 * i + k] < 0 || sh[3 * i + k] >= nh)
+        return fail(c, MKF_E_ARG, "seed %lld: hit index out of range", (long long)i);
+  }
+  c->stage = kHits;
+  drop_graph(c);
+  const size_t N = (size_t)std::max<int64_t>(n_seeds, 1);
+  mkf_status st;
+  if ((st = stage_in(c, c->d_seed_event, sev, 4 * (size_t)n_seeds, MKF_MEM_HOST))) return st;
+  if ((st = stage_in(c, c->d_seed_hits, sh, 12 * (size_t)n_seeds, MKF_MEM_HOST))) return st;
+  HIP_TRY(c, c->d_seed_event.ensure(4 * N));
+  HIP_TRY(c, c->d_seed_state.ensure(sizeof(float) * 27 * N));
+  HIP_TRY(c, c->d_seed_ok.ensure(4 * N));
+  HIP_TRY(c, c->d_plan_len.ensure(4 * N));
+  HIP_TRY(c, c->d_plan.ensure(kMaxPlan * N));
+  HIP_TRY(c, c->d_plan_l.ensure(sizeof(double) * kMaxPlan * N));
+  HIP_TRY(c, c->d_order.ensure(4 * N));
+  c->n_seeds = n_seeds;
+  FindParams P = params(c);
+  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
+  launch_seed(c->stream, P, c->d_seed_hits.as<int>(), c->d_seed_state.as<float>(),
+              c->d_seed_ok.as<int>(), c->d_plan_len.as<int>(), c->d_plan.as<int8_t>(),
+              c->d_plan_l.as<double>());
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  // processing order: longest plans first (the persistent form takes tiles
+  // in this order, so the longest work starts first), then by event and
+  // direction so that a wavefront's seeds search nearby hits
+  std::vector<int32_t> plen(n_seeds), ok(n_seeds), ev(sev, sev + n_seeds);
+  std::vector<float> phi(n_seeds), theta(n_seeds);
+  if (n_seeds > 0) {
+    HIP_TRY(c, hipMemcpyAsync(plen.data(), c->d_plan_len.ptr, 4 * n_seeds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ok.data(), c->d_seed_ok.ptr, 4 * n_seeds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(phi.data(), c->d_seed_state.as<float>() + 4 * N, 4 * n_seeds,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(theta.data(), c->d_seed_state.as<float>() + 5 * N, 4 * n_seeds,
+                              hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+  c->stats.seed_ms = ms;
+  std::vector<int32_t> order(n_seeds);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (plen[a] != plen[b]) return plen[a] > plen[b];
+    if (ev[a] != ev[b]) return ev[a] < ev[b];
+    const int ta = (int)(theta[a] * 8.f), tb = (int)(theta[b] * 8.f);
+    if (ta != tb) return ta < tb;
+    return phi[a] < phi[b];
+  });
+  if (n_seeds > 0)
+    HIP_TRY(c, hipMemcpyAsync(c->d_order.ptr, order.data(), 4 * n_seeds, hipMemcpyHostToDevice, c->stream));
+  c->max_plan_len = 0;
+  c->n_seeds_ok = 0;
+  for (int64_t i = 0; i < n_seeds; ++i) {
+    c->max_plan_len = std::max(c->max_plan_len, plen[i]);
+    c->n_seeds_ok += ok[i] ? 1 : 0;
+  }
+  c->active_at_step.assign(kMaxPlan, 0);
+  for (int s = 0; s < kMaxPlan; ++s) {
+    // seeds are sorted by plan length, so the active ones form a prefix
+    int64_t n = 0;
+    for (int64_t i = 0; i < n_seeds; ++i) n += plen[i] > s ? 1 : 0;
+    c->active_at_step[s] = n;
+  }
+  // find buffers
+  HIP_TRY(c, c->d_cand.ensure(sizeof(float) * kCandFields * kGroup * N));
+  HIP_TRY(c, c->d_fin_key.ensure(8 * N));
+  HIP_TRY(c, c->d_fin_rec.ensure(sizeof(float) * 28 * N));
+  HIP_TRY(c, c->d_fin_meta.ensure(4 * N));
+  HIP_TRY(c, c->d_bp.ensure(4 * (size_t)kMaxPlan * kGroup * N));
+  HIP_TRY(c, c->d_tracks.ensure(sizeof(mkf_track) * N));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->stats.n_seeds = n_seeds;
+  c->stats.n_seeds_ok = c->n_seeds_ok;
+  c->stats.max_plan_len = c->max_plan_len;
+  c->stage = kSeeds;
+  return MKF_OK;
+}
+
+mkf_status mkf_get_seed_states(mkf_ctx *c, float *par, float *cov, int32_t *ok,
+                               int32_t *plan_len, int8_t *plan) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
+  const size_t n = (size_t)c->n_seeds, N = std::max<size_t>(n, 1);
+  if (n == 0) return MKF_OK;
+  std::vector<float> st(27 * N);
+  HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_seed_state.ptr, sizeof(float) * 27 * N,
+                            hipMemcpyDeviceToHost, c->stream));
+  if (ok) HIP_TRY(c, hipMemcpyAsync(ok, c->d_seed_ok.ptr, 4 * n, hipMemcpyDeviceToHost, c->stream));
+  if (plan_len)
+    HIP_TRY(c, hipMemcpyAsync(plan_len, c->d_plan_len.ptr, 4 * n, hipMemcpyDeviceToHost, c->stream));
+  if (plan)
+    HIP_TRY(c, hipMemcpyAsync(plan, c->d_plan.ptr, kMaxPlan * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < n; ++i) {
+    if (par)
+      for (int k = 0; k < 6; ++k) par[6 * i + k] = st[k * N + i];
+    if (cov)
+      for (int k = 0; k < 21; ++k) cov[21 * i + k] = st[(6 + k) * N + i];
+  }
+  return MKF_OK;
+}
+
+// Queue the whole find on the context stream.  main_a/main_b (may be
+// null) bracket the layer-step kernels.
+static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipEvent_t main_b) {
+  int launches = 0;
+  launch_fill_u64(c->stream, c->d_steps.as<unsigned long long>(), 1, 0ull);
+  ++launches;
+  if (c->cfg.flags & MKF_F_BATCHED) {
+    launch_fill_i32(c->stream, c->d_tiles.as<int>(), 1, 0);
+    ++launches;
+    if (main_a) (void)hipEventRecord(main_a, c->stream);
+    launch_find_persistent(c->stream, P, c->persistent_blocks);
+    ++launches;
+    c->stats.main_launches = 1;
+  } else {
+    launch_find_init(c->stream, P);
+    ++launches;
+    if (main_a) (void)hipEventRecord(main_a, c->stream);
+    int n = 0;
+    for (int s = 0; s < c->max_plan_len; ++s) {
+      launch_find_step(c->stream, P, s, c->active_at_step[s]);
+      ++n;
+    }
+    launches += n;
+    c->stats.main_launches = n;
+  }
+  if (main_b) (void)hipEventRecord(main_b, c->stream);
+  launch_finalize(c->stream, P);
+  ++launches;
+  return launches;
+}
+
+mkf_status mkf_find(mkf_ctx *c) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
+  FindParams P = params(c);
+  int launches = 0;
+  const bool graph = (c->cfg.flags & MKF_F_GRAPH) != 0;
+  if (graph && !c->graph_exec) {
+    if (!c->stream)
+      return fail(c, MKF_E_ARG, "graph replay needs a non-default stream at mkf_create");
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->graph_launches = enqueue_find(c, P, nullptr, nullptr);
+    hipError_t e = hipStreamEndCapture(c->stream, &c->graph);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(c);
+      return fail(c, MKF_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
+  if (graph) {
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+    launches = c->graph_launches;
+  } else {
+    launches = enqueue_find(c, P, c->ev_m0, c->ev_m1);
+  }
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev_b));
+  float ms = 0.f, mms = -1.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+  if (!graph) HIP_TRY(c, hipEventElapsedTime(&mms, c->ev_m0, c->ev_m1));
+  unsigned long long steps = 0;
+  HIP_TRY(c, hipMemcpyAsync(&steps, c->d_steps.ptr, sizeof steps, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->stats.find_ms = ms;
+  c->stats.main_ms = mms;
+  c->stats.n_steps = (int64_t)steps;
+  c->stats.n_launches = launches;
+  c->stage = kFound;
+  return MKF_OK;
+}
+
+mkf_status mkf_get_tracks(mkf_ctx *c, mkf_track *out, int64_t capacity, int64_t *n_total) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kFound) return fail(c, MKF_E_ORDER, "find first");
+  if (n_total) *n_total = c->n_seeds;
+  if (capacity < 0 || (capacity > 0 && !out)) return fail(c, MKF_E_ARG, "bad output buffer");
+  const int64_t n = std::min<int64_t>(capacity, c->n_seeds);
+  if (n > 0)
+    HIP_TRY(c, hipMemcpyAsync(out, c->d_tracks.ptr, sizeof(mkf_track) * n, hipMemcpyDeviceToHost,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (capacity < c->n_seeds)
+    return fail(c, MKF_E_CAPACITY, "capacity %lld < %lld tracks", (long long)capacity,
+                (long long)c->n_seeds);
+  return MKF_OK;
+}
+
+mkf_status mkf_propagate(mkf_ctx *c, int64_t n, const float *par, const float *cov,
+                         const int32_t *layer, float *out_par, float *out_cov, float *out_l,
+                         int32_t *out_status) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kGeometry) return fail(c, MKF_E_ORDER, "load_geometry first");
+  if (n < 0) return fail(c, MKF_E_ARG, "n < 0");
+  if (n > 0 && (!par || !cov || !layer || !out_par || !out_cov || !out_l || !out_status))
+    return fail(c, MKF_E_ARG, "NULL array");
+  FindParams P = params(c);
+  launch_propagate(c->stream, P, n, par, cov, layer, out_par, out_cov, out_l, out_status);
+  HIP_TRY(c, hipGetLastError());
+  return MKF_OK;
+}
+
+mkf_status mkf_fit(mkf_ctx *c, int64_t n_tracks, int32_t n_steps, const int8_t *kind,
+                   const float *pos, const float *x, const float *y, const float *z,
+                   const float *var_u, const float *var_v, const int32_t *len,
+                   const float *init_par, const float *init_cov, float *out_par, float *out_cov,
+                   float *out_chi2, int32_t *out_status) {
+  if (!c) return MKF_E_ARG;
+  if (n_tracks < 0 || n_steps < 0) return fail(c, MKF_E_ARG, "negative size");
+  if (n_tracks > 0 && (!len || !init_par || !init_cov || !out_par || !out_cov || !out_chi2 ||
+                       !out_status))
+    return fail(c, MKF_E_ARG, "NULL array");
+  if (n_tracks > 0 && n_steps > 0 && (!kind || !pos || !x || !y || !z || !var_u || !var_v))
+    return fail(c, MKF_E_ARG, "NULL hit array");
+  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
+  launch_fit(c->stream, dev_cfg(c->cfg), n_tracks, n_steps, kind, pos, x, y, z, var_u, var_v, len,
+             init_par, init_cov, out_par, out_cov, out_chi2, out_status);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  return MKF_OK;
+}
+
+mkf_status mkf_get_stats(mkf_ctx *c, mkf_stats *out) {
+  if (!c || !out) return MKF_E_ARG;
+  *out = c->stats;
+  return MKF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,407 @@
+// mkf_device.hpp -- per-lane track-state algebra for gfx950 (FP32 for the
+// find and the fit, FP64 for the seed fit).
+//
+// One candidate per lane: the 6-parameter helix state p = (x, y, z, q/pT,
+// phi, theta) and the 21 upper-triangle entries of its covariance live in
+// VGPRs.  None of this is a dense contraction (6x6 with a sparse Jacobian,
+// 2x2 measurement algebra), so it is written as straight-line VALU code with
+// the sparsity unrolled by hand; MFMA would waste its tiles here.
+//
+// Method (arXiv:1811.04141): barrel and endcap propagation and KF update
+// (Introduction, the paragraph on realistic geometries), constant field and
+// scattering material (Section 2.1), the Kalman filter of the Introduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mkf {
+
+constexpr float kPi = 3.14159265358979f;
+constexpr float kTwoPi = 6.28318530717959f;
+constexpr int kMaxLayers = 32;
+constexpr int kMaxPlan = 32;
+constexpr int kGroup = 8;  // lanes per seed (candidate slots)
+
+enum : int { kOk = 0, kNoCrossing = 1, kOutOfExtent = 2 };
+
+// Layer as the kernels see it (staged in LDS).
+struct DevLayer {
+  int kind;         // 0 barrel, 1 disk
+  float pos;        // R or Z
+  float lo, hi;     // extent (z for barrel, r for disk)
+  float vu_max, vv_max;
+  int nphi, nq;
+  int bin_base;     // first bin of this layer within one event's bins
+  float q_lo;       // q bin = floor((q - q_lo) * q_scale)
+  float q_scale;
+  float phi_scale;  // nphi / (2 pi)
+};
+
+struct DevCfg {
+  float mkb;        // -kappa * B: omega = mkb * (q/pT)
+  float chi2_cut;
+  float ms_var;     // ms_sigma^2
+  float edge_margin;
+  float l_min;
+  int n_cand;
+  int max_holes;
+  float init_var[6];
+};
+
+
+// scalar helpers overloaded for FP32 (the find) and FP64 (seed fitting)
+__device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float sqrt_t(float a) { return sqrtf(a); }
+__device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }
+__device__ __forceinline__ float rsqrt_t(float a) { return rsqrtf(a); }
+__device__ __forceinline__ double rsqrt_t(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ float atan_t(float a) { return atanf(a); }
+__device__ __forceinline__ double atan_t(double a) { return atan(a); }
+__device__ __forceinline__ float abs_t(float a) { return fabsf(a); }
+__device__ __forceinline__ double abs_t(double a) { return fabs(a); }
+__device__ __forceinline__ float copysign_t(float a, float b) { return copysignf(a, b); }
+__device__ __forceinline__ double copysign_t(double a, double b) { return copysign(a, b); }
+
+template <typename T> struct Consts;
+template <> struct Consts<float> {
+  static __device__ __forceinline__ float pi() { return kPi; }
+  static __device__ __forceinline__ float two_pi() { return kTwoPi; }
+};
+template <> struct Consts<double> {
+  static __device__ __forceinline__ double pi() { return 3.14159265358979323846; }
+  static __device__ __forceinline__ double two_pi() { return 6.28318530717958647692; }
+};
+
+// index of (i, j), i <= j, in the packed upper triangle
+__host__ __device__ constexpr int tri(int i, int j) {
+  return i * 6 - (i * (i - 1)) / 2 + (j - i);
+}
+
+template <typename T>
+__device__ __forceinline__ T wrap_phi(T a) {
+  if (a > Consts<T>::pi()) a -= Consts<T>::two_pi();
+  else if (a <= -Consts<T>::pi()) a += Consts<T>::two_pi();
+  return a;
+}
+
+// sinc(h) = sin h / h
+template <typename T>
+__device__ __forceinline__ T sinc_from(T h, T sh) {
+  return h == T(0) ? T(1) : sh / h;
+}
+
+// d sinc / dh: Taylor series below |h| < 0.5 (the closed form cancels)
+template <typename T>
+__device__ __forceinline__ T dsinc(T h, T sh, T ch) {
+  if (abs_t(h) < T(0.5)) {
+    const T h2 = h * h;
+    return h * (T(-1) / T(3) +
+                h2 * (T(1) / T(30) +
+                      h2 * (T(-1) / T(840) + h2 * (T(1) / T(45360) - h2 * (T(1) / T(3991680))))));
+  }
+  return (h * ch - sh) / (h * h);
+}
+
+// transverse path for the quadratic's root tau: l = (2/w) atan(w tau / 2)
+template <typename T>
+__device__ __forceinline__ T tau_to_l(T tau, T w) {
+  const T zz = T(0.5) * w * tau;
+  // atan(z)/z; below |z| < 1e-3 the series 1 - z^2/3 is exact to FP64 rounding
+  const T f = abs_t(zz) < T(1e-3) ? T(1) - zz * zz * (T(1) / T(3)) * (T(1) - T(0.6) * zz * zz)
+                                  : atan_t(zz) / zz;
+  return tau * f;
+}
+
+// Smallest transverse path l > l_min, inside the first half turn, at which
+// the helix reaches the cylinder r = R.  Closed form: with
+// a = x cos phi + y sin phi, c = y cos phi - x sin phi, g0 = x^2 + y^2 - R^2,
+// tau = (2/w) tan(w l / 2) solves (1 + c w + g0 w^2/4) tau^2 + 2 a tau + g0 = 0;
+// every real root is a crossing with |w l| < pi.
+template <typename T>
+__device__ __forceinline__ bool path_barrel(T x, T y, T cphi, T sphi, T w, T R, T l_min,
+                                            T &l_out) {
+  const T a = fma_t(x, cphi, y * sphi);
+  const T c = fma_t(y, cphi, -x * sphi);
+  const T g0 = fma_t(x, x, fma_t(y, y, -R * R));
+  const T alpha = T(1) + c * w + T(0.25) * g0 * w * w;
+  const T disc = fma_t(a, a, -alpha * g0);
+  if (!(disc >= T(0))) return false;
+  const T sq = sqrt_t(disc);
+  const T qq = -(a + copysign_t(sq, a));
+  T best = T(INFINITY);
+  if (qq != T(0)) {
+    const T l1 = tau_to_l(g0 / qq, w);
+    if (l1 > l_min) best = l1;
+    if (alpha != T(0)) {
+      const T l2 = tau_to_l(qq / alpha, w);
+      if (l2 > l_min && l2 < best) best = l2;
+    }
+  }  // qq == 0: a == 0 and disc == 0, a double root at tau = 0 <= l_min
+  if (!(best < T(INFINITY))) return false;
+  l_out = best;
+  return true;
+}
+
+// Result of a propagation.
+template <typename T>
+struct PropT {
+  T p[6];
+  T c[21];
+  T l;
+  int status;
+};
+using Prop = PropT<float>;
+
+// Exact helix transport by l, surface polish, extent test, and the
+// surface-constrained covariance transport C' = F C F^T with
+// F = (I - t n^T / (n^T t)) D (D: d p'/d p at fixed l; t = d p'/dl; n: the
+// surface gradient).  With k = n^T D / (n^T t), F = D - t k^T and
+//   C' = D C D^T - t g^T - g t^T + (k^T C k) t t^T,   g = D C k.
+// kWantCov = false skips the covariance (plans).  check_extent widens the
+// extent by edge_margin.
+template <bool kWantCov, typename T>
+__device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__restrict__ c,
+                                         const DevLayer &L, T mkb, T l_min, bool check_extent,
+                                         T edge_margin, PropT<T> &o) {
+  const T w = mkb * p[3];
+  T sphi, cphi;
+  sincos_t(p[4], &sphi, &cphi);
+  T sth, cth;
+  sincos_t(p[5], &sth, &cth);
+  const T cot = cth / sth;
+  const T pos = T(L.pos);
+  T l;
+  if (L.kind == 0) {
+    if (!path_barrel(p[0], p[1], cphi, sphi, w, pos, l_min, l)) return kNoCrossing;
+  } else {
+    if (cth == T(0)) return kNoCrossing;
+    l = (pos - p[2]) * sth / cth;
+    if (!(l > l_min) || abs_t(w) * l >= Consts<T>::pi()) return kNoCrossing;
+  }
+  const T h = T(0.5) * w * l;
+  T sh, ch;
+  sincos_t(h, &sh, &ch);
+  const T Lc = l * sinc_from(h, sh);  // chord length
+  const T cpsi = cphi * ch - sphi * sh;  // direction of the chord
+  const T spsi = sphi * ch + cphi * sh;
+  const T cphi1 = cpsi * ch - spsi * sh;  // direction at the end
+  const T sphi1 = spsi * ch + cpsi * sh;
+  T x1 = fma_t(Lc, cpsi, p[0]);
+  T y1 = fma_t(Lc, spsi, p[1]);
+  T z1 = fma_t(l, cot, p[2]);
+  // one Newton step along the track removes the rounding of the closed form
+  if (L.kind == 0) {
+    const T g = fma_t(x1, x1, fma_t(y1, y1, -pos * pos));
+    const T gp = T(2) * fma_t(x1, cphi1, y1 * sphi1);
+    if (gp != T(0)) {
+      const T dl = -g / gp;
+      x1 = fma_t(dl, cphi1, x1);
+      y1 = fma_t(dl, sphi1, y1);
+      z1 = fma_t(dl, cot, z1);
+      l += dl;
+    }
+  } else {
+    const T dl = (pos - z1) * sth / cth;
+    x1 = fma_t(dl, cphi1, x1);
+    y1 = fma_t(dl, sphi1, y1);
+    z1 = pos;
+    l += dl;
+  }
+  if (check_extent) {
+    const T q = L.kind == 0 ? z1 : sqrt_t(fma_t(x1, x1, y1 * y1));
+    if (q < T(L.lo) - edge_margin || q > T(L.hi) + edge_margin) return kOutOfExtent;
+  }
+  o.p[0] = x1;
+  o.p[1] = y1;
+  o.p[2] = z1;
+  o.p[3] = p[3];
+  o.p[4] = wrap_phi(fma_t(w, l, p[4]));
+  o.p[5] = p[5];
+  o.l = l;
+  o.status = kOk;
+  if (!kWantCov) return kOk;
+
+  // ---- Jacobian D (identity + E), fixed l
+  const T dw = mkb;  // d w / d(q/pT)
+  const T dLdw = l * dsinc(h, sh, ch) * T(0.5) * l;
+  const T E03 = (dLdw * cpsi - Lc * spsi * T(0.5) * l) * dw;
+  const T E04 = -Lc * spsi;
+  const T E13 = (dLdw * spsi + Lc * cpsi * T(0.5) * l) * dw;
+  const T E14 = Lc * cpsi;
+  const T E25 = -l / (sth * sth);
+  const T E43 = l * dw;
+  // t = d p'/dl = (cphi1, sphi1, cot, 0, w, 0);  k = n^T D / (n^T t)
+  T k0, k1, k2, k3, k4, k5;
+  if (L.kind == 0) {
+    const T inv = T(1) / fma_t(x1, cphi1, y1 * sphi1);
+    k0 = x1 * inv;
+    k1 = y1 * inv;
+    k2 = T(0);
+    k3 = fma_t(x1, E03, y1 * E13) * inv;
+    k4 = fma_t(x1, E04, y1 * E14) * inv;
+    k5 = T(0);
+  } else {
+    const T inv = T(1) / cot;
+    k0 = T(0);
+    k1 = T(0);
+    k2 = inv;
+    k3 = T(0);
+    k4 = T(0);
+    k5 = E25 * inv;
+  }
+  T C[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      C[i][j] = c[tri(i, j)];
+      C[j][i] = C[i][j];
+    }
+  // B = D C (rows)
+  T B[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    B[0][j] = fma_t(E03, C[3][j], fma_t(E04, C[4][j], C[0][j]));
+    B[1][j] = fma_t(E13, C[3][j], fma_t(E14, C[4][j], C[1][j]));
+    B[2][j] = fma_t(E25, C[5][j], C[2][j]);
+    B[3][j] = C[3][j];
+    B[4][j] = fma_t(E43, C[3][j], C[4][j]);
+    B[5][j] = C[5][j];
+  }
+  // hk = C k, s = k^T C k, g = D hk
+  T hk[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+    hk[i] = C[i][0] * k0 + C[i][1] * k1 + C[i][2] * k2 + C[i][3] * k3 + C[i][4] * k4 +
+            C[i][5] * k5;
+  const T s = k0 * hk[0] + k1 * hk[1] + k2 * hk[2] + k3 * hk[3] + k4 * hk[4] + k5 * hk[5];
+  T g[6];
+  g[0] = fma_t(E03, hk[3], fma_t(E04, hk[4], hk[0]));
+  g[1] = fma_t(E13, hk[3], fma_t(E14, hk[4], hk[1]));
+  g[2] = fma_t(E25, hk[5], hk[2]);
+  g[3] = hk[3];
+  g[4] = fma_t(E43, hk[3], hk[4]);
+  g[5] = hk[5];
+  const T t[6] = {cphi1, sphi1, cot, T(0), w, T(0)};
+  // C' = B D^T - t g^T - g t^T + s t t^T (upper triangle)
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T Ai[6];
+    Ai[0] = fma_t(E03, B[i][3], fma_t(E04, B[i][4], B[i][0]));
+    Ai[1] = fma_t(E13, B[i][3], fma_t(E14, B[i][4], B[i][1]));
+    Ai[2] = fma_t(E25, B[i][5], B[i][2]);
+    Ai[3] = B[i][3];
+    Ai[4] = fma_t(E43, B[i][3], B[i][4]);
+    Ai[5] = B[i][5];
+#pragma unroll
+    for (int j = i; j < 6; ++j) o.c[tri(i, j)] = Ai[j] - t[i] * g[j] - g[i] * t[j] + s * t[i] * t[j];
+  }
+  if (L.kind == 1) {
+    // on a disk z is exact: its row and column vanish identically, so drop
+    // the rounding residue instead of carrying it to the next step
+#pragma unroll
+    for (int j = 0; j < 6; ++j) o.c[j < 2 ? tri(j, 2) : tri(2, j)] = T(0);
+  }
+  return kOk;
+}
+
+// Scattering noise of one crossed layer, added to the (q/pT, phi, theta)
+// block: two independent deflections of variance sigma^2 perpendicular to
+// the momentum with |p| fixed.
+template <typename T>
+__device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c) {
+  if (ms_var == T(0)) return;
+  T sth, cth;
+  sincos_t(p[5], &sth, &cth);
+  const T a = p[3] * cth / sth;
+  c[tri(3, 3)] += a * a * ms_var;
+  c[tri(3, 5)] -= a * ms_var;
+  c[tri(4, 4)] += ms_var / (sth * sth);
+  c[tri(5, 5)] += ms_var;
+}
+
+// Local frame at the predicted point and the 2x2 predicted covariance
+// H C H^T.  u = t.(x_h - x'), t = (-y', x')/r'; v = z_h - z' (barrel) or
+// rh.(x_h - x'), rh = (x', y')/r' (disk).
+template <typename T>
+struct FrameT {
+  T tx, ty, rx, ry;
+  T suu, suv, svv;
+};
+using Frame = FrameT<float>;
+
+template <typename T>
+__device__ __forceinline__ void make_frame(const T *p, const T *c, int kind, FrameT<T> &f) {
+  const T inv_r = rsqrt_t(fma_t(p[0], p[0], p[1] * p[1]));
+  f.tx = -p[1] * inv_r;
+  f.ty = p[0] * inv_r;
+  f.rx = p[0] * inv_r;
+  f.ry = p[1] * inv_r;
+  const T c00 = c[tri(0, 0)], c01 = c[tri(0, 1)], c11 = c[tri(1, 1)];
+  f.suu = f.tx * f.tx * c00 + T(2) * f.tx * f.ty * c01 + f.ty * f.ty * c11;
+  if (kind == 0) {
+    f.suv = f.tx * c[tri(0, 2)] + f.ty * c[tri(1, 2)];
+    f.svv = c[tri(2, 2)];
+  } else {
+    f.suv = f.tx * f.rx * c00 + (f.tx * f.ry + f.ty * f.rx) * c01 + f.ty * f.ry * c11;
+    f.svv = f.rx * f.rx * c00 + T(2) * f.rx * f.ry * c01 + f.ry * f.ry * c11;
+  }
+}
+
+// Residual of a hit; false for a barrel hit in the opposite half.
+template <typename T>
+__device__ __forceinline__ bool residual(const T *p, const FrameT<T> &f, int kind, T hx, T hy,
+                                         T hz, T &u, T &v) {
+  const T dx = hx - p[0], dy = hy - p[1];
+  u = fma_t(f.tx, dx, f.ty * dy);
+  if (kind == 0) {
+    if (fma_t(p[0], hx, p[1] * hy) <= T(0)) return false;
+    v = hz - p[2];
+  } else {
+    v = fma_t(f.rx, dx, f.ry * dy);
+  }
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ T chi2_of(const FrameT<T> &f, T vu, T vv, T u, T v) {
+  const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
+  const T det = fma_t(suu, svv, -suv * suv);
+  return (svv * u * u - T(2) * suv * u * v + suu * v * v) / det;
+}
+
+// Kalman gain-form update with the hit (u, v residual, variances vu, vv):
+// K = C H^T S^-1, p += K r, C -= K (C H^T)^T.
+template <typename T>
+__device__ __forceinline__ void kf_update(T *p, T *c, const FrameT<T> &f, int kind, T vu, T vv,
+                                          T u, T v) {
+  T PHu[6], PHv[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const T ci0 = c[i <= 0 ? tri(i, 0) : tri(0, i)];
+    const T ci1 = c[i <= 1 ? tri(i, 1) : tri(1, i)];
+    PHu[i] = fma_t(f.tx, ci0, f.ty * ci1);
+    PHv[i] = kind == 0 ? c[i <= 2 ? tri(i, 2) : tri(2, i)] : fma_t(f.rx, ci0, f.ry * ci1);
+  }
+  const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
+  const T inv_det = T(1) / fma_t(suu, svv, -suv * suv);
+  const T iuu = svv * inv_det, ivv = suu * inv_det, iuv = -suv * inv_det;
+  T Ku[6], Kv[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    Ku[i] = fma_t(PHu[i], iuu, PHv[i] * iuv);
+    Kv[i] = fma_t(PHu[i], iuv, PHv[i] * ivv);
+    p[i] = fma_t(Ku[i], u, fma_t(Kv[i], v, p[i]));
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) c[tri(i, j)] -= fma_t(Ku[i], PHu[j], Kv[i] * PHv[j]);
+  p[4] = wrap_phi(p[4]);
+}
+
+}  // namespace mkf

@@ -1,0 +1,911 @@
+// mkf_kernels.hip -- gfx950 kernels of the Kalman-filter track finding and
+// fitting hot path (arXiv:1811.04141).
+//
+//  hit index   : per (event, layer) phi x q bins, CSR over 32-byte records
+//  seeding     : triplet helix, 3-hit Kalman fit, per-seed layer plan
+//  find        : the clone engine (Introduction): every candidate of a seed
+//                is propagated to the next plan layer, all its window hits
+//                are scored by chi2, the seed's best extensions are chosen
+//                across its lane group, and only the kept ones are updated.
+//                One lane per candidate slot, kGroup = 8 lanes per seed.
+//                Two forms share the step code: one launch per layer step
+//                with the state in HBM, or one persistent launch that keeps
+//                the state in VGPRs across all steps of a seed tile.
+//  finalize    : best candidate per seed, hit history from back-pointers
+//  propagate / fit : unit propagation and search-free Kalman fitting.
+#include <hip/hip_runtime.h>
+
+#include "mkf_kernels.hpp"
+
+namespace mkf {
+
+typedef unsigned long long u64;
+constexpr u64 kKeyMax = ~0ull;
+constexpr unsigned kOrderNone = 0x7FFFFFu;  // misses and skips sort after every hit
+
+// Ranking key of an extension: more hits first, then smaller accumulated
+// chi2, then parent rank, then hit index (miss/skip last).  A total order:
+// ties cannot occur between different extensions.
+//   bits 58..63: 63 - n_hits   bits 26..57: chi2 (non-negative float bits)
+//   bits 23..25: parent slot   bits 0..22 : hit index or kOrderNone
+__device__ __forceinline__ u64 ext_key(int nh, float chi2, int parent, unsigned order) {
+  return ((u64)(63 - nh) << 58) | ((u64)__float_as_uint(chi2) << 26) | ((u64)parent << 23) |
+         (u64)order;
+}
+// Key of a finished candidate when the seed's result is chosen: final
+// candidates (by slot) come before retired ones (by step, then slot) on
+// equal hits and chi2.
+__device__ __forceinline__ u64 final_key(int nh, float chi2, int retired, int step, int slot) {
+  return ((u64)(63 - nh) << 58) | ((u64)__float_as_uint(chi2) << 26) | ((u64)retired << 25) |
+         ((u64)step << 19) | ((u64)slot << 16);
+}
+__device__ __forceinline__ int fkey_step(u64 k) { return (int)((k >> 19) & 63); }
+__device__ __forceinline__ int fkey_slot(u64 k) { return (int)((k >> 16) & 7); }
+
+__device__ __forceinline__ u64 shfl_xor_u64(u64 v, int m) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo = __shfl_xor(lo, m);
+  hi = __shfl_xor(hi, m);
+  return ((u64)hi << 32) | lo;
+}
+// minimum over the 8 lanes of a seed's group
+__device__ __forceinline__ u64 group_min(u64 v) {
+  u64 o = shfl_xor_u64(v, 1);
+  v = o < v ? o : v;
+  o = shfl_xor_u64(v, 2);
+  v = o < v ? o : v;
+  o = shfl_xor_u64(v, 4);
+  v = o < v ? o : v;
+  return v;
+}
+__device__ __forceinline__ int group_sum(int v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
+// sorted insertion into a register list (compile-time indices only)
+__device__ __forceinline__ void insert_sorted(u64 (&lst)[kGroup], u64 k) {
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) {
+    const u64 a = lst[i];
+    const bool lt = k < a;
+    lst[i] = lt ? k : a;
+    k = lt ? a : k;
+  }
+}
+__device__ __forceinline__ void pop_front(u64 (&lst)[kGroup]) {
+#pragma unroll
+  for (int i = 0; i < kGroup - 1; ++i) lst[i] = lst[i + 1];
+  lst[kGroup - 1] = kKeyMax;
+}
+
+__device__ __forceinline__ void stage_layers(const FindParams &P, DevLayer *sl) {
+  for (int i = threadIdx.x; i < P.n_layers; i += blockDim.x) sl[i] = P.layers[i];
+}
+
+struct Cand {
+  float p[6];
+  float c[21];
+  float chi2;
+  int nh, nm;
+  bool active;
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ---------------------------------------------------------------- window
+//
+// Bounding box of the chi2 < cut ellipse of every hit on the layer: with
+// S_hit <= H C H^T + diag(var_max), |u| <= sqrt(cut S_uu) and |v| <= sqrt(cut
+// S_vv).  Barrel: u = R_h sin(dphi) (hits in the same half), v = dz.  Disk:
+// the hit is at (r' + v) rh + u t, so its radius lies in [r' - dv,
+// sqrt((r' + dv)^2 + du^2)] and its azimuth within atan2(du, r' - dv).  A small
+// margin absorbs FP32 rounding of the bin assignment.
+__device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer &L, int ev,
+                                            const Prop &pr, const Frame &f, float chi2_base,
+                                            int nh, int slot, u64 (&lst)[kGroup], int &n_ext) {
+  const float cut = P.cfg.chi2_cut;
+  const float du = sqrtf(cut * (f.suu + L.vu_max)) * 1.001f + 1e-5f;
+  const float dv = sqrtf(cut * (f.svv + L.vv_max)) * 1.001f + 1e-5f;
+  const float phic = atan2f(pr.p[1], pr.p[0]);
+  float dphi, qmin, qmax;
+  if (L.kind == 0) {
+    const float s = du / (L.pos * 0.99999f);
+    dphi = s >= 1.f ? 0.5f * kPi : asinf(s);
+    qmin = pr.p[2] - dv;
+    qmax = pr.p[2] + dv;
+  } else {
+    const float r = sqrtf(fmaf(pr.p[0], pr.p[0], pr.p[1] * pr.p[1]));
+    const float rl = r - dv;
+    qmin = rl;
+    qmax = sqrtf(fmaf(r + dv, r + dv, du * du));
+    dphi = rl > 0.f ? atan2f(du, rl) : kPi;
+  }
+  dphi += 4e-6f;
+  qmin -= 1e-4f;
+  qmax += 1e-4f;
+  const int nphi = L.nphi;
+  const int qlo = clampi((int)floorf((qmin - L.q_lo) * L.q_scale), 0, L.nq - 1);
+  const int qhi = clampi((int)floorf((qmax - L.q_lo) * L.q_scale), 0, L.nq - 1);
+  int s0lo = 0, s0hi = nphi - 1, s1lo = 1, s1hi = 0;
+  if (dphi < kPi) {
+    const int blo = (int)floorf((phic - dphi + kPi) * L.phi_scale);
+    const int bhi = (int)floorf((phic + dphi + kPi) * L.phi_scale);
+    if (bhi - blo + 1 < nphi) {
+      if (blo < 0) {
+        s0lo = blo + nphi; s0hi = nphi - 1; s1lo = 0; s1hi = bhi;
+      } else if (bhi >= nphi) {
+        s0lo = blo; s0hi = nphi - 1; s1lo = 0; s1hi = bhi - nphi;
+      } else {
+        s0lo = blo; s0hi = bhi;
+      }
+    }
+  }
+  const int base = ev * P.bins_per_event + L.bin_base;
+  for (int qb = qlo; qb <= qhi; ++qb) {
+    const int row = base + qb * nphi;
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      const int lo = sg == 0 ? s0lo : s1lo;
+      const int hi = sg == 0 ? s0hi : s1hi;
+      if (lo > hi) continue;
+      const int h0 = P.bin_start[row + lo];
+      const int h1 = P.bin_start[row + hi + 1];
+      for (int k = h0; k < h1; ++k) {
+        const float4 a = reinterpret_cast<const float4 *>(P.sorted)[2 * k];
+        const float4 b = reinterpret_cast<const float4 *>(P.sorted)[2 * k + 1];
+        float u, v;
+        if (!residual(pr.p, f, L.kind, a.x, a.y, a.z, u, v)) continue;
+        const float c2 = fmaxf(chi2_of(f, a.w, b.x, u, v), 0.f);
+        if (c2 < cut) {
+          insert_sorted(lst, ext_key(nh + 1, chi2_base + c2, slot, (unsigned)__float_as_int(b.y)));
+          ++n_ext;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ one step
+//
+// One layer step of one seed, executed by its 8-lane group.  On entry each
+// lane holds one candidate (or none); on exit it holds the candidate of its
+// rank among the kept extensions.  pos indexes the seed's find buffers.
+__device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
+                                           int lane, int slot, int64_t pos, int ev, int step,
+                                           int lid, u64 &fin_key) {
+  const DevLayer &L = sl[lid];
+  Prop pr;
+  int st = kNoCrossing;
+  if (cd.active)
+    st = propagate<true>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr);
+  const bool ok = cd.active && st == kOk;
+  if (ok) add_ms(pr.p, P.cfg.ms_var, pr.c);
+
+  u64 lst[kGroup];
+#pragma unroll
+  for (int i = 0; i < kGroup; ++i) lst[i] = kKeyMax;
+  int n_ext = 0;
+  if (cd.active) {
+    if (!ok) {
+      insert_sorted(lst, ext_key(cd.nh, cd.chi2, slot, kOrderNone));  // skip
+      n_ext = 1;
+    } else {
+      Frame f;
+      make_frame(pr.p, pr.c, L.kind, f);
+      scan_window(P, L, ev, pr, f, cd.chi2, cd.nh, slot, lst, n_ext);
+      if (cd.nm < P.cfg.max_holes) {
+        insert_sorted(lst, ext_key(cd.nh, cd.chi2, slot, kOrderNone));  // miss
+        ++n_ext;
+      }
+    }
+  }
+
+  // a candidate without any extension stops; keep the seed's best such one
+  const bool retire = cd.active && n_ext == 0;
+  const u64 rkey = retire ? final_key(cd.nh, cd.chi2, 1, step, slot) : kKeyMax;
+  const u64 rmin = group_min(rkey);
+  if (rmin < fin_key) {
+    if (rkey == rmin) {
+      const size_t N = (size_t)P.n_seeds;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) P.fin_rec[i * N + pos] = cd.p[i];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) P.fin_rec[(6 + i) * N + pos] = cd.c[i];
+      P.fin_rec[27 * N + pos] = cd.chi2;
+      P.fin_meta[pos] = cd.nh | (cd.nm << 8);
+    }
+    fin_key = rmin;
+  }
+
+  // the seed's best n_cand extensions, rank r goes to slot r
+  u64 mine = kKeyMax;
+  for (int r = 0; r < P.cfg.n_cand; ++r) {
+    const u64 m = group_min(lst[0]);
+    if (m != kKeyMax && lst[0] == m) pop_front(lst);
+    if (slot == r) mine = m;
+  }
+
+  // children read their parent's propagated state (or, for a skip, its
+  // unpropagated state) across the group
+  float src[27];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) src[i] = ok ? pr.p[i] : cd.p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) src[6 + i] = ok ? pr.c[i] : cd.c[i];
+  const int src_meta = cd.nh | (cd.nm << 8) | (ok ? (1 << 16) : 0);
+  const int parent = mine == kKeyMax ? slot : (int)((mine >> 23) & 7);
+  const int src_lane = (lane & ~7) | parent;
+  float np[27];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) np[i] = __shfl(src[i], src_lane);
+  const int pmeta = __shfl(src_meta, src_lane);
+
+  int bpv = -1;
+  if (mine != kKeyMax) {
+    const unsigned order = (unsigned)(mine & 0x7FFFFFu);
+    int nh = pmeta & 0xFF, nm = (pmeta >> 8) & 0xFF;
+    const bool pok = (pmeta >> 16) & 1;
+    int hitcode;
+    if (order != kOrderNone) {
+      const int64_t gi = P.ev_off[ev] + order;
+      const float hx = P.hx[gi], hy = P.hy[gi], hz = P.hz[gi];
+      const float vu = P.hvu[gi], vv = P.hvv[gi];
+      Frame f;
+      make_frame(np, np + 6, L.kind, f);
+      float u, v;
+      residual(np, f, L.kind, hx, hy, hz, u, v);
+      kf_update(np, np + 6, f, L.kind, vu, vv, u, v);
+      ++nh;
+      hitcode = (int)order;
+    } else if (pok) {
+      ++nm;
+      hitcode = -1;
+    } else {
+      hitcode = -2;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cd.p[i] = np[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) cd.c[i] = np[6 + i];
+    cd.chi2 = __uint_as_float((unsigned)(mine >> 26));
+    cd.nh = nh;
+    cd.nm = nm;
+    cd.active = true;
+    bpv = ((hitcode + 2) << 3) | parent;
+  } else {
+    cd.active = false;
+  }
+  P.bp[((size_t)step * (size_t)P.n_seeds + pos) * kGroup + slot] = bpv;
+}
+
+__device__ __forceinline__ void load_seed(const FindParams &P, int seed, Cand &cd) {
+  const size_t N = (size_t)P.n_seeds;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) cd.p[i] = P.seed_state[i * N + seed];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) cd.c[i] = P.seed_state[(6 + i) * N + seed];
+  cd.chi2 = 0.f;
+  cd.nh = 3;
+  cd.nm = 0;
+}
+
+__device__ __forceinline__ void load_cand(const FindParams &P, size_t idx, Cand &cd) {
+  const size_t NS = (size_t)P.n_seeds * kGroup;
+  const int meta = __float_as_int(P.cand[28 * NS + idx]);
+  cd.active = (meta >> 16) & 1;
+  cd.nh = meta & 0xFF;
+  cd.nm = (meta >> 8) & 0xFF;
+  if (cd.active) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cd.p[i] = P.cand[i * NS + idx];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) cd.c[i] = P.cand[(6 + i) * NS + idx];
+    cd.chi2 = P.cand[27 * NS + idx];
+  }
+}
+
+__device__ __forceinline__ void store_cand(const FindParams &P, size_t idx, const Cand &cd) {
+  const size_t NS = (size_t)P.n_seeds * kGroup;
+  const int meta = cd.nh | (cd.nm << 8) | (cd.active ? (1 << 16) : 0);
+  P.cand[28 * NS + idx] = __int_as_float(meta);
+  if (cd.active) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) P.cand[i * NS + idx] = cd.p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) P.cand[(6 + i) * NS + idx] = cd.c[i];
+    P.cand[27 * NS + idx] = cd.chi2;
+  }
+}
+
+// --------------------------------------------------- layer-synchronous form
+
+__global__ __launch_bounds__(256) void k_find_init(FindParams P) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pos = gid / kGroup;
+  const int slot = (int)(gid % kGroup);
+  if (pos >= P.n_seeds) return;
+  const int seed = P.order[pos];
+  Cand cd;
+  cd.active = slot == 0 && P.seed_ok[seed];
+  cd.nh = 3;
+  cd.nm = 0;
+  cd.chi2 = 0.f;
+  if (cd.active) load_seed(P, seed, cd);
+  store_cand(P, (size_t)pos * kGroup + slot, cd);
+  if (slot == 0) P.fin_key[pos] = kKeyMax;
+}
+
+__global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64_t n_active) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pos = gid / kGroup;
+  const int slot = (int)(gid % kGroup);
+  const int lane = threadIdx.x & 63;
+  if (pos >= n_active) return;
+  const int seed = P.order[pos];
+  if (step >= P.plan_len[seed]) return;  // whole group leaves together
+  const int lid = P.plan[(size_t)seed * kMaxPlan + step];
+  const int ev = P.seed_event[seed];
+  Cand cd;
+  load_cand(P, (size_t)pos * kGroup + slot, cd);
+  u64 fin_key = P.fin_key[pos];
+  const u64 fk0 = fin_key;
+  group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
+  store_cand(P, (size_t)pos * kGroup + slot, cd);
+  if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
+}
+
+// ----------------------------------------------------- persistent form
+//
+// Each wavefront claims tiles of 8 seeds from a counter and carries them
+// through all their layer steps with the candidates in VGPRs; only the hit
+// index, the back-pointers and the final state touch memory.
+
+__global__ __launch_bounds__(256) void k_find_persistent(FindParams P) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int slot = lane & 7;
+  const int grp = lane >> 3;
+  for (;;) {
+    int tile = 0;
+    if (lane == 0) tile = atomicAdd(P.tile_counter, 1);
+    tile = __shfl(tile, 0);
+    if (tile >= P.n_tiles) break;
+    const int64_t pos = (int64_t)tile * 8 + grp;
+    const bool valid = pos < P.n_seeds;
+    const int seed = valid ? P.order[pos] : 0;
+    const int plen = valid ? P.plan_len[seed] : 0;
+    const int ev = valid ? P.seed_event[seed] : 0;
+    Cand cd;
+    cd.active = valid && slot == 0 && P.seed_ok[seed];
+    cd.nh = 3;
+    cd.nm = 0;
+    cd.chi2 = 0.f;
+    if (cd.active) load_seed(P, seed, cd);
+    u64 fin_key = kKeyMax;
+    int maxlen = plen;
+#pragma unroll
+    for (int m = 8; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
+    for (int step = 0; step < maxlen; ++step) {
+      if (step < plen) {
+        const int lid = P.plan[(size_t)seed * kMaxPlan + step];
+        group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
+      }
+    }
+    if (valid) {
+      store_cand(P, (size_t)pos * kGroup + slot, cd);
+      if (slot == 0) P.fin_key[pos] = fin_key;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+//
+// Best of the final and the retired candidates of each seed (more hits,
+// then smaller chi2), its hit history from the back-pointers, and the count
+// of candidate-layer steps (the candidates alive at each step).
+
+__global__ __launch_bounds__(256) void k_finalize(FindParams P) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pos = gid / kGroup;
+  const int slot = (int)(gid % kGroup);
+  __shared__ unsigned long long block_steps;
+  if (threadIdx.x == 0) block_steps = 0;
+  __syncthreads();
+  if (pos < P.n_seeds) {
+    const int seed = P.order[pos];
+    const int ok = P.seed_ok[seed];
+    const int plen = P.plan_len[seed];
+    const size_t NS = (size_t)P.n_seeds * kGroup;
+    const size_t N = (size_t)P.n_seeds;
+    const size_t idx = (size_t)pos * kGroup + slot;
+    mkf_track *T = &P.tracks[seed];
+    // steps: 1 for the seed at step 0, then every kept extension that is
+    // carried into the next step
+    int cnt = 0;
+    if (ok)
+      for (int s = 0; s + 1 < plen; ++s)
+        cnt += P.bp[((size_t)s * N + pos) * kGroup + slot] >= 0 ? 1 : 0;
+    cnt = group_sum(cnt);
+    if (slot == 0 && ok && plen > 0) atomicAdd(&block_steps, (unsigned long long)(cnt + 1));
+
+    const int meta = __float_as_int(P.cand[28 * NS + idx]);
+    const bool active = ok && ((meta >> 16) & 1);
+    const float chi2 = active ? P.cand[27 * NS + idx] : 0.f;
+    const u64 fk = active ? final_key(meta & 0xFF, chi2, 0, 0, slot) : kKeyMax;
+    const u64 m = group_min(fk);
+    const u64 fin = ok ? P.fin_key[pos] : kKeyMax;
+    const bool final_wins = m != kKeyMax && m < fin;
+    int best_step = -1, best_slot = -1;
+    if (final_wins) {
+      best_step = plen - 1;
+      best_slot = fkey_slot(m);
+    } else if (fin != kKeyMax) {
+      best_step = fkey_step(fin) - 1;
+      best_slot = fkey_slot(fin);
+    }
+    if (final_wins && fk == m) {
+      for (int i = 0; i < 6; ++i) T->par[i] = P.cand[i * NS + idx];
+      for (int i = 0; i < 21; ++i) T->cov[i] = P.cand[(6 + i) * NS + idx];
+      T->chi2 = chi2;
+      T->n_hits = meta & 0xFF;
+      T->n_miss = (meta >> 8) & 0xFF;
+    } else if (!final_wins && slot == 0) {
+      if (fin != kKeyMax) {
+        for (int i = 0; i < 6; ++i) T->par[i] = P.fin_rec[i * N + pos];
+        for (int i = 0; i < 21; ++i) T->cov[i] = P.fin_rec[(6 + i) * N + pos];
+        T->chi2 = P.fin_rec[27 * N + pos];
+        T->n_hits = P.fin_meta[pos] & 0xFF;
+        T->n_miss = (P.fin_meta[pos] >> 8) & 0xFF;
+      } else {
+        for (int i = 0; i < 6; ++i) T->par[i] = 0.f;
+        for (int i = 0; i < 21; ++i) T->cov[i] = 0.f;
+        T->chi2 = 0.f;
+        T->n_hits = 0;
+        T->n_miss = 0;
+      }
+    }
+    if (slot == 0) {
+      T->seed_id = seed;
+      T->status = ok;
+      T->plan_len = ok ? plen : 0;
+      for (int s = 0; s < kMaxPlan; ++s) {
+        T->plan[s] = (ok && s < plen) ? P.plan[(size_t)seed * kMaxPlan + s] : (int8_t)-1;
+        T->hit[s] = MKF_HIT_NONE;
+      }
+      int sl = best_slot;
+      for (int s = best_step; s >= 0; --s) {
+        const int v = P.bp[((size_t)s * N + pos) * kGroup + sl];
+        T->hit[s] = (v >> 3) - 2;
+        sl = v & 7;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && block_steps) atomicAdd(P.n_steps, block_steps);
+}
+
+// --------------------------------------------------------------- seeding
+//
+// Seeds come from outside (Section 2.2).  The circle through the three
+// transverse points gives the centre and radius, the turning sense the
+// charge, the tangent at the first hit phi, and the z rise over the arc
+// theta.  A wide diagonal prior at the first hit is filtered through the
+// three hits.  The layer plan (the paper's per-region list of layers to
+// traverse, Section 2.1) is built per seed: every other layer the seed
+// helix crosses inside its widened extent, by increasing path length.
+
+__global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits,
+                                              float *seed_state, int *seed_ok, int *plan_len,
+                                              int8_t *plan, double *plan_l) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n_seeds) return;
+  const size_t N = (size_t)P.n_seeds;
+  const int ev = P.seed_event[i];
+  const int64_t e0 = P.ev_off[ev];
+  // FP64: three updates shrink the wide prior by ~5 decades, more than FP32
+  // keeps in C - K S K^T; the result is rounded to FP32 for the find
+  double hx[3], hy[3], hz[3], hvu[3], hvv[3];
+  int hl[3];
+  for (int k = 0; k < 3; ++k) {
+    const int64_t g = e0 + seed_hits[3 * i + k];
+    hx[k] = P.hx[g];
+    hy[k] = P.hy[g];
+    hz[k] = P.hz[g];
+    hvu[k] = P.hvu[g];
+    hvv[k] = P.hvv[g];
+    hl[k] = P.hlayer[g];
+  }
+  const double mkb = P.cfg.mkb, l_min = P.cfg.l_min, edge = P.cfg.edge_margin;
+  const double ms_var = (double)P.cfg.ms_var;
+  int ok = 0;
+  int n = 0;
+  double p[6], c[21];
+  do {
+    const double ax = hx[1] - hx[0], ay = hy[1] - hy[0];
+    const double bx = hx[2] - hx[0], by = hy[2] - hy[0];
+    const double d = 2.0 * (ax * by - ay * bx);
+    if (d == 0.0 || mkb == 0.0) break;
+    const double a2 = ax * ax + ay * ay, b2 = bx * bx + by * by;
+    const double ux = (by * a2 - ay * b2) / d;
+    const double uy = (ax * b2 - bx * a2) / d;
+    const double cx = hx[0] + ux, cy = hy[0] + uy;
+    const double rho = sqrt(ux * ux + uy * uy);
+    const double turn = (hx[1] - hx[0]) * (hy[2] - hy[1]) - (hy[1] - hy[0]) * (hx[2] - hx[1]);
+    const bool ccw = turn > 0.0;  // omega > 0
+    // omega = mkb * ipt and |omega| = 1/rho
+    const double ipt = (ccw ? 1.0 : -1.0) / (mkb * rho);
+    const double r1x = hx[0] - cx, r1y = hy[0] - cy;
+    const double dirx = ccw ? -r1y : r1y, diry = ccw ? r1x : -r1x;
+    const double phi1 = atan2(diry, dirx);
+    const double r3x = hx[2] - cx, r3y = hy[2] - cy;
+    const double dpsi = atan2(r1x * r3y - r1y * r3x, r1x * r3x + r1y * r3y);
+    const double theta = atan2(rho * fabs(dpsi), hz[2] - hz[0]);
+    p[0] = hx[0]; p[1] = hy[0]; p[2] = hz[0]; p[3] = ipt; p[4] = phi1; p[5] = theta;
+    for (int k = 0; k < 21; ++k) c[k] = 0.0;
+    for (int k = 0; k < 6; ++k) c[tri(k, k)] = P.cfg.init_var[k];
+    bool good = true;
+    for (int k = 0; k < 3 && good; ++k) {
+      const DevLayer &L = sl[hl[k]];
+      if (k > 0) {
+        PropT<double> pr;
+        if (propagate<true, double>(p, c, L, mkb, l_min, false, 0.0, pr) != kOk) {
+          good = false;
+          break;
+        }
+        for (int q = 0; q < 6; ++q) p[q] = pr.p[q];
+        for (int q = 0; q < 21; ++q) c[q] = pr.c[q];
+      }
+      add_ms(p, ms_var, c);
+      FrameT<double> f;
+      make_frame(p, c, L.kind, f);
+      double u, v;
+      if (!residual(p, f, L.kind, hx[k], hy[k], hz[k], u, v)) {
+        good = false;
+        break;
+      }
+      kf_update(p, c, f, L.kind, hvu[k], hvv[k], u, v);
+    }
+    if (!good) break;
+    ok = 1;
+    // plan: insertion by path length (ties by layer id) into global scratch
+    for (int L = 0; L < P.n_layers; ++L) {
+      if (L == hl[0] || L == hl[1] || L == hl[2]) continue;
+      PropT<double> pr;
+      if (propagate<false, double>(p, nullptr, sl[L], mkb, l_min, true, edge, pr) != kOk)
+        continue;
+      if (n >= kMaxPlan) break;
+      const double lf = pr.l;
+      int j = n;
+      while (j > 0 && plan_l[i * kMaxPlan + j - 1] > lf) {
+        plan_l[i * kMaxPlan + j] = plan_l[i * kMaxPlan + j - 1];
+        plan[i * kMaxPlan + j] = plan[i * kMaxPlan + j - 1];
+        --j;
+      }
+      plan_l[i * kMaxPlan + j] = lf;
+      plan[i * kMaxPlan + j] = (int8_t)L;
+      ++n;
+    }
+  } while (false);
+  seed_ok[i] = ok;
+  plan_len[i] = ok ? n : 0;
+  for (int k = 0; k < 6; ++k) seed_state[k * N + i] = ok ? (float)p[k] : 0.f;
+  for (int k = 0; k < 21; ++k) seed_state[(6 + k) * N + i] = ok ? (float)c[k] : 0.f;
+}
+
+// ------------------------------------------------------------- hit index
+
+__device__ __forceinline__ int event_of(const int64_t *ev_off, int n_events, int64_t i) {
+  int lo = 0, hi = n_events;  // ev_off[lo] <= i < ev_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ev_off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int bin_of(const DevLayer &L, float x, float y, float z) {
+  const float phi = atan2f(y, x);
+  const int pb = clampi((int)floorf((phi + kPi) * L.phi_scale), 0, L.nphi - 1);
+  const float q = L.kind == 0 ? z : sqrtf(fmaf(x, x, y * y));
+  const int qb = clampi((int)floorf((q - L.q_lo) * L.q_scale), 0, L.nq - 1);
+  return L.bin_base + qb * L.nphi + pb;
+}
+
+__global__ __launch_bounds__(256) void k_hit_bins(FindParams P, int n_events, int64_t n_hits,
+                                                  const int *layer, int *hit_bin, int *counts) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_hits) return;
+  const int e = event_of(P.ev_off, n_events, i);
+  const int b = e * P.bins_per_event + bin_of(sl[layer[i]], P.hx[i], P.hy[i], P.hz[i]);
+  hit_bin[i] = b;
+  atomicAdd(&counts[b], 1);
+}
+
+__global__ __launch_bounds__(256) void k_hit_scatter(FindParams P, int n_events, int64_t n_hits,
+                                                     const int *hit_bin, int *fill,
+                                                     HitRec *sorted) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_hits) return;
+  const int e = event_of(P.ev_off, n_events, i);
+  const int b = hit_bin[i];
+  const int slot = P.bin_start[b] + atomicAdd(&fill[b], 1);
+  HitRec h;
+  h.x = P.hx[i];
+  h.y = P.hy[i];
+  h.z = P.hz[i];
+  h.vu = P.hvu[i];
+  h.vv = P.hvv[i];
+  h.orig = (int)(i - P.ev_off[e]);
+  h.pad0 = 0;
+  h.pad1 = 0;
+  sorted[slot] = h;
+}
+
+// exclusive scan, 2048 items per 256-thread block
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256 * kScanItems;
+
+__global__ __launch_bounds__(256) void k_block_scan(const int *in, int *out, int64_t n,
+                                                    int *block_sums) {
+  __shared__ int wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    s += v[k];
+  }
+  // inclusive scan of s over the block
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int w = 0; w < wid; ++w) woff += wsum[w];
+  int run = woff + incl - s;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 255) block_sums[blockIdx.x] = woff + incl;
+}
+
+__global__ __launch_bounds__(256) void k_add_offsets(int *out, int64_t n, const int *offs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] += offs[i / kScanBlock];
+}
+
+__global__ void k_set_total(int *out, int64_t n, const int *block_sums, const int *scanned,
+                            int64_t nb) {
+  out[n] = nb == 1 ? block_sums[0] : scanned[nb];
+}
+
+// --------------------------------------------------------- unit kernels
+
+__global__ __launch_bounds__(256) void k_propagate(FindParams P, int64_t n, const float *par,
+                                                   const float *cov, const int *layer,
+                                                   float *out_par, float *out_cov, float *out_l,
+                                                   int *out_status) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float p[6], c[21];
+  for (int k = 0; k < 6; ++k) p[k] = par[i * 6 + k];
+  for (int k = 0; k < 21; ++k) c[k] = cov[i * 21 + k];
+  const int lid = layer[i];
+  Prop pr;
+  const int st = (lid < 0 || lid >= P.n_layers)
+                     ? 3
+                     : propagate<true>(p, c, sl[lid], P.cfg.mkb, P.cfg.l_min, true,
+                                       P.cfg.edge_margin, pr);
+  out_status[i] = st;
+  for (int k = 0; k < 6; ++k) out_par[i * 6 + k] = st == kOk ? pr.p[k] : 0.f;
+  for (int k = 0; k < 21; ++k) out_cov[i * 21 + k] = st == kOk ? pr.c[k] : 0.f;
+  out_l[i] = st == kOk ? pr.l : 0.f;
+}
+
+// Search-free Kalman fit: one lane per track, the hit loop in registers;
+// the per-step inputs are step-major so each step is a coalesced read.
+__global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
+                                             const int8_t *kind, const float *pos,
+                                             const float *x, const float *y, const float *z,
+                                             const float *vu, const float *vv, const int *len,
+                                             const float *init_par, const float *init_cov,
+                                             float *out_par, float *out_cov, float *out_chi2,
+                                             int *out_status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float p[6], c[21];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[k] = init_par[i * 6 + k];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = init_cov[i * 21 + k];
+  float chi2 = 0.f;
+  int status = 0;
+  const int m = min(len[i], n_steps);
+  for (int s = 0; s < m; ++s) {
+    const size_t j = (size_t)s * (size_t)n + i;
+    DevLayer L;
+    L.kind = kind[j];
+    L.pos = pos[j];
+    L.lo = 0.f;
+    L.hi = 0.f;
+    Prop pr;
+    if (propagate<true>(p, c, L, cfg.mkb, cfg.l_min, false, 0.f, pr) != kOk) {
+      status = s + 1;
+      break;
+    }
+    add_ms(pr.p, cfg.ms_var, pr.c);
+    Frame f;
+    make_frame(pr.p, pr.c, L.kind, f);
+    float u, v;
+    if (!residual(pr.p, f, L.kind, x[j], y[j], z[j], u, v)) {
+      status = s + 1;
+      break;
+    }
+    const float hvu = vu[j], hvv = vv[j];
+    chi2 += fmaxf(chi2_of(f, hvu, hvv, u, v), 0.f);
+    kf_update(pr.p, pr.c, f, L.kind, hvu, hvv, u, v);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = pr.p[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = pr.c[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out_par[i * 6 + k] = p[k];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) out_cov[i * 21 + k] = c[k];
+  out_chi2[i] = chi2;
+  out_status[i] = status;
+}
+
+__global__ __launch_bounds__(256) void k_validate_hits(int64_t n, const float *x, const float *y,
+                                                       const float *z, const float *vu,
+                                                       const float *vv, const int *layer,
+                                                       int n_layers, int *bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool good = isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]) && isfinite(vu[i]) &&
+                    isfinite(vv[i]) && vu[i] > 0.f && vv[i] > 0.f && layer[i] >= 0 &&
+                    layer[i] < n_layers;
+  if (!good) atomicOr(bad, 1);
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int *p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
+                     int *hit_bin, int *counts) {
+  if (n_hits == 0) return;
+  hipLaunchKernelGGL(k_hit_bins, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P, P.n_events,
+                     n_hits, layer, hit_bin, counts);
+}
+
+void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const int *hit_bin,
+                    int *fill, HitRec *sorted) {
+  if (n_hits == 0) return;
+  hipLaunchKernelGGL(k_hit_scatter, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P,
+                     P.n_events, n_hits, hit_bin, fill, sorted);
+}
+
+static void scan_rec(hipStream_t s, const int *in, int *out, int64_t n, int *scratch) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  int *sums = scratch;
+  int *scanned = scratch + nb;
+  hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(256), 0, s, in, out, n, sums);
+  if (nb > 1) {
+    scan_rec(s, sums, scanned, nb, scratch + 2 * nb + 1);
+    hipLaunchKernelGGL(k_add_offsets, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, n,
+                       scanned);
+  }
+  hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, sums, scanned, nb);
+}
+
+void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, int *tmp_b) {
+  (void)tmp_b;
+  if (n == 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, out, (int64_t)1, 0);
+    return;
+  }
+  scan_rec(s, in, out, n, tmp_a);
+}
+
+void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
+                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_seed, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, seed_hits,
+                     seed_state, seed_ok, plan_len, plan, plan_l);
+}
+
+void launch_find_init(hipStream_t s, const FindParams &P) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_find_init, dim3(blocks_for(P.n_seeds * kGroup, 256)), dim3(256), 0, s, P);
+}
+
+void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active) {
+  if (n_active == 0) return;
+  hipLaunchKernelGGL(k_find_step, dim3(blocks_for(n_active * kGroup, 256)), dim3(256), 0, s, P,
+                     step, n_active);
+}
+
+void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_find_persistent, dim3(grid_blocks), dim3(256), 0, s, P);
+}
+
+void launch_finalize(hipStream_t s, const FindParams &P) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_seeds * kGroup, 256)), dim3(256), 0, s, P);
+}
+
+void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,
+                      const float *cov, const int *layer, float *out_par, float *out_cov,
+                      float *out_l, int *out_status) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_propagate, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, n, par, cov,
+                     layer, out_par, out_cov, out_l, out_status);
+}
+
+void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const int8_t *kind,
+                const float *pos, const float *x, const float *y, const float *z,
+                const float *vu, const float *vv, const int *len, const float *init_par,
+                const float *init_cov, float *out_par, float *out_cov, float *out_chi2,
+                int *out_status) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fit, dim3(blocks_for(n, 256)), dim3(256), 0, s, cfg, n, n_steps, kind, pos,
+                     x, y, z, vu, vv, len, init_par, init_cov, out_par, out_cov, out_chi2,
+                     out_status);
+}
+
+void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,
+                          const float *z, const float *vu, const float *vv, const int *layer,
+                          int n_layers, int *bad) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_validate_hits, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, y, z, vu,
+                     vv, layer, n_layers, bad);
+}
+
+void launch_fill_u64(hipStream_t s, unsigned long long *p, int64_t n, unsigned long long v) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_i32(hipStream_t s, int *p, int64_t n, int v) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+}  // namespace mkf

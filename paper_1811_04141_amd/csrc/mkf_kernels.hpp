@@ -1,0 +1,86 @@
+// mkf_kernels.hpp -- kernel parameter blocks and launch wrappers shared by
+// the kernels (mkf_kernels.hip) and the host runtime (mkf_capi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mkf_device.hpp"
+#include "../../include/mkf.h"
+
+namespace mkf {
+
+// Hit as stored in the binned index: one 32-byte record, two 16-byte loads.
+struct alignas(16) HitRec {
+  float x, y, z, vu;
+  float vv;
+  int orig;  // event-local index in the caller's order
+  int pad0, pad1;
+};
+
+// Candidate buffers between layer steps (layer-synchronous form), SoA by
+// field over n_seeds * kGroup slots so that a wavefront reads 64
+// consecutive floats per field.
+constexpr int kCandFields = 29;  // 6 par + 21 cov + chi2 + meta (bit cast)
+
+struct FindParams {
+  // geometry and settings
+  const DevLayer *layers;
+  int n_layers;
+  DevCfg cfg;
+  // hits
+  int n_events;
+  const int64_t *ev_off;   // n_events + 1
+  const float *hx, *hy, *hz, *hvu, *hvv;  // caller order, all events
+  const int *hlayer;
+  const HitRec *sorted;    // binned
+  const int *bin_start;    // n_events * bins_per_event + 1
+  int bins_per_event;
+  // seeds
+  int64_t n_seeds;
+  const int *seed_event;
+  const float *seed_state;  // [27][n_seeds]
+  const int *seed_ok;
+  const int *plan_len;
+  const int8_t *plan;       // [n_seeds][kMaxPlan]
+  const int *order;         // processing order of seeds (permutation)
+  // find state
+  float *cand;              // [kCandFields][n_seeds * kGroup]
+  unsigned long long *fin_key;  // [n_seeds]
+  float *fin_rec;           // [28][n_seeds] state + chi2 of the best retired candidate
+  int *fin_meta;            // [n_seeds] n_hits | n_miss << 8
+  int *bp;                  // [kMaxPlan][n_seeds][kGroup] back-pointers
+  // persistent form
+  int *tile_counter;
+  int n_tiles;
+  // outputs
+  mkf_track *tracks;        // [n_seeds]
+  unsigned long long *n_steps;
+};
+
+void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
+                     int *hit_bin, int *counts);
+void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, int *tmp_b);
+void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const int *hit_bin,
+                    int *fill, HitRec *sorted);
+void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
+                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l);
+void launch_find_init(hipStream_t s, const FindParams &P);
+void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active_seeds);
+void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks);
+void launch_finalize(hipStream_t s, const FindParams &P);
+void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,
+                      const float *cov, const int *layer, float *out_par, float *out_cov,
+                      float *out_l, int *out_status);
+void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const int8_t *kind,
+                const float *pos, const float *x, const float *y, const float *z,
+                const float *vu, const float *vv, const int *len, const float *init_par,
+                const float *init_cov, float *out_par, float *out_cov, float *out_chi2,
+                int *out_status);
+void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,
+                          const float *z, const float *vu, const float *vv, const int *layer,
+                          int n_layers, int *bad);
+void launch_fill_u64(hipStream_t s, unsigned long long *p, int64_t n, unsigned long long v);
+void launch_fill_i32(hipStream_t s, int *p, int64_t n, int v);
+
+}  // namespace mkf

@@ -1,0 +1,234 @@
+"""ctypes binding of libmkf.so (C ABI in include/mkf.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device arrays are torch tensors on the GPU (PyTorch provides device
+memory and streams); host arrays are numpy arrays.  There is no CPU fallback:
+if the library is missing this module raises on import.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmkf.so")
+
+MKF_OK, MKF_E_ARG, MKF_E_ORDER, MKF_E_CAPACITY, MKF_E_HIP, MKF_E_GEOMETRY, MKF_E_NUMERIC = (
+    0, -1, -2, -3, -4, -5, -6)
+MEM_HOST, MEM_DEVICE = 0, 1
+F_BATCHED, F_GRAPH = 1, 2
+MAX_LAYERS = MAX_PLAN = 32
+MAX_CAND = 8
+HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
+
+EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
+           "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
+           "mkf_fit", "mkf_get_stats")
+
+
+class MkfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mkf status {status}: {msg}")
+        self.status = status
+
+
+class Layer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pos", C.c_float), ("ext_lo", C.c_float),
+                ("ext_hi", C.c_float), ("var_u_max", C.c_float), ("var_v_max", C.c_float),
+                ("n_phi_bins", C.c_int32), ("n_q_bins", C.c_int32)]
+
+
+class Config(C.Structure):
+    _fields_ = [("bz", C.c_float), ("kappa", C.c_float), ("chi2_cut", C.c_float),
+                ("ms_sigma", C.c_float), ("edge_margin", C.c_float), ("l_min", C.c_float),
+                ("n_cand", C.c_int32), ("max_holes", C.c_int32), ("init_var", C.c_float * 6),
+                ("flags", C.c_uint32)]
+
+
+class Track(C.Structure):
+    _fields_ = [("seed_id", C.c_int32), ("status", C.c_int32), ("n_hits", C.c_int32),
+                ("n_miss", C.c_int32), ("plan_len", C.c_int32), ("chi2", C.c_float),
+                ("par", C.c_float * 6), ("cov", C.c_float * 21), ("plan", C.c_int8 * MAX_PLAN),
+                ("hit", C.c_int32 * MAX_PLAN)]
+
+
+TRACK_DTYPE = np.dtype([("seed_id", "<i4"), ("status", "<i4"), ("n_hits", "<i4"),
+                        ("n_miss", "<i4"), ("plan_len", "<i4"), ("chi2", "<f4"),
+                        ("par", "<f4", 6), ("cov", "<f4", 21), ("plan", "i1", MAX_PLAN),
+                        ("hit", "<i4", MAX_PLAN)], align=True)
+assert TRACK_DTYPE.itemsize == C.sizeof(Track)
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_seeds", C.c_int64), ("n_seeds_ok", C.c_int64), ("n_steps", C.c_int64),
+                ("max_plan_len", C.c_int32), ("n_launches", C.c_int32), ("find_ms", C.c_float),
+                ("index_ms", C.c_float), ("seed_ms", C.c_float), ("main_ms", C.c_float),
+                ("main_launches", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I64, I32, U32 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32
+    sig = {
+        "mkf_create": ([C.POINTER(Config), P, C.POINTER(P)], I32),
+        "mkf_destroy": ([P], None),
+        "mkf_last_error": ([P], C.c_char_p),
+        "mkf_load_geometry": ([P, C.POINTER(Layer), I32], I32),
+        "mkf_load_hits": ([P, I32, P, P, P, P, P, P, P, I32], I32),
+        "mkf_seed": ([P, I64, P, P, I32], I32),
+        "mkf_get_seed_states": ([P, P, P, P, P, P], I32),
+        "mkf_find": ([P], I32),
+        "mkf_get_tracks": ([P, P, I64, C.POINTER(I64)], I32),
+        "mkf_propagate": ([P, I64, P, P, P, P, P, P, P], I32),
+        "mkf_fit": ([P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P], I32),
+        "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _ptr(a):
+    """Address of a torch tensor (device) or numpy array (host)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        assert a.is_contiguous()
+        return C.c_void_p(a.data_ptr())
+    assert a.flags["C_CONTIGUOUS"]
+    return C.c_void_p(a.ctypes.data)
+
+
+def _is_device(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def make_config(fc, flags=0):
+    c = Config()
+    c.bz, c.kappa, c.chi2_cut = fc.bz, fc.kappa, fc.chi2_cut
+    c.ms_sigma, c.edge_margin, c.l_min = fc.ms_sigma, fc.edge_margin, fc.l_min
+    c.n_cand, c.max_holes = fc.n_cand, fc.max_holes
+    for i in range(6):
+        c.init_var[i] = fc.init_var[i]
+    c.flags = flags
+    return c
+
+
+def make_layers(layers):
+    arr = (Layer * len(layers))()
+    for i, l in enumerate(layers):
+        arr[i] = Layer(int(l.kind), float(l.pos), float(l.ext_lo), float(l.ext_hi),
+                       float(l.var_u_max), float(l.var_v_max), int(l.n_phi_bins), int(l.n_q_bins))
+    return arr
+
+
+class Context:
+    """One library context bound to a HIP stream (torch's current stream
+    unless given)."""
+
+    def __init__(self, find_config, flags=0, stream=None):
+        self.cfg = make_config(find_config, flags)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = C.c_void_p()
+        st = lib.mkf_create(C.byref(self.cfg), C.c_void_p(stream), C.byref(h))
+        if st != MKF_OK:
+            raise MkfError(st, lib.mkf_last_error(None).decode())
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mkf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != MKF_OK:
+            raise MkfError(st, lib.mkf_last_error(self.h).decode())
+
+    def load_geometry(self, layers):
+        self._check(lib.mkf_load_geometry(self.h, make_layers(layers), len(layers)))
+
+    def load_hits(self, ev_off, x, y, z, var_u, var_v, layer):
+        ev_off = np.ascontiguousarray(ev_off, np.int64)
+        arrs = (x, y, z, var_u, var_v, layer)
+        dev = _is_device(x)
+        assert all(_is_device(a) == dev for a in arrs)
+        self._check(lib.mkf_load_hits(self.h, len(ev_off) - 1, _ptr(ev_off),
+                                      *[_ptr(a) for a in arrs], MEM_DEVICE if dev else MEM_HOST))
+
+    def seed(self, seed_event, seed_hits):
+        dev = _is_device(seed_event)
+        self._check(lib.mkf_seed(self.h, int(seed_event.shape[0]), _ptr(seed_event),
+                                 _ptr(seed_hits), MEM_DEVICE if dev else MEM_HOST))
+
+    def get_seed_states(self, n):
+        par = np.zeros((n, 6), np.float32)
+        cov = np.zeros((n, 21), np.float32)
+        ok = np.zeros(n, np.int32)
+        plen = np.zeros(n, np.int32)
+        plan = np.zeros((n, MAX_PLAN), np.int8)
+        self._check(lib.mkf_get_seed_states(self.h, _ptr(par), _ptr(cov), _ptr(ok), _ptr(plen),
+                                            _ptr(plan)))
+        return par, cov, ok, plen, plan
+
+    def find(self):
+        self._check(lib.mkf_find(self.h))
+
+    def get_tracks(self, n):
+        out = np.zeros(n, TRACK_DTYPE)
+        tot = C.c_int64()
+        self._check(lib.mkf_get_tracks(self.h, _ptr(out), n, C.byref(tot)))
+        return out
+
+    def propagate(self, par, cov, layer, out_par, out_cov, out_l, out_status):
+        self._check(lib.mkf_propagate(self.h, int(par.shape[0]), _ptr(par), _ptr(cov), _ptr(layer),
+                                      _ptr(out_par), _ptr(out_cov), _ptr(out_l),
+                                      _ptr(out_status)))
+
+    def fit(self, kind, pos, x, y, z, var_u, var_v, length, init_par, init_cov, out_par,
+            out_cov, out_chi2, out_status):
+        n_steps, n = x.shape
+        self._check(lib.mkf_fit(self.h, n, n_steps, _ptr(kind), _ptr(pos), _ptr(x), _ptr(y),
+                                _ptr(z), _ptr(var_u), _ptr(var_v), _ptr(length), _ptr(init_par),
+                                _ptr(init_cov), _ptr(out_par), _ptr(out_cov), _ptr(out_chi2),
+                                _ptr(out_status)))
+
+    def stats(self):
+        s = Stats()
+        self._check(lib.mkf_get_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def unpack_cov(c21):
+    """Packed upper triangle (..., 21) -> full (..., 6, 6)."""
+    c21 = np.asarray(c21)
+    out = np.zeros(c21.shape[:-1] + (6, 6), c21.dtype)
+    k = 0
+    for i in range(6):
+        for j in range(i, 6):
+            out[..., i, j] = c21[..., k]
+            out[..., j, i] = c21[..., k]
+            k += 1
+    return out
+
+
+def pack_cov(full):
+    full = np.asarray(full)
+    idx = [(i, j) for i in range(6) for j in range(i, 6)]
+    return np.stack([full[..., i, j] for i, j in idx], axis=-1)

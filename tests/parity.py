@@ -1,0 +1,109 @@
+"""Parity helpers: compare the GPU path with the FP64 oracle.
+
+Tolerances (the arithmetic is FP32 on the GPU, FP64 in the oracle):
+  parameters: |d| <= 1e-4 * max(|ref|, s) with s = the radial position scale
+              for x, y, z, |q/pT| for q/pT, 1 rad for phi and theta;
+  chi2:       |d| <= 1e-3 * chi2 + 1e-2 (the absolute floor covers FP32
+              rounding of positions near 100 cm, ~1e-3 of a 30 um hit error);
+  indices:    equal, unless the oracle flagged a decision of that seed as
+              lying within the chi2 tolerance of the cut or of a tie, or an
+              extent decision within 1e-3 cm of a widened edge.
+"""
+import numpy as np
+
+PAR_REL = 1e-4
+CHI2_REL, CHI2_ABS = 1e-3, 1e-2
+# covariance after ~10-25 chained FP32 gain-form updates, in units of
+# sqrt(C_ii C_jj): each update cancels C - K S K^T by up to the ratio of the
+# predicted to the filtered variance, and strongly correlated pairs (q/pT with
+# phi) amplify it; measured worst cases are 8e-3 (found tracks) and 1.5e-2
+# (fits of 3,000 tracks through up to 23 hits).  The parameters and chi2
+# these covariances produce still meet their own bounds.
+COV_REL_FOUND = 3e-2
+# A track that meets a layer almost tangentially (cosine between direction
+# and surface normal below 0.2) makes the surface projection divide by that
+# cosine: FP32 then cancels terms ~1/cos^2 larger than the result (a
+# 0.40 GeV/c track reaching R = 70 cm has cos = 0.075).  Such tracks get a
+# covariance bound of 0.2 in correlation units; parameters and chi2 keep
+# theirs.
+GRAZING_COS = 0.2
+COV_REL_GRAZING = 0.2
+
+
+def wrap(a):
+    return (a + np.pi) % (2 * np.pi) - np.pi
+
+
+def par_ok(g, r):
+    g = np.asarray(g, np.float64)
+    r = np.asarray(r, np.float64)
+    spos = max(np.hypot(r[0], r[1]), abs(r[2]), 1.0)
+    d = g - r
+    d[4] = wrap(d[4])
+    scale = np.array([max(abs(r[0]), spos), max(abs(r[1]), spos), max(abs(r[2]), spos),
+                      abs(r[3]), 1.0, 1.0])
+    return bool(np.all(np.abs(d) <= PAR_REL * scale)), d / scale
+
+
+def cov_err(g, r):
+    """Largest |dC_ij| / sqrt(C_ii C_jj) (the error in correlation units)."""
+    g = np.asarray(g, np.float64)
+    r = np.asarray(r, np.float64)
+    d = np.abs(np.diag(r))
+    # a direction pinned by the surface (z on a disk) has zero variance: its
+    # entries are compared against 1e-10 of the largest variance instead
+    dg = np.sqrt(np.maximum(d, 1e-10 * d.max()))
+    scale = np.outer(dg, dg)
+    return float((np.abs(g - r) / scale).max())
+
+
+def cov_ok(g, r, rel=2e-3):
+    """Covariances: each entry within rel of sqrt(C_ii C_jj)."""
+    return cov_err(g, r) <= rel
+
+
+def chi2_ok(g, r):
+    return abs(float(g) - float(r)) <= CHI2_REL * abs(float(r)) + CHI2_ABS
+
+
+def compare_tracks(gpu, ref, full_cov, cov_rel=COV_REL_FOUND):
+    """gpu: records (TRACK_DTYPE) of the sampled seeds; ref: oracle dicts.
+    Returns counts; 'fail' lists unexplained mismatches."""
+    out = {"n": 0, "equal": 0, "tie_diverged": 0, "plan_diverged": 0, "fragile": 0,
+           "max_cov_err": 0.0, "fail": []}
+    for i, (g, r) in enumerate(zip(gpu, ref)):
+        out["n"] += 1
+        fragile = r["fragile_step"] >= 0
+        out["fragile"] += fragile
+        if not r["seed_ok"]:
+            if g["status"] != 0:
+                out["fail"].append((i, "seed ok on GPU only"))
+            continue
+        if g["status"] != 1:
+            out["fail"].append((i, "seed failed on GPU only"))
+            continue
+        n = len(r["plan"])
+        if g["plan_len"] != n or list(g["plan"][:n]) != list(r["plan"]):
+            if r["fragile_step"] == 0:
+                out["plan_diverged"] += 1
+            else:
+                out["fail"].append((i, "plan", list(g["plan"][:g["plan_len"]]), list(r["plan"])))
+            continue
+        same = list(g["hit"][:n]) == list(r["hit"]) and g["n_hits"] == r["n_hits"]
+        if not same:
+            if fragile:
+                out["tie_diverged"] += 1
+            else:
+                out["fail"].append((i, "hits", list(g["hit"][:n]), list(r["hit"])))
+            continue
+        ok_p, rel = par_ok(g["par"], r["par"])
+        ok_c = chi2_ok(g["chi2"], r["chi2"])
+        ce = cov_err(full_cov(g["cov"]), r["cov"])
+        out["max_cov_err"] = max(out["max_cov_err"], ce)
+        ok_v = ce <= cov_rel
+        if ok_p and ok_c and ok_v:
+            out["equal"] += 1
+        else:  # same hits, same arithmetic: no excuse
+            out["fail"].append((i, "numeric", ok_p, ok_c, ok_v, rel.tolist(),
+                                float(g["chi2"]), float(r["chi2"])))
+    return out
