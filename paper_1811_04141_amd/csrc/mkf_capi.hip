@@ -70,13 +70,15 @@ struct mkf_ctx {
   // seeds
   int64_t n_seeds = 0;
   DevBuf d_seed_event, d_seed_hits, d_seed_state, d_seed_ok, d_plan_len, d_plan, d_plan_l;
-  DevBuf d_order;
+  DevBuf d_order, d_pstate, d_pinfo, d_pevent, d_pplan;
+  std::vector<int32_t> h_order, h_plen, h_ok;
   std::vector<int64_t> active_at_step;  // seeds (in processing order) with plan_len > step
   int max_plan_len = 0;
   int64_t n_seeds_ok = 0;
 
   // find
-  DevBuf d_cand, d_fin_key, d_fin_rec, d_fin_meta, d_bp, d_tracks, d_steps, d_tiles;
+  DevBuf d_cand, d_fin_key, d_fin_rec, d_fin_meta, d_bp, d_steps, d_tiles, d_qoff;
+  DevBuf d_out_par, d_out_cov, d_out_chi2, d_out_meta, d_out_hit;
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_m0 = nullptr, ev_m1 = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -89,8 +91,10 @@ struct mkf_ctx {
     DevBuf *all[] = {&d_layers, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
                      &d_hit_bin, &d_counts, &d_fill, &d_bin_start, &d_scan_tmp, &d_sorted,
                      &d_bad, &d_seed_event, &d_seed_hits, &d_seed_state, &d_seed_ok,
-                     &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_cand, &d_fin_key,
-                     &d_fin_rec, &d_fin_meta, &d_bp, &d_tracks, &d_steps, &d_tiles};
+                     &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_pstate, &d_pinfo,
+                     &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
+                     &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out_par, &d_out_cov, &d_out_chi2,
+                     &d_out_meta, &d_out_hit};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -159,14 +163,23 @@ FindParams params(mkf_ctx *c) {
   P.plan_len = c->d_plan_len.as<int>();
   P.plan = c->d_plan.as<int8_t>();
   P.order = c->d_order.as<int>();
+  P.pstate = c->d_pstate.as<float>();
+  P.pinfo = c->d_pinfo.as<int>();
+  P.pevent = c->d_pevent.as<int>();
+  P.pplan = c->d_pplan.as<int8_t>();
+  P.out_par = c->d_out_par.as<float>();
+  P.out_cov = c->d_out_cov.as<float>();
+  P.out_chi2 = c->d_out_chi2.as<float>();
+  P.out_meta = c->d_out_meta.as<int>();
+  P.out_hit = c->d_out_hit.as<int>();
   P.cand = c->d_cand.as<float>();
   P.fin_key = c->d_fin_key.as<unsigned long long>();
   P.fin_rec = c->d_fin_rec.as<float>();
   P.fin_meta = c->d_fin_meta.as<int>();
   P.bp = c->d_bp.as<int>();
   P.tile_counter = c->d_tiles.as<int>();
+  P.q_off = c->d_qoff.as<int64_t>();
   P.n_tiles = (int)((c->n_seeds + 7) / 8);
-  P.tracks = c->d_tracks.as<mkf_track>();
   P.n_steps = c->d_steps.as<unsigned long long>();
   return P;
 }
@@ -222,7 +235,7 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   if (e == hipSuccess) e = hipEventCreate(&c->ev_m0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev_m1);
   if (e == hipSuccess) e = c->d_steps.ensure(sizeof(unsigned long long));
-  if (e == hipSuccess) e = c->d_tiles.ensure(sizeof(int));
+  if (e == hipSuccess) e = c->d_tiles.ensure(sizeof(int) * kQueues);
   if (e == hipSuccess) e = c->d_bad.ensure(sizeof(int));
   if (e != hipSuccess) {
     delete c;
@@ -444,13 +457,47 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   c->stats.seed_ms = ms;
   std::vector<int32_t> order(n_seeds);
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    if (plen[a] != plen[b]) return plen[a] > plen[b];
-    if (ev[a] != ev[b]) return ev[a] < ev[b];
-    const int ta = (int)(theta[a] * 8.f), tb = (int)(theta[b] * 8.f);
-    if (ta != tb) return ta < tb;
-    return phi[a] < phi[b];
-  });
+  int64_t q_off[kQueues + 1] = {};
+  if (c->cfg.flags & MKF_F_BATCHED) {
+    // whole events to the kQueues tile queues (one per XCD), balanced by
+    // their summed plan lengths (longest first to the least loaded queue);
+    // inside a queue event by event, longest plans first, then direction
+    std::vector<int64_t> cost(c->n_events, 0);
+    for (int64_t i = 0; i < n_seeds; ++i) cost[ev[i]] += plen[i] + 1;
+    std::vector<int> evs(c->n_events), ev_q(c->n_events, 0);
+    std::iota(evs.begin(), evs.end(), 0);
+    std::stable_sort(evs.begin(), evs.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int64_t load[kQueues] = {};
+    for (int e : evs) {
+      int q = 0;
+      for (int k = 1; k < kQueues; ++k)
+        if (load[k] < load[q]) q = k;
+      ev_q[e] = q;
+      load[q] += cost[e];
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (ev_q[ev[a]] != ev_q[ev[b]]) return ev_q[ev[a]] < ev_q[ev[b]];
+      if (ev[a] != ev[b]) return ev[a] < ev[b];
+      if (plen[a] != plen[b]) return plen[a] > plen[b];
+      const int ta = (int)(theta[a] * 8.f), tb = (int)(theta[b] * 8.f);
+      if (ta != tb) return ta < tb;
+      return phi[a] < phi[b];
+    });
+    for (int64_t p = 0; p < n_seeds; ++p) q_off[ev_q[ev[order[p]]] + 1]++;
+    for (int q = 0; q < kQueues; ++q) q_off[q + 1] += q_off[q];
+  } else {
+    // longest plans first, so the seeds still active at a step form a prefix
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (plen[a] != plen[b]) return plen[a] > plen[b];
+      if (ev[a] != ev[b]) return ev[a] < ev[b];
+      const int ta = (int)(theta[a] * 8.f), tb = (int)(theta[b] * 8.f);
+      if (ta != tb) return ta < tb;
+      return phi[a] < phi[b];
+    });
+    for (int q = 1; q <= kQueues; ++q) q_off[q] = n_seeds;
+  }
+  HIP_TRY(c, c->d_qoff.ensure(sizeof(q_off)));
+  HIP_TRY(c, hipMemcpyAsync(c->d_qoff.ptr, q_off, sizeof(q_off), hipMemcpyHostToDevice, c->stream));
   if (n_seeds > 0)
     HIP_TRY(c, hipMemcpyAsync(c->d_order.ptr, order.data(), 4 * n_seeds, hipMemcpyHostToDevice, c->stream));
   c->max_plan_len = 0;
@@ -461,10 +508,11 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   }
   c->active_at_step.assign(kMaxPlan, 0);
   for (int s = 0; s < kMaxPlan; ++s) {
-    // seeds are sorted by plan length, so the active ones form a prefix
+    // the layer-synchronous form keeps the longest plans first: the seeds
+    // still active at step s form a prefix of the positions
     int64_t n = 0;
     for (int64_t i = 0; i < n_seeds; ++i) n += plen[i] > s ? 1 : 0;
-    c->active_at_step[s] = n;
+    c->active_at_step[s] = (c->cfg.flags & MKF_F_BATCHED) ? n_seeds : n;
   }
   // find buffers
   HIP_TRY(c, c->d_cand.ensure(sizeof(float) * kCandFields * kGroup * N));
@@ -472,7 +520,24 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   HIP_TRY(c, c->d_fin_rec.ensure(sizeof(float) * 28 * N));
   HIP_TRY(c, c->d_fin_meta.ensure(4 * N));
   HIP_TRY(c, c->d_bp.ensure(4 * (size_t)kMaxPlan * kGroup * N));
-  HIP_TRY(c, c->d_tracks.ensure(sizeof(mkf_track) * N));
+  HIP_TRY(c, c->d_pstate.ensure(sizeof(float) * 27 * N));
+  HIP_TRY(c, c->d_pinfo.ensure(4 * N));
+  HIP_TRY(c, c->d_pevent.ensure(4 * N));
+  HIP_TRY(c, c->d_pplan.ensure(kMaxPlan * N));
+  HIP_TRY(c, c->d_out_par.ensure(sizeof(float) * 6 * N));
+  HIP_TRY(c, c->d_out_cov.ensure(sizeof(float) * 21 * N));
+  HIP_TRY(c, c->d_out_chi2.ensure(4 * N));
+  HIP_TRY(c, c->d_out_meta.ensure(4 * N));
+  HIP_TRY(c, c->d_out_hit.ensure(4 * (size_t)kMaxPlan * N));
+  {
+    FindParams Q = params(c);
+    launch_permute_seeds(c->stream, Q, c->d_pstate.as<float>(), c->d_pinfo.as<int>(),
+                         c->d_pevent.as<int>(), c->d_pplan.as<int8_t>());
+    HIP_TRY(c, hipGetLastError());
+  }
+  c->h_order = order;
+  c->h_plen = plen;
+  c->h_ok = ok;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->stats.n_seeds = n_seeds;
   c->stats.n_seeds_ok = c->n_seeds_ok;
@@ -512,7 +577,7 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
   launch_fill_u64(c->stream, c->d_steps.as<unsigned long long>(), 1, 0ull);
   ++launches;
   if (c->cfg.flags & MKF_F_BATCHED) {
-    launch_fill_i32(c->stream, c->d_tiles.as<int>(), 1, 0);
+    launch_fill_i32(c->stream, c->d_tiles.as<int>(), kQueues, 0);
     ++launches;
     if (main_a) (void)hipEventRecord(main_a, c->stream);
     launch_find_persistent(c->stream, P, c->persistent_blocks);
@@ -531,8 +596,10 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
     c->stats.main_launches = n;
   }
   if (main_b) (void)hipEventRecord(main_b, c->stream);
-  launch_finalize(c->stream, P);
-  ++launches;
+  if (!(c->cfg.flags & MKF_F_BATCHED)) {
+    launch_finalize(c->stream, P);
+    ++launches;
+  }
   return launches;
 }
 
@@ -584,11 +651,41 @@ mkf_status mkf_get_tracks(mkf_ctx *c, mkf_track *out, int64_t capacity, int64_t 
   if (c->stage < kFound) return fail(c, MKF_E_ORDER, "find first");
   if (n_total) *n_total = c->n_seeds;
   if (capacity < 0 || (capacity > 0 && !out)) return fail(c, MKF_E_ARG, "bad output buffer");
-  const int64_t n = std::min<int64_t>(capacity, c->n_seeds);
-  if (n > 0)
-    HIP_TRY(c, hipMemcpyAsync(out, c->d_tracks.ptr, sizeof(mkf_track) * n, hipMemcpyDeviceToHost,
-                              c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t N = (size_t)c->n_seeds;
+  if (N > 0) {
+    // results are kept by processing position, structure of arrays
+    std::vector<float> par(6 * N), cov(21 * N), chi2(N);
+    std::vector<int32_t> meta(N), hit((size_t)kMaxPlan * N);
+    std::vector<int8_t> plan((size_t)kMaxPlan * N);
+    HIP_TRY(c, hipMemcpyAsync(par.data(), c->d_out_par.ptr, 4 * 6 * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(cov.data(), c->d_out_cov.ptr, 4 * 21 * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(chi2.data(), c->d_out_chi2.ptr, 4 * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(meta.data(), c->d_out_meta.ptr, 4 * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(hit.data(), c->d_out_hit.ptr, 4 * (size_t)kMaxPlan * N,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(plan.data(), c->d_plan.ptr, (size_t)kMaxPlan * N,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t pos = 0; pos < N; ++pos) {
+      const int seed = c->h_order[pos];
+      if (seed >= capacity) continue;
+      mkf_track &T = out[seed];
+      const bool ok = c->h_ok[seed] != 0;
+      const int plen = ok ? c->h_plen[seed] : 0;
+      T.seed_id = seed;
+      T.status = ok ? 1 : 0;
+      T.n_hits = meta[pos] & 0xFF;
+      T.n_miss = (meta[pos] >> 8) & 0xFF;
+      T.plan_len = plen;
+      T.chi2 = chi2[pos];
+      for (int i = 0; i < 6; ++i) T.par[i] = par[i * N + pos];
+      for (int i = 0; i < 21; ++i) T.cov[i] = cov[i * N + pos];
+      for (int k = 0; k < kMaxPlan; ++k) {
+        T.plan[k] = k < plen ? plan[(size_t)seed * kMaxPlan + k] : (int8_t)-1;
+        T.hit[k] = k < plen ? hit[(size_t)k * N + pos] : MKF_HIT_NONE;
+      }
+    }
+  }
   if (capacity < c->n_seeds)
     return fail(c, MKF_E_CAPACITY, "capacity %lld < %lld tracks", (long long)capacity,
                 (long long)c->n_seeds);

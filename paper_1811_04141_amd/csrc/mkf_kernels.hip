@@ -281,12 +281,12 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   P.bp[((size_t)step * (size_t)P.n_seeds + pos) * kGroup + slot] = bpv;
 }
 
-__device__ __forceinline__ void load_seed(const FindParams &P, int seed, Cand &cd) {
+__device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand &cd) {
   const size_t N = (size_t)P.n_seeds;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) cd.p[i] = P.seed_state[i * N + seed];
+  for (int i = 0; i < 6; ++i) cd.p[i] = P.pstate[i * N + pos];
 #pragma unroll
-  for (int i = 0; i < 21; ++i) cd.c[i] = P.seed_state[(6 + i) * N + seed];
+  for (int i = 0; i < 21; ++i) cd.c[i] = P.pstate[(6 + i) * N + pos];
   cd.chi2 = 0.f;
   cd.nh = 3;
   cd.nm = 0;
@@ -320,6 +320,43 @@ __device__ __forceinline__ void store_cand(const FindParams &P, size_t idx, cons
   }
 }
 
+// The chosen candidate of a seed: state and counts, and its hit history
+// followed back through the per-step back-pointers from (best_step,
+// best_slot).  Plan steps after the candidate stopped read MKF_HIT_NONE.
+__device__ __forceinline__ void write_result(const FindParams &P, int64_t pos, const float *p,
+                                             const float *c, float chi2, int nh, int nm,
+                                             int best_step, int best_slot, int plen) {
+  const size_t N = (size_t)P.n_seeds;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) P.out_par[i * N + pos] = p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) P.out_cov[i * N + pos] = c[i];
+  P.out_chi2[pos] = chi2;
+  P.out_meta[pos] = nh | (nm << 8);
+  for (int s = plen - 1; s > best_step; --s) P.out_hit[s * N + pos] = MKF_HIT_NONE;
+  int sl = best_slot;
+  for (int s = best_step; s >= 0; --s) {
+    const int v = P.bp[((size_t)s * N + pos) * kGroup + sl];
+    P.out_hit[s * N + pos] = (v >> 3) - 2;
+    sl = v & 7;
+  }
+}
+
+__device__ __forceinline__ void write_retired(const FindParams &P, int64_t pos, u64 fin, int plen) {
+  const size_t N = (size_t)P.n_seeds;
+  float p[6], c[21];
+  for (int i = 0; i < 6; ++i) p[i] = P.fin_rec[i * N + pos];
+  for (int i = 0; i < 21; ++i) c[i] = P.fin_rec[(6 + i) * N + pos];
+  const int fm = P.fin_meta[pos];
+  write_result(P, pos, p, c, P.fin_rec[27 * N + pos], fm & 0xFF, (fm >> 8) & 0xFF,
+               fkey_step(fin) - 1, fkey_slot(fin), plen);
+}
+
+__device__ __forceinline__ void write_empty(const FindParams &P, int64_t pos) {
+  const float z[21] = {};
+  write_result(P, pos, z, z, 0.f, 0, 0, -1, 0, 0);
+}
+
 // --------------------------------------------------- layer-synchronous form
 
 __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
@@ -327,13 +364,12 @@ __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
   const int64_t pos = gid / kGroup;
   const int slot = (int)(gid % kGroup);
   if (pos >= P.n_seeds) return;
-  const int seed = P.order[pos];
   Cand cd;
-  cd.active = slot == 0 && P.seed_ok[seed];
+  cd.active = slot == 0 && ((P.pinfo[pos] >> 8) & 1);
   cd.nh = 3;
   cd.nm = 0;
   cd.chi2 = 0.f;
-  if (cd.active) load_seed(P, seed, cd);
+  if (cd.active) load_seed(P, pos, cd);
   store_cand(P, (size_t)pos * kGroup + slot, cd);
   if (slot == 0) P.fin_key[pos] = kKeyMax;
 }
@@ -342,15 +378,19 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
   __syncthreads();
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD x (blocks x, x + 8, ...) takes the x-th contiguous share of the
+  // positions, so that an XCD's L2 serves a few events' hits
+  // (the grid is a multiple of kQueues blocks, so this is a permutation)
+  const int64_t per = gridDim.x / kQueues;
+  const int64_t b = (int64_t)(blockIdx.x % kQueues) * per + blockIdx.x / kQueues;
+  const int64_t gid = b * blockDim.x + threadIdx.x;
   const int64_t pos = gid / kGroup;
   const int slot = (int)(gid % kGroup);
   const int lane = threadIdx.x & 63;
   if (pos >= n_active) return;
-  const int seed = P.order[pos];
-  if (step >= P.plan_len[seed]) return;  // whole group leaves together
-  const int lid = P.plan[(size_t)seed * kMaxPlan + step];
-  const int ev = P.seed_event[seed];
+  if (step >= (P.pinfo[pos] & 0xFF)) return;  // whole group leaves together
+  const int lid = P.pplan[(size_t)pos * kMaxPlan + step];
+  const int ev = P.pevent[pos];
   Cand cd;
   load_cand(P, (size_t)pos * kGroup + slot, cd);
   u64 fin_key = P.fin_key[pos];
@@ -360,136 +400,136 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
 }
 
+// Best of the final and the retired candidates of each seed (more hits,
+// then smaller chi2) and the count of candidate-layer steps (1 for the seed
+// at step 0, then every kept extension carried into the next step).  One
+// lane per seed.
+__global__ __launch_bounds__(256) void k_finalize(FindParams P) {
+  __shared__ unsigned long long block_steps;
+  if (threadIdx.x == 0) block_steps = 0;
+  __syncthreads();
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos < P.n_seeds) {
+    const int info = P.pinfo[pos];
+    const int plen = info & 0xFF;
+    const bool ok = (info >> 8) & 1;
+    const size_t N = (size_t)P.n_seeds;
+    const size_t NS = N * kGroup;
+    int cnt = (ok && plen > 0) ? 1 : 0;
+    for (int s = 0; s + 1 < plen; ++s)
+      for (int j = 0; j < kGroup; ++j) cnt += P.bp[((size_t)s * N + pos) * kGroup + j] >= 0;
+    if (cnt) atomicAdd(&block_steps, (unsigned long long)cnt);
+    u64 m = kKeyMax;
+    int best = 0;
+    if (ok)
+      for (int j = 0; j < kGroup; ++j) {
+        const int meta = __float_as_int(P.cand[28 * NS + pos * kGroup + j]);
+        if (!((meta >> 16) & 1)) continue;
+        const u64 fk = final_key(meta & 0xFF, P.cand[27 * NS + pos * kGroup + j], 0, 0, j);
+        if (fk < m) {
+          m = fk;
+          best = j;
+        }
+      }
+    const u64 fin = ok ? P.fin_key[pos] : kKeyMax;
+    if (m != kKeyMax && m < fin) {
+      Cand cd;
+      load_cand(P, (size_t)pos * kGroup + best, cd);
+      write_result(P, pos, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, best, plen);
+    } else if (fin != kKeyMax) {
+      write_retired(P, pos, fin, plen);
+    } else {
+      write_empty(P, pos);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && block_steps) atomicAdd(P.n_steps, block_steps);
+}
+
 // ----------------------------------------------------- persistent form
 //
 // Each wavefront claims tiles of 8 seeds from a counter and carries them
-// through all their layer steps with the candidates in VGPRs; only the hit
-// index, the back-pointers and the final state touch memory.
+// through all their layer steps with the candidates in VGPRs; the seed's
+// result is chosen in registers at the end.  Only the hit index, the
+// back-pointers and the results touch memory.
 
 __global__ __launch_bounds__(256) void k_find_persistent(FindParams P) {
   __shared__ DevLayer sl[kMaxLayers];
+  __shared__ unsigned long long block_steps;
   stage_layers(P, sl);
+  if (threadIdx.x == 0) block_steps = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int slot = lane & 7;
   const int grp = lane >> 3;
+  int my_steps = 0;
+  int q = blockIdx.x % kQueues;  // this block's XCD
+  int tried = 0;
   for (;;) {
     int tile = 0;
-    if (lane == 0) tile = atomicAdd(P.tile_counter, 1);
+    if (lane == 0) tile = atomicAdd(&P.tile_counter[q], 1);
     tile = __shfl(tile, 0);
-    if (tile >= P.n_tiles) break;
-    const int64_t pos = (int64_t)tile * 8 + grp;
-    const bool valid = pos < P.n_seeds;
-    const int seed = valid ? P.order[pos] : 0;
-    const int plen = valid ? P.plan_len[seed] : 0;
-    const int ev = valid ? P.seed_event[seed] : 0;
+    const int64_t start = P.q_off[q] + (int64_t)tile * 8;
+    const int64_t end = P.q_off[q + 1];
+    if (start >= end) {
+      // queue exhausted: help the next one; stop after all were tried
+      if (++tried >= kQueues) break;
+      q = (q + 1) % kQueues;
+      continue;
+    }
+    const int64_t pos = start + grp;
+    const bool valid = pos < end;
+    const int info = valid ? P.pinfo[pos] : 0;
+    const int plen = info & 0xFF;
+    const int ev = valid ? P.pevent[pos] : 0;
     Cand cd;
-    cd.active = valid && slot == 0 && P.seed_ok[seed];
+    cd.active = valid && slot == 0 && ((info >> 8) & 1);
     cd.nh = 3;
     cd.nm = 0;
     cd.chi2 = 0.f;
-    if (cd.active) load_seed(P, seed, cd);
+    if (cd.active) load_seed(P, pos, cd);
     u64 fin_key = kKeyMax;
     int maxlen = plen;
 #pragma unroll
     for (int m = 8; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
     for (int step = 0; step < maxlen; ++step) {
       if (step < plen) {
-        const int lid = P.plan[(size_t)seed * kMaxPlan + step];
+        my_steps += cd.active ? 1 : 0;
+        const int lid = P.pplan[(size_t)pos * kMaxPlan + step];
         group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
       }
     }
     if (valid) {
-      store_cand(P, (size_t)pos * kGroup + slot, cd);
-      if (slot == 0) P.fin_key[pos] = fin_key;
-    }
-  }
-}
-
-// ---------------------------------------------------------------- finalize
-//
-// Best of the final and the retired candidates of each seed (more hits,
-// then smaller chi2), its hit history from the back-pointers, and the count
-// of candidate-layer steps (the candidates alive at each step).
-
-__global__ __launch_bounds__(256) void k_finalize(FindParams P) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t pos = gid / kGroup;
-  const int slot = (int)(gid % kGroup);
-  __shared__ unsigned long long block_steps;
-  if (threadIdx.x == 0) block_steps = 0;
-  __syncthreads();
-  if (pos < P.n_seeds) {
-    const int seed = P.order[pos];
-    const int ok = P.seed_ok[seed];
-    const int plen = P.plan_len[seed];
-    const size_t NS = (size_t)P.n_seeds * kGroup;
-    const size_t N = (size_t)P.n_seeds;
-    const size_t idx = (size_t)pos * kGroup + slot;
-    mkf_track *T = &P.tracks[seed];
-    // steps: 1 for the seed at step 0, then every kept extension that is
-    // carried into the next step
-    int cnt = 0;
-    if (ok)
-      for (int s = 0; s + 1 < plen; ++s)
-        cnt += P.bp[((size_t)s * N + pos) * kGroup + slot] >= 0 ? 1 : 0;
-    cnt = group_sum(cnt);
-    if (slot == 0 && ok && plen > 0) atomicAdd(&block_steps, (unsigned long long)(cnt + 1));
-
-    const int meta = __float_as_int(P.cand[28 * NS + idx]);
-    const bool active = ok && ((meta >> 16) & 1);
-    const float chi2 = active ? P.cand[27 * NS + idx] : 0.f;
-    const u64 fk = active ? final_key(meta & 0xFF, chi2, 0, 0, slot) : kKeyMax;
-    const u64 m = group_min(fk);
-    const u64 fin = ok ? P.fin_key[pos] : kKeyMax;
-    const bool final_wins = m != kKeyMax && m < fin;
-    int best_step = -1, best_slot = -1;
-    if (final_wins) {
-      best_step = plen - 1;
-      best_slot = fkey_slot(m);
-    } else if (fin != kKeyMax) {
-      best_step = fkey_step(fin) - 1;
-      best_slot = fkey_slot(fin);
-    }
-    if (final_wins && fk == m) {
-      for (int i = 0; i < 6; ++i) T->par[i] = P.cand[i * NS + idx];
-      for (int i = 0; i < 21; ++i) T->cov[i] = P.cand[(6 + i) * NS + idx];
-      T->chi2 = chi2;
-      T->n_hits = meta & 0xFF;
-      T->n_miss = (meta >> 8) & 0xFF;
-    } else if (!final_wins && slot == 0) {
-      if (fin != kKeyMax) {
-        for (int i = 0; i < 6; ++i) T->par[i] = P.fin_rec[i * N + pos];
-        for (int i = 0; i < 21; ++i) T->cov[i] = P.fin_rec[(6 + i) * N + pos];
-        T->chi2 = P.fin_rec[27 * N + pos];
-        T->n_hits = P.fin_meta[pos] & 0xFF;
-        T->n_miss = (P.fin_meta[pos] >> 8) & 0xFF;
-      } else {
-        for (int i = 0; i < 6; ++i) T->par[i] = 0.f;
-        for (int i = 0; i < 21; ++i) T->cov[i] = 0.f;
-        T->chi2 = 0.f;
-        T->n_hits = 0;
-        T->n_miss = 0;
-      }
-    }
-    if (slot == 0) {
-      T->seed_id = seed;
-      T->status = ok;
-      T->plan_len = ok ? plen : 0;
-      for (int s = 0; s < kMaxPlan; ++s) {
-        T->plan[s] = (ok && s < plen) ? P.plan[(size_t)seed * kMaxPlan + s] : (int8_t)-1;
-        T->hit[s] = MKF_HIT_NONE;
-      }
-      int sl = best_slot;
-      for (int s = best_step; s >= 0; --s) {
-        const int v = P.bp[((size_t)s * N + pos) * kGroup + sl];
-        T->hit[s] = (v >> 3) - 2;
-        sl = v & 7;
+      const u64 fk = cd.active ? final_key(cd.nh, cd.chi2, 0, 0, slot) : kKeyMax;
+      const u64 m = group_min(fk);
+      if (m != kKeyMax && m < fin_key) {
+        if (fk == m) write_result(P, pos, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, slot, plen);
+      } else if (slot == 0) {
+        if (fin_key != kKeyMax) write_retired(P, pos, fin_key, plen);
+        else write_empty(P, pos);
       }
     }
   }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) my_steps += __shfl_xor(my_steps, m);
+  if (lane == 0 && my_steps) atomicAdd(&block_steps, (unsigned long long)my_steps);
   __syncthreads();
   if (threadIdx.x == 0 && block_steps) atomicAdd(P.n_steps, block_steps);
+}
+
+// Gather the seed results into processing order (untimed preparation), so
+// that every read of the find is by position.
+__global__ __launch_bounds__(256) void k_permute_seeds(FindParams P, float *pstate, int *pinfo,
+                                                       int *pevent, int8_t *pplan) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const size_t N = (size_t)P.n_seeds;
+  const int seed = P.order[pos];
+  for (int i = 0; i < 27; ++i) pstate[i * N + pos] = P.seed_state[i * N + seed];
+  pinfo[pos] = P.plan_len[seed] | (P.seed_ok[seed] << 8);
+  pevent[pos] = P.seed_event[seed];
+  for (int s = 0; s < kMaxPlan; ++s)
+    pplan[(size_t)pos * kMaxPlan + s] = P.plan[(size_t)seed * kMaxPlan + s];
 }
 
 // --------------------------------------------------------------- seeding
@@ -858,8 +898,9 @@ void launch_find_init(hipStream_t s, const FindParams &P) {
 
 void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active) {
   if (n_active == 0) return;
-  hipLaunchKernelGGL(k_find_step, dim3(blocks_for(n_active * kGroup, 256)), dim3(256), 0, s, P,
-                     step, n_active);
+  const unsigned nb = blocks_for(n_active * kGroup, 256);
+  const unsigned grid = (nb + kQueues - 1) / kQueues * kQueues;  // whole XCD shares
+  hipLaunchKernelGGL(k_find_step, dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks) {
@@ -869,7 +910,14 @@ void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks)
 
 void launch_finalize(hipStream_t s, const FindParams &P) {
   if (P.n_seeds == 0) return;
-  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_seeds * kGroup, 256)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P);
+}
+
+void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int *pinfo,
+                          int *pevent, int8_t *pplan) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_permute_seeds, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     pstate, pinfo, pevent, pplan);
 }
 
 void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,

@@ -22,6 +22,8 @@ struct alignas(16) HitRec {
 // field over n_seeds * kGroup slots so that a wavefront reads 64
 // consecutive floats per field.
 constexpr int kCandFields = 29;  // 6 par + 21 cov + chi2 + meta (bit cast)
+// workgroups are dealt to the 8 XCDs of an MI355X round-robin by index
+constexpr int kQueues = 8;
 
 struct FindParams {
   // geometry and settings
@@ -36,25 +38,37 @@ struct FindParams {
   const HitRec *sorted;    // binned
   const int *bin_start;    // n_events * bins_per_event + 1
   int bins_per_event;
-  // seeds
+  // seeds, by seed id (written by the seed kernel)
   int64_t n_seeds;
   const int *seed_event;
   const float *seed_state;  // [27][n_seeds]
   const int *seed_ok;
   const int *plan_len;
   const int8_t *plan;       // [n_seeds][kMaxPlan]
-  const int *order;         // processing order of seeds (permutation)
+  const int *order;         // processing position -> seed id
+  // the same, gathered once into processing order (read by the find)
+  const float *pstate;      // [27][n_seeds]
+  const int *pinfo;         // [n_seeds] plan_len | ok << 8
+  const int *pevent;        // [n_seeds]
+  const int8_t *pplan;      // [n_seeds][kMaxPlan]
+  // results, by processing position (structure of arrays)
+  float *out_par;           // [6][n_seeds]
+  float *out_cov;           // [21][n_seeds]
+  float *out_chi2;          // [n_seeds]
+  int *out_meta;            // [n_seeds] n_hits | n_miss << 8
+  int *out_hit;             // [kMaxPlan][n_seeds]
   // find state
   float *cand;              // [kCandFields][n_seeds * kGroup]
   unsigned long long *fin_key;  // [n_seeds]
   float *fin_rec;           // [28][n_seeds] state + chi2 of the best retired candidate
   int *fin_meta;            // [n_seeds] n_hits | n_miss << 8
   int *bp;                  // [kMaxPlan][n_seeds][kGroup] back-pointers
-  // persistent form
-  int *tile_counter;
+  // persistent form: kQueues tile queues, queue q owning positions
+  // [q_off[q], q_off[q+1]) (whole events); the blocks of XCD x start on
+  // queue x and move on to the others when it is empty
+  int *tile_counter;        // [kQueues]
+  const int64_t *q_off;     // [kQueues + 1]
   int n_tiles;
-  // outputs
-  mkf_track *tracks;        // [n_seeds]
   unsigned long long *n_steps;
 };
 
@@ -65,6 +79,8 @@ void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const in
                     int *fill, HitRec *sorted);
 void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
                  int *seed_ok, int *plan_len, int8_t *plan, double *plan_l);
+void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int *pinfo,
+                          int *pevent, int8_t *pplan);
 void launch_find_init(hipStream_t s, const FindParams &P);
 void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active_seeds);
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks);
