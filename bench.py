@@ -88,6 +88,7 @@ def main():
             ctx.load_geometry(w.layers)
             ctx.load_hits(batch.ev_off, *hits)
             ctx.seed(*seeds)
+            tuning = ctx.autotune(repeats=2) if flags & mkf.F_BATCHED else None
             for _ in range(args.warmup):
                 ctx.find()
             torch.cuda.synchronize()
@@ -117,6 +118,7 @@ def main():
             "n_steps": st["n_steps"],
             "value": st["n_steps"] / wall,
             "identical_to_first_form": bool(same),
+            "tuning": tuning,
         }
         log(name, json.dumps(results[name]))
 

@@ -195,6 +195,26 @@ mkf_status mkf_fit(mkf_ctx *ctx, int64_t n_tracks, int32_t n_steps, const int8_t
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);
 
+/* Launch shape of the persistent find (MKF_F_BATCHED).  Results do not
+ * depend on it. */
+typedef struct {
+  int32_t waves_per_simd; /* register budget of the persistent kernel, 1..4
+                             (more waves hide more latency, but spill) */
+  int32_t blocks_per_cu;  /* persistent grid = blocks_per_cu x compute units, 1..32 */
+} mkf_tuning;
+
+mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t);
+mkf_status mkf_get_tuning(mkf_ctx *ctx, mkf_tuning *t);
+
+/* Time the persistent find for each candidate launch shape on the loaded
+ * seeds (best of `repeats` runs each, repeats >= 1) and keep the fastest
+ * (written to *best if not NULL).  cache_path (may be NULL) names a text
+ * file of earlier results keyed by GPU architecture, compute units and
+ * workload size: a matching line is used without searching, a search
+ * appends its result.  Blocks until done. */
+mkf_status mkf_autotune(mkf_ctx *ctx, int32_t repeats, const char *cache_path,
+                        mkf_tuning *best);
+
 #ifdef __cplusplus
 }
 #endif

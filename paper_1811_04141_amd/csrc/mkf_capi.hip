@@ -84,7 +84,9 @@ struct mkf_ctx {
   hipGraphExec_t graph_exec = nullptr;
   int graph_launches = 0;
   mkf_stats stats{};
-  int persistent_blocks = 0;
+  int n_cu = 0;
+  std::string arch;
+  mkf_tuning tuning{2, 8};
 
   // fit scratch (host-side inputs are staged here)
   ~mkf_ctx() {
@@ -244,7 +246,11 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   int dev = 0, n_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  c->persistent_blocks = std::max(1, n_cu) * 8;
+  c->n_cu = std::max(1, n_cu);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) c->arch = prop.gcnArchName;
+  for (char &ch : c->arch)
+    if (ch == ' ' || ch == ':') ch = '_';
   c->err = "no error";
   *out = c;
   return MKF_OK;
@@ -580,7 +586,8 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
     launch_fill_i32(c->stream, c->d_tiles.as<int>(), kQueues, 0);
     ++launches;
     if (main_a) (void)hipEventRecord(main_a, c->stream);
-    launch_find_persistent(c->stream, P, c->persistent_blocks);
+    launch_find_persistent(c->stream, P, c->tuning.blocks_per_cu * c->n_cu,
+                           c->tuning.waves_per_simd);
     ++launches;
     c->stats.main_launches = 1;
   } else {
@@ -729,6 +736,90 @@ mkf_status mkf_fit(mkf_ctx *c, int64_t n_tracks, int32_t n_steps, const int8_t *
 mkf_status mkf_get_stats(mkf_ctx *c, mkf_stats *out) {
   if (!c || !out) return MKF_E_ARG;
   *out = c->stats;
+  return MKF_OK;
+}
+
+mkf_status mkf_set_tuning(mkf_ctx *c, const mkf_tuning *t) {
+  if (!c) return MKF_E_ARG;
+  if (!t || t->waves_per_simd < 1 || t->waves_per_simd > 4 || t->blocks_per_cu < 1 ||
+      t->blocks_per_cu > 32)
+    return fail(c, MKF_E_ARG, "tuning out of range");
+  c->tuning = *t;
+  drop_graph(c);
+  return MKF_OK;
+}
+
+mkf_status mkf_get_tuning(mkf_ctx *c, mkf_tuning *t) {
+  if (!c || !t) return MKF_E_ARG;
+  *t = c->tuning;
+  return MKF_OK;
+}
+
+mkf_status mkf_autotune(mkf_ctx *c, int32_t repeats, const char *cache_path, mkf_tuning *best) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
+  if (!(c->cfg.flags & MKF_F_BATCHED)) return fail(c, MKF_E_ARG, "autotune needs MKF_F_BATCHED");
+  if (repeats < 1) return fail(c, MKF_E_ARG, "repeats must be >= 1");
+  // workload key: architecture, compute units, candidate budget, sizes
+  int lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= c->n_seeds) ++lg;
+  char key[256];
+  snprintf(key, sizeof key, "%s cu%d cand%d seeds2^%d events%d layers%d",
+           c->arch.empty() ? "unknown" : c->arch.c_str(), c->n_cu, c->cfg.n_cand, lg,
+           c->n_events, c->n_layers);
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "r")) {
+      char line[512];
+      mkf_tuning hit{0, 0};
+      while (fgets(line, sizeof line, f)) {
+        const size_t kl = strlen(key);
+        int w = 0, b = 0;
+        if (strncmp(line, key, kl) == 0 && line[kl] == '\t' &&
+            sscanf(line + kl + 1, "%d %d", &w, &b) == 2)
+          hit = mkf_tuning{w, b};
+      }
+      fclose(f);
+      if (hit.waves_per_simd >= 1 && hit.waves_per_simd <= 4 && hit.blocks_per_cu >= 1 &&
+          hit.blocks_per_cu <= 32) {
+        c->tuning = hit;
+        drop_graph(c);
+        if (best) *best = hit;
+        return MKF_OK;
+      }
+    }
+  }
+  const uint32_t flags = c->cfg.flags;
+  c->cfg.flags &= ~MKF_F_GRAPH;  // time eager launches
+  drop_graph(c);
+  mkf_tuning keep = c->tuning, win = c->tuning;
+  float win_ms = 1e30f;
+  for (int w = 1; w <= 4; ++w)
+    for (int mult = 1; mult <= 2; ++mult) {
+      c->tuning = mkf_tuning{w, w * mult};
+      float ms = 1e30f;
+      for (int r = 0; r < repeats; ++r) {
+        mkf_status st = mkf_find(c);
+        if (st != MKF_OK) {
+          c->tuning = keep;
+          c->cfg.flags = flags;
+          return st;
+        }
+        ms = std::min(ms, c->stats.main_ms);
+      }
+      if (ms < win_ms) {
+        win_ms = ms;
+        win = c->tuning;
+      }
+    }
+  c->tuning = win;
+  c->cfg.flags = flags;
+  if (best) *best = win;
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "a")) {
+      fprintf(f, "%s\t%d %d %.4f\n", key, win.waves_per_simd, win.blocks_per_cu, win_ms);
+      fclose(f);
+    }
+  }
   return MKF_OK;
 }
 

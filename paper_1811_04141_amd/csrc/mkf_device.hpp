@@ -261,17 +261,6 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
       C[i][j] = c[tri(i, j)];
       C[j][i] = C[i][j];
     }
-  // B = D C (rows)
-  T B[6][6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    B[0][j] = fma_t(E03, C[3][j], fma_t(E04, C[4][j], C[0][j]));
-    B[1][j] = fma_t(E13, C[3][j], fma_t(E14, C[4][j], C[1][j]));
-    B[2][j] = fma_t(E25, C[5][j], C[2][j]);
-    B[3][j] = C[3][j];
-    B[4][j] = fma_t(E43, C[3][j], C[4][j]);
-    B[5][j] = C[5][j];
-  }
   // hk = C k, s = k^T C k, g = D hk
   T hk[6];
 #pragma unroll
@@ -287,16 +276,27 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   g[4] = fma_t(E43, hk[3], hk[4]);
   g[5] = hk[5];
   const T t[6] = {cphi1, sphi1, cot, T(0), w, T(0)};
-  // C' = B D^T - t g^T - g t^T + s t t^T (upper triangle)
+  // C' = B D^T - t g^T - g t^T + s t t^T (upper triangle), with B = D C
+  // formed one row at a time to keep register pressure down
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
+    T Bi[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      T v = C[i][j];
+      if (i == 0) v = fma_t(E03, C[3][j], fma_t(E04, C[4][j], v));
+      if (i == 1) v = fma_t(E13, C[3][j], fma_t(E14, C[4][j], v));
+      if (i == 2) v = fma_t(E25, C[5][j], v);
+      if (i == 4) v = fma_t(E43, C[3][j], v);
+      Bi[j] = v;
+    }
     T Ai[6];
-    Ai[0] = fma_t(E03, B[i][3], fma_t(E04, B[i][4], B[i][0]));
-    Ai[1] = fma_t(E13, B[i][3], fma_t(E14, B[i][4], B[i][1]));
-    Ai[2] = fma_t(E25, B[i][5], B[i][2]);
-    Ai[3] = B[i][3];
-    Ai[4] = fma_t(E43, B[i][3], B[i][4]);
-    Ai[5] = B[i][5];
+    Ai[0] = fma_t(E03, Bi[3], fma_t(E04, Bi[4], Bi[0]));
+    Ai[1] = fma_t(E13, Bi[3], fma_t(E14, Bi[4], Bi[1]));
+    Ai[2] = fma_t(E25, Bi[5], Bi[2]);
+    Ai[3] = Bi[3];
+    Ai[4] = fma_t(E43, Bi[3], Bi[4]);
+    Ai[5] = Bi[5];
 #pragma unroll
     for (int j = i; j < 6; ++j) o.c[tri(i, j)] = Ai[j] - t[i] * g[j] - g[i] * t[j] + s * t[i] * t[j];
   }

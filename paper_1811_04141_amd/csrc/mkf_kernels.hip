@@ -453,7 +453,11 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
 // result is chosen in registers at the end.  Only the hit index, the
 // back-pointers and the results touch memory.
 
-__global__ __launch_bounds__(256) void k_find_persistent(FindParams P) {
+// kWaves: the occupancy the register allocation targets (waves per SIMD);
+// more waves hide more latency but spill part of the state to scratch.
+// The autotuner picks the instantiation.
+template <int kWaves>
+__global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   __shared__ DevLayer sl[kMaxLayers];
   __shared__ unsigned long long block_steps;
   stage_layers(P, sl);
@@ -903,9 +907,14 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
   hipLaunchKernelGGL(k_find_step, dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
-void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks) {
+void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves) {
   if (P.n_seeds == 0) return;
-  hipLaunchKernelGGL(k_find_persistent, dim3(grid_blocks), dim3(256), 0, s, P);
+  switch (waves) {
+    case 1: hipLaunchKernelGGL(k_find_persistent<1>, dim3(grid_blocks), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL(k_find_persistent<3>, dim3(grid_blocks), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL(k_find_persistent<4>, dim3(grid_blocks), dim3(256), 0, s, P); break;
+    default: hipLaunchKernelGGL(k_find_persistent<2>, dim3(grid_blocks), dim3(256), 0, s, P); break;
+  }
 }
 
 void launch_finalize(hipStream_t s, const FindParams &P) {

@@ -23,7 +23,7 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_get_stats")
+           "mkf_fit", "mkf_get_stats", "mkf_set_tuning", "mkf_get_tuning", "mkf_autotune")
 
 
 class MkfError(RuntimeError):
@@ -66,6 +66,10 @@ class Stats(C.Structure):
                 ("main_launches", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("waves_per_simd", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
@@ -84,6 +88,9 @@ def _load():
         "mkf_propagate": ([P, I64, P, P, P, P, P, P, P], I32),
         "mkf_fit": ([P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P], I32),
         "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
+        "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
+        "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
+        "mkf_autotune": ([P, I32, C.c_char_p, C.POINTER(Tuning)], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -208,6 +215,20 @@ class Context:
                                 _ptr(z), _ptr(var_u), _ptr(var_v), _ptr(length), _ptr(init_par),
                                 _ptr(init_cov), _ptr(out_par), _ptr(out_cov), _ptr(out_chi2),
                                 _ptr(out_status)))
+
+    def set_tuning(self, waves_per_simd, blocks_per_cu):
+        self._check(lib.mkf_set_tuning(self.h, C.byref(Tuning(waves_per_simd, blocks_per_cu))))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(lib.mkf_get_tuning(self.h, C.byref(t)))
+        return {"waves_per_simd": t.waves_per_simd, "blocks_per_cu": t.blocks_per_cu}
+
+    def autotune(self, repeats=2, cache_path=None):
+        t = Tuning()
+        self._check(lib.mkf_autotune(self.h, repeats,
+                                     cache_path.encode() if cache_path else None, C.byref(t)))
+        return {"waves_per_simd": t.waves_per_simd, "blocks_per_cu": t.blocks_per_cu}
 
     def stats(self):
         s = Stats()

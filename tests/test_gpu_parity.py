@@ -175,6 +175,33 @@ def test_batched_equals_layer_synchronous_bitwise(mkf):
     assert a.tobytes() == c.tobytes()
 
 
+def test_launch_shapes_do_not_change_results(mkf, tmp_path):
+    """Every persistent-kernel launch shape the autotuner may pick gives
+    bitwise the same tracks; the autotuner's cache round-trips."""
+    w = barrel_endcap()
+    b = generate(w, events=[5, 6])
+    ctx = mkf.Context(w.find, flags=mkf.F_BATCHED)
+    ctx.load_geometry(w.layers)
+    ctx.load_hits(b.ev_off, dev(b.x), dev(b.y), dev(b.z), dev(b.var_u), dev(b.var_v),
+                  dev(b.layer))
+    ctx.seed(dev(b.seed_event), dev(b.seed_hits))
+    n = b.seed_hits.shape[0]
+    ref = None
+    for waves, bpc in [(2, 8), (1, 1), (3, 3), (4, 8)]:
+        ctx.set_tuning(waves, bpc)
+        ctx.find()
+        tr = ctx.get_tracks(n)
+        ref = tr if ref is None else ref
+        assert tr.tobytes() == ref.tobytes(), (waves, bpc)
+    cache = str(tmp_path / "tune.txt")
+    t1 = ctx.autotune(repeats=1, cache_path=cache)
+    t2 = ctx.autotune(repeats=1, cache_path=cache)
+    assert t1 == t2 and open(cache).read().count("\n") == 1
+    ctx.find()
+    assert ctx.get_tracks(n).tobytes() == ref.tobytes()
+    ctx.close()
+
+
 def test_find_edge_cases(mkf):
     """An event without hits, an event whose seeds have empty plans, seeds
     with a candidate budget of one, and no seeds at all."""
