@@ -34,6 +34,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter record
+    (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or None if the
+    kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        rec = json.load(open(path))
+        if not rec["kernel"].startswith(kernel):
+            continue
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() == rec["source_sha256"]:
+            return rec["hbm_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,7 +156,7 @@ def main():
         roof = {"kernel": "k_find_persistent", "bound": "alu", "achieved": achieved,
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = profiled_traffic(roof["kernel"])
     roof["avg_launch_ms"] = per_launch_ms
 
     cpu = None
