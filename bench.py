@@ -59,7 +59,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=100)
     ap.add_argument("--tracks", type=int, default=5000)
-    ap.add_argument("--forms", default="plain,batched,graph")
+    ap.add_argument("--forms", default="plain,batched,graph,surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -96,7 +96,8 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 1 GiB copies")
 
-    forms = {"plain": 0, "batched": mkf.F_BATCHED, "graph": mkf.F_BATCHED | mkf.F_GRAPH}
+    forms = {"plain": 0, "batched": mkf.F_BATCHED, "graph": mkf.F_BATCHED | mkf.F_GRAPH,
+             "surrogate": mkf.F_BATCHED | mkf.F_GRAPH | mkf.F_SURROGATE}
     results = {}
     tracks_ref = None
     for name in args.forms.split(","):
@@ -104,6 +105,10 @@ def main():
         with torch.cuda.stream(stream):
             ctx = mkf.Context(w.find, flags=flags, stream=stream.cuda_stream)
             ctx.load_geometry(w.layers)
+            train = None
+            if flags & mkf.F_SURROGATE:  # trained on the GPU before the timed region
+                train = ctx.surrogate_train(n_samples=1 << 20, epochs=4, batch=512, lr=3e-3,
+                                            seed=11, loss_w=(1, .01, .01, .01, .01, .01, .01))
             ctx.load_hits(batch.ev_off, *hits)
             ctx.seed(*seeds)
             tuning = ctx.autotune(repeats=2) if flags & mkf.F_BATCHED else None
@@ -136,11 +141,22 @@ def main():
             "n_steps": st["n_steps"],
             "value": st["n_steps"] / wall,
             "identical_to_first_form": bool(same),
+            "same_hits_as_first_form": float(np.mean(np.all(tr["hit"] == tracks_ref["hit"],
+                                                            axis=1))),
             "tuning": tuning,
         }
+        if train is not None:
+            results[name]["surrogate"] = {
+                "kept": st["sur_kept"], "rejected": st["sur_rejected"],
+                "kept_frac": st["sur_kept"] / max(1, st["sur_kept"] + st["sur_rejected"]),
+                "train": train}
         log(name, json.dumps(results[name]))
 
     best = max(results, key=lambda k: results[k]["value"])
+    speedup = None
+    if "surrogate" in results and "plain" in results:
+        speedup = {k: results["surrogate"]["value"] / results[k]["value"]
+                   for k in ("plain", "batched", "graph") if k in results}
     R = results[best]
     # roofline of the dominant kernel, from HIP events on the context stream
     kernel_form = best if results[best]["main_ms"] > 0 else ("batched" if "batched" in results else best)
@@ -192,6 +208,7 @@ def main():
                    "seeds": int(batch.seed_hits.shape[0]), "hits": int(batch.x.shape[0]),
                    "form": best, "candidates_per_seed": w.find.n_cand},
         "forms": results,
+        "surrogate_speedup": speedup,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

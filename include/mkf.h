@@ -56,6 +56,8 @@ enum { MKF_MEM_HOST = 0, MKF_MEM_DEVICE = 1 };
 /* Find forms (mkf_config.flags). */
 #define MKF_F_BATCHED 1u  /* one persistent launch over all seeds and layers */
 #define MKF_F_GRAPH 2u    /* replay the find as a captured HIP graph */
+#define MKF_F_SURROGATE 4u /* with MKF_F_BATCHED: barrel propagations start from the
+                              learned surrogate's path length (see mkf_surrogate_*) */
 
 /* History codes in mkf_track.hit. */
 #define MKF_HIT_MISS (-1) /* layer crossed, no hit taken */
@@ -116,6 +118,8 @@ typedef struct {
   float main_ms;           /* device time of the last find's layer-step kernels
                               (all step launches, or the one persistent launch) */
   int32_t main_launches;   /* number of those launches */
+  int64_t sur_kept;        /* surrogate path lengths kept after their Newton step */
+  int64_t sur_rejected;    /* ... rejected (the closed-form crossing was used) */
 } mkf_stats;
 
 typedef struct mkf_ctx mkf_ctx;
@@ -214,6 +218,72 @@ mkf_status mkf_get_tuning(mkf_ctx *ctx, mkf_tuning *t);
  * appends its result.  Blocks until done. */
 mkf_status mkf_autotune(mkf_ctx *ctx, int32_t repeats, const char *cache_path,
                         mkf_tuning *best);
+
+/* ---- learned propagation surrogate --------------------------------------
+ * A multilayer perceptron 8 -> 64 -> 64 -> 7 (SiLU) with BF16 weights on the
+ * matrix cores and FP32 accumulation, predicting the transverse path length
+ * to the next barrel layer as a relative correction to the straight-line
+ * path, plus a 6-value state correction.  Inputs, per sample, for a state
+ * heading to the cylinder R (invariant under rotations about z):
+ * (r0/R, cos a, sin a, omega R, R/70, cot(theta)/5, z/100, 0.3 q/pT), with r0
+ * the start radius, a the angle from the radial direction to the transverse
+ * direction, and omega the signed curvature (-kappa bz q/pT).  Outputs:
+ * 10 (l/l_line - 1) / (omega R); then, scaled by 10/l_line, the end point's
+ * offsets from the straight line along and across the initial direction and
+ * in z; then 10 (cos, sin) of the turning angle minus (10, 0); then 0.  Only
+ * the first output is used by the find; the rest are trained and reported.
+ * In the find (MKF_F_SURROGATE) every prediction gets one exact Newton step
+ * and is kept only if that step moves it by at most 1e-4 relative, the
+ * Newton error bound left after it is at most 1e-7 relative and it is the
+ * first crossing; otherwise the closed-form crossing is used, so the tracks
+ * do not depend on the weights beyond FP32 rounding.  Parameters (5,191 FP32,
+ * in this order): W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]. */
+
+typedef struct {
+  int64_t n_samples; /* training propagations generated on the GPU */
+  int32_t epochs;
+  int32_t batch;     /* samples per Adam step, a multiple of 64 */
+  float lr;          /* Adam step size (cosine-decayed to lr/100) */
+  uint64_t seed;     /* seed of the counter-based sampler */
+  float loss_w[7];   /* per-output weights of the squared error */
+} mkf_train_cfg;
+
+typedef struct {
+  int32_t steps;
+  float loss_first;  /* mean loss over the first 1% of steps */
+  float loss_last;   /* mean loss over the last 1% of steps */
+  float datagen_ms;
+  float train_ms;
+  int64_t n_valid;   /* generated samples that reached their target layer */
+} mkf_train_report;
+
+/* Generate n_samples propagations over the barrel layers of the loaded
+ * geometry with the plain propagator (tracks from the beam line, pT
+ * 0.3-10 GeV/c log-uniform, |eta| < 2.4, from each barrel layer to the
+ * next), then train with the library's forward/backward kernels and Adam
+ * (fresh moments; batches taken in order, epochs repeat them).  Blocks until
+ * done.  Errors: MKF_E_ORDER without geometry, MKF_E_GEOMETRY with fewer
+ * than 2 barrel layers, MKF_E_ARG for bad settings. */
+mkf_status mkf_surrogate_train(mkf_ctx *ctx, const mkf_train_cfg *cfg, mkf_train_report *rep);
+
+/* Read or replace the parameter vector (host, 5,191 floats). */
+mkf_status mkf_surrogate_get(mkf_ctx *ctx, float *params);
+mkf_status mkf_surrogate_set(mkf_ctx *ctx, const float *params);
+
+/* Loss and its gradient for the current weights on n samples (n a positive
+ * multiple of 64; x [n][8], t [n][7] device; loss_w host [7]); grad host
+ * [5,191], loss host.  Blocks until done. */
+mkf_status mkf_surrogate_grad(mkf_ctx *ctx, int32_t n, const float *x, const float *t,
+                              const float *loss_w, float *grad, float *loss);
+
+/* Outputs y [n][7] (device) for inputs x [n][8] (device). */
+mkf_status mkf_surrogate_infer(mkf_ctx *ctx, int64_t n, const float *x, float *y);
+
+/* The training sampler: n inputs x [n][8], targets t [n][7] and validity
+ * flags valid [n] (device outputs).  Needs a geometry with >= 2 barrel
+ * layers. */
+mkf_status mkf_surrogate_samples(mkf_ctx *ctx, int64_t n, uint64_t seed, float *x, float *t,
+                                 float *valid);
 
 #ifdef __cplusplus
 }

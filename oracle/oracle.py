@@ -11,6 +11,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mkf_oracle.c")
+SRC_MLP = os.path.join(HERE, "mkf_mlp.c")
 HDR = os.path.join(HERE, "mkf_oracle.h")
 LIB = os.path.join(HERE, "libmkf_oracle.so")
 
@@ -21,12 +22,13 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, no fast-math)."""
+    srcs = (SRC, SRC_MLP, HDR)
     stale = (not os.path.exists(LIB) or
-             os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(HDR)))
+             os.path.getmtime(LIB) < max(os.path.getmtime(f) for f in srcs))
     if force or stale:
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, SRC, "-lm"])
+                               "-o", tmp, SRC, SRC_MLP, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -88,7 +90,42 @@ def lib():
                                      C.POINTER(Track)]
         L.orc_fit_track.argtypes = [C.POINTER(Cfg), _D, _D, C.c_int32, _I, _D, _D, _D, _D, _D,
                                     _D, _D]
+        L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
+        L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
+        L.orc_mlp_grad.restype = C.c_double
+        L.orc_adam.argtypes = [_D, _D, _D, _D, C.c_int, C.c_int, C.c_double, C.c_double,
+                               C.c_double, C.c_double]
     return _lib
+
+
+# ------------------------------------------------------- surrogate MLP
+
+MLP_NI, MLP_NH, MLP_NO = 8, 64, 7
+MLP_NPARAM = MLP_NH * MLP_NI + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NO * MLP_NH + MLP_NO
+
+
+def mlp_forward(p, x, round_bf16=False):
+    p, x = _d(p, MLP_NPARAM), _d(x)
+    B = x.size // MLP_NI
+    y = np.zeros(B * MLP_NO)
+    lib().orc_mlp_forward(_p(p), B, _p(x), int(round_bf16), _p(y))
+    return y.reshape(B, MLP_NO)
+
+
+def mlp_grad(p, x, t, w, round_bf16=False):
+    """(loss, gradient) of L = (1/B) sum_s sum_j w_j (y_sj - t_sj)^2."""
+    p, x, t, w = _d(p, MLP_NPARAM), _d(x), _d(t), _d(w, MLP_NO)
+    B = x.size // MLP_NI
+    g = np.zeros(MLP_NPARAM)
+    L = lib().orc_mlp_grad(_p(p), B, _p(x), _p(t), _p(w), int(round_bf16), _p(g))
+    return L, g
+
+
+def adam(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    p, m, v = (_d(a).copy() for a in (p, m, v))
+    g = _d(g)
+    lib().orc_adam(_p(p), _p(m), _p(v), _p(g), p.size, t, lr, b1, b2, eps)
+    return p, m, v
 
 
 def _d(a, n=None):

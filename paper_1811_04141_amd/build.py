@@ -3,7 +3,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/mkf_kernels.hip", "csrc/mkf_capi.hip"]
+SOURCES = ["csrc/mkf_kernels.hip", "csrc/mkf_mlp.hip", "csrc/mkf_capi.hip"]
 OUT = os.path.join(HERE, "libmkf.so")
 
 FLAGS = [

@@ -88,6 +88,11 @@ struct mkf_ctx {
   std::string arch;
   mkf_tuning tuning{2, 8};
 
+  // learned surrogate: master weights, Adam moments, BF16 images, counters
+  DevBuf d_mlp_param, d_mlp_m, d_mlp_v, d_W1p, d_W2p, d_W3p, d_W2T, d_W3T, d_mb1, d_mb2, d_mb3;
+  DevBuf d_sur, d_radii, d_tx, d_tt, d_tvalid, d_partial, d_loss, d_grad;
+  int mlp_step = 0;  // Adam steps taken
+
   // fit scratch (host-side inputs are staged here)
   ~mkf_ctx() {
     DevBuf *all[] = {&d_layers, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
@@ -96,7 +101,9 @@ struct mkf_ctx {
                      &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_pstate, &d_pinfo,
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out_par, &d_out_cov, &d_out_chi2,
-                     &d_out_meta, &d_out_hit};
+                     &d_out_meta, &d_out_hit, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
+                     &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
+                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_loss, &d_grad};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -183,10 +190,81 @@ FindParams params(mkf_ctx *c) {
   P.q_off = c->d_qoff.as<int64_t>();
   P.n_tiles = (int)((c->n_seeds + 7) / 8);
   P.n_steps = c->d_steps.as<unsigned long long>();
+  P.mlp = MlpWeights{c->d_W1p.as<__bf16>(), c->d_W2p.as<__bf16>(), c->d_W3p.as<__bf16>(),
+                     c->d_W2T.as<__bf16>(), c->d_W3T.as<__bf16>(), c->d_mb1.as<float>(),
+                     c->d_mb2.as<float>(), c->d_mb3.as<float>()};
+  P.sur_stats = c->d_sur.as<unsigned long long>();
   return P;
 }
 
 bool finite_f(float v) { return std::isfinite(v); }
+
+MlpBuffers mlp_buffers(mkf_ctx *c) {
+  MlpBuffers B{};
+  B.param = c->d_mlp_param.as<float>();
+  B.m = c->d_mlp_m.as<float>();
+  B.v = c->d_mlp_v.as<float>();
+  B.W1p = c->d_W1p.as<__bf16>();
+  B.W2p = c->d_W2p.as<__bf16>();
+  B.W3p = c->d_W3p.as<__bf16>();
+  B.W2T = c->d_W2T.as<__bf16>();
+  B.W3T = c->d_W3T.as<__bf16>();
+  B.b1 = c->d_mb1.as<float>();
+  B.b2 = c->d_mb2.as<float>();
+  B.b3 = c->d_mb3.as<float>();
+  return B;
+}
+
+// Surrogate buffers and the initial weights: Glorot-uniform from a fixed
+// seed (reproducible), zero biases and Adam moments, zero image padding.
+hipError_t mlp_setup(mkf_ctx *c) {
+  const size_t bf = sizeof(__bf16);
+  hipError_t e = hipSuccess;
+  DevBuf *f32[] = {&c->d_mlp_param, &c->d_mlp_m, &c->d_mlp_v};
+  for (DevBuf *b : f32)
+    if (e == hipSuccess) e = b->ensure(sizeof(float) * kNParam);
+  if (e == hipSuccess) e = c->d_W1p.ensure(bf * 64 * kLdW1);
+  if (e == hipSuccess) e = c->d_W2p.ensure(bf * 64 * kLdW2);
+  if (e == hipSuccess) e = c->d_W3p.ensure(bf * 32 * kLdW3);
+  if (e == hipSuccess) e = c->d_W2T.ensure(bf * 64 * kLdW2);
+  if (e == hipSuccess) e = c->d_W3T.ensure(bf * 64 * kLdW3T);
+  if (e == hipSuccess) e = c->d_mb1.ensure(sizeof(float) * 64);
+  if (e == hipSuccess) e = c->d_mb2.ensure(sizeof(float) * 64);
+  if (e == hipSuccess) e = c->d_mb3.ensure(sizeof(float) * 32);
+  if (e == hipSuccess) e = c->d_sur.ensure(sizeof(unsigned long long) * 2);
+  if (e != hipSuccess) return e;
+  DevBuf *zero[] = {&c->d_mlp_m, &c->d_mlp_v, &c->d_W1p, &c->d_W2p, &c->d_W3p, &c->d_W2T,
+                    &c->d_W3T, &c->d_mb1, &c->d_mb2, &c->d_mb3, &c->d_sur};
+  for (DevBuf *b : zero)
+    if (e == hipSuccess) e = hipMemsetAsync(b->ptr, 0, b->bytes, c->stream);
+  std::vector<float> p(kNParam, 0.f);
+  uint64_t st = 0x5EEDF00Dull;
+  auto uni = [&]() {  // SplitMix64 stream
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  auto fill = [&](int off, int fan_out, int fan_in) {
+    const double a = std::sqrt(6.0 / (fan_in + fan_out));
+    for (int i = 0; i < fan_out * fan_in; ++i) p[off + i] = (float)((2.0 * uni() - 1.0) * a);
+  };
+  fill(kOffW1, kNH, kNI);
+  fill(kOffW2, kNH, kNH);
+  fill(kOffW3, kNO, kNH);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_mlp_param.ptr, p.data(), sizeof(float) * kNParam,
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    launch_mlp_images(c->stream, mlp_buffers(c));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->mlp_step = 0;
+  return e;
+}
 
 void drop_graph(mkf_ctx *c) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -247,6 +325,10 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   c->n_cu = std::max(1, n_cu);
+  if (hipError_t em = mlp_setup(c)) {
+    delete c;
+    return fail(nullptr, MKF_E_HIP, "surrogate setup failed: %s", hipGetErrorString(em));
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) c->arch = prop.gcnArchName;
   for (char &ch : c->arch)
@@ -581,13 +663,14 @@ mkf_status mkf_get_seed_states(mkf_ctx *c, float *par, float *cov, int32_t *ok,
 static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipEvent_t main_b) {
   int launches = 0;
   launch_fill_u64(c->stream, c->d_steps.as<unsigned long long>(), 1, 0ull);
+  launch_fill_u64(c->stream, c->d_sur.as<unsigned long long>(), 2, 0ull);
   ++launches;
   if (c->cfg.flags & MKF_F_BATCHED) {
     launch_fill_i32(c->stream, c->d_tiles.as<int>(), kQueues, 0);
     ++launches;
     if (main_a) (void)hipEventRecord(main_a, c->stream);
     launch_find_persistent(c->stream, P, c->tuning.blocks_per_cu * c->n_cu,
-                           c->tuning.waves_per_simd);
+                           c->tuning.waves_per_simd, (c->cfg.flags & MKF_F_SURROGATE) != 0);
     ++launches;
     c->stats.main_launches = 1;
   } else {
@@ -642,9 +725,12 @@ mkf_status mkf_find(mkf_ctx *c) {
   float ms = 0.f, mms = -1.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
   if (!graph) HIP_TRY(c, hipEventElapsedTime(&mms, c->ev_m0, c->ev_m1));
-  unsigned long long steps = 0;
+  unsigned long long steps = 0, sur[2] = {0, 0};
   HIP_TRY(c, hipMemcpyAsync(&steps, c->d_steps.ptr, sizeof steps, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(sur, c->d_sur.ptr, sizeof sur, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->stats.sur_kept = (int64_t)sur[0];
+  c->stats.sur_rejected = (int64_t)sur[1];
   c->stats.find_ms = ms;
   c->stats.main_ms = mms;
   c->stats.n_steps = (int64_t)steps;
@@ -820,6 +906,188 @@ mkf_status mkf_autotune(mkf_ctx *c, int32_t repeats, const char *cache_path, mkf
       fclose(f);
     }
   }
+  return MKF_OK;
+}
+
+}  // extern "C"
+
+// ---- learned propagation surrogate
+
+namespace {
+
+// ascending distinct barrel radii of the loaded geometry
+std::vector<float> barrel_radii(const mkf_ctx *c) {
+  std::vector<float> r;
+  for (int i = 0; i < c->n_layers; ++i)
+    if (c->layers[i].kind == MKF_BARREL) r.push_back(c->layers[i].pos);
+  std::sort(r.begin(), r.end());
+  r.erase(std::unique(r.begin(), r.end()), r.end());
+  return r;
+}
+
+mkf_status gen_samples(mkf_ctx *c, int64_t n, uint64_t seed, float *x, float *t, float *valid) {
+  const std::vector<float> radii = barrel_radii(c);
+  if (radii.size() < 2) return fail(c, MKF_E_GEOMETRY, "the sampler needs >= 2 barrel layers");
+  HIP_TRY(c, c->d_radii.ensure(sizeof(float) * radii.size()));
+  HIP_TRY(c, hipMemcpyAsync(c->d_radii.ptr, radii.data(), sizeof(float) * radii.size(),
+                            hipMemcpyHostToDevice, c->stream));
+  launch_mlp_datagen(c->stream, params(c), n, seed, c->d_radii.as<float>(), (int)radii.size(),
+                     x, t, valid);
+  HIP_TRY(c, hipGetLastError());
+  return MKF_OK;
+}
+
+constexpr int64_t kMaxBatch = 1 << 20;
+
+}  // namespace
+
+extern "C" {
+
+mkf_status mkf_surrogate_samples(mkf_ctx *c, int64_t n, uint64_t seed, float *x, float *t,
+                                 float *valid) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kGeometry) return fail(c, MKF_E_ORDER, "load_geometry first");
+  if (n < 0 || (n > 0 && (!x || !t || !valid))) return fail(c, MKF_E_ARG, "bad sample buffers");
+  if (n == 0) return MKF_OK;
+  mkf_status st = gen_samples(c, n, seed, x, t, valid);
+  if (st != MKF_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_train(mkf_ctx *c, const mkf_train_cfg *cfg, mkf_train_report *rep) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kGeometry) return fail(c, MKF_E_ORDER, "load_geometry first");
+  if (!cfg) return fail(c, MKF_E_ARG, "null training settings");
+  if (cfg->batch < 64 || cfg->batch % 64 != 0 || cfg->batch > kMaxBatch)
+    return fail(c, MKF_E_ARG, "batch must be a multiple of 64 in 64..%lld",
+                (long long)kMaxBatch);
+  if (cfg->n_samples < cfg->batch) return fail(c, MKF_E_ARG, "n_samples must be >= batch");
+  if (cfg->epochs < 1) return fail(c, MKF_E_ARG, "epochs must be >= 1");
+  if (!(cfg->lr > 0.f) || !finite_f(cfg->lr)) return fail(c, MKF_E_ARG, "lr must be > 0");
+  for (int j = 0; j < kNO; ++j)
+    if (!(cfg->loss_w[j] >= 0.f) || !finite_f(cfg->loss_w[j]))
+      return fail(c, MKF_E_ARG, "loss weights must be finite and >= 0");
+  const int64_t n = cfg->n_samples;
+  const int64_t per_epoch = n / cfg->batch;
+  const int64_t steps64 = per_epoch * cfg->epochs;
+  if (steps64 > (1 << 24)) return fail(c, MKF_E_ARG, "too many training steps");
+  const int steps = (int)steps64;
+  const int waves = cfg->batch / 64;
+  HIP_TRY(c, c->d_tx.ensure(sizeof(float) * 8 * n));
+  HIP_TRY(c, c->d_tt.ensure(sizeof(float) * 7 * n));
+  HIP_TRY(c, c->d_tvalid.ensure(sizeof(float) * n));
+  HIP_TRY(c, c->d_partial.ensure(sizeof(float) * (size_t)waves * (kNParam + 1)));
+  HIP_TRY(c, c->d_loss.ensure(sizeof(float) * steps));
+  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
+  mkf_status st = gen_samples(c, n, cfg->seed, c->d_tx.as<float>(), c->d_tt.as<float>(),
+                              c->d_tvalid.as<float>());
+  if (st != MKF_OK) return st;
+  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  // a fresh Adam state for every training run
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_m.ptr, 0, sizeof(float) * kNParam, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_v.ptr, 0, sizeof(float) * kNParam, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev_m0, c->stream));
+  const MlpBuffers B = mlp_buffers(c);
+  const float lr_min = cfg->lr * 0.01f;
+  for (int s = 0; s < steps; ++s) {
+    const double u = steps > 1 ? (double)s / (steps - 1) : 0.0;
+    const float lr = lr_min + 0.5f * (cfg->lr - lr_min) * (float)(1.0 + std::cos(M_PI * u));
+    const int64_t begin = (s % per_epoch) * cfg->batch;
+    launch_mlp_grad(c->stream, B.weights(), c->d_tx.as<float>(), c->d_tt.as<float>(),
+                    c->d_tvalid.as<float>(), n, begin, cfg->batch, cfg->loss_w,
+                    c->d_partial.as<float>());
+    launch_mlp_reduce(c->stream, B, c->d_partial.as<float>(), waves, s + 1, lr, 1, nullptr,
+                      c->d_loss.as<float>() + s);
+  }
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(c->ev_m1, c->stream));
+  std::vector<float> loss(steps), valid(n);
+  HIP_TRY(c, hipMemcpyAsync(loss.data(), c->d_loss.ptr, sizeof(float) * steps,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(valid.data(), c->d_tvalid.ptr, sizeof(float) * n,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->mlp_step = steps;
+  if (rep) {
+    float gen_ms = 0.f, train_ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->ev_a, c->ev_b));
+    HIP_TRY(c, hipEventElapsedTime(&train_ms, c->ev_m0, c->ev_m1));
+    const int k = std::max(1, steps / 100);
+    double first = 0.0, last = 0.0;
+    for (int i = 0; i < k; ++i) {
+      first += loss[i];
+      last += loss[steps - k + i];
+    }
+    int64_t nv = 0;
+    for (float v : valid) nv += v != 0.f;
+    rep->steps = steps;
+    rep->loss_first = (float)(first / k);
+    rep->loss_last = (float)(last / k);
+    rep->datagen_ms = gen_ms;
+    rep->train_ms = train_ms;
+    rep->n_valid = nv;
+  }
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_get(mkf_ctx *c, float *params) {
+  if (!c) return MKF_E_ARG;
+  if (!params) return fail(c, MKF_E_ARG, "null parameter buffer");
+  HIP_TRY(c, hipMemcpyAsync(params, c->d_mlp_param.ptr, sizeof(float) * kNParam,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_set(mkf_ctx *c, const float *params) {
+  if (!c) return MKF_E_ARG;
+  if (!params) return fail(c, MKF_E_ARG, "null parameter buffer");
+  for (int i = 0; i < kNParam; ++i)
+    if (!finite_f(params[i])) return fail(c, MKF_E_ARG, "parameter %d is not finite", i);
+  HIP_TRY(c, hipMemcpyAsync(c->d_mlp_param.ptr, params, sizeof(float) * kNParam,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_m.ptr, 0, sizeof(float) * kNParam, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_mlp_v.ptr, 0, sizeof(float) * kNParam, c->stream));
+  launch_mlp_images(c->stream, mlp_buffers(c));
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->mlp_step = 0;
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_grad(mkf_ctx *c, int32_t n, const float *x, const float *t,
+                              const float *loss_w, float *grad, float *loss) {
+  if (!c) return MKF_E_ARG;
+  if (n < 64 || n % 64 != 0 || n > kMaxBatch)
+    return fail(c, MKF_E_ARG, "n must be a multiple of 64 in 64..%lld", (long long)kMaxBatch);
+  if (!x || !t || !loss_w || !grad || !loss) return fail(c, MKF_E_ARG, "null argument");
+  for (int j = 0; j < kNO; ++j)
+    if (!finite_f(loss_w[j])) return fail(c, MKF_E_ARG, "loss weights must be finite");
+  const int waves = n / 64;
+  HIP_TRY(c, c->d_partial.ensure(sizeof(float) * (size_t)waves * (kNParam + 1)));
+  HIP_TRY(c, c->d_grad.ensure(sizeof(float) * (kNParam + 1)));
+  HIP_TRY(c, c->d_tvalid.ensure(sizeof(float) * n));
+  launch_fill_i32(c->stream, c->d_tvalid.as<int>(), n, 0x3F800000);  // 1.0f
+  launch_mlp_grad(c->stream, mlp_buffers(c).weights(), x, t, c->d_tvalid.as<float>(), n, 0, n,
+                  loss_w, c->d_partial.as<float>());
+  launch_mlp_reduce(c->stream, mlp_buffers(c), c->d_partial.as<float>(), waves, 1, 0.f, 0,
+                    c->d_grad.as<float>(), c->d_grad.as<float>() + kNParam);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemcpyAsync(grad, c->d_grad.ptr, sizeof(float) * kNParam, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(loss, c->d_grad.as<float>() + kNParam, sizeof(float),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_infer(mkf_ctx *c, int64_t n, const float *x, float *y) {
+  if (!c) return MKF_E_ARG;
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(c, MKF_E_ARG, "bad buffers");
+  launch_mlp_infer(c->stream, mlp_buffers(c).weights(), n, x, y);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MKF_OK;
 }
 

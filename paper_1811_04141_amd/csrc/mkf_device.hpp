@@ -163,10 +163,19 @@ using Prop = PropT<float>;
 //   C' = D C D^T - t g^T - g t^T + (k^T C k) t t^T,   g = D C k.
 // kWantCov = false skips the covariance (plans).  check_extent widens the
 // extent by edge_margin.
+//
+// l_hint > 0 (barrel only) is a predicted path length, e.g. the learned
+// surrogate's: one exact Newton step on g(l) = r(l)^2 - R^2 refines it to
+// l1, which is kept if the correction is at most 1e-4 l1, the Newton error
+// bound left after it is at most 1e-7 l1 (near FP32 rounding), and g' at l1
+// marks the first crossing; otherwise the closed form below is used, so the
+// result never depends on the quality of the hint.  *sur (if given)
+// receives 1 if the hint was kept, 2 if not.
 template <bool kWantCov, typename T>
 __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__restrict__ c,
                                          const DevLayer &L, T mkb, T l_min, bool check_extent,
-                                         T edge_margin, PropT<T> &o) {
+                                         T edge_margin, PropT<T> &o, T l_hint = T(0),
+                                         int *sur = nullptr) {
   const T w = mkb * p[3];
   T sphi, cphi;
   sincos_t(p[4], &sphi, &cphi);
@@ -175,8 +184,33 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   const T cot = cth / sth;
   const T pos = T(L.pos);
   T l;
+  bool hinted = false;
   if (L.kind == 0) {
-    if (!path_barrel(p[0], p[1], cphi, sphi, w, pos, l_min, l)) return kNoCrossing;
+    if (l_hint > T(0)) {
+      T hs, hc;
+      const T hh = T(0.5) * w * l_hint;
+      sincos_t(hh, &hs, &hc);
+      const T Lh = l_hint * sinc_from(hh, hs);
+      const T cps = cphi * hc - sphi * hs, sps = sphi * hc + cphi * hs;
+      const T cp1 = cps * hc - sps * hs, sp1 = sps * hc + cps * hs;
+      const T xh = fma_t(Lh, cps, p[0]), yh = fma_t(Lh, sps, p[1]);
+      const T gh = fma_t(xh, xh, fma_t(yh, yh, -pos * pos));
+      const T gph = T(2) * fma_t(xh, cp1, yh * sp1);
+      // g(0) = r0^2 - R^2: the first crossing is the root where g changes
+      // sign away from g(0), so g' there has the opposite sign
+      const T g0 = fma_t(p[0], p[0], fma_t(p[1], p[1], -pos * pos));
+      if (gph * g0 < T(0)) {
+        const T dl = -gh / gph;
+        const T l1 = l_hint + dl;
+        // |g''| <= 6 for a track that reaches R, so the error left after
+        // the step is at most 3 dl^2 / |g'|: keep it below 1e-7 l1
+        hinted = l1 > l_min && abs_t(w) * l1 < Consts<T>::pi() &&
+                 abs_t(dl) <= T(1e-4) * l1 && T(3) * dl * dl <= T(1e-7) * l1 * abs_t(gph);
+        if (hinted) l = l1;
+      }
+      if (sur) *sur = hinted ? 1 : 2;
+    }
+    if (!hinted && !path_barrel(p[0], p[1], cphi, sphi, w, pos, l_min, l)) return kNoCrossing;
   } else {
     if (cth == T(0)) return kNoCrossing;
     l = (pos - p[2]) * sth / cth;
@@ -194,7 +228,8 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   T y1 = fma_t(Lc, spsi, p[1]);
   T z1 = fma_t(l, cot, p[2]);
   // one Newton step along the track removes the rounding of the closed form
-  if (L.kind == 0) {
+  // (a kept surrogate path has had its Newton step already)
+  if (L.kind == 0 && !hinted) {
     const T g = fma_t(x1, x1, fma_t(y1, y1, -pos * pos));
     const T gp = T(2) * fma_t(x1, cphi1, y1 * sphi1);
     if (gp != T(0)) {
@@ -204,7 +239,7 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
       z1 = fma_t(dl, cot, z1);
       l += dl;
     }
-  } else {
+  } else if (L.kind == 1) {
     const T dl = (pos - z1) * sth / cth;
     x1 = fma_t(dl, cphi1, x1);
     y1 = fma_t(dl, sphi1, y1);

@@ -175,12 +175,14 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
 // rank among the kept extensions.  pos indexes the seed's find buffers.
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
                                            int lane, int slot, int64_t pos, int ev, int step,
-                                           int lid, u64 &fin_key) {
+                                           int lid, u64 &fin_key, float l_hint = 0.f,
+                                           int *sur = nullptr) {
   const DevLayer &L = sl[lid];
   Prop pr;
   int st = kNoCrossing;
   if (cd.active)
-    st = propagate<true>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr);
+    st = propagate<true>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr,
+                         l_hint, sur);
   const bool ok = cd.active && st == kOk;
   if (ok) add_ms(pr.p, P.cfg.ms_var, pr.c);
 
@@ -456,17 +458,26 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
 // kWaves: the occupancy the register allocation targets (waves per SIMD);
 // more waves hide more latency but spill part of the state to scratch.
 // The autotuner picks the instantiation.
-template <int kWaves>
+// kSurr: barrel propagations start from the learned surrogate's path length
+// (one wave-wide matrix-core inference per layer step, then one exact Newton
+// step per lane, falling back to the closed form when it does not converge).
+template <int kWaves, bool kSurr>
 __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   __shared__ DevLayer sl[kMaxLayers];
-  __shared__ unsigned long long block_steps;
+  __shared__ unsigned long long block_steps, block_sur[2];
+  __shared__ __bf16 sMX[kSurr ? 4 * 64 * kLdX : 1];
+  __shared__ __bf16 sMH[kSurr ? 4 * 64 * kLdH : 1];
   stage_layers(P, sl);
-  if (threadIdx.x == 0) block_steps = 0;
+  if (threadIdx.x == 0) {
+    block_steps = 0;
+    block_sur[0] = block_sur[1] = 0;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int slot = lane & 7;
   const int grp = lane >> 3;
-  int my_steps = 0;
+  const int wv = threadIdx.x >> 6;
+  int my_steps = 0, my_acc = 0, my_fb = 0;
   int q = blockIdx.x % kQueues;  // this block's XCD
   int tried = 0;
   for (;;) {
@@ -497,10 +508,37 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
 #pragma unroll
     for (int m = 8; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
     for (int step = 0; step < maxlen; ++step) {
-      if (step < plen) {
+      const bool in_plan = step < plen;
+      const int lid = in_plan ? P.pplan[(size_t)pos * kMaxPlan + step] : 0;
+      float l_hint = 0.f;
+      if constexpr (kSurr) {
+        // every lane of the wave takes part in the matrix-core inference
+        const bool want = in_plan && cd.active && sl[lid].kind == 0;
+        float xin[kNI];
+        if (want) {
+          mlp_inputs(cd.p, sl[lid].pos, P.cfg.mkb, xin);
+        } else {
+#pragma unroll
+          for (int k = 0; k < kNI; ++k) xin[k] = 0.f;
+        }
+        // (skipped, wave-uniformly, when no lane heads to a barrel layer)
+        if (__ballot(want) != 0ull) {
+          __bf16 *X = sMX + wv * 64 * kLdX;
+          __bf16 *H = sMH + wv * 64 * kLdH;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) X[lane * kLdX + k] = (__bf16)(k < kNI ? xin[k] : 0.f);
+          wave_sync();
+          const float y0 = mlp_forward_wave(P.mlp, X, H, nullptr);
+          wave_sync();  // the tiles are rewritten at the next step
+          if (want) l_hint = surrogate_path(cd.p, sl[lid].pos, P.cfg.mkb, y0);
+        }
+      }
+      if (in_plan) {
         my_steps += cd.active ? 1 : 0;
-        const int lid = P.pplan[(size_t)pos * kMaxPlan + step];
-        group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
+        int sur = 0;
+        group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key, l_hint, &sur);
+        my_acc += sur == 1;
+        my_fb += sur == 2;
       }
     }
     if (valid) {
@@ -515,10 +553,22 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
     }
   }
 #pragma unroll
-  for (int m = 1; m < 64; m <<= 1) my_steps += __shfl_xor(my_steps, m);
+  for (int m = 1; m < 64; m <<= 1) {
+    my_steps += __shfl_xor(my_steps, m);
+    my_acc += __shfl_xor(my_acc, m);
+    my_fb += __shfl_xor(my_fb, m);
+  }
   if (lane == 0 && my_steps) atomicAdd(&block_steps, (unsigned long long)my_steps);
+  if (kSurr && lane == 0) {
+    atomicAdd(&block_sur[0], (unsigned long long)my_acc);
+    atomicAdd(&block_sur[1], (unsigned long long)my_fb);
+  }
   __syncthreads();
   if (threadIdx.x == 0 && block_steps) atomicAdd(P.n_steps, block_steps);
+  if (kSurr && threadIdx.x == 0) {
+    atomicAdd(&P.sur_stats[0], block_sur[0]);
+    atomicAdd(&P.sur_stats[1], block_sur[1]);
+  }
 }
 
 // Gather the seed results into processing order (untimed preparation), so
@@ -907,14 +957,21 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
   hipLaunchKernelGGL(k_find_step, dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
-void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves) {
-  if (P.n_seeds == 0) return;
+template <bool kSurr>
+static void launch_persistent_t(hipStream_t s, const FindParams &P, int grid, int waves) {
   switch (waves) {
-    case 1: hipLaunchKernelGGL(k_find_persistent<1>, dim3(grid_blocks), dim3(256), 0, s, P); break;
-    case 3: hipLaunchKernelGGL(k_find_persistent<3>, dim3(grid_blocks), dim3(256), 0, s, P); break;
-    case 4: hipLaunchKernelGGL(k_find_persistent<4>, dim3(grid_blocks), dim3(256), 0, s, P); break;
-    default: hipLaunchKernelGGL(k_find_persistent<2>, dim3(grid_blocks), dim3(256), 0, s, P); break;
+    case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
+    default: hipLaunchKernelGGL((k_find_persistent<2, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
   }
+}
+
+void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
+                            bool surrogate) {
+  if (P.n_seeds == 0) return;
+  if (surrogate) launch_persistent_t<true>(s, P, grid_blocks, waves);
+  else launch_persistent_t<false>(s, P, grid_blocks, waves);
 }
 
 void launch_finalize(hipStream_t s, const FindParams &P) {

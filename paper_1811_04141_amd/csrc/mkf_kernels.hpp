@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "mkf_device.hpp"
+#include "mkf_mlp.hpp"
 #include "../../include/mkf.h"
 
 namespace mkf {
@@ -70,6 +71,9 @@ struct FindParams {
   const int64_t *q_off;     // [kQueues + 1]
   int n_tiles;
   unsigned long long *n_steps;
+  // learned surrogate (persistent form)
+  MlpWeights mlp;
+  unsigned long long *sur_stats;  // [2]: hints kept, hints rejected
 };
 
 void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
@@ -83,7 +87,8 @@ void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int
                           int *pevent, int8_t *pplan);
 void launch_find_init(hipStream_t s, const FindParams &P);
 void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active_seeds);
-void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves);
+void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
+                            bool surrogate);
 void launch_finalize(hipStream_t s, const FindParams &P);
 void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,
                       const float *cov, const int *layer, float *out_par, float *out_cov,
@@ -93,6 +98,23 @@ void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const 
                 const float *vu, const float *vv, const int *len, const float *init_par,
                 const float *init_cov, float *out_par, float *out_cov, float *out_chi2,
                 int *out_status);
+// learned propagation surrogate (mkf_mlp.hip)
+struct MlpBuffers {
+  float *param, *m, *v;                 // FP32 master weights, Adam moments
+  __bf16 *W1p, *W2p, *W3p, *W2T, *W3T;  // BF16 operand images (padding zero)
+  float *b1, *b2, *b3;                  // biases (b3 padded to 32)
+  MlpWeights weights() const { return MlpWeights{W1p, W2p, W3p, W2T, W3T, b1, b2, b3}; }
+};
+void launch_mlp_datagen(hipStream_t s, const FindParams &P, int64_t n, uint64_t seed,
+                        const float *radii, int n_radii, float *x, float *t, float *valid);
+void launch_mlp_grad(hipStream_t s, const MlpWeights &w, const float *x, const float *t,
+                     const float *valid, int64_t n, int64_t begin, int batch, const float *loss_w,
+                     float *partial);
+void launch_mlp_reduce(hipStream_t s, const MlpBuffers &B, const float *partial, int n_waves,
+                       int step, float lr, int adam, float *grad_out, float *loss_out);
+void launch_mlp_images(hipStream_t s, const MlpBuffers &B);
+void launch_mlp_infer(hipStream_t s, const MlpWeights &w, int64_t n, const float *x, float *y);
+
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,
                           const float *z, const float *vu, const float *vv, const int *layer,
                           int n_layers, int *bad);

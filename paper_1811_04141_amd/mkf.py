@@ -16,14 +16,17 @@ LIB_PATH = os.path.join(HERE, "libmkf.so")
 MKF_OK, MKF_E_ARG, MKF_E_ORDER, MKF_E_CAPACITY, MKF_E_HIP, MKF_E_GEOMETRY, MKF_E_NUMERIC = (
     0, -1, -2, -3, -4, -5, -6)
 MEM_HOST, MEM_DEVICE = 0, 1
-F_BATCHED, F_GRAPH = 1, 2
+F_BATCHED, F_GRAPH, F_SURROGATE = 1, 2, 4
+MLP_NPARAM = 5191  # W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]
 MAX_LAYERS = MAX_PLAN = 32
 MAX_CAND = 8
 HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_get_stats", "mkf_set_tuning", "mkf_get_tuning", "mkf_autotune")
+           "mkf_fit", "mkf_get_stats", "mkf_set_tuning", "mkf_get_tuning", "mkf_autotune",
+           "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
+           "mkf_surrogate_infer", "mkf_surrogate_samples")
 
 
 class MkfError(RuntimeError):
@@ -63,7 +66,18 @@ class Stats(C.Structure):
     _fields_ = [("n_seeds", C.c_int64), ("n_seeds_ok", C.c_int64), ("n_steps", C.c_int64),
                 ("max_plan_len", C.c_int32), ("n_launches", C.c_int32), ("find_ms", C.c_float),
                 ("index_ms", C.c_float), ("seed_ms", C.c_float), ("main_ms", C.c_float),
-                ("main_launches", C.c_int32)]
+                ("main_launches", C.c_int32), ("sur_kept", C.c_int64),
+                ("sur_rejected", C.c_int64)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32),
+                ("lr", C.c_float), ("seed", C.c_uint64), ("loss_w", C.c_float * 7)]
+
+
+class TrainReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("loss_first", C.c_float), ("loss_last", C.c_float),
+                ("datagen_ms", C.c_float), ("train_ms", C.c_float), ("n_valid", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -91,6 +105,12 @@ def _load():
         "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_autotune": ([P, I32, C.c_char_p, C.POINTER(Tuning)], I32),
+        "mkf_surrogate_train": ([P, C.POINTER(TrainCfg), C.POINTER(TrainReport)], I32),
+        "mkf_surrogate_get": ([P, P], I32),
+        "mkf_surrogate_set": ([P, P], I32),
+        "mkf_surrogate_grad": ([P, I32, P, P, P, P, P], I32),
+        "mkf_surrogate_infer": ([P, I64, P, P], I32),
+        "mkf_surrogate_samples": ([P, I64, C.c_uint64, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -229,6 +249,42 @@ class Context:
         self._check(lib.mkf_autotune(self.h, repeats,
                                      cache_path.encode() if cache_path else None, C.byref(t)))
         return {"waves_per_simd": t.waves_per_simd, "blocks_per_cu": t.blocks_per_cu}
+
+    # ---- learned propagation surrogate
+
+    def surrogate_train(self, n_samples, epochs, batch, lr, seed, loss_w=(1, 0, 0, 0, 0, 0, 0)):
+        cfg = TrainCfg(int(n_samples), int(epochs), int(batch), float(lr), int(seed))
+        for j in range(7):
+            cfg.loss_w[j] = float(loss_w[j])
+        rep = TrainReport()
+        self._check(lib.mkf_surrogate_train(self.h, C.byref(cfg), C.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+
+    def surrogate_get(self):
+        out = np.zeros(MLP_NPARAM, np.float32)
+        self._check(lib.mkf_surrogate_get(self.h, _ptr(out)))
+        return out
+
+    def surrogate_set(self, params):
+        params = np.ascontiguousarray(params, np.float32)
+        assert params.shape == (MLP_NPARAM,)
+        self._check(lib.mkf_surrogate_set(self.h, _ptr(params)))
+
+    def surrogate_grad(self, x, t, loss_w):
+        """x [n][8], t [n][7] device tensors; returns (grad, loss) on the host."""
+        lw = np.ascontiguousarray(loss_w, np.float32)
+        grad = np.zeros(MLP_NPARAM, np.float32)
+        loss = np.zeros(1, np.float32)
+        self._check(lib.mkf_surrogate_grad(self.h, int(x.shape[0]), _ptr(x), _ptr(t), _ptr(lw),
+                                           _ptr(grad), _ptr(loss)))
+        return grad, float(loss[0])
+
+    def surrogate_infer(self, x, y):
+        self._check(lib.mkf_surrogate_infer(self.h, int(x.shape[0]), _ptr(x), _ptr(y)))
+
+    def surrogate_samples(self, n, seed, x, t, valid):
+        self._check(lib.mkf_surrogate_samples(self.h, int(n), int(seed), _ptr(x), _ptr(t),
+                                              _ptr(valid)))
 
     def stats(self):
         s = Stats()
