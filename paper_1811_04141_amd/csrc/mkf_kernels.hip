@@ -48,37 +48,64 @@ __device__ __forceinline__ u64 shfl_xor_u64(u64 v, int m) {
   hi = __shfl_xor(hi, m);
   return ((u64)hi << 32) | lo;
 }
-// minimum over the 8 lanes of a seed's group
-__device__ __forceinline__ u64 group_min(u64 v) {
-  u64 o = shfl_xor_u64(v, 1);
-  v = o < v ? o : v;
-  o = shfl_xor_u64(v, 2);
-  v = o < v ? o : v;
-  o = shfl_xor_u64(v, 4);
-  v = o < v ? o : v;
-  return v;
-}
-__device__ __forceinline__ int group_sum(int v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  return v;
+__device__ __forceinline__ u64 shfl_u64(u64 v, int src) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo = __shfl(lo, src);
+  hi = __shfl(hi, src);
+  return ((u64)hi << 32) | lo;
 }
 
+// Lane groups of a seed: G consecutive lanes of a wavefront, one per
+// candidate slot.  G = 8 (8 seeds per wave, any candidate budget) reduces
+// with xor butterflies; G = 6 (10 seeds per wave, lanes 60-63 idle, for
+// budgets up to 6) reduces over the three lane pairs by rotation.
+template <int G> struct Grp;
+template <> struct Grp<8> {
+  static constexpr int kSeeds = 8;
+  __device__ static int slot(int lane) { return lane & 7; }
+  __device__ static int base(int lane) { return lane & ~7; }
+  __device__ static u64 min(u64 v, int lane) {
+    u64 o = shfl_xor_u64(v, 1);
+    v = o < v ? o : v;
+    o = shfl_xor_u64(v, 2);
+    v = o < v ? o : v;
+    o = shfl_xor_u64(v, 4);
+    return o < v ? o : v;
+  }
+};
+template <> struct Grp<6> {
+  static constexpr int kSeeds = 10;
+  __device__ static int slot(int lane) { return lane % 6; }
+  __device__ static int base(int lane) { return lane - lane % 6; }
+  // pairs (0,1) (2,3) (4,5); then the next pair's minimum, then the one
+  // after (whose value already includes the first pair)
+  __device__ static u64 min(u64 v, int lane) {
+    const int sl = lane % 6, b = lane - sl;
+    u64 o = shfl_xor_u64(v, 1);
+    v = o < v ? o : v;
+    o = shfl_u64(v, b + (sl < 4 ? sl + 2 : sl - 4));
+    v = o < v ? o : v;
+    o = shfl_u64(v, b + (sl < 2 ? sl + 4 : sl - 2));
+    return o < v ? o : v;
+  }
+};
+
 // sorted insertion into a register list (compile-time indices only)
-__device__ __forceinline__ void insert_sorted(u64 (&lst)[kGroup], u64 k) {
+template <int N>
+__device__ __forceinline__ void insert_sorted(u64 (&lst)[N], u64 k) {
 #pragma unroll
-  for (int i = 0; i < kGroup; ++i) {
+  for (int i = 0; i < N; ++i) {
     const u64 a = lst[i];
     const bool lt = k < a;
     lst[i] = lt ? k : a;
     k = lt ? a : k;
   }
 }
-__device__ __forceinline__ void pop_front(u64 (&lst)[kGroup]) {
+template <int N>
+__device__ __forceinline__ void pop_front(u64 (&lst)[N]) {
 #pragma unroll
-  for (int i = 0; i < kGroup - 1; ++i) lst[i] = lst[i + 1];
-  lst[kGroup - 1] = kKeyMax;
+  for (int i = 0; i < N - 1; ++i) lst[i] = lst[i + 1];
+  lst[N - 1] = kKeyMax;
 }
 
 __device__ __forceinline__ void stage_layers(const FindParams &P, DevLayer *sl) {
@@ -99,13 +126,18 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 //
 // Bounding box of the chi2 < cut ellipse of every hit on the layer: with
 // S_hit <= H C H^T + diag(var_max), |u| <= sqrt(cut S_uu) and |v| <= sqrt(cut
-// S_vv).  Barrel: u = R_h sin(dphi) (hits in the same half), v = dz.  Disk:
-// the hit is at (r' + v) rh + u t, so its radius lies in [r' - dv,
-// sqrt((r' + dv)^2 + du^2)] and its azimuth within atan2(du, r' - dv).  A small
-// margin absorbs FP32 rounding of the bin assignment.
+// S_vv).  Barrel: u = R_h sin(dphi) (hits in the same half), v = dz, so
+// |dphi| <= asin(s) <= s / sqrt(1 - s^2) with s = du / R.  Disk: the hit is at
+// (r' + v) rh + u t, so its radius lies in [r' - dv, sqrt((r' + dv)^2 +
+// du^2)] and its azimuth within atan(du / (r' - dv)) <= du / (r' - dv).  The
+// box only has to contain the ellipse (the chi2 test decides), so these
+// cheaper upper bounds replace asin and atan; a small margin absorbs FP32
+// rounding of the bin assignment.  Hits are read four at a time (indices
+// clamped into the bin range) so that their loads overlap.
+template <int N>
 __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer &L, int ev,
                                             const Prop &pr, const Frame &f, float chi2_base,
-                                            int nh, int slot, u64 (&lst)[kGroup], int &n_ext) {
+                                            int nh, int slot, u64 (&lst)[N], int &n_ext) {
   const float cut = P.cfg.chi2_cut;
   const float du = sqrtf(cut * (f.suu + L.vu_max)) * 1.001f + 1e-5f;
   const float dv = sqrtf(cut * (f.svv + L.vv_max)) * 1.001f + 1e-5f;
@@ -113,7 +145,7 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
   float dphi, qmin, qmax;
   if (L.kind == 0) {
     const float s = du / (L.pos * 0.99999f);
-    dphi = s >= 1.f ? 0.5f * kPi : asinf(s);
+    dphi = s >= 0.99f ? kPi : s * rsqrtf(fmaf(-s, s, 1.f)) * 1.0001f;
     qmin = pr.p[2] - dv;
     qmax = pr.p[2] + dv;
   } else {
@@ -121,7 +153,7 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
     const float rl = r - dv;
     qmin = rl;
     qmax = sqrtf(fmaf(r + dv, r + dv, du * du));
-    dphi = rl > 0.f ? atan2f(du, rl) : kPi;
+    dphi = rl > 0.f ? fminf(du / rl * 1.0001f, kPi) : kPi;
   }
   dphi += 4e-6f;
   qmin -= 1e-4f;
@@ -153,15 +185,26 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
       if (lo > hi) continue;
       const int h0 = P.bin_start[row + lo];
       const int h1 = P.bin_start[row + hi + 1];
-      for (int k = h0; k < h1; ++k) {
-        const float4 a = reinterpret_cast<const float4 *>(P.sorted)[2 * k];
-        const float4 b = reinterpret_cast<const float4 *>(P.sorted)[2 * k + 1];
-        float u, v;
-        if (!residual(pr.p, f, L.kind, a.x, a.y, a.z, u, v)) continue;
-        const float c2 = fmaxf(chi2_of(f, a.w, b.x, u, v), 0.f);
-        if (c2 < cut) {
-          insert_sorted(lst, ext_key(nh + 1, chi2_base + c2, slot, (unsigned)__float_as_int(b.y)));
-          ++n_ext;
+      const float4 *hits = reinterpret_cast<const float4 *>(P.sorted);
+      for (int k = h0; k < h1; k += 4) {
+        float4 a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int kk = min(k + j, h1 - 1);
+          a[j] = hits[2 * kk];
+          b[j] = hits[2 * kk + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (k + j >= h1) break;
+          float u, v;
+          if (!residual(pr.p, f, L.kind, a[j].x, a[j].y, a[j].z, u, v)) continue;
+          const float c2 = fmaxf(chi2_of(f, a[j].w, b[j].x, u, v), 0.f);
+          if (c2 < cut) {
+            insert_sorted(lst, ext_key(nh + 1, chi2_base + c2, slot,
+                                       (unsigned)__float_as_int(b[j].y)));
+            ++n_ext;
+          }
         }
       }
     }
@@ -170,9 +213,11 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
 
 // ------------------------------------------------------------ one step
 //
-// One layer step of one seed, executed by its 8-lane group.  On entry each
+// One layer step of one seed, executed by its G-lane group.  On entry each
 // lane holds one candidate (or none); on exit it holds the candidate of its
-// rank among the kept extensions.  pos indexes the seed's find buffers.
+// rank among the kept extensions.  pos indexes the seed's find buffers
+// (back-pointers keep kGroup = 8 slots per seed for either G).
+template <int G>
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
                                            int lane, int slot, int64_t pos, int ev, int step,
                                            int lid, u64 &fin_key, float l_hint = 0.f,
@@ -186,9 +231,9 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   const bool ok = cd.active && st == kOk;
   if (ok) add_ms(pr.p, P.cfg.ms_var, pr.c);
 
-  u64 lst[kGroup];
+  u64 lst[G];  // this lane's best extensions (G >= n_cand)
 #pragma unroll
-  for (int i = 0; i < kGroup; ++i) lst[i] = kKeyMax;
+  for (int i = 0; i < G; ++i) lst[i] = kKeyMax;
   int n_ext = 0;
   if (cd.active) {
     if (!ok) {
@@ -208,7 +253,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   // a candidate without any extension stops; keep the seed's best such one
   const bool retire = cd.active && n_ext == 0;
   const u64 rkey = retire ? final_key(cd.nh, cd.chi2, 1, step, slot) : kKeyMax;
-  const u64 rmin = group_min(rkey);
+  const u64 rmin = Grp<G>::min(rkey, lane);
   if (rmin < fin_key) {
     if (rkey == rmin) {
       const size_t N = (size_t)P.n_seeds;
@@ -225,7 +270,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   // the seed's best n_cand extensions, rank r goes to slot r
   u64 mine = kKeyMax;
   for (int r = 0; r < P.cfg.n_cand; ++r) {
-    const u64 m = group_min(lst[0]);
+    const u64 m = Grp<G>::min(lst[0], lane);
     if (m != kKeyMax && lst[0] == m) pop_front(lst);
     if (slot == r) mine = m;
   }
@@ -239,7 +284,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   for (int i = 0; i < 21; ++i) src[6 + i] = ok ? pr.c[i] : cd.c[i];
   const int src_meta = cd.nh | (cd.nm << 8) | (ok ? (1 << 16) : 0);
   const int parent = mine == kKeyMax ? slot : (int)((mine >> 23) & 7);
-  const int src_lane = (lane & ~7) | parent;
+  const int src_lane = Grp<G>::base(lane) + parent;
   float np[27];
 #pragma unroll
   for (int i = 0; i < 27; ++i) np[i] = __shfl(src[i], src_lane);
@@ -397,7 +442,7 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   load_cand(P, (size_t)pos * kGroup + slot, cd);
   u64 fin_key = P.fin_key[pos];
   const u64 fk0 = fin_key;
-  group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
+  group_step<kGroup>(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
   store_cand(P, (size_t)pos * kGroup + slot, cd);
   if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
 }
@@ -461,7 +506,8 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
 // kSurr: barrel propagations start from the learned surrogate's path length
 // (one wave-wide matrix-core inference per layer step, then one exact Newton
 // step per lane, falling back to the closed form when it does not converge).
-template <int kWaves, bool kSurr>
+// G: lanes per seed (8, or 6 for candidate budgets up to 6).
+template <int kWaves, bool kSurr, int G>
 __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   __shared__ DevLayer sl[kMaxLayers];
   __shared__ unsigned long long block_steps, block_sur[2];
@@ -474,8 +520,8 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int slot = lane & 7;
-  const int grp = lane >> 3;
+  const int slot = Grp<G>::slot(lane);
+  const int grp = lane / G;  // G = 6: lanes 60-63 form no seed group
   const int wv = threadIdx.x >> 6;
   int my_steps = 0, my_acc = 0, my_fb = 0;
   int q = blockIdx.x % kQueues;  // this block's XCD
@@ -484,7 +530,7 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
     int tile = 0;
     if (lane == 0) tile = atomicAdd(&P.tile_counter[q], 1);
     tile = __shfl(tile, 0);
-    const int64_t start = P.q_off[q] + (int64_t)tile * 8;
+    const int64_t start = P.q_off[q] + (int64_t)tile * Grp<G>::kSeeds;
     const int64_t end = P.q_off[q + 1];
     if (start >= end) {
       // queue exhausted: help the next one; stop after all were tried
@@ -493,7 +539,7 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
       continue;
     }
     const int64_t pos = start + grp;
-    const bool valid = pos < end;
+    const bool valid = grp < Grp<G>::kSeeds && pos < end;
     const int info = valid ? P.pinfo[pos] : 0;
     const int plen = info & 0xFF;
     const int ev = valid ? P.pevent[pos] : 0;
@@ -506,7 +552,7 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
     u64 fin_key = kKeyMax;
     int maxlen = plen;
 #pragma unroll
-    for (int m = 8; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
+    for (int m = 1; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
     for (int step = 0; step < maxlen; ++step) {
       const bool in_plan = step < plen;
       const int lid = in_plan ? P.pplan[(size_t)pos * kMaxPlan + step] : 0;
@@ -536,14 +582,14 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
       if (in_plan) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
-        group_step(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key, l_hint, &sur);
+        group_step<G>(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key, l_hint, &sur);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
     }
     if (valid) {
       const u64 fk = cd.active ? final_key(cd.nh, cd.chi2, 0, 0, slot) : kKeyMax;
-      const u64 m = group_min(fk);
+      const u64 m = Grp<G>::min(fk, lane);
       if (m != kKeyMax && m < fin_key) {
         if (fk == m) write_result(P, pos, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, slot, plen);
       } else if (slot == 0) {
@@ -959,11 +1005,15 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
 
 template <bool kSurr>
 static void launch_persistent_t(hipStream_t s, const FindParams &P, int grid, int waves) {
+  if (P.cfg.n_cand > 6) {  // 8-lane groups, one occupancy target
+    hipLaunchKernelGGL((k_find_persistent<2, kSurr, 8>), dim3(grid), dim3(256), 0, s, P);
+    return;
+  }
   switch (waves) {
-    case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
-    case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
-    case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
-    default: hipLaunchKernelGGL((k_find_persistent<2, kSurr>), dim3(grid), dim3(256), 0, s, P); break;
+    case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
+    case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
+    case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
+    default: hipLaunchKernelGGL((k_find_persistent<2, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
   }
 }
 

@@ -166,11 +166,16 @@ def test_find_realistic_events_match_oracle(mkf, flags):
         check(PT.compare_tracks(tr[pick], ref, mkf.unpack_cov))
 
 
-def test_batched_equals_layer_synchronous_bitwise(mkf):
+@pytest.mark.parametrize("n_cand", [6, 8, 3])
+def test_batched_equals_layer_synchronous_bitwise(mkf, n_cand):
+    """The persistent form (6-lane seed groups for budgets up to 6, else 8)
+    and the layer-synchronous form (8-lane groups) give the same bytes."""
+    import dataclasses
     w = barrel_endcap()
+    fc = dataclasses.replace(w.find, n_cand=n_cand)
     b = generate(w, events=[2, 3, 4])
-    a, _, sa = run_find(mkf, w, b, flags=0)
-    c, _, sc = run_find(mkf, w, b, flags=1)
+    a, _, sa = run_find(mkf, w, b, flags=0, fc=fc)
+    c, _, sc = run_find(mkf, w, b, flags=1, fc=fc)
     assert sa["n_steps"] == sc["n_steps"]
     assert a.tobytes() == c.tobytes()
 
