@@ -188,7 +188,7 @@ FindParams params(mkf_ctx *c) {
   P.bp = c->d_bp.as<int>();
   P.tile_counter = c->d_tiles.as<int>();
   P.q_off = c->d_qoff.as<int64_t>();
-  P.n_tiles = (int)((c->n_seeds + 7) / 8);
+  P.max_plan = c->max_plan_len;
   P.n_steps = c->d_steps.as<unsigned long long>();
   P.mlp = MlpWeights{c->d_W1p.as<__bf16>(), c->d_W2p.as<__bf16>(), c->d_W3p.as<__bf16>(),
                      c->d_W2T.as<__bf16>(), c->d_W3T.as<__bf16>(), c->d_mb1.as<float>(),

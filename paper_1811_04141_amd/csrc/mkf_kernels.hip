@@ -122,6 +122,61 @@ struct Cand {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// ------------------------------------------------------------ records
+//
+// Per-seed records a find keeps besides the candidates: the back-pointers
+// of every step and the best retired candidate.  The layer-synchronous form
+// keeps them in HBM by position; the persistent form keeps them in the
+// wavefront's LDS for the seed tile it is working on.
+struct GlobalRec {
+  const FindParams *P;
+  int64_t pos;
+  __device__ void put_bp(int step, int slot, int v) const {
+    P->bp[((size_t)step * (size_t)P->n_seeds + pos) * kGroup + slot] = v;
+  }
+  __device__ int get_bp(int step, int slot) const {
+    return P->bp[((size_t)step * (size_t)P->n_seeds + pos) * kGroup + slot];
+  }
+  __device__ void put_fin(const Cand &cd) const {
+    const size_t N = (size_t)P->n_seeds;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) P->fin_rec[i * N + pos] = cd.p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) P->fin_rec[(6 + i) * N + pos] = cd.c[i];
+    P->fin_rec[27 * N + pos] = cd.chi2;
+    P->fin_meta[pos] = cd.nh | (cd.nm << 8);
+  }
+  __device__ void get_fin(float *p, float *c, float &chi2, int &meta) const {
+    const size_t N = (size_t)P->n_seeds;
+    for (int i = 0; i < 6; ++i) p[i] = P->fin_rec[i * N + pos];
+    for (int i = 0; i < 21; ++i) c[i] = P->fin_rec[(6 + i) * N + pos];
+    chi2 = P->fin_rec[27 * N + pos];
+    meta = P->fin_meta[pos];
+  }
+};
+
+struct LdsRec {
+  int *bp;       // this seed's back-pointers: step s, slot j at bp[s * stride + j]
+  int stride;
+  float *fin;    // this seed's best retired candidate [kFinWords]
+  __device__ void put_bp(int step, int slot, int v) const { bp[step * stride + slot] = v; }
+  __device__ int get_bp(int step, int slot) const { return bp[step * stride + slot]; }
+  __device__ void put_fin(const Cand &cd) const {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) fin[i] = cd.p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) fin[6 + i] = cd.c[i];
+    fin[27] = cd.chi2;
+    fin[28] = __int_as_float(cd.nh | (cd.nm << 8));
+  }
+  __device__ void get_fin(float *p, float *c, float &chi2, int &meta) const {
+    for (int i = 0; i < 6; ++i) p[i] = fin[i];
+    for (int i = 0; i < 21; ++i) c[i] = fin[6 + i];
+    chi2 = fin[27];
+    meta = __float_as_int(fin[28]);
+  }
+};
+
 // ---------------------------------------------------------------- window
 //
 // Bounding box of the chi2 < cut ellipse of every hit on the layer: with
@@ -217,9 +272,9 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
 // lane holds one candidate (or none); on exit it holds the candidate of its
 // rank among the kept extensions.  pos indexes the seed's find buffers
 // (back-pointers keep kGroup = 8 slots per seed for either G).
-template <int G>
+template <int G, class Rec>
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
-                                           int lane, int slot, int64_t pos, int ev, int step,
+                                           int lane, int slot, const Rec &rec, int ev, int step,
                                            int lid, u64 &fin_key, float l_hint = 0.f,
                                            int *sur = nullptr) {
   const DevLayer &L = sl[lid];
@@ -255,15 +310,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   const u64 rkey = retire ? final_key(cd.nh, cd.chi2, 1, step, slot) : kKeyMax;
   const u64 rmin = Grp<G>::min(rkey, lane);
   if (rmin < fin_key) {
-    if (rkey == rmin) {
-      const size_t N = (size_t)P.n_seeds;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) P.fin_rec[i * N + pos] = cd.p[i];
-#pragma unroll
-      for (int i = 0; i < 21; ++i) P.fin_rec[(6 + i) * N + pos] = cd.c[i];
-      P.fin_rec[27 * N + pos] = cd.chi2;
-      P.fin_meta[pos] = cd.nh | (cd.nm << 8);
-    }
+    if (rkey == rmin) rec.put_fin(cd);
     fin_key = rmin;
   }
 
@@ -325,7 +372,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   } else {
     cd.active = false;
   }
-  P.bp[((size_t)step * (size_t)P.n_seeds + pos) * kGroup + slot] = bpv;
+  rec.put_bp(step, slot, bpv);
 }
 
 __device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand &cd) {
@@ -370,9 +417,10 @@ __device__ __forceinline__ void store_cand(const FindParams &P, size_t idx, cons
 // The chosen candidate of a seed: state and counts, and its hit history
 // followed back through the per-step back-pointers from (best_step,
 // best_slot).  Plan steps after the candidate stopped read MKF_HIT_NONE.
-__device__ __forceinline__ void write_result(const FindParams &P, int64_t pos, const float *p,
-                                             const float *c, float chi2, int nh, int nm,
-                                             int best_step, int best_slot, int plen) {
+template <class Rec>
+__device__ __forceinline__ void write_result(const FindParams &P, int64_t pos, const Rec &rec,
+                                             const float *p, const float *c, float chi2, int nh,
+                                             int nm, int best_step, int best_slot, int plen) {
   const size_t N = (size_t)P.n_seeds;
 #pragma unroll
   for (int i = 0; i < 6; ++i) P.out_par[i * N + pos] = p[i];
@@ -383,25 +431,26 @@ __device__ __forceinline__ void write_result(const FindParams &P, int64_t pos, c
   for (int s = plen - 1; s > best_step; --s) P.out_hit[s * N + pos] = MKF_HIT_NONE;
   int sl = best_slot;
   for (int s = best_step; s >= 0; --s) {
-    const int v = P.bp[((size_t)s * N + pos) * kGroup + sl];
+    const int v = rec.get_bp(s, sl);
     P.out_hit[s * N + pos] = (v >> 3) - 2;
     sl = v & 7;
   }
 }
 
-__device__ __forceinline__ void write_retired(const FindParams &P, int64_t pos, u64 fin, int plen) {
-  const size_t N = (size_t)P.n_seeds;
-  float p[6], c[21];
-  for (int i = 0; i < 6; ++i) p[i] = P.fin_rec[i * N + pos];
-  for (int i = 0; i < 21; ++i) c[i] = P.fin_rec[(6 + i) * N + pos];
-  const int fm = P.fin_meta[pos];
-  write_result(P, pos, p, c, P.fin_rec[27 * N + pos], fm & 0xFF, (fm >> 8) & 0xFF,
-               fkey_step(fin) - 1, fkey_slot(fin), plen);
+template <class Rec>
+__device__ __forceinline__ void write_retired(const FindParams &P, int64_t pos, const Rec &rec,
+                                              u64 fin, int plen) {
+  float p[6], c[21], chi2;
+  int fm;
+  rec.get_fin(p, c, chi2, fm);
+  write_result(P, pos, rec, p, c, chi2, fm & 0xFF, (fm >> 8) & 0xFF, fkey_step(fin) - 1,
+               fkey_slot(fin), plen);
 }
 
-__device__ __forceinline__ void write_empty(const FindParams &P, int64_t pos) {
+template <class Rec>
+__device__ __forceinline__ void write_empty(const FindParams &P, int64_t pos, const Rec &rec) {
   const float z[21] = {};
-  write_result(P, pos, z, z, 0.f, 0, 0, -1, 0, 0);
+  write_result(P, pos, rec, z, z, 0.f, 0, 0, -1, 0, 0);
 }
 
 // --------------------------------------------------- layer-synchronous form
@@ -442,7 +491,7 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   load_cand(P, (size_t)pos * kGroup + slot, cd);
   u64 fin_key = P.fin_key[pos];
   const u64 fk0 = fin_key;
-  group_step<kGroup>(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key);
+  group_step<kGroup>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, step, lid, fin_key);
   store_cand(P, (size_t)pos * kGroup + slot, cd);
   if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
 }
@@ -479,14 +528,15 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
         }
       }
     const u64 fin = ok ? P.fin_key[pos] : kKeyMax;
+    const GlobalRec rec{&P, pos};
     if (m != kKeyMax && m < fin) {
       Cand cd;
       load_cand(P, (size_t)pos * kGroup + best, cd);
-      write_result(P, pos, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, best, plen);
+      write_result(P, pos, rec, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, best, plen);
     } else if (fin != kKeyMax) {
-      write_retired(P, pos, fin, plen);
+      write_retired(P, pos, rec, fin, plen);
     } else {
-      write_empty(P, pos);
+      write_empty(P, pos, rec);
     }
   }
   __syncthreads();
@@ -523,6 +573,14 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   const int slot = Grp<G>::slot(lane);
   const int grp = lane / G;  // G = 6: lanes 60-63 form no seed group
   const int wv = threadIdx.x >> 6;
+  // this wave's records in dynamic LDS: back-pointers [max_plan][kSeeds][G],
+  // then the retired records [kSeeds][kFinWords]
+  extern __shared__ int s_rec[];
+  constexpr int kS = Grp<G>::kSeeds;
+  int *wrec = s_rec + wv * persistent_rec_words(P.max_plan, G, kS);
+  const int gi = grp < kS ? grp : 0;
+  const LdsRec rec{wrec + gi * G, kS * G,
+                   reinterpret_cast<float *>(wrec + P.max_plan * kS * G) + gi * kFinWords};
   int my_steps = 0, my_acc = 0, my_fb = 0;
   int q = blockIdx.x % kQueues;  // this block's XCD
   int tried = 0;
@@ -582,21 +640,24 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
       if (in_plan) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
-        group_step<G>(P, sl, cd, lane, slot, pos, ev, step, lid, fin_key, l_hint, &sur);
+        group_step<G>(P, sl, cd, lane, slot, rec, ev, step, lid, fin_key, l_hint, &sur);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
     }
+    wave_sync();  // the group's records were written by its other lanes
     if (valid) {
       const u64 fk = cd.active ? final_key(cd.nh, cd.chi2, 0, 0, slot) : kKeyMax;
       const u64 m = Grp<G>::min(fk, lane);
       if (m != kKeyMax && m < fin_key) {
-        if (fk == m) write_result(P, pos, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, slot, plen);
+        if (fk == m)
+          write_result(P, pos, rec, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, slot, plen);
       } else if (slot == 0) {
-        if (fin_key != kKeyMax) write_retired(P, pos, fin_key, plen);
-        else write_empty(P, pos);
+        if (fin_key != kKeyMax) write_retired(P, pos, rec, fin_key, plen);
+        else write_empty(P, pos, rec);
       }
     }
+    wave_sync();  // read before the next tile overwrites them
   }
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
@@ -1006,14 +1067,16 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
 template <bool kSurr>
 static void launch_persistent_t(hipStream_t s, const FindParams &P, int grid, int waves) {
   if (P.cfg.n_cand > 6) {  // 8-lane groups, one occupancy target
-    hipLaunchKernelGGL((k_find_persistent<2, kSurr, 8>), dim3(grid), dim3(256), 0, s, P);
+    const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 8, Grp<8>::kSeeds);
+    hipLaunchKernelGGL((k_find_persistent<2, kSurr, 8>), dim3(grid), dim3(256), lds, s, P);
     return;
   }
+  const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 6, Grp<6>::kSeeds);
   switch (waves) {
-    case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
-    case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
-    case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
-    default: hipLaunchKernelGGL((k_find_persistent<2, kSurr, 6>), dim3(grid), dim3(256), 0, s, P); break;
+    case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
+    case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
+    case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
+    default: hipLaunchKernelGGL((k_find_persistent<2, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
   }
 }
 

@@ -69,12 +69,19 @@ struct FindParams {
   // queue x and move on to the others when it is empty
   int *tile_counter;        // [kQueues]
   const int64_t *q_off;     // [kQueues + 1]
-  int n_tiles;
+  int max_plan;             // longest layer plan (sizes the persistent form's LDS records)
   unsigned long long *n_steps;
   // learned surrogate (persistent form)
   MlpWeights mlp;
   unsigned long long *sur_stats;  // [2]: hints kept, hints rejected
 };
+
+// 32-bit words of one wavefront's LDS records in the persistent form:
+// back-pointers [max_plan][seeds][G] and retired candidates [seeds][kFinWords]
+constexpr int kFinWords = 29;  // 6 + 21 state, chi2, counts
+constexpr __host__ __device__ int persistent_rec_words(int max_plan, int g, int seeds) {
+  return (max_plan > 0 ? max_plan : 1) * seeds * g + seeds * kFinWords;
+}
 
 void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
                      int *hit_bin, int *counts);
