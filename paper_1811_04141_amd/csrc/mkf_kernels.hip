@@ -189,6 +189,14 @@ struct LdsRec {
 // cheaper upper bounds replace asin and atan; a small margin absorbs FP32
 // rounding of the bin assignment.  Hits are read four at a time (indices
 // clamped into the bin range) so that their loads overlap.
+// chi2 of a window hit, with the hardware reciprocal (1 ulp) in place of a
+// correctly rounded division; both forms of the find score hits with it
+__device__ __forceinline__ float chi2_hit(const Frame &f, float vu, float vv, float u, float v) {
+  const float suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
+  const float det = fmaf(suu, svv, -suv * suv);
+  return (svv * u * u - 2.f * suv * u * v + suu * v * v) * __builtin_amdgcn_rcpf(det);
+}
+
 template <int N>
 __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer &L, int ev,
                                             const Prop &pr, const Frame &f, float chi2_base,
@@ -254,7 +262,7 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
           if (k + j >= h1) break;
           float u, v;
           if (!residual(pr.p, f, L.kind, a[j].x, a[j].y, a[j].z, u, v)) continue;
-          const float c2 = fmaxf(chi2_of(f, a[j].w, b[j].x, u, v), 0.f);
+          const float c2 = fmaxf(chi2_hit(f, a[j].w, b[j].x, u, v), 0.f);
           if (c2 < cut) {
             insert_sorted(lst, ext_key(nh + 1, chi2_base + c2, slot,
                                        (unsigned)__float_as_int(b[j].y)));
@@ -611,9 +619,17 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
     int maxlen = plen;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
+    // the plan is read four layer ids at a time, one word ahead
+    const int *plan_w = reinterpret_cast<const int *>(P.pplan) + (size_t)pos * (kMaxPlan / 4);
+    int w_cur = plen > 0 ? plan_w[0] : 0;
+    int w_next = plen > 4 ? plan_w[1] : 0;
     for (int step = 0; step < maxlen; ++step) {
       const bool in_plan = step < plen;
-      const int lid = in_plan ? P.pplan[(size_t)pos * kMaxPlan + step] : 0;
+      if (step > 0 && (step & 3) == 0) {
+        w_cur = w_next;
+        w_next = step + 4 < plen ? plan_w[step / 4 + 1] : 0;
+      }
+      const int lid = in_plan ? (w_cur >> (8 * (step & 3))) & 0xFF : 0;
       float l_hint = 0.f;
       if constexpr (kSurr) {
         // every lane of the wave takes part in the matrix-core inference
