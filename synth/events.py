@@ -311,7 +311,21 @@ def make_batch(events: List[Event]) -> EventBatch:
                       cat("layer"), se, sh, events)
 
 
-def generate(w: Workload, events=None) -> EventBatch:
+def _gen_one(args):
+    return generate_event(*args)
+
+
+def generate(w: Workload, events=None, workers: int = 1) -> EventBatch:
+    """Events of a workload (all by default).  workers > 1 generates them in
+    that many spawned processes; every event depends only on its own key, so
+    the result is the same."""
     if events is None:
         events = range(w.n_events)
-    return make_batch([generate_event(w, e) for e in events])
+    events = list(events)
+    if workers > 1 and len(events) > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            evs = pool.map(_gen_one, [(w, e) for e in events], chunksize=1)
+    else:
+        evs = [generate_event(w, e) for e in events]
+    return make_batch(evs)
