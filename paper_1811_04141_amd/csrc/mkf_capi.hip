@@ -65,7 +65,7 @@ struct mkf_ctx {
   int64_t n_hits = 0;
   std::vector<int64_t> ev_off;
   DevBuf d_ev_off, d_x, d_y, d_z, d_vu, d_vv, d_layer;
-  DevBuf d_hit_bin, d_counts, d_fill, d_bin_start, d_scan_tmp, d_sorted, d_bad;
+  DevBuf d_hit_bin, d_counts, d_fill, d_bin_start, d_scan_tmp, d_sorted, d_byorig, d_bad;
 
   // seeds
   int64_t n_seeds = 0;
@@ -78,7 +78,7 @@ struct mkf_ctx {
 
   // find
   DevBuf d_cand, d_fin_key, d_fin_rec, d_fin_meta, d_bp, d_steps, d_tiles, d_qoff;
-  DevBuf d_out_par, d_out_cov, d_out_chi2, d_out_meta, d_out_hit;
+  DevBuf d_out;  // result rows (kOut*), n_seeds words each
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_m0 = nullptr, ev_m1 = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -97,11 +97,10 @@ struct mkf_ctx {
   ~mkf_ctx() {
     DevBuf *all[] = {&d_layers, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
                      &d_hit_bin, &d_counts, &d_fill, &d_bin_start, &d_scan_tmp, &d_sorted,
-                     &d_bad, &d_seed_event, &d_seed_hits, &d_seed_state, &d_seed_ok,
+                     &d_byorig, &d_bad, &d_seed_event, &d_seed_hits, &d_seed_state, &d_seed_ok,
                      &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_pstate, &d_pinfo,
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
-                     &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out_par, &d_out_cov, &d_out_chi2,
-                     &d_out_meta, &d_out_hit, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
+                     &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
                      &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
                      &d_tx, &d_tt, &d_tvalid, &d_partial, &d_loss, &d_grad};
     for (DevBuf *b : all) b->release();
@@ -163,6 +162,7 @@ FindParams params(mkf_ctx *c) {
   P.hvv = c->d_vv.as<float>();
   P.hlayer = c->d_layer.as<int>();
   P.sorted = c->d_sorted.as<HitRec>();
+  P.byorig = c->d_byorig.as<HitRec>();
   P.bin_start = c->d_bin_start.as<int>();
   P.bins_per_event = c->bins_per_event;
   P.n_seeds = c->n_seeds;
@@ -176,11 +176,7 @@ FindParams params(mkf_ctx *c) {
   P.pinfo = c->d_pinfo.as<int>();
   P.pevent = c->d_pevent.as<int>();
   P.pplan = c->d_pplan.as<int8_t>();
-  P.out_par = c->d_out_par.as<float>();
-  P.out_cov = c->d_out_cov.as<float>();
-  P.out_chi2 = c->d_out_chi2.as<float>();
-  P.out_meta = c->d_out_meta.as<int>();
-  P.out_hit = c->d_out_hit.as<int>();
+  P.out = c->d_out.as<float>();
   P.cand = c->d_cand.as<float>();
   P.fin_key = c->d_fin_key.as<unsigned long long>();
   P.fin_rec = c->d_fin_rec.as<float>();
@@ -457,6 +453,7 @@ mkf_status mkf_load_hits(mkf_ctx *c, int32_t n_events, const int64_t *ev_off, co
   HIP_TRY(c, c->d_bin_start.ensure(sizeof(int) * (size_t)(total_bins + 1)));
   HIP_TRY(c, c->d_scan_tmp.ensure(sizeof(int) * (size_t)(4 * (total_bins / 2048 + 4) + 64)));
   HIP_TRY(c, c->d_sorted.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, c->d_byorig.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   launch_fill_i32(c->stream, c->d_counts.as<int>(), total_bins, 0);
   launch_fill_i32(c->stream, c->d_fill.as<int>(), total_bins, 0);
@@ -466,7 +463,7 @@ mkf_status mkf_load_hits(mkf_ctx *c, int32_t n_events, const int64_t *ev_off, co
   launch_scan(c->stream, c->d_counts.as<int>(), c->d_bin_start.as<int>(), total_bins,
               c->d_scan_tmp.as<int>(), nullptr);
   launch_scatter(c->stream, P, n_hits, c->d_hit_bin.as<int>(), c->d_fill.as<int>(),
-                 c->d_sorted.as<HitRec>());
+                 c->d_sorted.as<HitRec>(), c->d_byorig.as<HitRec>());
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
   HIP_TRY(c, hipEventSynchronize(c->ev_b));
@@ -612,11 +609,7 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   HIP_TRY(c, c->d_pinfo.ensure(4 * N));
   HIP_TRY(c, c->d_pevent.ensure(4 * N));
   HIP_TRY(c, c->d_pplan.ensure(kMaxPlan * N));
-  HIP_TRY(c, c->d_out_par.ensure(sizeof(float) * 6 * N));
-  HIP_TRY(c, c->d_out_cov.ensure(sizeof(float) * 21 * N));
-  HIP_TRY(c, c->d_out_chi2.ensure(4 * N));
-  HIP_TRY(c, c->d_out_meta.ensure(4 * N));
-  HIP_TRY(c, c->d_out_hit.ensure(4 * (size_t)kMaxPlan * N));
+  HIP_TRY(c, c->d_out.ensure(sizeof(float) * kOutRows * N));
   {
     FindParams Q = params(c);
     launch_permute_seeds(c->stream, Q, c->d_pstate.as<float>(), c->d_pinfo.as<int>(),
@@ -746,15 +739,10 @@ mkf_status mkf_get_tracks(mkf_ctx *c, mkf_track *out, int64_t capacity, int64_t 
   if (capacity < 0 || (capacity > 0 && !out)) return fail(c, MKF_E_ARG, "bad output buffer");
   const size_t N = (size_t)c->n_seeds;
   if (N > 0) {
-    // results are kept by processing position, structure of arrays
-    std::vector<float> par(6 * N), cov(21 * N), chi2(N);
-    std::vector<int32_t> meta(N), hit((size_t)kMaxPlan * N);
+    // results are kept by processing position, in rows of N words
+    std::vector<float> res((size_t)kOutRows * N);
     std::vector<int8_t> plan((size_t)kMaxPlan * N);
-    HIP_TRY(c, hipMemcpyAsync(par.data(), c->d_out_par.ptr, 4 * 6 * N, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(cov.data(), c->d_out_cov.ptr, 4 * 21 * N, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(chi2.data(), c->d_out_chi2.ptr, 4 * N, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(meta.data(), c->d_out_meta.ptr, 4 * N, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(hit.data(), c->d_out_hit.ptr, 4 * (size_t)kMaxPlan * N,
+    HIP_TRY(c, hipMemcpyAsync(res.data(), c->d_out.ptr, sizeof(float) * kOutRows * N,
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(plan.data(), c->d_plan.ptr, (size_t)kMaxPlan * N,
                               hipMemcpyDeviceToHost, c->stream));
@@ -767,15 +755,22 @@ mkf_status mkf_get_tracks(mkf_ctx *c, mkf_track *out, int64_t capacity, int64_t 
       const int plen = ok ? c->h_plen[seed] : 0;
       T.seed_id = seed;
       T.status = ok ? 1 : 0;
-      T.n_hits = meta[pos] & 0xFF;
-      T.n_miss = (meta[pos] >> 8) & 0xFF;
+      auto row = [&](int r) { return res[(size_t)r * N + pos]; };
+      auto irow = [&](int r) {
+        int32_t v;
+        std::memcpy(&v, &res[(size_t)r * N + pos], 4);
+        return v;
+      };
+      const int32_t meta = irow(kOutMeta);
+      T.n_hits = meta & 0xFF;
+      T.n_miss = (meta >> 8) & 0xFF;
       T.plan_len = plen;
-      T.chi2 = chi2[pos];
-      for (int i = 0; i < 6; ++i) T.par[i] = par[i * N + pos];
-      for (int i = 0; i < 21; ++i) T.cov[i] = cov[i * N + pos];
+      T.chi2 = row(kOutChi2);
+      for (int i = 0; i < 6; ++i) T.par[i] = row(kOutPar + i);
+      for (int i = 0; i < 21; ++i) T.cov[i] = row(kOutCov + i);
       for (int k = 0; k < kMaxPlan; ++k) {
         T.plan[k] = k < plen ? plan[(size_t)seed * kMaxPlan + k] : (int8_t)-1;
-        T.hit[k] = k < plen ? hit[(size_t)k * N + pos] : MKF_HIT_NONE;
+        T.hit[k] = k < plen ? irow(kOutHit + k) : MKF_HIT_NONE;
       }
     }
   }

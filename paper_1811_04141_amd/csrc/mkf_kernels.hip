@@ -282,9 +282,9 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
 // (back-pointers keep kGroup = 8 slots per seed for either G).
 template <int G, class Rec>
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
-                                           int lane, int slot, const Rec &rec, int ev, int step,
-                                           int lid, u64 &fin_key, float l_hint = 0.f,
-                                           int *sur = nullptr) {
+                                           int lane, int slot, const Rec &rec, int ev,
+                                           int64_t ev_base, int step, int lid, u64 &fin_key,
+                                           float l_hint = 0.f, int *sur = nullptr) {
   const DevLayer &L = sl[lid];
   Prop pr;
   int st = kNoCrossing;
@@ -352,9 +352,9 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
     const bool pok = (pmeta >> 16) & 1;
     int hitcode;
     if (order != kOrderNone) {
-      const int64_t gi = P.ev_off[ev] + order;
-      const float hx = P.hx[gi], hy = P.hy[gi], hz = P.hz[gi];
-      const float vu = P.hvu[gi], vv = P.hvv[gi];
+      const float4 *hr = reinterpret_cast<const float4 *>(P.byorig + ev_base + order);
+      const float4 ha = hr[0], hb = hr[1];
+      const float hx = ha.x, hy = ha.y, hz = ha.z, vu = ha.w, vv = hb.x;
       Frame f;
       make_frame(np, np + 6, L.kind, f);
       float u, v;
@@ -430,17 +430,18 @@ __device__ __forceinline__ void write_result(const FindParams &P, int64_t pos, c
                                              const float *p, const float *c, float chi2, int nh,
                                              int nm, int best_step, int best_slot, int plen) {
   const size_t N = (size_t)P.n_seeds;
+  float *out = P.out + pos;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) P.out_par[i * N + pos] = p[i];
+  for (int i = 0; i < 6; ++i) out[(kOutPar + i) * N] = p[i];
 #pragma unroll
-  for (int i = 0; i < 21; ++i) P.out_cov[i * N + pos] = c[i];
-  P.out_chi2[pos] = chi2;
-  P.out_meta[pos] = nh | (nm << 8);
-  for (int s = plen - 1; s > best_step; --s) P.out_hit[s * N + pos] = MKF_HIT_NONE;
+  for (int i = 0; i < 21; ++i) out[(kOutCov + i) * N] = c[i];
+  out[kOutChi2 * N] = chi2;
+  out[kOutMeta * N] = __int_as_float(nh | (nm << 8));
+  for (int s = plen - 1; s > best_step; --s) out[(kOutHit + s) * N] = __int_as_float(MKF_HIT_NONE);
   int sl = best_slot;
   for (int s = best_step; s >= 0; --s) {
     const int v = rec.get_bp(s, sl);
-    P.out_hit[s * N + pos] = (v >> 3) - 2;
+    out[(kOutHit + s) * N] = __int_as_float((v >> 3) - 2);
     sl = v & 7;
   }
 }
@@ -499,7 +500,8 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   load_cand(P, (size_t)pos * kGroup + slot, cd);
   u64 fin_key = P.fin_key[pos];
   const u64 fk0 = fin_key;
-  group_step<kGroup>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, step, lid, fin_key);
+  group_step<kGroup>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, P.ev_off[ev], step, lid,
+                     fin_key);
   store_cand(P, (size_t)pos * kGroup + slot, cd);
   if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
 }
@@ -609,6 +611,7 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
     const int info = valid ? P.pinfo[pos] : 0;
     const int plen = info & 0xFF;
     const int ev = valid ? P.pevent[pos] : 0;
+    const int64_t ev_base = valid ? P.ev_off[ev] : 0;
     Cand cd;
     cd.active = valid && slot == 0 && ((info >> 8) & 1);
     cd.nh = 3;
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
       if (in_plan) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
-        group_step<G>(P, sl, cd, lane, slot, rec, ev, step, lid, fin_key, l_hint, &sur);
+        group_step<G>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, l_hint, &sur);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
@@ -854,7 +857,7 @@ __global__ __launch_bounds__(256) void k_hit_bins(FindParams P, int n_events, in
 
 __global__ __launch_bounds__(256) void k_hit_scatter(FindParams P, int n_events, int64_t n_hits,
                                                      const int *hit_bin, int *fill,
-                                                     HitRec *sorted) {
+                                                     HitRec *sorted, HitRec *byorig) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_hits) return;
   const int e = event_of(P.ev_off, n_events, i);
@@ -870,6 +873,7 @@ __global__ __launch_bounds__(256) void k_hit_scatter(FindParams P, int n_events,
   h.pad0 = 0;
   h.pad1 = 0;
   sorted[slot] = h;
+  byorig[i] = h;
 }
 
 // exclusive scan, 2048 items per 256-thread block
@@ -1033,10 +1037,10 @@ void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const i
 }
 
 void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const int *hit_bin,
-                    int *fill, HitRec *sorted) {
+                    int *fill, HitRec *sorted, HitRec *byorig) {
   if (n_hits == 0) return;
   hipLaunchKernelGGL(k_hit_scatter, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P,
-                     P.n_events, n_hits, hit_bin, fill, sorted);
+                     P.n_events, n_hits, hit_bin, fill, sorted, byorig);
 }
 
 static void scan_rec(hipStream_t s, const int *in, int *out, int64_t n, int *scratch) {

@@ -23,6 +23,9 @@ struct alignas(16) HitRec {
 // field over n_seeds * kGroup slots so that a wavefront reads 64
 // consecutive floats per field.
 constexpr int kCandFields = 29;  // 6 par + 21 cov + chi2 + meta (bit cast)
+// rows of the result buffer (each n_seeds words; meta and hit are int32)
+constexpr int kOutPar = 0, kOutCov = 6, kOutChi2 = 27, kOutMeta = 28, kOutHit = 29;
+constexpr int kOutRows = kOutHit + kMaxPlan;
 // workgroups are dealt to the 8 XCDs of an MI355X round-robin by index
 constexpr int kQueues = 8;
 
@@ -37,6 +40,7 @@ struct FindParams {
   const float *hx, *hy, *hz, *hvu, *hvv;  // caller order, all events
   const int *hlayer;
   const HitRec *sorted;    // binned
+  const HitRec *byorig;    // the same records in the caller's order
   const int *bin_start;    // n_events * bins_per_event + 1
   int bins_per_event;
   // seeds, by seed id (written by the seed kernel)
@@ -52,12 +56,9 @@ struct FindParams {
   const int *pinfo;         // [n_seeds] plan_len | ok << 8
   const int *pevent;        // [n_seeds]
   const int8_t *pplan;      // [n_seeds][kMaxPlan]
-  // results, by processing position (structure of arrays)
-  float *out_par;           // [6][n_seeds]
-  float *out_cov;           // [21][n_seeds]
-  float *out_chi2;          // [n_seeds]
-  int *out_meta;            // [n_seeds] n_hits | n_miss << 8
-  int *out_hit;             // [kMaxPlan][n_seeds]
+  // results, by processing position, rows of n_seeds words (kOut* below):
+  // par[6], cov[21], chi2, meta (n_hits | n_miss << 8), hit[kMaxPlan]
+  float *out;
   // find state
   float *cand;              // [kCandFields][n_seeds * kGroup]
   unsigned long long *fin_key;  // [n_seeds]
@@ -87,7 +88,7 @@ void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const i
                      int *hit_bin, int *counts);
 void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, int *tmp_b);
 void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const int *hit_bin,
-                    int *fill, HitRec *sorted);
+                    int *fill, HitRec *sorted, HitRec *byorig);
 void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
                  int *seed_ok, int *plan_len, int8_t *plan, double *plan_l);
 void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int *pinfo,
