@@ -249,13 +249,15 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
       const int h0 = P.bin_start[row + lo];
       const int h1 = P.bin_start[row + hi + 1];
       const float4 *hits = reinterpret_cast<const float4 *>(P.sorted);
+      const float2 *hits2 = reinterpret_cast<const float2 *>(P.sorted);
       for (int k = h0; k < h1; k += 4) {
-        float4 a[4], b[4];
+        float4 a[4];
+        float2 b[4];  // (var_v, index); the record's padding is not read
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int kk = min(k + j, h1 - 1);
           a[j] = hits[2 * kk];
-          b[j] = hits[2 * kk + 1];
+          b[j] = hits2[4 * kk + 2];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -594,10 +596,14 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   int my_steps = 0, my_acc = 0, my_fb = 0;
   int q = blockIdx.x % kQueues;  // this block's XCD
   int tried = 0;
+  // the next tile of queue q is claimed one tile ahead, so that the atomic's
+  // latency overlaps the current tile's work (lane 0 holds it; -1: none)
+  int ahead = -1;
   for (;;) {
     int tile = 0;
-    if (lane == 0) tile = atomicAdd(&P.tile_counter[q], 1);
+    if (lane == 0) tile = ahead >= 0 ? ahead : atomicAdd(&P.tile_counter[q], 1);
     tile = __shfl(tile, 0);
+    ahead = -1;
     const int64_t start = P.q_off[q] + (int64_t)tile * Grp<G>::kSeeds;
     const int64_t end = P.q_off[q + 1];
     if (start >= end) {
@@ -606,6 +612,7 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
       q = (q + 1) % kQueues;
       continue;
     }
+    if (lane == 0 && start + Grp<G>::kSeeds < end) ahead = atomicAdd(&P.tile_counter[q], 1);
     const int64_t pos = start + grp;
     const bool valid = grp < Grp<G>::kSeeds && pos < end;
     const int info = valid ? P.pinfo[pos] : 0;
