@@ -159,10 +159,14 @@ def main():
                    for k in ("plain", "batched", "graph") if k in results}
     R = results[best]
     # roofline of the dominant kernel, from HIP events on the context stream
-    kernel_form = best if results[best]["main_ms"] > 0 else ("batched" if "batched" in results else best)
+    # (a graph replay cannot bracket the kernel with events: take the same
+    # kernel's eager form, else the whole find of the best form)
+    timed = [k for k in (best, "batched", "plain") if k in results and results[k]["main_ms"] > 0]
+    kernel_form = timed[0] if timed else best
     K = results[kernel_form]
+    kernel_ms = K["main_ms"] if K["main_ms"] > 0 else K["find_ms"]
     per_launch_steps = K["n_steps"] / max(1, K["main_launches"])
-    per_launch_ms = K["main_ms"] / max(1, K["main_launches"])
+    per_launch_ms = kernel_ms / max(1, K["main_launches"])
     if kernel_form == "plain":
         achieved = PLAIN_BYTES_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e9
         roof = {"kernel": "k_find_step", "bound": "hbm", "achieved": achieved,

@@ -573,8 +573,8 @@ template <int kWaves, bool kSurr, int G>
 __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   __shared__ DevLayer sl[kMaxLayers];
   __shared__ unsigned long long block_steps, block_sur[2];
-  __shared__ __bf16 sMX[kSurr ? 4 * 64 * kLdX : 1];
-  __shared__ __bf16 sMH[kSurr ? 4 * 64 * kLdH : 1];
+  __shared__ __attribute__((aligned(16))) __bf16 sMX[kSurr ? 4 * 64 * kLdX : 1];
+  __shared__ __attribute__((aligned(16))) __bf16 sMH[kSurr ? 4 * 64 * kLdH : 1];
   stage_layers(P, sl);
   if (threadIdx.x == 0) {
     block_steps = 0;
@@ -651,14 +651,37 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
 #pragma unroll
           for (int k = 0; k < kNI; ++k) xin[k] = 0.f;
         }
-        // (skipped, wave-uniformly, when no lane heads to a barrel layer)
-        if (__ballot(want) != 0ull) {
+        // The lanes that head to a barrel layer write their inputs to
+        // consecutive sample rows; one 32-sample tile suffices when at most
+        // 32 of them do (no inference at all when none does).
+        const unsigned long long m = __ballot(want);
+        if (m != 0ull) {
+          const int cnt = __popcll(m);
+          const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
           __bf16 *X = sMX + wv * 64 * kLdX;
           __bf16 *H = sMH + wv * 64 * kLdH;
+          if (want) {
+            bf16x8 xv, zv;
 #pragma unroll
-          for (int k = 0; k < 16; ++k) X[lane * kLdX + k] = (__bf16)(k < kNI ? xin[k] : 0.f);
+            for (int k = 0; k < kNI; ++k) {
+              xv[k] = (__bf16)xin[k];
+              zv[k] = (__bf16)0.f;
+            }
+            reinterpret_cast<bf16x8 *>(X + rank * kLdX)[0] = xv;
+            reinterpret_cast<bf16x8 *>(X + rank * kLdX)[1] = zv;
+          }
           wave_sync();
-          const float y0 = mlp_forward_wave(P.mlp, X, H, nullptr);
+          float y0;
+          if (cnt <= 32) {
+            f32x16 y[1][1];
+            mlp_forward_tiles<1>(P.mlp, X, H, y);
+            y0 = mlp_output<1>(y, rank & 31, 0);
+          } else {
+            f32x16 y[1][2];
+            mlp_forward_tiles<2>(P.mlp, X, H, y);
+            y0 = mlp_output<2>(y, rank, 0);
+          }
           wave_sync();  // the tiles are rewritten at the next step
           if (want) l_hint = surrogate_path(cd.p, sl[lid].pos, P.cfg.mkb, y0);
         }

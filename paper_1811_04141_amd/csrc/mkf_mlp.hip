@@ -155,11 +155,11 @@ __device__ __forceinline__ void store_unit_major(const f32x16 (&acc)[MT][2], __b
 }
 
 __global__ __launch_bounds__(64) void k_mlp_grad(GradParams G) {
-  __shared__ __bf16 sX[64 * kLdX];
-  __shared__ __bf16 sXu[32 * kLdU];
-  __shared__ __bf16 sH1[64 * kLdH], sH1u[64 * kLdU], sH2[64 * kLdH], sH2u[64 * kLdU];
-  __shared__ __bf16 sDY[64 * kLdY], sDYu[32 * kLdU];
-  __shared__ __bf16 sDZ2[64 * kLdH], sDZ2u[64 * kLdU], sDZ1u[64 * kLdU];
+  __shared__ __attribute__((aligned(16))) __bf16 sX[64 * kLdX];
+  __shared__ __attribute__((aligned(16))) __bf16 sXu[32 * kLdU];
+  __shared__ __attribute__((aligned(16))) __bf16 sH1[64 * kLdH], sH1u[64 * kLdU], sH2[64 * kLdH], sH2u[64 * kLdU];
+  __shared__ __attribute__((aligned(16))) __bf16 sDY[64 * kLdY], sDYu[32 * kLdU];
+  __shared__ __attribute__((aligned(16))) __bf16 sDZ2[64 * kLdH], sDZ2u[64 * kLdU], sDZ1u[64 * kLdU];
   const int lane = threadIdx.x, r = lane & 31, h = lane >> 5;
   const int64_t base = G.begin + (int64_t)blockIdx.x * 64;
   const int64_t s = (base + lane) % G.n;
@@ -366,8 +366,8 @@ __global__ __launch_bounds__(256) void k_mlp_images(AdamParams A) {
 
 __global__ __launch_bounds__(256) void k_mlp_infer(MlpWeights w, int64_t n, const float *x,
                                                    float *y) {
-  __shared__ __bf16 sX[4][64 * kLdX];
-  __shared__ __bf16 sH[4][64 * kLdH];
+  __shared__ __attribute__((aligned(16))) __bf16 sX[4][64 * kLdX];
+  __shared__ __attribute__((aligned(16))) __bf16 sH[4][64 * kLdH];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool valid = s < n;

@@ -17,6 +17,7 @@
 namespace mkf {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kNI = 8, kNH = 64, kNO = 7;
@@ -92,91 +93,118 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.f + __expf(-z)); }
+// The activations are stored as bfloat16 (8 significant bits), so the
+// logistic uses the hardware exponential and reciprocal.
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.f + __expf(-z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float dsilu(float z) {
-  const float s = 1.f / (1.f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.f + z * (1.f - s));
 }
 
 __device__ __forceinline__ int acc_row(int i, int h) { return 8 * (i / 4) + 4 * h + (i % 4); }
 
 // acc[mt][nt] = bias + W (MT*32 x KC*16, row-major, ld) . act^T, where act is
-// the sample-major LDS tile [64][lda] (columns = units, k).
-template <int MT, int KC>
+// the sample-major LDS tile [32 NT][lda] (columns = units, k).
+template <int MT, int KC, int NT = 2>
 __device__ __forceinline__ void gemm_w_act(const __bf16 *W, int ldw, const __bf16 *act, int lda,
-                                           const float *bias, f32x16 (&acc)[MT][2]) {
+                                           const float *bias, f32x16 (&acc)[MT][NT]) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[mt][nt][i] = bias ? bias[32 * mt + acc_row(i, h)] : 0.f;
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) {
-    bf16x8 a[MT], b[2];
+    bf16x8 a[MT], b[NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
       a[mt] = *reinterpret_cast<const bf16x8 *>(W + (32 * mt + r) * ldw + 16 * kc + 8 * h);
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
       b[nt] = *reinterpret_cast<const bf16x8 *>(act + (32 * nt + r) * lda + 16 * kc + 8 * h);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
         acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
   }
 }
 
 // Store silu(acc) (or acc itself) as BF16 into a sample-major LDS tile.
-template <int MT, bool kSilu>
-__device__ __forceinline__ void store_act(const f32x16 (&acc)[MT][2], __bf16 *out, int ldo) {
+// Accumulator registers 4q .. 4q + 3 hold four consecutive units of one
+// sample, written as one 8-byte store.
+template <int MT, bool kSilu, int NT = 2>
+__device__ __forceinline__ void store_act(const f32x16 (&acc)[MT][NT], __bf16 *out, int ldo) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const float v = kSilu ? silu(acc[mt][nt][i]) : acc[mt][nt][i];
-        out[(32 * nt + r) * ldo + 32 * mt + acc_row(i, h)] = (__bf16)v;
+      for (int q = 0; q < 4; ++q) {
+        bf16x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float a = acc[mt][nt][4 * q + e];
+          v[e] = (__bf16)(kSilu ? silu(a) : a);
+        }
+        *reinterpret_cast<bf16x4 *>(out + (32 * nt + r) * ldo + 32 * mt + acc_row(4 * q, h)) = v;
       }
 }
 
-// Forward pass of the wave's 64 samples; X is the sample-major input tile
-// (k 0..7 inputs, 8..15 zero), H a [64][kLdH] scratch tile.  Returns the
-// first output (y0) of the lane's own sample; all 7 outputs go to y[7] if
-// not null (this lane's sample).
+// Forward pass of the first 32 NT samples of the wave's tiles; X is the
+// sample-major input tile (k 0..7 inputs, 8..15 zero), H a [64][kLdH]
+// scratch tile.  y receives the output layer's accumulators: output j of
+// sample s is column s % 32 of tile s / 32, row j (see mlp_output).
+template <int NT>
+__device__ __forceinline__ void mlp_forward_tiles(const MlpWeights &w, const __bf16 *X, __bf16 *H,
+                                                  f32x16 (&y)[1][NT]) {
+  {
+    f32x16 acc[2][NT];
+    gemm_w_act<2, 1, NT>(w.W1p, kLdW1, X, kLdX, w.b1, acc);
+    store_act<2, true, NT>(acc, H, kLdH);
+  }
+  wave_sync();
+  {
+    f32x16 acc[2][NT];
+    gemm_w_act<2, 4, NT>(w.W2p, kLdW2, H, kLdH, w.b2, acc);
+    wave_sync();  // every lane has read h1 before h2 overwrites it
+    store_act<2, true, NT>(acc, H, kLdH);
+  }
+  wave_sync();
+  gemm_w_act<1, 4, NT>(w.W3p, kLdW3, H, kLdH, w.b3, y);
+}
+
+// Output j of sample s (any lane may ask for any sample): row j < 4 is in
+// half 0, register j; rows 4..6 in half 1, register j - 4.
+template <int NT>
+__device__ __forceinline__ float mlp_output(const f32x16 (&y)[1][NT], int s, int j) {
+  const int reg = j & 3;
+  const int src = (s & 31) + (j < 4 ? 0 : 32);
+  float v = __shfl(y[0][0][reg], src);
+  if (NT == 2) {
+    const float v1 = __shfl(y[0][NT - 1][reg], src);
+    v = s >= 32 ? v1 : v;
+  }
+  return v;
+}
+
+// Forward pass of the wave's 64 samples (sample = lane); returns the first
+// output (y0) of the lane's own sample; all 7 outputs go to y_all[7] if not
+// null.
 __device__ __forceinline__ float mlp_forward_wave(const MlpWeights &w, const __bf16 *X, __bf16 *H,
                                                   float *y_all) {
-  const int lane = threadIdx.x & 63, h = lane >> 5;
-  {
-    f32x16 acc[2][2];
-    gemm_w_act<2, 1>(w.W1p, kLdW1, X, kLdX, w.b1, acc);
-    store_act<2, true>(acc, H, kLdH);
-  }
-  wave_sync();
-  {
-    f32x16 acc[2][2];
-    gemm_w_act<2, 4>(w.W2p, kLdW2, H, kLdH, w.b2, acc);
-    wave_sync();  // every lane has read h1 before h2 overwrites it
-    store_act<2, true>(acc, H, kLdH);
-  }
-  wave_sync();
-  f32x16 acc[1][2];
-  gemm_w_act<1, 4>(w.W3p, kLdW3, H, kLdH, w.b3, acc);
-  // row j < 4: half 0, register j; rows 4..6: half 1, register j - 4.
-  // This lane's sample (lane) is column lane % 32 of sample tile lane / 32.
+  const int lane = threadIdx.x & 63;
+  f32x16 y[1][2];
+  mlp_forward_tiles<2>(w, X, H, y);
   float own[kNO];
 #pragma unroll
-  for (int j = 0; j < kNO; ++j) {
-    const int reg = j & 3;
-    const int src = (lane & 31) + (j < 4 ? 0 : 32);
-    const float t0 = __shfl(acc[0][0][reg], src);
-    const float t1 = __shfl(acc[0][1][reg], src);
-    own[j] = h ? t1 : t0;
-  }
+  for (int j = 0; j < kNO; ++j) own[j] = mlp_output<2>(y, lane, j);
   if (y_all)
 #pragma unroll
     for (int j = 0; j < kNO; ++j) y_all[j] = own[j];
