@@ -316,17 +316,22 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   }
 
   // a candidate without any extension stops; keep the seed's best such one
+  // (the group reductions below are skipped, wave-uniformly, once no lane
+  // of the wavefront has anything left to contribute)
   const bool retire = cd.active && n_ext == 0;
-  const u64 rkey = retire ? final_key(cd.nh, cd.chi2, 1, step, slot) : kKeyMax;
-  const u64 rmin = Grp<G>::min(rkey, lane);
-  if (rmin < fin_key) {
-    if (rkey == rmin) rec.put_fin(cd);
-    fin_key = rmin;
+  if (__ballot(retire) != 0ull) {
+    const u64 rkey = retire ? final_key(cd.nh, cd.chi2, 1, step, slot) : kKeyMax;
+    const u64 rmin = Grp<G>::min(rkey, lane);
+    if (rmin < fin_key) {
+      if (rkey == rmin) rec.put_fin(cd);
+      fin_key = rmin;
+    }
   }
 
   // the seed's best n_cand extensions, rank r goes to slot r
   u64 mine = kKeyMax;
   for (int r = 0; r < P.cfg.n_cand; ++r) {
+    if (__ballot(lst[0] != kKeyMax) == 0ull) break;
     const u64 m = Grp<G>::min(lst[0], lane);
     if (m != kKeyMax && lst[0] == m) pop_front(lst);
     if (slot == r) mine = m;
