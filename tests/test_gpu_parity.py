@@ -237,6 +237,29 @@ def test_find_edge_cases(mkf):
     assert tr0.shape[0] == 0 and st0["n_steps"] == 0
 
 
+def test_find_maximum_layers_and_plan(mkf):
+    """The largest geometry the library takes (32 cylinders) with plans of
+    29 layers: the oracle on every seed, and the two forms bitwise equal
+    (the persistent form sizes its LDS records by the longest plan)."""
+    from synth import EventRecipe, Workload
+    from synth.workloads import SIGMA_RPHI, SIGMA_Z
+    radii = np.linspace(3.0, 100.0, 32)
+    layers = [Layer(BARREL, float(r), -200.0, 200.0, SIGMA_RPHI ** 2, SIGMA_Z ** 2) for r in radii]
+    w = Workload(name="barrel32_1x400", layers=tuple(layers),
+                 recipe=EventRecipe(pt_lo=1.0, pt_hi=10.0, eta_max=1.0, ms_sigma=0.001,
+                                    hit_ineff=0.02, noise_frac=0.3),
+                 find=FindConfig(), n_events=1, n_tracks=(400, 400), master_seed=0x5EED0007)
+    b = generate(w)
+    a, seeds, sa = run_find(mkf, w, b, flags=0)
+    c, _, sc = run_find(mkf, w, b, flags=mkf.F_BATCHED)
+    plen = seeds[3]
+    say("plan lengths: max", plen.max(), "mean", plen.mean())
+    assert plen.max() == 29
+    assert sa["n_steps"] == sc["n_steps"] and a.tobytes() == c.tobytes()
+    ref = O.find_event(w.find, w.layers, b.events[0])
+    check(PT.compare_tracks(a, ref, mkf.unpack_cov))
+
+
 # ------------------------------------------------------------------- fit
 
 def test_fit_matches_oracle(mkf):
