@@ -28,6 +28,15 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # layer-synchronous form must move through HBM.
 FLOPS_PER_STEP = 780.0
 PLAIN_BYTES_PER_STEP = 256.0
+# fit: one track-layer update (crossing, transport, Jacobian, covariance,
+# scattering, chi2, Kalman update) = the step count above without the window
+FIT_FLOPS_PER_UPDATE = 727.0
+# surrogate network per sample: forward 2 (8*64 + 64*64 + 7*64) = 10,112;
+# backward (input errors of layers 3 and 2, weight gradients of all three)
+# 19,200
+MLP_FWD_FLOPS = 10112.0
+MLP_FWD_BWD_FLOPS = 29312.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -52,6 +61,62 @@ def profiled_traffic(kernel):
     return None
 
 
+def measure_kernels(mkf, w, stream, T, f):
+    """Throughput of the other hot-path kernels, each from HIP events on the
+    context stream around one launch after a warm-up: the search-free fit
+    (262,144 tracks x 26 layers) and the surrogate network's inference and
+    gradient (2^20 samples from its training sampler)."""
+    import numpy as np
+    import torch
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    def alu(flops, ms, peak, unit_count, unit):
+        ach = flops / (ms * 1e-3) / 1e12
+        return {"ms": ms, "throughput": unit_count / (ms * 1e-3), "unit": unit,
+                "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}
+
+    out = {}
+    with torch.cuda.stream(stream):
+        ctx = mkf.Context(w.find, stream=stream.cuda_stream)
+        ctx.load_geometry(w.layers)
+        k, n = f.x.shape
+        ins = [T(a) for a in (f.kind, f.pos, f.x, f.y, f.z, f.var_u, f.var_v, f.length,
+                              f.init_par, f.init_cov)]
+        outs = [torch.zeros((n, 6), device=ins[0].device), torch.zeros((n, 21), device=ins[0].device),
+                torch.zeros(n, device=ins[0].device),
+                torch.zeros(n, dtype=torch.int32, device=ins[0].device)]
+        ms = timed(lambda: ctx.fit(*ins, *outs))
+        out["k_fit"] = dict(alu(FIT_FLOPS_PER_UPDATE * n * k, ms, FP32_VECTOR_PEAK_TFLOPS, n * k,
+                                "track-layer updates/s"), bound="alu",
+                            workload=f"{n} tracks x {k} layers")
+        m = 1 << 20
+        dev = ins[0].device
+        x = torch.zeros((m, 8), device=dev)
+        t = torch.zeros((m, 7), device=dev)
+        v = torch.zeros(m, device=dev)
+        ctx.surrogate_samples(m, 5, x, t, v)
+        y = torch.zeros((m, 7), device=dev)
+        ms = timed(lambda: ctx.surrogate_infer(x, y))
+        out["k_mlp_infer"] = dict(alu(MLP_FWD_FLOPS * m, ms, BF16_MFMA_PEAK_TFLOPS, m,
+                                      "samples/s"), bound="mfma", workload=f"{m} samples")
+        lw = np.ones(7, np.float32)
+        ms = timed(lambda: ctx.surrogate_grad(x, t, lw))
+        out["k_mlp_grad+reduce"] = dict(alu(MLP_FWD_BWD_FLOPS * m, ms, BF16_MFMA_PEAK_TFLOPS, m,
+                                            "samples/s"), bound="mfma", workload=f"{m} samples")
+        ctx.close()
+    log("kernels", json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +127,8 @@ def main():
     ap.add_argument("--forms", default="plain,batched,graph,surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline (0 disables)")
+    ap.add_argument("--kernels", type=int, default=1,
+                    help="also time the fit and the surrogate network kernels (0 disables)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -72,15 +139,20 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     from synth import barrel_endcap, generate
-    from paper_1811_04141_amd import mkf
 
     w = barrel_endcap(args.events, args.tracks)
     t0 = time.time()
     batch = generate(w)
     log(f"generated {w.name}: {batch.x.shape[0]} hits, {batch.seed_hits.shape[0]} seeds "
         f"in {time.time() - t0:.1f}s")
+    fit_inputs = None
+    if args.kernels:  # generated (in worker processes) before the GPU library loads
+        from synth.fitstress import fit_stress
+        fit_inputs = fit_stress(262144, 26, workers=max(1, min(8, os.cpu_count() or 1)))
+
+    import torch
+    from paper_1811_04141_amd import mkf
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)  # default priority
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -179,6 +251,8 @@ def main():
     roof["traffic"] = profiled_traffic(roof["kernel"])
     roof["avg_launch_ms"] = per_launch_ms
 
+    kernels = measure_kernels(mkf, w, stream, T, fit_inputs) if args.kernels else None
+
     cpu = None
     if args.cpu_seconds > 0:
         from oracle import oracle as O
@@ -213,6 +287,7 @@ def main():
                    "form": best, "candidates_per_seed": w.find.n_cand},
         "forms": results,
         "surrogate_speedup": speedup,
+        "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

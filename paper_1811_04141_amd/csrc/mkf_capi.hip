@@ -90,7 +90,7 @@ struct mkf_ctx {
 
   // learned surrogate: master weights, Adam moments, BF16 images, counters
   DevBuf d_mlp_param, d_mlp_m, d_mlp_v, d_W1p, d_W2p, d_W3p, d_W2T, d_W3T, d_mb1, d_mb2, d_mb3;
-  DevBuf d_sur, d_radii, d_tx, d_tt, d_tvalid, d_partial, d_loss, d_grad;
+  DevBuf d_sur, d_radii, d_tx, d_tt, d_tvalid, d_partial, d_partial2, d_loss, d_grad;
   int mlp_step = 0;  // Adam steps taken
 
   // fit scratch (host-side inputs are staged here)
@@ -102,7 +102,7 @@ struct mkf_ctx {
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
                      &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
-                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_loss, &d_grad};
+                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -973,6 +973,8 @@ mkf_status mkf_surrogate_train(mkf_ctx *c, const mkf_train_cfg *cfg, mkf_train_r
   HIP_TRY(c, c->d_tt.ensure(sizeof(float) * 7 * n));
   HIP_TRY(c, c->d_tvalid.ensure(sizeof(float) * n));
   HIP_TRY(c, c->d_partial.ensure(sizeof(float) * (size_t)waves * (kNParam + 1)));
+  HIP_TRY(c, c->d_partial2.ensure(sizeof(float) * (size_t)(waves / kReduceGroup + 1) *
+                                  (kNParam + 1)));
   HIP_TRY(c, c->d_loss.ensure(sizeof(float) * steps));
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   mkf_status st = gen_samples(c, n, cfg->seed, c->d_tx.as<float>(), c->d_tt.as<float>(),
@@ -993,7 +995,7 @@ mkf_status mkf_surrogate_train(mkf_ctx *c, const mkf_train_cfg *cfg, mkf_train_r
                     c->d_tvalid.as<float>(), n, begin, cfg->batch, cfg->loss_w,
                     c->d_partial.as<float>());
     launch_mlp_reduce(c->stream, B, c->d_partial.as<float>(), waves, s + 1, lr, 1, nullptr,
-                      c->d_loss.as<float>() + s);
+                      c->d_loss.as<float>() + s, c->d_partial2.as<float>());
   }
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_m1, c->stream));
@@ -1061,13 +1063,16 @@ mkf_status mkf_surrogate_grad(mkf_ctx *c, int32_t n, const float *x, const float
     if (!finite_f(loss_w[j])) return fail(c, MKF_E_ARG, "loss weights must be finite");
   const int waves = n / 64;
   HIP_TRY(c, c->d_partial.ensure(sizeof(float) * (size_t)waves * (kNParam + 1)));
+  HIP_TRY(c, c->d_partial2.ensure(sizeof(float) * (size_t)(waves / kReduceGroup + 1) *
+                                  (kNParam + 1)));
   HIP_TRY(c, c->d_grad.ensure(sizeof(float) * (kNParam + 1)));
   HIP_TRY(c, c->d_tvalid.ensure(sizeof(float) * n));
   launch_fill_i32(c->stream, c->d_tvalid.as<int>(), n, 0x3F800000);  // 1.0f
   launch_mlp_grad(c->stream, mlp_buffers(c).weights(), x, t, c->d_tvalid.as<float>(), n, 0, n,
                   loss_w, c->d_partial.as<float>());
   launch_mlp_reduce(c->stream, mlp_buffers(c), c->d_partial.as<float>(), waves, 1, 0.f, 0,
-                    c->d_grad.as<float>(), c->d_grad.as<float>() + kNParam);
+                    c->d_grad.as<float>(), c->d_grad.as<float>() + kNParam,
+                    c->d_partial2.as<float>());
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipMemcpyAsync(grad, c->d_grad.ptr, sizeof(float) * kNParam, hipMemcpyDeviceToHost,
                             c->stream));

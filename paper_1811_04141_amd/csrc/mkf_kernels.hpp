@@ -118,8 +118,13 @@ void launch_mlp_datagen(hipStream_t s, const FindParams &P, int64_t n, uint64_t 
 void launch_mlp_grad(hipStream_t s, const MlpWeights &w, const float *x, const float *t,
                      const float *valid, int64_t n, int64_t begin, int batch, const float *loss_w,
                      float *partial);
+// Sums n_waves partial rows (through scratch, ceil(n_waves / kReduceGroup)
+// rows, when n_waves > kReduceGroup), then writes the gradient or takes an
+// Adam step.
+constexpr int kReduceGroup = 64;
 void launch_mlp_reduce(hipStream_t s, const MlpBuffers &B, const float *partial, int n_waves,
-                       int step, float lr, int adam, float *grad_out, float *loss_out);
+                       int step, float lr, int adam, float *grad_out, float *loss_out,
+                       float *scratch);
 void launch_mlp_images(hipStream_t s, const MlpBuffers &B);
 void launch_mlp_infer(hipStream_t s, const MlpWeights &w, int64_t n, const float *x, float *y);
 

@@ -355,6 +355,19 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(AdamParams A) {
   write_images(A, p, np);
 }
 
+// First level of the partial-gradient sum for large batches: row g of out
+// is the sum of partial rows g * group .. g * group + group - 1 (in order).
+__global__ __launch_bounds__(256) void k_mlp_partial_sum(const float *in, int n_in, int group,
+                                                         float *out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kNParam) return;
+  const int g = blockIdx.y;
+  const int w1 = min(n_in, (g + 1) * group);
+  float acc = 0.f;
+  for (int w = g * group; w < w1; ++w) acc += in[(size_t)w * (kNParam + 1) + p];
+  out[(size_t)g * (kNParam + 1) + p] = acc;
+}
+
 // BF16 images of the given master weights (padding stays zero).
 __global__ __launch_bounds__(256) void k_mlp_images(AdamParams A) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -406,7 +419,15 @@ void launch_mlp_grad(hipStream_t s, const MlpWeights &w, const float *x, const f
 }
 
 void launch_mlp_reduce(hipStream_t s, const MlpBuffers &B, const float *partial, int n_waves,
-                       int step, float lr, int adam, float *grad_out, float *loss_out) {
+                       int step, float lr, int adam, float *grad_out, float *loss_out,
+                       float *scratch) {
+  if (n_waves > kReduceGroup) {  // two levels, both in a fixed order
+    const int n1 = (n_waves + kReduceGroup - 1) / kReduceGroup;
+    hipLaunchKernelGGL(k_mlp_partial_sum, dim3((kNParam + 1 + 255) / 256, n1), dim3(256), 0, s,
+                       partial, n_waves, kReduceGroup, scratch);
+    partial = scratch;
+    n_waves = n1;
+  }
   AdamParams A{};
   A.param = B.param;
   A.m = B.m;
