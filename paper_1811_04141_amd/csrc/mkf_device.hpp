@@ -409,8 +409,14 @@ __device__ __forceinline__ T chi2_of(const FrameT<T> &f, T vu, T vv, T u, T v) {
   return (svv * u * u - T(2) * suv * u * v + suu * v * v) / det;
 }
 
-// Kalman gain-form update with the hit (u, v residual, variances vu, vv):
-// K = C H^T S^-1, p += K r, C -= K (C H^T)^T.
+// Kalman update with the hit (u, v residual, variances vu, vv): K = C H^T
+// S^-1, p += K r, and the covariance in Joseph form,
+//   C' = (I - K H) C (I - K H)^T + K V K^T = C - K (CH^T)^T - B K^T,
+// with B = C H^T - K (H C H^T + V), which is zero in exact arithmetic and
+// in FP32 carries the first-order effect of the rounding of K.  The plain
+// gain form C - K (C H^T)^T loses the covariance where the prediction is
+// much wider than the hit (tracks that meet a layer nearly tangentially),
+// because its result is a small difference of large terms.
 template <typename T>
 __device__ __forceinline__ void kf_update(T *p, T *c, const FrameT<T> &f, int kind, T vu, T vv,
                                           T u, T v) {
@@ -425,17 +431,20 @@ __device__ __forceinline__ void kf_update(T *p, T *c, const FrameT<T> &f, int ki
   const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
   const T inv_det = T(1) / fma_t(suu, svv, -suv * suv);
   const T iuu = svv * inv_det, ivv = suu * inv_det, iuv = -suv * inv_det;
-  T Ku[6], Kv[6];
+  T Ku[6], Kv[6], Bu[6], Bv[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     Ku[i] = fma_t(PHu[i], iuu, PHv[i] * iuv);
     Kv[i] = fma_t(PHu[i], iuv, PHv[i] * ivv);
     p[i] = fma_t(Ku[i], u, fma_t(Kv[i], v, p[i]));
+    Bu[i] = PHu[i] - fma_t(Ku[i], suu, Kv[i] * suv);
+    Bv[i] = PHv[i] - fma_t(Ku[i], suv, Kv[i] * svv);
   }
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = i; j < 6; ++j) c[tri(i, j)] -= fma_t(Ku[i], PHu[j], Kv[i] * PHv[j]);
+    for (int j = i; j < 6; ++j)
+      c[tri(i, j)] -= fma_t(Ku[i], PHu[j], fma_t(Kv[i], PHv[j], fma_t(Bu[i], Ku[j], Bv[i] * Kv[j])));
   p[4] = wrap_phi(p[4]);
 }
 

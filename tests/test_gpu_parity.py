@@ -298,7 +298,7 @@ def test_fit_matches_oracle(mkf):
     ctx.close()
     worst = worst_graze = 0.0
     n_graze = 0
-    for t in range(0, n, 7):
+    for t in range(n):
         rest = tracks[t][3:]
         rc, p, Cm, c2 = O.fit_track(fc, init_par[t].astype(float),
                                     mkf.unpack_cov(init_cov[t]).astype(float),
