@@ -64,7 +64,7 @@ def profiled_traffic(kernel):
 def measure_kernels(mkf, w, stream, T, f):
     """Throughput of the other hot-path kernels, each from HIP events on the
     context stream around one launch after a warm-up: the search-free fit
-    (262,144 tracks x 26 layers) and the surrogate network's inference and
+    (131,072 tracks x 26 layers) and the surrogate network's inference and
     gradient (2^20 samples from its training sampler)."""
     import numpy as np
     import torch
@@ -147,9 +147,9 @@ def main():
     log(f"generated {w.name}: {batch.x.shape[0]} hits, {batch.seed_hits.shape[0]} seeds "
         f"in {time.time() - t0:.1f}s")
     fit_inputs = None
-    if args.kernels:  # generated (in worker processes) before the GPU library loads
+    if args.kernels:  # (in this process: no children under a profiler)
         from synth.fitstress import fit_stress
-        fit_inputs = fit_stress(262144, 26, workers=max(1, min(8, os.cpu_count() or 1)))
+        fit_inputs = fit_stress(131072, 26)
 
     import torch
     from paper_1811_04141_amd import mkf
