@@ -605,7 +605,7 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   HIP_TRY(c, c->d_fin_rec.ensure(sizeof(float) * 28 * N));
   HIP_TRY(c, c->d_fin_meta.ensure(4 * N));
   HIP_TRY(c, c->d_bp.ensure(4 * (size_t)kMaxPlan * kGroup * N));
-  HIP_TRY(c, c->d_pstate.ensure(sizeof(float) * 27 * N));
+  HIP_TRY(c, c->d_pstate.ensure(sizeof(float) * kSeedWords * N));
   HIP_TRY(c, c->d_pinfo.ensure(4 * N));
   HIP_TRY(c, c->d_pevent.ensure(4 * N));
   HIP_TRY(c, c->d_pplan.ensure(kMaxPlan * N));

@@ -391,11 +391,21 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
 }
 
 __device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand &cd) {
-  const size_t N = (size_t)P.n_seeds;
+  // one seed's 27 words are contiguous: seven 16-byte loads
+  const float4 *src = reinterpret_cast<const float4 *>(P.pstate + (size_t)pos * kSeedWords);
+  float w[28];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) cd.p[i] = P.pstate[i * N + pos];
+  for (int k = 0; k < 7; ++k) {
+    const float4 v = src[k];
+    w[4 * k] = v.x;
+    w[4 * k + 1] = v.y;
+    w[4 * k + 2] = v.z;
+    w[4 * k + 3] = v.w;
+  }
 #pragma unroll
-  for (int i = 0; i < 21; ++i) cd.c[i] = P.pstate[(6 + i) * N + pos];
+  for (int i = 0; i < 6; ++i) cd.p[i] = w[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) cd.c[i] = w[6 + i];
   cd.chi2 = 0.f;
   cd.nh = 3;
   cd.nm = 0;
@@ -740,7 +750,8 @@ __global__ __launch_bounds__(256) void k_permute_seeds(FindParams P, float *psta
   if (pos >= P.n_seeds) return;
   const size_t N = (size_t)P.n_seeds;
   const int seed = P.order[pos];
-  for (int i = 0; i < 27; ++i) pstate[i * N + pos] = P.seed_state[i * N + seed];
+  for (int i = 0; i < 27; ++i) pstate[(size_t)pos * kSeedWords + i] = P.seed_state[i * N + seed];
+  pstate[(size_t)pos * kSeedWords + 27] = 0.f;
   pinfo[pos] = P.plan_len[seed] | (P.seed_ok[seed] << 8);
   pevent[pos] = P.seed_event[seed];
   for (int s = 0; s < kMaxPlan; ++s)

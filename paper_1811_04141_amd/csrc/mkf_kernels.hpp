@@ -23,6 +23,7 @@ struct alignas(16) HitRec {
 // field over n_seeds * kGroup slots so that a wavefront reads 64
 // consecutive floats per field.
 constexpr int kCandFields = 29;  // 6 par + 21 cov + chi2 + meta (bit cast)
+constexpr int kSeedWords = 28;   // a seed's state in processing order (112 bytes)
 // rows of the result buffer (each n_seeds words; meta and hit are int32)
 constexpr int kOutPar = 0, kOutCov = 6, kOutChi2 = 27, kOutMeta = 28, kOutHit = 29;
 constexpr int kOutRows = kOutHit + kMaxPlan;
@@ -52,7 +53,7 @@ struct FindParams {
   const int8_t *plan;       // [n_seeds][kMaxPlan]
   const int *order;         // processing position -> seed id
   // the same, gathered once into processing order (read by the find)
-  const float *pstate;      // [27][n_seeds]
+  const float *pstate;      // [n_seeds][kSeedWords]: 6 par, 21 cov, pad
   const int *pinfo;         // [n_seeds] plan_len | ok << 8
   const int *pevent;        // [n_seeds]
   const int8_t *pplan;      // [n_seeds][kMaxPlan]
