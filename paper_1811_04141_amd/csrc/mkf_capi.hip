@@ -609,7 +609,7 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   HIP_TRY(c, c->d_pinfo.ensure(4 * N));
   HIP_TRY(c, c->d_pevent.ensure(4 * N));
   HIP_TRY(c, c->d_pplan.ensure(kMaxPlan * N));
-  HIP_TRY(c, c->d_out.ensure(sizeof(float) * kOutRows * N));
+  HIP_TRY(c, c->d_out.ensure(sizeof(float) * kOutWords * N));
   {
     FindParams Q = params(c);
     launch_permute_seeds(c->stream, Q, c->d_pstate.as<float>(), c->d_pinfo.as<int>(),
@@ -739,10 +739,10 @@ mkf_status mkf_get_tracks(mkf_ctx *c, mkf_track *out, int64_t capacity, int64_t 
   if (capacity < 0 || (capacity > 0 && !out)) return fail(c, MKF_E_ARG, "bad output buffer");
   const size_t N = (size_t)c->n_seeds;
   if (N > 0) {
-    // results are kept by processing position, in rows of N words
-    std::vector<float> res((size_t)kOutRows * N);
+    // results are kept by processing position, one record per seed
+    std::vector<float> res((size_t)kOutWords * N);
     std::vector<int8_t> plan((size_t)kMaxPlan * N);
-    HIP_TRY(c, hipMemcpyAsync(res.data(), c->d_out.ptr, sizeof(float) * kOutRows * N,
+    HIP_TRY(c, hipMemcpyAsync(res.data(), c->d_out.ptr, sizeof(float) * kOutWords * N,
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(plan.data(), c->d_plan.ptr, (size_t)kMaxPlan * N,
                               hipMemcpyDeviceToHost, c->stream));
@@ -755,10 +755,10 @@ mkf_status mkf_get_tracks(mkf_ctx *c, mkf_track *out, int64_t capacity, int64_t 
       const int plen = ok ? c->h_plen[seed] : 0;
       T.seed_id = seed;
       T.status = ok ? 1 : 0;
-      auto row = [&](int r) { return res[(size_t)r * N + pos]; };
+      auto row = [&](int r) { return res[pos * kOutWords + r]; };
       auto irow = [&](int r) {
         int32_t v;
-        std::memcpy(&v, &res[(size_t)r * N + pos], 4);
+        std::memcpy(&v, &res[pos * kOutWords + r], 4);
         return v;
       };
       const int32_t meta = irow(kOutMeta);

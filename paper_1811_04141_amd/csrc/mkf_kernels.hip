@@ -446,19 +446,25 @@ template <class Rec>
 __device__ __forceinline__ void write_result(const FindParams &P, int64_t pos, const Rec &rec,
                                              const float *p, const float *c, float chi2, int nh,
                                              int nm, int best_step, int best_slot, int plen) {
-  const size_t N = (size_t)P.n_seeds;
-  float *out = P.out + pos;
+  float *out = P.out + (size_t)pos * kOutWords;
+  float w[kOutHit];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) out[(kOutPar + i) * N] = p[i];
+  for (int i = 0; i < 6; ++i) w[kOutPar + i] = p[i];
 #pragma unroll
-  for (int i = 0; i < 21; ++i) out[(kOutCov + i) * N] = c[i];
-  out[kOutChi2 * N] = chi2;
-  out[kOutMeta * N] = __int_as_float(nh | (nm << 8));
-  for (int s = plen - 1; s > best_step; --s) out[(kOutHit + s) * N] = __int_as_float(MKF_HIT_NONE);
+  for (int i = 0; i < 21; ++i) w[kOutCov + i] = c[i];
+  w[kOutChi2] = chi2;
+  w[kOutMeta] = __int_as_float(nh | (nm << 8));
+#pragma unroll
+  for (int i = kOutMeta + 1; i < kOutHit; ++i) w[i] = 0.f;
+#pragma unroll
+  for (int k = 0; k < kOutHit / 4; ++k)
+    reinterpret_cast<float4 *>(out)[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+  int *hit = reinterpret_cast<int *>(out + kOutHit);
+  for (int s = plen - 1; s > best_step; --s) hit[s] = MKF_HIT_NONE;
   int sl = best_slot;
   for (int s = best_step; s >= 0; --s) {
     const int v = rec.get_bp(s, sl);
-    out[(kOutHit + s) * N] = __int_as_float((v >> 3) - 2);
+    hit[s] = (v >> 3) - 2;
     sl = v & 7;
   }
 }

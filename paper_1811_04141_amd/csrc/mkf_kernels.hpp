@@ -24,9 +24,11 @@ struct alignas(16) HitRec {
 // consecutive floats per field.
 constexpr int kCandFields = 29;  // 6 par + 21 cov + chi2 + meta (bit cast)
 constexpr int kSeedWords = 28;   // a seed's state in processing order (112 bytes)
-// rows of the result buffer (each n_seeds words; meta and hit are int32)
-constexpr int kOutPar = 0, kOutCov = 6, kOutChi2 = 27, kOutMeta = 28, kOutHit = 29;
-constexpr int kOutRows = kOutHit + kMaxPlan;
+// one result record per seed (processing order), kOutWords words: par[6],
+// cov[21], chi2, meta (int32 n_hits | n_miss << 8), pad, then hit[kMaxPlan]
+// (int32); 256 bytes, so a tile's records are contiguous
+constexpr int kOutPar = 0, kOutCov = 6, kOutChi2 = 27, kOutMeta = 28, kOutHit = 32;
+constexpr int kOutWords = kOutHit + kMaxPlan;
 // workgroups are dealt to the 8 XCDs of an MI355X round-robin by index
 constexpr int kQueues = 8;
 
@@ -57,8 +59,7 @@ struct FindParams {
   const int *pinfo;         // [n_seeds] plan_len | ok << 8
   const int *pevent;        // [n_seeds]
   const int8_t *pplan;      // [n_seeds][kMaxPlan]
-  // results, by processing position, rows of n_seeds words (kOut* below):
-  // par[6], cov[21], chi2, meta (n_hits | n_miss << 8), hit[kMaxPlan]
+  // results, by processing position: one kOutWords record per seed
   float *out;
   // find state
   float *cand;              // [kCandFields][n_seeds * kGroup]
