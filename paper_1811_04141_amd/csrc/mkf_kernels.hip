@@ -48,6 +48,17 @@ __device__ __forceinline__ u64 shfl_xor_u64(u64 v, int m) {
   hi = __shfl_xor(hi, m);
   return ((u64)hi << 32) | lo;
 }
+// lane i <- lane i ^ 1 and i ^ 2 within quads, by DPP (no trip through the
+// LDS crossbar)
+template <int kCtrl>
+__device__ __forceinline__ u64 dpp_u64(u64 v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, kCtrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), kCtrl, 0xF, 0xF, true);
+  return ((u64)(unsigned)hi << 32) | (u64)(unsigned)lo;
+}
+constexpr int kDppXor1 = 0xB1;  // quad_perm(1, 0, 3, 2)
+constexpr int kDppXor2 = 0x4E;  // quad_perm(2, 3, 0, 1)
+
 __device__ __forceinline__ u64 shfl_u64(u64 v, int src) {
   unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
   lo = __shfl(lo, src);
@@ -65,9 +76,9 @@ template <> struct Grp<8> {
   __device__ static int slot(int lane) { return lane & 7; }
   __device__ static int base(int lane) { return lane & ~7; }
   __device__ static u64 min(u64 v, int lane) {
-    u64 o = shfl_xor_u64(v, 1);
+    u64 o = dpp_u64<kDppXor1>(v);
     v = o < v ? o : v;
-    o = shfl_xor_u64(v, 2);
+    o = dpp_u64<kDppXor2>(v);
     v = o < v ? o : v;
     o = shfl_xor_u64(v, 4);
     return o < v ? o : v;
@@ -81,7 +92,7 @@ template <> struct Grp<6> {
   // after (whose value already includes the first pair)
   __device__ static u64 min(u64 v, int lane) {
     const int sl = lane % 6, b = lane - sl;
-    u64 o = shfl_xor_u64(v, 1);
+    u64 o = dpp_u64<kDppXor1>(v);
     v = o < v ? o : v;
     o = shfl_u64(v, b + (sl < 4 ? sl + 2 : sl - 4));
     v = o < v ? o : v;
@@ -337,6 +348,17 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
     if (slot == r) mine = m;
   }
 
+  // the kept hit's record is requested first, so that its latency overlaps
+  // the state exchange below
+  const unsigned order = mine != kKeyMax ? (unsigned)(mine & 0x7FFFFFu) : kOrderNone;
+  float4 ha = make_float4(0.f, 0.f, 0.f, 0.f);
+  float hvv = 0.f;
+  if (order != kOrderNone) {
+    const float4 *hr = reinterpret_cast<const float4 *>(P.byorig + ev_base + order);
+    ha = hr[0];
+    hvv = reinterpret_cast<const float *>(hr + 1)[0];
+  }
+
   // children read their parent's propagated state (or, for a skip, its
   // unpropagated state) across the group
   float src[27];
@@ -354,14 +376,11 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
 
   int bpv = -1;
   if (mine != kKeyMax) {
-    const unsigned order = (unsigned)(mine & 0x7FFFFFu);
     int nh = pmeta & 0xFF, nm = (pmeta >> 8) & 0xFF;
     const bool pok = (pmeta >> 16) & 1;
     int hitcode;
     if (order != kOrderNone) {
-      const float4 *hr = reinterpret_cast<const float4 *>(P.byorig + ev_base + order);
-      const float4 ha = hr[0], hb = hr[1];
-      const float hx = ha.x, hy = ha.y, hz = ha.z, vu = ha.w, vv = hb.x;
+      const float hx = ha.x, hy = ha.y, hz = ha.z, vu = ha.w, vv = hvv;
       Frame f;
       make_frame(np, np + 6, L.kind, f);
       float u, v;
