@@ -638,9 +638,29 @@ template <int kWaves, bool kSurr, int G>
 __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   __shared__ DevLayer sl[kMaxLayers];
   __shared__ unsigned long long block_steps, block_sur[2];
-  __shared__ __attribute__((aligned(16))) __bf16 sMX[kSurr ? 4 * 64 * kLdX : 1];
-  __shared__ __attribute__((aligned(16))) __bf16 sMH[kSurr ? 4 * 64 * kLdH : 1];
+  // surrogate: the network's BF16 weight images and biases, shared by the
+  // block, and one activation tile per wave (the input tile overlays it)
+  constexpr int kW1n = 64 * kLdW1, kW2n = 64 * kLdW2, kW3n = 32 * kLdW3;
+  __shared__ __attribute__((aligned(16))) __bf16 sMW[kSurr ? kW1n + kW2n + kW3n : 8];
+  __shared__ __attribute__((aligned(16))) float sMB[kSurr ? 64 + 64 + 32 : 4];
+  __shared__ __attribute__((aligned(16))) __bf16 sMH[kSurr ? 4 * 64 * kLdH : 8];
   stage_layers(P, sl);
+  MlpWeights mw{};
+  if constexpr (kSurr) {
+    const int4 *g1 = reinterpret_cast<const int4 *>(P.mlp.W1p);
+    const int4 *g2 = reinterpret_cast<const int4 *>(P.mlp.W2p);
+    const int4 *g3 = reinterpret_cast<const int4 *>(P.mlp.W3p);
+    int4 *d = reinterpret_cast<int4 *>(sMW);
+    for (int i = threadIdx.x; i < kW1n / 8; i += blockDim.x) d[i] = g1[i];
+    for (int i = threadIdx.x; i < kW2n / 8; i += blockDim.x) d[kW1n / 8 + i] = g2[i];
+    for (int i = threadIdx.x; i < kW3n / 8; i += blockDim.x) d[(kW1n + kW2n) / 8 + i] = g3[i];
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+      sMB[i] = P.mlp.b1[i];
+      sMB[64 + i] = P.mlp.b2[i];
+      if (i < 32) sMB[128 + i] = P.mlp.b3[i];
+    }
+    mw = MlpWeights{sMW, sMW + kW1n, sMW + kW1n + kW2n, nullptr, nullptr, sMB, sMB + 64, sMB + 128};
+  }
   if (threadIdx.x == 0) {
     block_steps = 0;
     block_sur[0] = block_sur[1] = 0;
@@ -724,8 +744,8 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
           const int cnt = __popcll(m);
           const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-          __bf16 *X = sMX + wv * 64 * kLdX;
           __bf16 *H = sMH + wv * 64 * kLdH;
+          __bf16 *X = H;  // the input tile overlays the activation tile
           if (want) {
             bf16x8 xv, zv;
 #pragma unroll
@@ -740,11 +760,11 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
           float y0;
           if (cnt <= 32) {
             f32x16 y[1][1];
-            mlp_forward_tiles<1>(P.mlp, X, H, y);
+            mlp_forward_tiles<1>(mw, X, H, y);
             y0 = mlp_output<1>(y, rank & 31, 0);
           } else {
             f32x16 y[1][2];
-            mlp_forward_tiles<2>(P.mlp, X, H, y);
+            mlp_forward_tiles<2>(mw, X, H, y);
             y0 = mlp_output<2>(y, rank, 0);
           }
           wave_sync();  // the tiles are rewritten at the next step

@@ -159,7 +159,7 @@ __device__ __forceinline__ void store_act(const f32x16 (&acc)[MT][NT], __bf16 *o
 
 // Forward pass of the first 32 NT samples of the wave's tiles; X is the
 // sample-major input tile (k 0..7 inputs, 8..15 zero), H a [64][kLdH]
-// scratch tile.  y receives the output layer's accumulators: output j of
+// scratch tile (X may lie inside H).  y receives the output layer's accumulators: output j of
 // sample s is column s % 32 of tile s / 32, row j (see mlp_output).
 template <int NT>
 __device__ __forceinline__ void mlp_forward_tiles(const MlpWeights &w, const __bf16 *X, __bf16 *H,
@@ -167,6 +167,7 @@ __device__ __forceinline__ void mlp_forward_tiles(const MlpWeights &w, const __b
   {
     f32x16 acc[2][NT];
     gemm_w_act<2, 1, NT>(w.W1p, kLdW1, X, kLdX, w.b1, acc);
+    wave_sync();  // X may overlay H: every lane has read it before h1 is stored
     store_act<2, true, NT>(acc, H, kLdH);
   }
   wave_sync();
