@@ -750,3 +750,112 @@ int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36], i
   *chi2_sum = sum;
   return 0;
 }
+
+/* ------------------------------------------------------- backward fit */
+
+/* The same helix run the other way: the track of the opposite charge
+ * moving in the opposite direction, q/pT -> -q/pT, phi -> phi + pi,
+ * theta -> pi - theta.  The map is linear in the parameters it changes, so
+ * the covariance becomes D C D with D = diag(1, 1, 1, -1, 1, -1). */
+void orc_flip(double p[6], double C[36]) {
+  p[3] = -p[3];
+  p[4] = wrap_phi(p[4] + M_PI);
+  p[5] = M_PI - p[5];
+  if (!C) return;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      int si = (i == 3 || i == 5), sj = (j == 3 || j == 5);
+      if (si != sj) C[i * 6 + j] = -C[i * 6 + j];
+    }
+}
+
+/* Backward fit of a found track (the layer plan's flags for layers used
+ * only when fitting backwards, Section 2.1; the Kalman filter of the
+ * Introduction run in the reverse order).  Reading: the surfaces are the
+ * crossed plan layers (hit or miss) from the last to the first, then the
+ * three seed layers from the third to the first; the filter starts at the
+ * first of them from the track's final state with the seed fit's wide
+ * diagonal prior, less its extent along that surface's normal (the state
+ * lies on the surface), and runs the seed fit's loop over them: propagate (from
+ * the second surface on, on the reversed helix, without extent test), add
+ * the layer's scattering, update with the surface's hit if it has one.
+ * Returns 1 with the state on the first seed layer, 0 for a track whose
+ * seed fit failed, -k when propagation to (or the update on) the k-th
+ * surface failed. */
+int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
+                     const float *x, const float *y, const float *z, const float *var_u,
+                     const float *var_v, const int32_t *layer, const int32_t seed_hits[3],
+                     const orc_track *trk, double p_out[6], double C_out[36], double *chi2_sum,
+                     int32_t *n_updates) {
+  memset(p_out, 0, 6 * sizeof(double));
+  memset(C_out, 0, 36 * sizeof(double));
+  *chi2_sum = 0.0;
+  *n_updates = 0;
+  if (!trk->seed_ok) return 0;
+  int32_t lay[ORC_MAX_PLAN + 3], hit[ORC_MAX_PLAN + 3];
+  int n = 0;
+  for (int s = trk->plan_len - 1; s >= 0; --s) {
+    if (trk->hit[s] < ORC_HIT_MISS) continue; /* not crossed, or after the end */
+    lay[n] = trk->plan[s];
+    hit[n] = trk->hit[s];
+    ++n;
+  }
+  for (int j = 2; j >= 0; --j) {
+    lay[n] = layer[seed_hits[j]];
+    hit[n] = seed_hits[j];
+    ++n;
+  }
+  double p[6], C[36], sum = 0.0;
+  memcpy(p, trk->par, sizeof(p));
+  memset(C, 0, sizeof(C));
+  for (int i = 0; i < 6; ++i) C[i * 6 + i] = cfg->init_var[i];
+  if (lay[0] < 0 || lay[0] >= n_layers) return -1;
+  {
+    /* the state lies on the first surface: its prior has no extent along
+     * the surface normal (P C P^T with P = 1 - n n^T on the position) */
+    double nv[3] = {0.0, 0.0, 1.0};
+    if (layers[lay[0]].kind == 0) {
+      double r = hypot(p[0], p[1]);
+      nv[0] = p[0] / r;
+      nv[1] = p[1] / r;
+      nv[2] = 0.0;
+    }
+    double P[36], T[36], Pt[36];
+    memset(P, 0, sizeof(P));
+    for (int i = 0; i < 6; ++i) P[i * 6 + i] = 1.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[i * 6 + j] -= nv[i] * nv[j];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) Pt[i * 6 + j] = P[j * 6 + i];
+    matmul6(P, C, T);
+    matmul6(T, Pt, C);
+  }
+  int nu = 0;
+  for (int k = 0; k < n; ++k) {
+    if (lay[k] < 0 || lay[k] >= n_layers) return -(k + 1);
+    const orc_layer *Lr = &layers[lay[k]];
+    if (k > 0) {
+      double pp[6], Cp[36];
+      orc_flip(p, C);
+      if (orc_propagate(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL) !=
+          ORC_OK)
+        return -(k + 1);
+      orc_flip(pp, Cp);
+      memcpy(p, pp, sizeof(pp));
+      memcpy(C, Cp, sizeof(Cp));
+    }
+    orc_add_ms(p, cfg->ms_sigma, C);
+    if (hit[k] >= 0) {
+      const double h[3] = {x[hit[k]], y[hit[k]], z[hit[k]]};
+      double c2;
+      if (!orc_update_hit(p, C, Lr->kind, h, var_u[hit[k]], var_v[hit[k]], &c2)) return -(k + 1);
+      sum += c2;
+      ++nu;
+    }
+  }
+  memcpy(p_out, p, sizeof(p));
+  memcpy(C_out, C, sizeof(C));
+  *chi2_sum = sum;
+  *n_updates = nu;
+  return 1;
+}

@@ -161,6 +161,21 @@ int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36],
                   const double *var_v, double p_out[6], double C_out[36],
                   double *chi2_sum);
 
+/* Reverse the direction of motion on the same helix (q/pT, phi + pi,
+ * pi - theta); C (may be NULL) becomes D C D, D = diag(1,1,1,-1,1,-1). */
+void orc_flip(double p[6], double C[36]);
+
+/* Backward fit of one found track of an event: the Kalman filter over its
+ * hits in reverse order (crossed plan layers last to first, then the seed
+ * layers third to first), from its final state with the seed prior.
+ * Returns 1 (state on the first seed layer), 0 (seed fit failed) or -k
+ * (surface k of the reversed sequence not reached or its update failed). */
+int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
+                     const float *x, const float *y, const float *z, const float *var_u,
+                     const float *var_v, const int32_t *layer, const int32_t seed_hits[3],
+                     const orc_track *trk, double p_out[6], double C_out[36], double *chi2_sum,
+                     int32_t *n_updates);
+
 #ifdef __cplusplus
 }
 #endif

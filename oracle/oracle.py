@@ -90,6 +90,9 @@ def lib():
                                      C.POINTER(Track)]
         L.orc_fit_track.argtypes = [C.POINTER(Cfg), _D, _D, C.c_int32, _I, _D, _D, _D, _D, _D,
                                     _D, _D]
+        L.orc_flip.argtypes = [_D, _D]
+        L.orc_backward_fit.argtypes = [C.POINTER(Cfg), C.POINTER(Layer), C.c_int32, _F, _F, _F,
+                                       _F, _F, _I, _I, C.POINTER(Track), _D, _D, _D, _I]
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
         L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
         L.orc_mlp_grad.restype = C.c_double
@@ -287,3 +290,40 @@ def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v):
     rc = lib().orc_fit_track(C.byref(cfg), _p(p0), _p(C0), n, _p(kinds, _I), _p(pos), _p(hits),
                              _p(var_u), _p(var_v), _p(po), _p(Co), _p(c2))
     return rc, po, Co.reshape(6, 6), float(c2[0])
+
+
+def flip(p, Cm=None):
+    """The same helix traversed the other way (q/pT, phi + pi, pi - theta)."""
+    p = _d(p, 6).copy()
+    if Cm is None:
+        lib().orc_flip(_p(p), None)
+        return p
+    Cm = _d(Cm, 36).copy()
+    lib().orc_flip(_p(p), _p(Cm))
+    return p, Cm.reshape(6, 6)
+
+
+def backward_fit(fc, layers, ev, seed_hits, trk):
+    """Backward fit of one found track of event ev (a find_event result
+    dict, or any dict with seed_ok, plan, hit, par).  Returns (status, par,
+    cov 6x6, chi2, n_updates)."""
+    cfg = make_cfg(fc)
+    lay = make_layers(layers)
+    t = Track()
+    t.seed_ok = int(bool(trk["seed_ok"]))
+    plan = np.asarray(trk["plan"], np.int32)
+    hit = np.asarray(trk["hit"], np.int32)
+    t.plan_len = int(plan.shape[0])
+    for i in range(t.plan_len):
+        t.plan[i] = int(plan[i])
+        t.hit[i] = int(hit[i])
+    for i in range(6):
+        t.par[i] = float(trk["par"][i])
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z, ev.var_u, ev.var_v)]
+    layer = np.ascontiguousarray(ev.layer, np.int32)
+    sh = np.ascontiguousarray(seed_hits, np.int32).reshape(3)
+    po, Co, c2, nu = np.zeros(6), np.zeros(36), np.zeros(1), np.zeros(1, np.int32)
+    st = lib().orc_backward_fit(C.byref(cfg), lay, len(layers), *[_p(a, _F) for a in arrs],
+                                _p(layer, _I), _p(sh, _I), C.byref(t), _p(po), _p(Co), _p(c2),
+                                _p(nu, _I))
+    return int(st), po, Co.reshape(6, 6), float(c2[0]), int(nu[0])
