@@ -196,6 +196,27 @@ mkf_status mkf_fit(mkf_ctx *ctx, int64_t n_tracks, int32_t n_steps, const int8_t
                    const float *init_par, const float *init_cov, float *out_par,
                    float *out_cov, float *out_chi2, int32_t *out_status);
 
+/* Backward fit of the tracks of the last mkf_find (the layer plan's
+ * steering carries layers used only when fitting backwards, Section 2.1;
+ * the filter is the Kalman filter of the Introduction run in the reverse
+ * order).  For every seed: the track's crossed plan layers (hit or
+ * MKF_HIT_MISS) from the last to the first, then its three seed layers
+ * from the third to the first.  The filter starts on the first of these
+ * surfaces from the track's final state with the seed prior cfg.init_var
+ * less its extent along the surface normal, and on every surface
+ * propagates (from the second on, backwards along the helix, no extent
+ * test), adds cfg.ms_sigma scattering and updates with the surface's hit
+ * if it has one.  Device outputs in seed order: out_par [n_seeds][6] and
+ * out_cov [n_seeds][21] (state on the first seed layer), out_chi2
+ * [n_seeds] (sum over all the track's hits), out_status [n_seeds] (1 ok;
+ * 0 the seed fit failed; -k: the k-th surface was not reached or its hit
+ * lies in the other half of the layer; outputs zero unless 1).  The first
+ * three hits are filtered in FP64 (they shrink the wide prior), the rest
+ * in FP32.  Asynchronous on the context's stream; the caller owns the
+ * outputs.  MKF_E_ORDER before a find. */
+mkf_status mkf_backward_fit(mkf_ctx *ctx, float *out_par, float *out_cov, float *out_chi2,
+                            int32_t *out_status);
+
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);
 

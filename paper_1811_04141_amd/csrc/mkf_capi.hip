@@ -814,6 +814,18 @@ mkf_status mkf_fit(mkf_ctx *c, int64_t n_tracks, int32_t n_steps, const int8_t *
   return MKF_OK;
 }
 
+mkf_status mkf_backward_fit(mkf_ctx *c, float *out_par, float *out_cov, float *out_chi2,
+                            int32_t *out_status) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kFound) return fail(c, MKF_E_ORDER, "find first");
+  if (c->n_seeds > 0 && (!out_par || !out_cov || !out_chi2 || !out_status))
+    return fail(c, MKF_E_ARG, "NULL output array");
+  FindParams P = params(c);
+  launch_backfit(c->stream, P, c->d_seed_hits.as<int>(), out_par, out_cov, out_chi2, out_status);
+  HIP_TRY(c, hipGetLastError());
+  return MKF_OK;
+}
+
 mkf_status mkf_get_stats(mkf_ctx *c, mkf_stats *out) {
   if (!c || !out) return MKF_E_ARG;
   *out = c->stats;

@@ -1120,6 +1120,193 @@ __global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
   out_status[i] = status;
 }
 
+// ---------------------------------------------------------- backward fit
+//
+// The layer plan's steering marks layers used only when a track is fitted
+// backwards (Section 2.1).  A found track is fitted backwards by the same
+// Kalman filter (Introduction) run over its hits in the reverse order: its
+// crossed plan layers from the last to the first, then its three seed
+// layers from the third to the first.  The filter starts at the first of
+// these surfaces from the track's final state, with the seed prior less its
+// extent along that surface's normal, and on every surface it propagates
+// (from the second on), adds the layer's scattering and takes the hit if
+// the surface has one.  Backward propagation is forward propagation of the
+// reversed helix (opposite charge, opposite direction).
+
+// q/pT -> -q/pT, phi -> phi + pi, theta -> pi - theta; the covariance
+// becomes D C D with D = diag(1, 1, 1, -1, 1, -1)
+template <typename T>
+__device__ __forceinline__ void flip_state(T *p, T *c) {
+  p[3] = -p[3];
+  p[4] = p[4] > T(0) ? p[4] - Consts<T>::pi() : p[4] + Consts<T>::pi();
+  p[5] = Consts<T>::pi() - p[5];
+  c[tri(0, 3)] = -c[tri(0, 3)];
+  c[tri(1, 3)] = -c[tri(1, 3)];
+  c[tri(2, 3)] = -c[tri(2, 3)];
+  c[tri(3, 4)] = -c[tri(3, 4)];
+  c[tri(0, 5)] = -c[tri(0, 5)];
+  c[tri(1, 5)] = -c[tri(1, 5)];
+  c[tri(2, 5)] = -c[tri(2, 5)];
+  c[tri(4, 5)] = -c[tri(4, 5)];
+}
+
+// The prior on the first surface: diag(init_var) less its extent along the
+// surface normal n, i.e. P D P^T with P = 1 - n n^T on the position block
+// (the other blocks of the diagonal prior are unchanged).
+template <typename T>
+__device__ __forceinline__ void surface_prior(const DevCfg &cfg, const T *p, int kind, T *c) {
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c[tri(k, k)] = T(cfg.init_var[k]);
+  T nv[3] = {T(0), T(0), T(1)};
+  if (kind == 0) {
+    const T r = sqrt_t(p[0] * p[0] + p[1] * p[1]);
+    nv[0] = p[0] / r;
+    nv[1] = p[1] / r;
+    nv[2] = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      T a = T(0);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const T pim = (i == m ? T(1) : T(0)) - nv[i] * nv[m];
+        const T pjm = (j == m ? T(1) : T(0)) - nv[j] * nv[m];
+        a += pim * T(cfg.init_var[m]) * pjm;
+      }
+      c[tri(i, j)] = a;
+    }
+}
+
+// One surface of the backward fit: propagate the reversed helix to it
+// (except on the first), add its scattering, take its hit (code >= 0).
+// Returns false if the surface is not reached or the hit lies in the
+// other half of the layer.
+template <typename T>
+__device__ __forceinline__ bool backfit_surface(const FindParams &P, const DevLayer &L,
+                                                bool first, int code, int64_t ev_base, T *p,
+                                                T *c, float &chi2) {
+  if (first) {
+    surface_prior(P.cfg, p, L.kind, c);
+  } else {
+    flip_state(p, c);
+    PropT<T> pr;
+    if (propagate<true, T>(p, c, L, T(P.cfg.mkb), T(P.cfg.l_min), false, T(0), pr) != kOk)
+      return false;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) p[m] = pr.p[m];
+#pragma unroll
+    for (int m = 0; m < 21; ++m) c[m] = pr.c[m];
+    flip_state(p, c);
+  }
+  add_ms(p, T(P.cfg.ms_var), c);
+  if (code >= 0) {
+    const HitRec h = P.byorig[ev_base + code];
+    FrameT<T> f;
+    make_frame(p, c, L.kind, f);
+    T u, v;
+    if (!residual(p, f, L.kind, T(h.x), T(h.y), T(h.z), u, v)) return false;
+    chi2 += fmaxf((float)chi2_of(f, T(h.vu), T(h.vv), u, v), 0.f);
+    kf_update(p, c, f, L.kind, T(h.vu), T(h.vv), u, v);
+  }
+  return true;
+}
+
+// one lane per seed (processing position); results by seed id.  As in the
+// seed fit, the wide prior is filtered through the first three hits in
+// FP64 (they shrink it by ~5 decades, more than FP32 keeps in the
+// covariance update); the rest of the track runs in FP32.
+__global__ __launch_bounds__(256) void k_backfit(FindParams P, const int *seed_hits,
+                                                 float *out_par, float *out_cov,
+                                                 float *out_chi2, int *out_status) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const int seed = P.order[pos];
+  const int info = P.pinfo[pos];
+  const int plen = info & 0xFF;
+  float p[6], c[21];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = 0.f;
+  float chi2 = 0.f;
+  int status = 0;
+  if ((info >> 8) & 1) {
+    const float *row = P.out + (size_t)pos * kOutWords;
+    const int *hit = reinterpret_cast<const int *>(row + kOutHit);
+    const int8_t *plan = P.pplan + (size_t)pos * kMaxPlan;
+    const int ev = P.pevent[pos];
+    const int64_t ev_base = P.ev_off[ev];
+    const int64_t ev_hits = P.ev_off[ev + 1] - ev_base;
+    const int *sh = seed_hits + (size_t)seed * 3;
+    double pd[6], cd[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pd[k] = row[kOutPar + k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cd[k] = 0.0;
+    status = 1;
+    int k = 0, taken = 0;
+    // surface of index t: plan step t - 3 for t >= 3, seed hit t below;
+    // returns false for a plan step the track did not cross
+    auto surface = [&](int t, int &lid, int &code) {
+      if (t >= 3) {
+        code = hit[t - 3];
+        lid = plan[t - 3];
+        return code >= MKF_HIT_MISS;  // not crossed, or after the track ended
+      }
+      code = sh[t];
+      lid = P.hlayer[ev_base + code];
+      return true;
+    };
+    int t = plen + 2;
+    for (; t >= 0 && taken < 3; --t) {
+      int lid, code;
+      if (!surface(t, lid, code)) continue;
+      if (lid < 0 || lid >= P.n_layers || code >= ev_hits ||
+          !backfit_surface<double>(P, sl[lid], k == 0, code, ev_base, pd, cd, chi2)) {
+        status = -(k + 1);
+        break;
+      }
+      taken += code >= 0;
+      ++k;
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) p[m] = (float)pd[m];
+#pragma unroll
+    for (int m = 0; m < 21; ++m) c[m] = (float)cd[m];
+    for (; status == 1 && t >= 0; --t) {
+      int lid, code;
+      if (!surface(t, lid, code)) continue;
+      if (lid < 0 || lid >= P.n_layers || code >= ev_hits ||
+          !backfit_surface<float>(P, sl[lid], k == 0, code, ev_base, p, c, chi2)) {
+        status = -(k + 1);
+        break;
+      }
+      ++k;
+    }
+    if (status != 1) {
+      // a failed fit reports no state
+#pragma unroll
+      for (int m = 0; m < 6; ++m) p[m] = 0.f;
+#pragma unroll
+      for (int m = 0; m < 21; ++m) c[m] = 0.f;
+      chi2 = 0.f;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out_par[(size_t)seed * 6 + k] = p[k];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) out_cov[(size_t)seed * 21 + k] = c[k];
+  out_chi2[seed] = chi2;
+  out_status[seed] = status;
+}
+
 __global__ __launch_bounds__(256) void k_validate_hits(int64_t n, const float *x, const float *y,
                                                        const float *z, const float *vu,
                                                        const float *vv, const int *layer,
@@ -1252,6 +1439,13 @@ void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const 
   hipLaunchKernelGGL(k_fit, dim3(blocks_for(n, 256)), dim3(256), 0, s, cfg, n, n_steps, kind, pos,
                      x, y, z, vu, vv, len, init_par, init_cov, out_par, out_cov, out_chi2,
                      out_status);
+}
+
+void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, float *out_par,
+                    float *out_cov, float *out_chi2, int *out_status) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_backfit, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, seed_hits,
+                     out_par, out_cov, out_chi2, out_status);
 }
 
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,

@@ -24,7 +24,7 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_get_stats", "mkf_set_tuning", "mkf_get_tuning", "mkf_autotune",
+           "mkf_fit", "mkf_backward_fit", "mkf_get_stats", "mkf_set_tuning", "mkf_get_tuning", "mkf_autotune",
            "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
 
@@ -101,6 +101,7 @@ def _load():
         "mkf_get_tracks": ([P, P, I64, C.POINTER(I64)], I32),
         "mkf_propagate": ([P, I64, P, P, P, P, P, P, P], I32),
         "mkf_fit": ([P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P], I32),
+        "mkf_backward_fit": ([P, P, P, P, P], I32),
         "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
         "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
@@ -235,6 +236,12 @@ class Context:
                                 _ptr(z), _ptr(var_u), _ptr(var_v), _ptr(length), _ptr(init_par),
                                 _ptr(init_cov), _ptr(out_par), _ptr(out_cov), _ptr(out_chi2),
                                 _ptr(out_status)))
+
+    def backward_fit(self, out_par, out_cov, out_chi2, out_status):
+        """Backward fit of the last find's tracks into device arrays (seed
+        order): out_par [n][6], out_cov [n][21], out_chi2 [n], out_status [n]."""
+        self._check(lib.mkf_backward_fit(self.h, _ptr(out_par), _ptr(out_cov), _ptr(out_chi2),
+                                         _ptr(out_status)))
 
     def set_tuning(self, waves_per_simd, blocks_per_cu):
         self._check(lib.mkf_set_tuning(self.h, C.byref(Tuning(waves_per_simd, blocks_per_cu))))
