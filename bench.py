@@ -98,10 +98,11 @@ def cpu_baseline(w, batch, seconds, workers):
                       f"brute-force hit scan)"}
 
 
-def measure_kernels(mkf, w, stream, T, f):
+def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
     """Throughput of the other hot-path kernels, each from HIP events on the
     context stream around one launch after a warm-up: the search-free fit
-    (131,072 tracks x 26 layers) and the surrogate network's inference and
+    (131,072 tracks x 26 layers), the backward fit of the benchmark
+    workload's found tracks, and the surrogate network's inference and
     gradient (2^20 samples from its training sampler)."""
     import numpy as np
     import torch
@@ -135,8 +136,27 @@ def measure_kernels(mkf, w, stream, T, f):
         out["k_fit"] = dict(alu(FIT_FLOPS_PER_UPDATE * n * k, ms, FP32_VECTOR_PEAK_TFLOPS, n * k,
                                 "track-layer updates/s"), bound="alu",
                             workload=f"{n} tracks x {k} layers")
-        m = 1 << 20
+        # backward fit of the tracks found in the benchmark workload,
+        # counted by its updates (one per hit, the seed hits included; the
+        # propagations through layers without a hit are not counted)
+        ctx2 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+        ctx2.load_geometry(w.layers)
+        ctx2.load_hits(batch.ev_off, *hits)
+        ctx2.seed(*seeds)
+        ctx2.find()
+        ns = batch.seed_hits.shape[0]
+        tr = ctx2.get_tracks(ns)
         dev = ins[0].device
+        bouts = [torch.zeros((ns, 6), device=dev), torch.zeros((ns, 21), device=dev),
+                 torch.zeros(ns, device=dev), torch.zeros(ns, dtype=torch.int32, device=dev)]
+        ms = timed(lambda: ctx2.backward_fit(*bouts))
+        ok = bouts[3].cpu().numpy() == 1
+        upd = int(tr["n_hits"][ok].sum())
+        out["k_backfit"] = dict(alu(FIT_FLOPS_PER_UPDATE * upd, ms, FP32_VECTOR_PEAK_TFLOPS, upd,
+                                    "track-hit updates/s"), bound="alu",
+                                workload=f"{int(ok.sum())} found tracks, {upd} hits")
+        ctx2.close()
+        m = 1 << 20
         x = torch.zeros((m, 8), device=dev)
         t = torch.zeros((m, 7), device=dev)
         v = torch.zeros(m, device=dev)
@@ -290,7 +310,8 @@ def main():
     roof["traffic"] = profiled_traffic(roof["kernel"])
     roof["avg_launch_ms"] = per_launch_ms
 
-    kernels = measure_kernels(mkf, w, stream, T, fit_inputs) if args.kernels else None
+    kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, hits, seeds)
+               if args.kernels else None)
 
     cpu = None
     if args.cpu_seconds > 0:

@@ -1215,59 +1215,59 @@ __device__ __forceinline__ bool backfit_surface(const FindParams &P, const DevLa
   return true;
 }
 
-// one lane per seed (processing position); results by seed id.  As in the
-// seed fit, the wide prior is filtered through the first three hits in
-// FP64 (they shrink it by ~5 decades, more than FP32 keeps in the
-// covariance update); the rest of the track runs in FP32.
-__global__ __launch_bounds__(256) void k_backfit(FindParams P, const int *seed_hits,
-                                                 float *out_par, float *out_cov,
-                                                 float *out_chi2, int *out_status) {
+// Surface t of a track's backward sequence: plan step t - 3 for t >= 3,
+// seed hit t below.  False for a plan step the track did not cross.
+__device__ __forceinline__ bool backfit_seq(const FindParams &P, const int *hit,
+                                            const int8_t *plan, const int *sh, int64_t ev_base,
+                                            int t, int &lid, int &code) {
+  if (t >= 3) {
+    code = hit[t - 3];
+    lid = plan[t - 3];
+    return code >= MKF_HIT_MISS;  // not crossed, or after the track ended
+  }
+  code = sh[t];
+  lid = P.hlayer[ev_base + code];
+  return true;
+}
+
+// Carried from the FP64 head to the FP32 tail, per processing position:
+// state and covariance (27 words), chi2, then status, surfaces done and the
+// next sequence index as integers.
+constexpr int kBfWords = 32;
+
+// Head, one lane per seed: as in the seed fit, the wide prior is filtered
+// through the track's first three hits in FP64 (they shrink it by ~5
+// decades, more than FP32 keeps in the covariance update).
+__global__ __launch_bounds__(256) void k_backfit_head(FindParams P, const int *seed_hits,
+                                                      float *tmp) {
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
   __syncthreads();
   const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pos >= P.n_seeds) return;
-  const int seed = P.order[pos];
   const int info = P.pinfo[pos];
   const int plen = info & 0xFF;
-  float p[6], c[21];
+  double pd[6], cd[21];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) p[k] = 0.f;
+  for (int k = 0; k < 6; ++k) pd[k] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 21; ++k) c[k] = 0.f;
+  for (int k = 0; k < 21; ++k) cd[k] = 0.0;
   float chi2 = 0.f;
-  int status = 0;
+  int status = 0, k = 0, t = -1;
   if ((info >> 8) & 1) {
     const float *row = P.out + (size_t)pos * kOutWords;
     const int *hit = reinterpret_cast<const int *>(row + kOutHit);
     const int8_t *plan = P.pplan + (size_t)pos * kMaxPlan;
-    const int ev = P.pevent[pos];
-    const int64_t ev_base = P.ev_off[ev];
-    const int64_t ev_hits = P.ev_off[ev + 1] - ev_base;
-    const int *sh = seed_hits + (size_t)seed * 3;
-    double pd[6], cd[21];
+    const int64_t ev_base = P.ev_off[P.pevent[pos]];
+    const int64_t ev_hits = P.ev_off[P.pevent[pos] + 1] - ev_base;
+    const int *sh = seed_hits + (size_t)P.order[pos] * 3;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pd[k] = row[kOutPar + k];
-#pragma unroll
-    for (int k = 0; k < 21; ++k) cd[k] = 0.0;
+    for (int m = 0; m < 6; ++m) pd[m] = row[kOutPar + m];
     status = 1;
-    int k = 0, taken = 0;
-    // surface of index t: plan step t - 3 for t >= 3, seed hit t below;
-    // returns false for a plan step the track did not cross
-    auto surface = [&](int t, int &lid, int &code) {
-      if (t >= 3) {
-        code = hit[t - 3];
-        lid = plan[t - 3];
-        return code >= MKF_HIT_MISS;  // not crossed, or after the track ended
-      }
-      code = sh[t];
-      lid = P.hlayer[ev_base + code];
-      return true;
-    };
-    int t = plen + 2;
-    for (; t >= 0 && taken < 3; --t) {
+    int taken = 0;
+    for (t = plen + 2; t >= 0 && taken < 3; --t) {
       int lid, code;
-      if (!surface(t, lid, code)) continue;
+      if (!backfit_seq(P, hit, plan, sh, ev_base, t, lid, code)) continue;
       if (lid < 0 || lid >= P.n_layers || code >= ev_hits ||
           !backfit_surface<double>(P, sl[lid], k == 0, code, ev_base, pd, cd, chi2)) {
         status = -(k + 1);
@@ -1276,13 +1276,64 @@ __global__ __launch_bounds__(256) void k_backfit(FindParams P, const int *seed_h
       taken += code >= 0;
       ++k;
     }
+  }
+  float w[kBfWords];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) p[m] = (float)pd[m];
+  for (int m = 0; m < 6; ++m) w[m] = (float)pd[m];
 #pragma unroll
-    for (int m = 0; m < 21; ++m) c[m] = (float)cd[m];
-    for (; status == 1 && t >= 0; --t) {
+  for (int m = 0; m < 21; ++m) w[6 + m] = (float)cd[m];
+  w[27] = chi2;
+  w[28] = __int_as_float(status);
+  w[29] = __int_as_float(k);
+  w[30] = __int_as_float(t);
+  w[31] = 0.f;
+  float4 *dst = reinterpret_cast<float4 *>(tmp + (size_t)pos * kBfWords);
+#pragma unroll
+  for (int q = 0; q < kBfWords / 4; ++q)
+    dst[q] = make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// Tail, one lane per seed: the rest of the sequence in FP32; results by
+// seed id (a failed fit reports zeros).
+__global__ __launch_bounds__(256) void k_backfit_tail(FindParams P, const int *seed_hits,
+                                                      const float *tmp, float *out_par,
+                                                      float *out_cov, float *out_chi2,
+                                                      int *out_status) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const int seed = P.order[pos];
+  float w[kBfWords];
+  const float4 *src = reinterpret_cast<const float4 *>(tmp + (size_t)pos * kBfWords);
+#pragma unroll
+  for (int q = 0; q < kBfWords / 4; ++q) {
+    const float4 v = src[q];
+    w[4 * q] = v.x;
+    w[4 * q + 1] = v.y;
+    w[4 * q + 2] = v.z;
+    w[4 * q + 3] = v.w;
+  }
+  float p[6], c[21];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) p[m] = w[m];
+#pragma unroll
+  for (int m = 0; m < 21; ++m) c[m] = w[6 + m];
+  float chi2 = w[27];
+  int status = __float_as_int(w[28]);
+  int k = __float_as_int(w[29]);
+  int t = __float_as_int(w[30]);
+  if (status == 1) {
+    const float *row = P.out + (size_t)pos * kOutWords;
+    const int *hit = reinterpret_cast<const int *>(row + kOutHit);
+    const int8_t *plan = P.pplan + (size_t)pos * kMaxPlan;
+    const int64_t ev_base = P.ev_off[P.pevent[pos]];
+    const int64_t ev_hits = P.ev_off[P.pevent[pos] + 1] - ev_base;
+    const int *sh = seed_hits + (size_t)seed * 3;
+    for (; t >= 0; --t) {
       int lid, code;
-      if (!surface(t, lid, code)) continue;
+      if (!backfit_seq(P, hit, plan, sh, ev_base, t, lid, code)) continue;
       if (lid < 0 || lid >= P.n_layers || code >= ev_hits ||
           !backfit_surface<float>(P, sl[lid], k == 0, code, ev_base, p, c, chi2)) {
         status = -(k + 1);
@@ -1290,19 +1341,18 @@ __global__ __launch_bounds__(256) void k_backfit(FindParams P, const int *seed_h
       }
       ++k;
     }
-    if (status != 1) {
-      // a failed fit reports no state
+  }
+  if (status != 1) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m) p[m] = 0.f;
+    for (int m = 0; m < 6; ++m) p[m] = 0.f;
 #pragma unroll
-      for (int m = 0; m < 21; ++m) c[m] = 0.f;
-      chi2 = 0.f;
-    }
+    for (int m = 0; m < 21; ++m) c[m] = 0.f;
+    chi2 = 0.f;
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) out_par[(size_t)seed * 6 + k] = p[k];
+  for (int m = 0; m < 6; ++m) out_par[(size_t)seed * 6 + m] = p[m];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) out_cov[(size_t)seed * 21 + k] = c[k];
+  for (int m = 0; m < 21; ++m) out_cov[(size_t)seed * 21 + m] = c[m];
   out_chi2[seed] = chi2;
   out_status[seed] = status;
 }
@@ -1441,11 +1491,13 @@ void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const 
                      out_status);
 }
 
-void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, float *out_par,
-                    float *out_cov, float *out_chi2, int *out_status) {
+void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, float *tmp,
+                    float *out_par, float *out_cov, float *out_chi2, int *out_status) {
   if (P.n_seeds == 0) return;
-  hipLaunchKernelGGL(k_backfit, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, seed_hits,
-                     out_par, out_cov, out_chi2, out_status);
+  hipLaunchKernelGGL(k_backfit_head, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     seed_hits, tmp);
+  hipLaunchKernelGGL(k_backfit_tail, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     seed_hits, tmp, out_par, out_cov, out_chi2, out_status);
 }
 
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,

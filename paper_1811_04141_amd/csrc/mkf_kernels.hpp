@@ -103,8 +103,9 @@ void launch_finalize(hipStream_t s, const FindParams &P);
 void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,
                       const float *cov, const int *layer, float *out_par, float *out_cov,
                       float *out_l, int *out_status);
-void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, float *out_par,
-                    float *out_cov, float *out_chi2, int *out_status);
+// backward fit: tmp holds 32 words per seed between its FP64 head and FP32 tail
+void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, float *tmp,
+                    float *out_par, float *out_cov, float *out_chi2, int *out_status);
 void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const int8_t *kind,
                 const float *pos, const float *x, const float *y, const float *z,
                 const float *vu, const float *vv, const int *len, const float *init_par,
