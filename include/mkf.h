@@ -217,6 +217,24 @@ mkf_status mkf_fit(mkf_ctx *ctx, int64_t n_tracks, int32_t n_steps, const int8_t
 mkf_status mkf_backward_fit(mkf_ctx *ctx, float *out_par, float *out_cov, float *out_chi2,
                             int32_t *out_status);
 
+/* Rauch-Tung-Striebel smoothing of the tracks of the last mkf_find (the
+ * backward pass the layer plan's steering provides for, Section 2.1,
+ * applied to the Kalman filter of the Introduction).  Surfaces of a track:
+ * the seed's third layer (where the find starts), then every plan layer the
+ * track crossed (hit or MKF_HIT_MISS), in plan order.  The forward pass is
+ * the find's filter along the track in FP32 (propagate, add cfg.ms_sigma
+ * scattering, update with the hit if there is one); the backward pass
+ * forms xs(k) = x(k) + A (xs(k+1) - xp(k+1)), Cs(k) = C(k) + A (Cs(k+1) -
+ * Cp(k+1)) A^T, A = C(k) F^T Cp(k+1)^-1, in FP64 with the inverse taken in
+ * the five free coordinates of surface k+1.  Device outputs in seed order:
+ * out_par [n_seeds][MKF_MAX_PLAN + 1][6], out_cov [n_seeds][MKF_MAX_PLAN +
+ * 1][21] (the first out_n entries of a seed are written), out_n [n_seeds]
+ * (surfaces; 0 the seed fit failed; -1 a propagation or hit update failed;
+ * -2 a predicted covariance was not positive definite on its surface).
+ * Device scratch: 364 bytes per surface and seed, held by the context.
+ * Asynchronous on the context's stream.  MKF_E_ORDER before a find. */
+mkf_status mkf_smooth(mkf_ctx *ctx, float *out_par, float *out_cov, int32_t *out_n);
+
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);
 

@@ -393,6 +393,33 @@ int orc_update_hit(double p[6], double C[36], int kind, const double hit[3],
   return 1;
 }
 
+/* ------------------------------------------------------------- priors */
+
+/* The wide diagonal prior diag(init_var) for a state that lies on a layer:
+ * less its extent along the layer's normal n at p (a state on a surface has
+ * no freedom there), C = P diag(init_var) P^T with P = 1 - n n^T on the
+ * position. */
+static void surface_prior(const orc_cfg *cfg, const double p[6], int kind, double C[36]) {
+  memset(C, 0, 36 * sizeof(double));
+  for (int i = 0; i < 6; ++i) C[i * 6 + i] = cfg->init_var[i];
+  double nv[3] = {0.0, 0.0, 1.0};
+  if (kind == 0) {
+    double r = hypot(p[0], p[1]);
+    nv[0] = p[0] / r;
+    nv[1] = p[1] / r;
+    nv[2] = 0.0;
+  }
+  double P[36], T[36], Pt[36];
+  memset(P, 0, sizeof(P));
+  for (int i = 0; i < 6; ++i) P[i * 6 + i] = 1.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[i * 6 + j] -= nv[i] * nv[j];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) Pt[i * 6 + j] = P[j * 6 + i];
+  matmul6(P, C, T);
+  matmul6(T, Pt, C);
+}
+
 /* ------------------------------------------------------------ seeding */
 
 static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
@@ -405,9 +432,10 @@ static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
  * radius rho; the turning sense gives the charge; pT = kappa |B| rho; phi
  * is the tangent at the first hit in the direction of motion; cot(theta)
  * is the z rise over the transverse arc from the first to the third hit.
- * The state starts at the first hit with a wide diagonal prior and is filtered
- * through the three hits (propagate, scatter, update), ending on the third
- * seed layer.  The layer plan (the paper's per-region list of layers to
+ * The state starts at the first hit with a wide diagonal prior, less its
+ * extent along the first seed layer's normal (the state lies on that layer),
+ * and is filtered through the three hits (propagate, scatter, update),
+ * ending on the third seed layer.  The layer plan (the paper's per-region list of layers to
  * traverse, Section 2.1) is read per seed: every non-seed layer the seed
  * helix crosses inside its widened extent in the remaining half turn,
  * ordered by path length. */
@@ -441,8 +469,7 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
 
   double p[6] = {x1, y1, z1, ipt, phi1, theta};
   double C[36];
-  memset(C, 0, sizeof(C));
-  for (int i = 0; i < 6; ++i) C[i * 6 + i] = cfg->init_var[i];
+  surface_prior(cfg, p, layers[hl[0]].kind, C);
 
   for (int k = 0; k < 3; ++k) {
     const orc_layer *Lr = &layers[hl[k]];
@@ -774,9 +801,8 @@ void orc_flip(double p[6], double C[36]) {
  * Introduction run in the reverse order).  Reading: the surfaces are the
  * crossed plan layers (hit or miss) from the last to the first, then the
  * three seed layers from the third to the first; the filter starts at the
- * first of them from the track's final state with the seed fit's wide
- * diagonal prior, less its extent along that surface's normal (the state
- * lies on the surface), and runs the seed fit's loop over them: propagate (from
+ * first of them from the track's final state with the seed fit's prior on
+ * that surface, and runs the seed fit's loop over them: propagate (from
  * the second surface on, on the reversed helix, without extent test), add
  * the layer's scattering, update with the surface's hit if it has one.
  * Returns 1 with the state on the first seed layer, 0 for a track whose
@@ -807,29 +833,8 @@ int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
   }
   double p[6], C[36], sum = 0.0;
   memcpy(p, trk->par, sizeof(p));
-  memset(C, 0, sizeof(C));
-  for (int i = 0; i < 6; ++i) C[i * 6 + i] = cfg->init_var[i];
   if (lay[0] < 0 || lay[0] >= n_layers) return -1;
-  {
-    /* the state lies on the first surface: its prior has no extent along
-     * the surface normal (P C P^T with P = 1 - n n^T on the position) */
-    double nv[3] = {0.0, 0.0, 1.0};
-    if (layers[lay[0]].kind == 0) {
-      double r = hypot(p[0], p[1]);
-      nv[0] = p[0] / r;
-      nv[1] = p[1] / r;
-      nv[2] = 0.0;
-    }
-    double P[36], T[36], Pt[36];
-    memset(P, 0, sizeof(P));
-    for (int i = 0; i < 6; ++i) P[i * 6 + i] = 1.0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) P[i * 6 + j] -= nv[i] * nv[j];
-    for (int i = 0; i < 6; ++i)
-      for (int j = 0; j < 6; ++j) Pt[i * 6 + j] = P[j * 6 + i];
-    matmul6(P, C, T);
-    matmul6(T, Pt, C);
-  }
+  surface_prior(cfg, p, layers[lay[0]].kind, C);
   int nu = 0;
   for (int k = 0; k < n; ++k) {
     if (lay[k] < 0 || lay[k] >= n_layers) return -(k + 1);
@@ -858,4 +863,140 @@ int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
   *chi2_sum = sum;
   *n_updates = nu;
   return 1;
+}
+
+/* ---------------------------------------------------------- smoothing */
+
+/* Inverse of a general n x n matrix by Gauss-Jordan elimination with
+ * partial pivoting; 0 if singular. */
+static int inv_gauss(int n, const double *A, double *Ai) {
+  double M[6][12];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      M[i][j] = A[i * n + j];
+      M[i][n + j] = i == j ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (M[piv][c] == 0.0) return 0;
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) {
+        double t = M[c][j];
+        M[c][j] = M[piv][j];
+        M[piv][j] = t;
+      }
+    double d = M[c][c];
+    for (int j = 0; j < 2 * n; ++j) M[c][j] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = M[r][c];
+      for (int j = 0; j < 2 * n; ++j) M[r][j] -= f * M[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ai[i * n + j] = M[i][n + j];
+  return 1;
+}
+
+/* Rauch-Tung-Striebel smoothing of a found track (the second half of the
+ * backward pass the layer plan's steering provides for, Section 2.1; the
+ * filter is the Kalman filter of the Introduction).  Surfaces: the seed's
+ * third layer, where the find starts from the seed fit's state, then the
+ * plan layers the track crossed (hit or miss), in plan order.  Forward:
+ * the find's filter along the track (propagate, add the layer's
+ * scattering, update with the hit if there is one), keeping on every
+ * surface the filtered state x(k), C(k), the predicted state xp(k), Cp(k)
+ * after scattering and the transport Jacobian F(k) from the previous
+ * surface.  Backward, from the last surface where the smoothed state is
+ * the filtered one:
+ *   A = C(k) F(k+1)^T Cp(k+1)^-1,
+ *   xs(k) = x(k) + A (xs(k+1) - xp(k+1)),
+ *   Cs(k) = C(k) + A (Cs(k+1) - Cp(k+1)) A^T.
+ * Cp(k+1) has no extent along the normal n of its surface and every vector
+ * it is applied to lies in the surface, so its inverse is taken as that of
+ * Cp + s n n^T (s: the largest position variance), which is the same there.
+ * Outputs (up to ORC_MAX_PLAN + 1 surfaces): the layer id of each surface,
+ * the smoothed states [k][6] and covariances [k][36].  Returns the number
+ * of surfaces, 0 for a track whose seed fit failed, -1 on a failed
+ * propagation or update, -2 on a singular predicted covariance. */
+int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
+                     const float *x, const float *y, const float *z, const float *var_u,
+                     const float *var_v, int32_t seed_layer, const double seed_par[6],
+                     const double seed_cov[36], const orc_track *trk, int32_t *surf_layer,
+                     double *par_out, double *cov_out) {
+  if (!trk->seed_ok) return 0;
+  enum { NS = ORC_MAX_PLAN + 1 };
+  double xf[NS][6], Cf[NS][36], xp[NS][6], Cpr[NS][36], F[NS][36];
+  int n = 1;
+  memcpy(xf[0], seed_par, sizeof(xf[0]));
+  memcpy(Cf[0], seed_cov, sizeof(Cf[0]));
+  surf_layer[0] = seed_layer;
+  for (int s = 0; s < trk->plan_len; ++s) {
+    int code = trk->hit[s];
+    if (code < ORC_HIT_MISS) continue;
+    int L = trk->plan[s];
+    if (L < 0 || L >= n_layers) return -1;
+    const orc_layer *Lr = &layers[L];
+    double pp[6], Cp[36];
+    if (orc_propagate(xf[n - 1], Cf[n - 1], Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp,
+                      F[n], NULL) != ORC_OK)
+      return -1;
+    orc_add_ms(pp, cfg->ms_sigma, Cp);
+    memcpy(xp[n], pp, sizeof(pp));
+    memcpy(Cpr[n], Cp, sizeof(Cp));
+    if (code >= 0) {
+      const double h[3] = {x[code], y[code], z[code]};
+      double c2;
+      if (!orc_update_hit(pp, Cp, Lr->kind, h, var_u[code], var_v[code], &c2)) return -1;
+    }
+    memcpy(xf[n], pp, sizeof(pp));
+    memcpy(Cf[n], Cp, sizeof(Cp));
+    surf_layer[n] = L;
+    ++n;
+  }
+  memcpy(&par_out[6 * (n - 1)], xf[n - 1], sizeof(xf[0]));
+  memcpy(&cov_out[36 * (n - 1)], Cf[n - 1], sizeof(Cf[0]));
+  for (int k = n - 2; k >= 0; --k) {
+    const double *xs1 = &par_out[6 * (k + 1)], *Cs1 = &cov_out[36 * (k + 1)];
+    /* the predicted covariance on surface k+1, made invertible along n */
+    double nv[3] = {0.0, 0.0, 1.0};
+    if (layers[surf_layer[k + 1]].kind == 0) {
+      double r = hypot(xp[k + 1][0], xp[k + 1][1]);
+      nv[0] = xp[k + 1][0] / r;
+      nv[1] = xp[k + 1][1] / r;
+      nv[2] = 0.0;
+    }
+    double S[36], Si[36];
+    memcpy(S, Cpr[k + 1], sizeof(S));
+    double sc = fmax(S[0], fmax(S[7], S[14]));
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) S[i * 6 + j] += sc * nv[i] * nv[j];
+    if (!inv_gauss(6, S, Si)) return -2;
+    /* A = C(k) F^T S^-1 */
+    double Ft[36], CFt[36], A[36];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) Ft[i * 6 + j] = F[k + 1][j * 6 + i];
+    matmul6(Cf[k], Ft, CFt);
+    matmul6(CFt, Si, A);
+    double d[6];
+    for (int i = 0; i < 6; ++i) d[i] = xs1[i] - xp[k + 1][i];
+    d[4] = wrap_phi(d[4]);
+    double *xs = &par_out[6 * k], *Cs = &cov_out[36 * k];
+    for (int i = 0; i < 6; ++i) {
+      double a = xf[k][i];
+      for (int j = 0; j < 6; ++j) a += A[i * 6 + j] * d[j];
+      xs[i] = a;
+    }
+    xs[4] = wrap_phi(xs[4]);
+    double D[36], AD[36], At[36], ADAt[36];
+    for (int i = 0; i < 36; ++i) D[i] = Cs1[i] - Cpr[k + 1][i];
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) At[i * 6 + j] = A[j * 6 + i];
+    matmul6(A, D, AD);
+    matmul6(AD, At, ADAt);
+    for (int i = 0; i < 36; ++i) Cs[i] = Cf[k][i] + ADAt[i];
+  }
+  return n;
 }

@@ -176,6 +176,19 @@ int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
                      const orc_track *trk, double p_out[6], double C_out[36], double *chi2_sum,
                      int32_t *n_updates);
 
+/* Rauch-Tung-Striebel smoothing of one found track: on the seed's third
+ * layer (seed_layer, starting from the seed fit's seed_par, seed_cov) and
+ * on every plan layer the track crossed, the state given all its hits.
+ * Writes surf_layer [n], par_out [n][6], cov_out [n][36] with n <=
+ * ORC_MAX_PLAN + 1 and returns n; 0 if the seed fit failed, -1 if a
+ * propagation or update failed, -2 if a predicted covariance is singular
+ * on its surface. */
+int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
+                     const float *x, const float *y, const float *z, const float *var_u,
+                     const float *var_v, int32_t seed_layer, const double seed_par[6],
+                     const double seed_cov[36], const orc_track *trk, int32_t *surf_layer,
+                     double *par_out, double *cov_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,8 @@ def lib():
         L.orc_flip.argtypes = [_D, _D]
         L.orc_backward_fit.argtypes = [C.POINTER(Cfg), C.POINTER(Layer), C.c_int32, _F, _F, _F,
                                        _F, _F, _I, _I, C.POINTER(Track), _D, _D, _D, _I]
+        L.orc_smooth_track.argtypes = [C.POINTER(Cfg), C.POINTER(Layer), C.c_int32, _F, _F, _F,
+                                       _F, _F, C.c_int32, _D, _D, C.POINTER(Track), _I, _D, _D]
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
         L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
         L.orc_mlp_grad.restype = C.c_double
@@ -327,3 +329,37 @@ def backward_fit(fc, layers, ev, seed_hits, trk):
                                 _p(layer, _I), _p(sh, _I), C.byref(t), _p(po), _p(Co), _p(c2),
                                 _p(nu, _I))
     return int(st), po, Co.reshape(6, 6), float(c2[0]), int(nu[0])
+
+
+def _track_struct(trk):
+    t = Track()
+    t.seed_ok = int(bool(trk["seed_ok"]))
+    plan = np.asarray(trk["plan"], np.int32)
+    hit = np.asarray(trk["hit"], np.int32)
+    t.plan_len = int(plan.shape[0])
+    for i in range(t.plan_len):
+        t.plan[i] = int(plan[i])
+        t.hit[i] = int(hit[i])
+    for i in range(6):
+        t.par[i] = float(trk["par"][i])
+    return t
+
+
+def smooth_track(fc, layers, ev, seed_layer, seed_par, seed_cov, trk):
+    """RTS smoothing of one found track of event ev, starting from the seed
+    state (seed_par, seed_cov 6x6) on seed_layer.  Returns (n, layers [n],
+    par [n][6], cov [n][6][6]); n <= 0 on failure."""
+    cfg = make_cfg(fc)
+    lay = make_layers(layers)
+    t = _track_struct(trk)
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z, ev.var_u, ev.var_v)]
+    sp, sc = _d(seed_par, 6), _d(seed_cov, 36)
+    ns = MAX_PLAN + 1
+    sl = np.zeros(ns, np.int32)
+    po, Co = np.zeros(6 * ns), np.zeros(36 * ns)
+    n = lib().orc_smooth_track(C.byref(cfg), lay, len(layers), *[_p(a, _F) for a in arrs],
+                               int(seed_layer), _p(sp), _p(sc), C.byref(t), _p(sl, _I), _p(po),
+                               _p(Co))
+    m = max(n, 0)
+    return (int(n), sl[:m].copy(), po.reshape(ns, 6)[:m].copy(),
+            Co.reshape(ns, 6, 6)[:m].copy())

@@ -72,6 +72,7 @@ struct mkf_ctx {
   DevBuf d_seed_event, d_seed_hits, d_seed_state, d_seed_ok, d_plan_len, d_plan, d_plan_l;
   DevBuf d_order, d_pstate, d_pinfo, d_pevent, d_pplan;
   DevBuf d_bf_tmp;  // backward fit: state between its FP64 and FP32 parts
+  DevBuf d_sm_wk, d_sm_n;  // smoothing: forward-pass states per surface, surface counts
   std::vector<int32_t> h_order, h_plen, h_ok;
   std::vector<int64_t> active_at_step;  // seeds (in processing order) with plan_len > step
   int max_plan_len = 0;
@@ -103,7 +104,7 @@ struct mkf_ctx {
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
                      &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
-                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp};
+                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -825,6 +826,21 @@ mkf_status mkf_backward_fit(mkf_ctx *c, float *out_par, float *out_cov, float *o
   FindParams P = params(c);
   launch_backfit(c->stream, P, c->d_seed_hits.as<int>(), c->d_bf_tmp.as<float>(), out_par,
                  out_cov, out_chi2, out_status);
+  HIP_TRY(c, hipGetLastError());
+  return MKF_OK;
+}
+
+mkf_status mkf_smooth(mkf_ctx *c, float *out_par, float *out_cov, int32_t *out_n) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kFound) return fail(c, MKF_E_ORDER, "find first");
+  if (c->n_seeds > 0 && (!out_par || !out_cov || !out_n))
+    return fail(c, MKF_E_ARG, "NULL output array");
+  const size_t N = (size_t)std::max<int64_t>(c->n_seeds, 1);
+  HIP_TRY(c, c->d_sm_wk.ensure(sizeof(float) * 91 * (size_t)(c->max_plan_len + 1) * N));
+  HIP_TRY(c, c->d_sm_n.ensure(sizeof(int) * N));
+  FindParams P = params(c);
+  launch_smooth(c->stream, P, c->d_seed_hits.as<int>(), c->d_sm_wk.as<float>(),
+                c->d_sm_n.as<int>(), out_par, out_cov, out_n);
   HIP_TRY(c, hipGetLastError());
   return MKF_OK;
 }

@@ -171,11 +171,14 @@ using Prop = PropT<float>;
 // marks the first crossing; otherwise the closed form below is used, so the
 // result never depends on the quality of the hint.  *sur (if given)
 // receives 1 if the hint was kept, 2 if not.
-template <bool kWantCov, typename T>
+//
+// kWantFC: fc receives F C, 6x6 row-major (the cross-covariance of the
+// start and end states, which smoothing needs).
+template <bool kWantCov, typename T, bool kWantFC = false>
 __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__restrict__ c,
                                          const DevLayer &L, T mkb, T l_min, bool check_extent,
                                          T edge_margin, PropT<T> &o, T l_hint = T(0),
-                                         int *sur = nullptr) {
+                                         int *sur = nullptr, T *fc = nullptr) {
   const T w = mkb * p[3];
   T sphi, cphi;
   sincos_t(p[4], &sphi, &cphi);
@@ -334,6 +337,11 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
     Ai[5] = Bi[5];
 #pragma unroll
     for (int j = i; j < 6; ++j) o.c[tri(i, j)] = Ai[j] - t[i] * g[j] - g[i] * t[j] + s * t[i] * t[j];
+    if constexpr (kWantFC) {
+      // F C = D C - t (C k)^T; on a disk the z row vanishes identically
+#pragma unroll
+      for (int j = 0; j < 6; ++j) fc[i * 6 + j] = (L.kind == 1 && i == 2) ? T(0) : Bi[j] - t[i] * hk[j];
+    }
   }
   if (L.kind == 1) {
     // on a disk z is exact: its row and column vanish identically, so drop
@@ -342,6 +350,39 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
     for (int j = 0; j < 6; ++j) o.c[j < 2 ? tri(j, 2) : tri(2, j)] = T(0);
   }
   return kOk;
+}
+
+// The wide diagonal prior diag(init_var) of a state that lies on a layer
+// (a seed's first hit, a backward fit's first surface), less its extent
+// along the layer's normal n at p: a state on a surface has no freedom
+// there.  P D P^T with P = 1 - n n^T on the position block (the other
+// blocks of the diagonal prior are unchanged).
+template <typename T>
+__device__ __forceinline__ void surface_prior(const DevCfg &cfg, const T *p, int kind, T *c) {
+#pragma unroll
+  for (int k = 0; k < 21; ++k) c[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c[tri(k, k)] = T(cfg.init_var[k]);
+  T nv[3] = {T(0), T(0), T(1)};
+  if (kind == 0) {
+    const T r = sqrt_t(p[0] * p[0] + p[1] * p[1]);
+    nv[0] = p[0] / r;
+    nv[1] = p[1] / r;
+    nv[2] = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      T a = T(0);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const T pim = (i == m ? T(1) : T(0)) - nv[i] * nv[m];
+        const T pjm = (j == m ? T(1) : T(0)) - nv[j] * nv[m];
+        a += pim * T(cfg.init_var[m]) * pjm;
+      }
+      c[tri(i, j)] = a;
+    }
 }
 
 // Scattering noise of one crossed layer, added to the (q/pT, phi, theta)

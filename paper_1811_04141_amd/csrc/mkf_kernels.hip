@@ -888,8 +888,7 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     const double dpsi = atan2(r1x * r3y - r1y * r3x, r1x * r3x + r1y * r3y);
     const double theta = atan2(rho * fabs(dpsi), hz[2] - hz[0]);
     p[0] = hx[0]; p[1] = hy[0]; p[2] = hz[0]; p[3] = ipt; p[4] = phi1; p[5] = theta;
-    for (int k = 0; k < 21; ++k) c[k] = 0.0;
-    for (int k = 0; k < 6; ++k) c[tri(k, k)] = P.cfg.init_var[k];
+    surface_prior(P.cfg, p, sl[hl[0]].kind, c);
     bool good = true;
     for (int k = 0; k < 3 && good; ++k) {
       const DevLayer &L = sl[hl[k]];
@@ -1150,37 +1149,6 @@ __device__ __forceinline__ void flip_state(T *p, T *c) {
   c[tri(4, 5)] = -c[tri(4, 5)];
 }
 
-// The prior on the first surface: diag(init_var) less its extent along the
-// surface normal n, i.e. P D P^T with P = 1 - n n^T on the position block
-// (the other blocks of the diagonal prior are unchanged).
-template <typename T>
-__device__ __forceinline__ void surface_prior(const DevCfg &cfg, const T *p, int kind, T *c) {
-#pragma unroll
-  for (int k = 0; k < 21; ++k) c[k] = T(0);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) c[tri(k, k)] = T(cfg.init_var[k]);
-  T nv[3] = {T(0), T(0), T(1)};
-  if (kind == 0) {
-    const T r = sqrt_t(p[0] * p[0] + p[1] * p[1]);
-    nv[0] = p[0] / r;
-    nv[1] = p[1] / r;
-    nv[2] = T(0);
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i; j < 3; ++j) {
-      T a = T(0);
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const T pim = (i == m ? T(1) : T(0)) - nv[i] * nv[m];
-        const T pjm = (j == m ? T(1) : T(0)) - nv[j] * nv[m];
-        a += pim * T(cfg.init_var[m]) * pjm;
-      }
-      c[tri(i, j)] = a;
-    }
-}
-
 // One surface of the backward fit: propagate the reversed helix to it
 // (except on the first), add its scattering, take its hit (code >= 0).
 // Returns false if the surface is not reached or the hit lies in the
@@ -1357,6 +1325,286 @@ __global__ __launch_bounds__(256) void k_backfit_tail(FindParams P, const int *s
   out_status[seed] = status;
 }
 
+// ------------------------------------------------------------- smoothing
+//
+// Rauch-Tung-Striebel smoothing of the found tracks (the backward pass the
+// layer plan's steering provides for, Section 2.1, applied to the Kalman
+// filter of the Introduction): on the seed's third layer and on every plan
+// layer a track crossed, its state given all its hits.
+// * Forward (k_smooth_fwd, FP32): the find's filter along the track from the
+//   seed state (propagate, add the layer's scattering, update with the hit
+//   if there is one), keeping per surface the filtered state x, C, the
+//   predicted state xp, Cp after scattering and F C (F: the transport from
+//   the previous surface, C: the filtered covariance there).
+// * Backward (k_smooth_bwd, FP64): from the last surface, where the smoothed
+//   state is the filtered one,
+//     xs(k) = x(k) + A (xs(k+1) - xp(k+1)),
+//     Cs(k) = C(k) + A (Cs(k+1) - Cp(k+1)) A^T,   A = C(k) F^T Cp(k+1)^-1.
+//   Cp(k+1) has no extent along its surface's normal and every vector it
+//   meets lies in the surface, so the inverse is taken in the surface's five
+//   free coordinates J: A = (J F C)^T (J Cp J^T)^-1 J, with a Cholesky
+//   factor of J Cp J^T.
+
+// per surface, SoA over positions: filtered 27, predicted 27, F C 36, layer
+constexpr int kSmFields = 91;
+constexpr int kSmFilt = 0, kSmPred = 27, kSmFC = 54, kSmLayer = 90;
+
+__global__ __launch_bounds__(256) void k_smooth_fwd(FindParams P, const int *seed_hits,
+                                                    float *wk, int *n_surf) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const size_t N = (size_t)P.n_seeds;
+  auto at = [&](int j, int f) -> float & { return wk[((size_t)j * kSmFields + f) * N + pos]; };
+  const int info = P.pinfo[pos];
+  const int plen = info & 0xFF;
+  int n = 0;
+  if ((info >> 8) & 1) {
+    const float *row = P.out + (size_t)pos * kOutWords;
+    const int *hit = reinterpret_cast<const int *>(row + kOutHit);
+    const int8_t *plan = P.pplan + (size_t)pos * kMaxPlan;
+    const int64_t ev_base = P.ev_off[P.pevent[pos]];
+    const int64_t ev_hits = P.ev_off[P.pevent[pos] + 1] - ev_base;
+    const int *sh = seed_hits + (size_t)P.order[pos] * 3;
+    float p[6], c[21];
+    const float *st = P.pstate + (size_t)pos * kSeedWords;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) p[m] = st[m];
+#pragma unroll
+    for (int m = 0; m < 21; ++m) c[m] = st[6 + m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) at(0, kSmFilt + m) = p[m];
+#pragma unroll
+    for (int m = 0; m < 21; ++m) at(0, kSmFilt + 6 + m) = c[m];
+    at(0, kSmLayer) = __int_as_float(P.hlayer[ev_base + sh[2]]);
+    n = 1;
+    for (int s = 0; s < plen; ++s) {
+      const int code = hit[s];
+      if (code < MKF_HIT_MISS) continue;  // not crossed, or after the track ended
+      const int lid = plan[s];
+      if (lid < 0 || lid >= P.n_layers || code >= ev_hits) {
+        n = -1;
+        break;
+      }
+      const DevLayer &L = sl[lid];
+      Prop pr;
+      float fc[36];
+      if (propagate<true, float, true>(p, c, L, P.cfg.mkb, P.cfg.l_min, false, 0.f, pr, 0.f,
+                                       nullptr, fc) != kOk) {
+        n = -1;
+        break;
+      }
+      add_ms(pr.p, P.cfg.ms_var, pr.c);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) at(n, kSmPred + m) = pr.p[m];
+#pragma unroll
+      for (int m = 0; m < 21; ++m) at(n, kSmPred + 6 + m) = pr.c[m];
+#pragma unroll
+      for (int m = 0; m < 36; ++m) at(n, kSmFC + m) = fc[m];
+      if (code >= 0) {
+        const HitRec h = P.byorig[ev_base + code];
+        Frame f;
+        make_frame(pr.p, pr.c, L.kind, f);
+        float u, v;
+        if (!residual(pr.p, f, L.kind, h.x, h.y, h.z, u, v)) {
+          n = -1;
+          break;
+        }
+        kf_update(pr.p, pr.c, f, L.kind, h.vu, h.vv, u, v);
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) p[m] = pr.p[m];
+#pragma unroll
+      for (int m = 0; m < 21; ++m) c[m] = pr.c[m];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) at(n, kSmFilt + m) = p[m];
+#pragma unroll
+      for (int m = 0; m < 21; ++m) at(n, kSmFilt + 6 + m) = c[m];
+      at(n, kSmLayer) = __int_as_float(lid);
+      ++n;
+    }
+  }
+  n_surf[pos] = n;
+}
+
+// the surface's five free coordinates: u0 = a0 v0 + a1 v1 (barrel: along
+// the azimuth; disk: x), u1 = b0 v0 + b1 v1 + b2 v2 (barrel: z; disk: y),
+// u2..u4 = q/pT, phi, theta
+struct FreeCoords {
+  double a0, a1, b0, b1, b2;
+  __device__ void apply(const double *v, double *u) const {
+    u[0] = a0 * v[0] + a1 * v[1];
+    u[1] = b0 * v[0] + b1 * v[1] + b2 * v[2];
+    u[2] = v[3];
+    u[3] = v[4];
+    u[4] = v[5];
+  }
+};
+
+// solve (L L^T) x = b in place, L lower-triangular 5x5 packed by rows
+__device__ __forceinline__ void chol_solve5(const double *Lp, double *b) {
+  double y[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double a = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) a -= Lp[i * (i + 1) / 2 + k] * y[k];
+    y[i] = a / Lp[i * (i + 1) / 2 + i];
+  }
+#pragma unroll
+  for (int i = 4; i >= 0; --i) {
+    double a = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 5; ++k) a -= Lp[k * (k + 1) / 2 + i] * b[k];
+    b[i] = a / Lp[i * (i + 1) / 2 + i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_smooth_bwd(FindParams P, const float *wk,
+                                                    const int *n_surf, float *out_par,
+                                                    float *out_cov, int *out_n) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const size_t N = (size_t)P.n_seeds;
+  auto at = [&](int j, int f) { return wk[((size_t)j * kSmFields + f) * N + pos]; };
+  const int seed = P.order[pos];
+  int n = n_surf[pos];
+  float *op = out_par + (size_t)seed * (kMaxPlan + 1) * 6;
+  float *oc = out_cov + (size_t)seed * (kMaxPlan + 1) * 21;
+  if (n > 0) {
+    double xs[6], Cs[21];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) xs[m] = at(n - 1, kSmFilt + m);
+#pragma unroll
+    for (int m = 0; m < 21; ++m) Cs[m] = at(n - 1, kSmFilt + 6 + m);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) op[(n - 1) * 6 + m] = (float)xs[m];
+#pragma unroll
+    for (int m = 0; m < 21; ++m) oc[(n - 1) * 21 + m] = (float)Cs[m];
+    for (int k = n - 2; k >= 0; --k) {
+      // surface k+1: its free coordinates at the predicted point
+      double xp[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) xp[m] = at(k + 1, kSmPred + m);
+      const int lid = __float_as_int(at(k + 1, kSmLayer));
+      FreeCoords J;
+      if (P.layers[lid].kind == 0) {
+        const double r = sqrt(xp[0] * xp[0] + xp[1] * xp[1]);
+        J = FreeCoords{-xp[1] / r, xp[0] / r, 0.0, 0.0, 1.0};
+      } else {
+        J = FreeCoords{1.0, 0.0, 0.0, 1.0, 0.0};
+      }
+      // Sr = J Cp J^T and dPr = J (Cs - Cp) J^T, column by column
+      double Sr[15], dPr[15];
+      {
+        double JCp[5][6], JdP[5][6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          double col[6], dcol[6];
+#pragma unroll
+          for (int i = 0; i < 6; ++i) {
+            const double cp = at(k + 1, kSmPred + 6 + (i <= j ? tri(i, j) : tri(j, i)));
+            col[i] = cp;
+            dcol[i] = Cs[i <= j ? tri(i, j) : tri(j, i)] - cp;
+          }
+          double u[5], du[5];
+          J.apply(col, u);
+          J.apply(dcol, du);
+#pragma unroll
+          for (int a = 0; a < 5; ++a) {
+            JCp[a][j] = u[a];
+            JdP[a][j] = du[a];
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+          double u[5], du[5];
+          J.apply(JCp[a], u);
+          J.apply(JdP[a], du);
+#pragma unroll
+          for (int b = 0; b <= a; ++b) {
+            Sr[a * (a + 1) / 2 + b] = u[b];
+            dPr[a * (a + 1) / 2 + b] = du[b];
+          }
+        }
+      }
+      // Cholesky factor of Sr in place
+      bool pd = true;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+          double a = Sr[i * (i + 1) / 2 + j];
+#pragma unroll
+          for (int q = 0; q < j; ++q) a -= Sr[i * (i + 1) / 2 + q] * Sr[j * (j + 1) / 2 + q];
+          if (i == j) {
+            pd = pd && a > 0.0;
+            Sr[i * (i + 1) / 2 + i] = sqrt(a > 0.0 ? a : 1.0);
+          } else {
+            Sr[i * (i + 1) / 2 + j] = a / Sr[j * (j + 1) / 2 + j];
+          }
+        }
+      }
+      if (!pd) {
+        n = -2;
+        break;
+      }
+      // u = Sr^-1 J (xs - xp)
+      double d[6], u[5];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) d[m] = xs[m] - xp[m];
+      d[4] = wrap_phi(d[4]);
+      J.apply(d, u);
+      chol_solve5(Sr, u);
+      // M = J F C (5 x 6), one column at a time; xs(k) = x(k) + M^T u and
+      // W = Sr^-1 M
+      double W[5][6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double col[6], w[5];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) col[i] = at(k + 1, kSmFC + i * 6 + j);
+        J.apply(col, w);
+        double a = at(k, kSmFilt + j);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a += w[q] * u[q];
+        xs[j] = a;
+        chol_solve5(Sr, w);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) W[q][j] = w[q];
+      }
+      xs[4] = wrap_phi(xs[4]);
+      // Cs(k) = C(k) + W^T dPr W
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double t[5];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+          double v = 0.0;
+#pragma unroll
+          for (int b = 0; b < 5; ++b)
+            v += dPr[a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a] * W[b][i];
+          t[a] = v;
+        }
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+          double v = at(k, kSmFilt + 6 + tri(i, j));
+#pragma unroll
+          for (int a = 0; a < 5; ++a) v += t[a] * W[a][j];
+          Cs[tri(i, j)] = v;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) op[k * 6 + m] = (float)xs[m];
+#pragma unroll
+      for (int m = 0; m < 21; ++m) oc[k * 21 + m] = (float)Cs[m];
+    }
+  }
+  out_n[seed] = n;
+}
+
 __global__ __launch_bounds__(256) void k_validate_hits(int64_t n, const float *x, const float *y,
                                                        const float *z, const float *vu,
                                                        const float *vv, const int *layer,
@@ -1498,6 +1746,15 @@ void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, fl
                      seed_hits, tmp);
   hipLaunchKernelGGL(k_backfit_tail, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
                      seed_hits, tmp, out_par, out_cov, out_chi2, out_status);
+}
+
+void launch_smooth(hipStream_t s, const FindParams &P, const int *seed_hits, float *wk,
+                   int *n_surf, float *out_par, float *out_cov, int *out_n) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_smooth_fwd, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     seed_hits, wk, n_surf);
+  hipLaunchKernelGGL(k_smooth_bwd, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, wk,
+                     n_surf, out_par, out_cov, out_n);
 }
 
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,

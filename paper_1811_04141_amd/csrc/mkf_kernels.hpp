@@ -106,6 +106,10 @@ void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float
 // backward fit: tmp holds 32 words per seed between its FP64 head and FP32 tail
 void launch_backfit(hipStream_t s, const FindParams &P, const int *seed_hits, float *tmp,
                     float *out_par, float *out_cov, float *out_chi2, int *out_status);
+// smoothing: wk holds 91 words per surface and seed (max_plan + 1 surfaces),
+// n_surf one int per seed
+void launch_smooth(hipStream_t s, const FindParams &P, const int *seed_hits, float *wk,
+                   int *n_surf, float *out_par, float *out_cov, int *out_n);
 void launch_fit(hipStream_t s, const DevCfg &cfg, int64_t n, int n_steps, const int8_t *kind,
                 const float *pos, const float *x, const float *y, const float *z,
                 const float *vu, const float *vv, const int *len, const float *init_par,

@@ -24,8 +24,8 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_backward_fit", "mkf_get_stats", "mkf_set_tuning", "mkf_get_tuning", "mkf_autotune",
-           "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
+           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_get_stats", "mkf_set_tuning",
+           "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
 
 
@@ -102,6 +102,7 @@ def _load():
         "mkf_propagate": ([P, I64, P, P, P, P, P, P, P], I32),
         "mkf_fit": ([P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P], I32),
         "mkf_backward_fit": ([P, P, P, P, P], I32),
+        "mkf_smooth": ([P, P, P, P], I32),
         "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
         "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
@@ -242,6 +243,12 @@ class Context:
         order): out_par [n][6], out_cov [n][21], out_chi2 [n], out_status [n]."""
         self._check(lib.mkf_backward_fit(self.h, _ptr(out_par), _ptr(out_cov), _ptr(out_chi2),
                                          _ptr(out_status)))
+
+    def smooth(self, out_par, out_cov, out_n):
+        """Smoothed states of the last find's tracks into device arrays (seed
+        order): out_par [n][MAX_PLAN + 1][6], out_cov [n][MAX_PLAN + 1][21],
+        out_n [n] (surfaces per track)."""
+        self._check(lib.mkf_smooth(self.h, _ptr(out_par), _ptr(out_cov), _ptr(out_n)))
 
     def set_tuning(self, waves_per_simd, blocks_per_cu):
         self._check(lib.mkf_set_tuning(self.h, C.byref(Tuning(waves_per_simd, blocks_per_cu))))

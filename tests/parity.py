@@ -119,3 +119,18 @@ def compare_tracks(gpu, ref, full_cov, cov_rel=COV_REL_FOUND):
             out["fail"].append((i, "numeric", ok_p, ok_c, ok_v, rel.tolist(),
                                 float(g["chi2"]), float(r["chi2"])))
     return out
+
+
+def conditioning(w, ev, hits):
+    """Smallest cosine between the true direction and the surface normal
+    over the track's hits (noise hits have no truth and are left out)."""
+    cmin = 1.0
+    for i in hits:
+        s = ev.truth_state[i]
+        if not np.all(np.isfinite(s)):
+            continue
+        d = np.array([np.cos(s[4]), np.sin(s[4]), 1 / np.tan(s[5])])
+        nrm = (np.array([s[0], s[1], 0.0]) if w.layers[ev.layer[i]].kind == 0
+               else np.array([0.0, 0.0, 1.0]))
+        cmin = min(cmin, abs(d @ nrm) / np.linalg.norm(d) / np.linalg.norm(nrm))
+    return cmin

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from synth import BARREL, barrel_endcap, generate, small_barrel
+from synth import barrel_endcap, generate, small_barrel
 import parity as PT
 
 pytestmark = pytest.mark.gpu
@@ -55,21 +55,6 @@ def find_and_backfit(M, w, b, flags=0):
     return tr, [o.cpu().numpy() for o in outs], ms
 
 
-def conditioning(w, ev, hits):
-    """Smallest cosine between the true direction and the surface normal
-    over the track's hits (noise hits have no truth and are left out)."""
-    cmin = 1.0
-    for i in hits:
-        s = ev.truth_state[i]
-        if not np.all(np.isfinite(s)):
-            continue
-        d = np.array([np.cos(s[4]), np.sin(s[4]), 1 / np.tan(s[5])])
-        nrm = (np.array([s[0], s[1], 0.0]) if w.layers[ev.layer[i]].kind == BARREL
-               else np.array([0.0, 0.0, 1.0]))
-        cmin = min(cmin, abs(d @ nrm) / np.linalg.norm(d) / np.linalg.norm(nrm))
-    return cmin
-
-
 def compare_backfit(M, w, ev, seeds, gtr, gbf, ref):
     """gtr: GPU track records of the seeds; gbf: (par, cov, chi2, status)
     rows of the same seeds; ref: the oracle's find results for them."""
@@ -97,7 +82,7 @@ def compare_backfit(M, w, ev, seeds, gtr, gbf, ref):
         ok_c = PT.chi2_ok(g_chi[i], c2)
         ce = PT.cov_err(M.unpack_cov(g_cov[i]), Cm)
         hits = [h for h in r["hit"] if h >= 0] + list(seeds[i])
-        graze = conditioning(w, ev, hits) < PT.GRAZING_COS
+        graze = PT.conditioning(w, ev, hits) < PT.GRAZING_COS
         if graze:
             out["grazing"] += 1
             out["max_cov_err_grazing"] = max(out["max_cov_err_grazing"], ce)
