@@ -31,6 +31,10 @@ PLAIN_BYTES_PER_STEP = 256.0
 # fit: one track-layer update (crossing, transport, Jacobian, covariance,
 # scattering, chi2, Kalman update) = the step count above without the window
 FIT_FLOPS_PER_UPDATE = 727.0
+# smoothing, per surface of a found track: the forward pass writes 91 words
+# (filtered and predicted state, F C, layer), the backward pass reads them
+# and writes the 27-word smoothed state (inputs not counted)
+SMOOTH_BYTES_PER_SURFACE = 4.0 * (91 + 91 + 27)
 # surrogate network per sample: forward 2 (8*64 + 64*64 + 7*64) = 10,112;
 # backward (input errors of layers 3 and 2, weight gradients of all three)
 # 19,200
@@ -101,9 +105,9 @@ def cpu_baseline(w, batch, seconds, workers):
 def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
     """Throughput of the other hot-path kernels, each from HIP events on the
     context stream around one launch after a warm-up: the search-free fit
-    (131,072 tracks x 26 layers), the backward fit of the benchmark
-    workload's found tracks, and the surrogate network's inference and
-    gradient (2^20 samples from its training sampler)."""
+    (131,072 tracks x 26 layers), the backward fit and the smoothing of the
+    benchmark workload's found tracks, and the surrogate network's inference
+    and gradient (2^20 samples from its training sampler)."""
     import numpy as np
     import torch
 
@@ -155,6 +159,18 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         out["k_backfit"] = dict(alu(FIT_FLOPS_PER_UPDATE * upd, ms, FP32_VECTOR_PEAK_TFLOPS, upd,
                                     "track-hit updates/s"), bound="alu",
                                 workload=f"{int(ok.sum())} found tracks, {upd} hits")
+        sm = [torch.zeros((ns, 33, 6), device=dev), torch.zeros((ns, 33, 21), device=dev),
+              torch.zeros(ns, dtype=torch.int32, device=dev)]
+        ms = timed(lambda: ctx2.smooth(*sm))
+        nsurf = int(sm[2].clamp(min=0).sum().item())
+        gbs = SMOOTH_BYTES_PER_SURFACE * nsurf / (ms * 1e-3) / 1e9
+        out["k_smooth_fwd+bwd"] = {"ms": ms, "throughput": nsurf / (ms * 1e-3),
+                                   "unit": "track-surface states/s", "achieved_gbs": gbs,
+                                   "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+                                   "bound": "hbm",
+                                   "workload": f"{int((sm[2] > 0).sum().item())} found tracks, "
+                                               f"{nsurf} surfaces"}
+        del sm
         ctx2.close()
         m = 1 << 20
         x = torch.zeros((m, 8), device=dev)

@@ -225,8 +225,8 @@ mkf_status mkf_backward_fit(mkf_ctx *ctx, float *out_par, float *out_cov, float 
  * the find's filter along the track in FP32 (propagate, add cfg.ms_sigma
  * scattering, update with the hit if there is one); the backward pass
  * forms xs(k) = x(k) + A (xs(k+1) - xp(k+1)), Cs(k) = C(k) + A (Cs(k+1) -
- * Cp(k+1)) A^T, A = C(k) F^T Cp(k+1)^-1, in FP64 with the inverse taken in
- * the five free coordinates of surface k+1.  Device outputs in seed order:
+ * Cp(k+1)) A^T, A = C(k) F^T Cp(k+1)^-1, in FP32 with the inverse taken in
+ * the five free coordinates of surface k+1 (a Cholesky solve).  Device outputs in seed order:
  * out_par [n_seeds][MKF_MAX_PLAN + 1][6], out_cov [n_seeds][MKF_MAX_PLAN +
  * 1][21] (the first out_n entries of a seed are written), out_n [n_seeds]
  * (surfaces; 0 the seed fit failed; -1 a propagation or hit update failed;

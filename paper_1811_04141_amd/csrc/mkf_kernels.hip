@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(256) void k_backfit_tail(FindParams P, const int *s
 //   if there is one), keeping per surface the filtered state x, C, the
 //   predicted state xp, Cp after scattering and F C (F: the transport from
 //   the previous surface, C: the filtered covariance there).
-// * Backward (k_smooth_bwd, FP64): from the last surface, where the smoothed
+// * Backward (k_smooth_bwd, FP32): from the last surface, where the smoothed
 //   state is the filtered one,
 //     xs(k) = x(k) + A (xs(k+1) - xp(k+1)),
 //     Cs(k) = C(k) + A (Cs(k+1) - Cp(k+1)) A^T,   A = C(k) F^T Cp(k+1)^-1.
@@ -1433,35 +1433,74 @@ __global__ __launch_bounds__(256) void k_smooth_fwd(FindParams P, const int *see
 // the azimuth; disk: x), u1 = b0 v0 + b1 v1 + b2 v2 (barrel: z; disk: y),
 // u2..u4 = q/pT, phi, theta
 struct FreeCoords {
-  double a0, a1, b0, b1, b2;
-  __device__ void apply(const double *v, double *u) const {
-    u[0] = a0 * v[0] + a1 * v[1];
-    u[1] = b0 * v[0] + b1 * v[1] + b2 * v[2];
+  float a0, a1, b0, b1, b2;
+  __device__ void apply(const float *v, float *u) const {
+    u[0] = fmaf(a0, v[0], a1 * v[1]);
+    u[1] = fmaf(b0, v[0], fmaf(b1, v[1], b2 * v[2]));
     u[2] = v[3];
     u[3] = v[4];
     u[4] = v[5];
   }
+  // row a of J as a 6-vector
+  __device__ void row(int a, float *r) const {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r[i] = 0.f;
+    if (a == 0) {
+      r[0] = a0;
+      r[1] = a1;
+    } else if (a == 1) {
+      r[0] = b0;
+      r[1] = b1;
+      r[2] = b2;
+    } else {
+      r[a + 1] = 1.f;
+    }
+  }
 };
 
+// J M J^T (5 x 5, lower triangle packed by rows) of a symmetric 6 x 6 M
+// (upper triangle packed)
+__device__ __forceinline__ void sandwich5(const FreeCoords &J, const float *M, float *out) {
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    float r[6], v[6];
+    J.row(b, r);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      float a = 0.f;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a = fmaf(M[i <= j ? tri(i, j) : tri(j, i)], r[j], a);
+      v[i] = a;
+    }
+    float u[5];
+    J.apply(v, u);
+#pragma unroll
+    for (int a = b; a < 5; ++a) out[a * (a + 1) / 2 + b] = u[a];
+  }
+}
+
 // solve (L L^T) x = b in place, L lower-triangular 5x5 packed by rows
-__device__ __forceinline__ void chol_solve5(const double *Lp, double *b) {
-  double y[5];
+__device__ __forceinline__ void chol_solve5(const float *Lp, float *b) {
+  float y[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    double a = b[i];
+    float a = b[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) a -= Lp[i * (i + 1) / 2 + k] * y[k];
+    for (int k = 0; k < i; ++k) a = fmaf(-Lp[i * (i + 1) / 2 + k], y[k], a);
     y[i] = a / Lp[i * (i + 1) / 2 + i];
   }
 #pragma unroll
   for (int i = 4; i >= 0; --i) {
-    double a = y[i];
+    float a = y[i];
 #pragma unroll
-    for (int k = i + 1; k < 5; ++k) a -= Lp[k * (k + 1) / 2 + i] * b[k];
+    for (int k = i + 1; k < 5; ++k) a = fmaf(-Lp[k * (k + 1) / 2 + i], b[k], a);
     b[i] = a / Lp[i * (i + 1) / 2 + i];
   }
 }
 
+// Backward pass, FP32: the 5 x 5 systems are well conditioned once scaled
+// by their diagonal (condition numbers of the correlation matrices up to
+// ~500 on the benchmark's tracks), which a Cholesky solve respects.
 __global__ __launch_bounds__(256) void k_smooth_bwd(FindParams P, const float *wk,
                                                     const int *n_surf, float *out_par,
                                                     float *out_cov, int *out_n) {
@@ -1474,61 +1513,38 @@ __global__ __launch_bounds__(256) void k_smooth_bwd(FindParams P, const float *w
   float *op = out_par + (size_t)seed * (kMaxPlan + 1) * 6;
   float *oc = out_cov + (size_t)seed * (kMaxPlan + 1) * 21;
   if (n > 0) {
-    double xs[6], Cs[21];
+    float xs[6], Cs[21];
 #pragma unroll
     for (int m = 0; m < 6; ++m) xs[m] = at(n - 1, kSmFilt + m);
 #pragma unroll
     for (int m = 0; m < 21; ++m) Cs[m] = at(n - 1, kSmFilt + 6 + m);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) op[(n - 1) * 6 + m] = (float)xs[m];
+    for (int m = 0; m < 6; ++m) op[(n - 1) * 6 + m] = xs[m];
 #pragma unroll
-    for (int m = 0; m < 21; ++m) oc[(n - 1) * 21 + m] = (float)Cs[m];
+    for (int m = 0; m < 21; ++m) oc[(n - 1) * 21 + m] = Cs[m];
     for (int k = n - 2; k >= 0; --k) {
       // surface k+1: its free coordinates at the predicted point
-      double xp[6];
+      float xp[6];
 #pragma unroll
       for (int m = 0; m < 6; ++m) xp[m] = at(k + 1, kSmPred + m);
       const int lid = __float_as_int(at(k + 1, kSmLayer));
       FreeCoords J;
       if (P.layers[lid].kind == 0) {
-        const double r = sqrt(xp[0] * xp[0] + xp[1] * xp[1]);
-        J = FreeCoords{-xp[1] / r, xp[0] / r, 0.0, 0.0, 1.0};
+        const float ir = rsqrtf(fmaf(xp[0], xp[0], xp[1] * xp[1]));
+        J = FreeCoords{-xp[1] * ir, xp[0] * ir, 0.f, 0.f, 1.f};
       } else {
-        J = FreeCoords{1.0, 0.0, 0.0, 1.0, 0.0};
+        J = FreeCoords{1.f, 0.f, 0.f, 1.f, 0.f};
       }
-      // Sr = J Cp J^T and dPr = J (Cs - Cp) J^T, column by column
-      double Sr[15], dPr[15];
+      // Sr = J Cp J^T, then dPr = J (Cs - Cp) J^T
+      float Sr[15], dPr[15];
       {
-        double JCp[5][6], JdP[5][6];
+        float Cp[21];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          double col[6], dcol[6];
+        for (int m = 0; m < 21; ++m) Cp[m] = at(k + 1, kSmPred + 6 + m);
+        sandwich5(J, Cp, Sr);
 #pragma unroll
-          for (int i = 0; i < 6; ++i) {
-            const double cp = at(k + 1, kSmPred + 6 + (i <= j ? tri(i, j) : tri(j, i)));
-            col[i] = cp;
-            dcol[i] = Cs[i <= j ? tri(i, j) : tri(j, i)] - cp;
-          }
-          double u[5], du[5];
-          J.apply(col, u);
-          J.apply(dcol, du);
-#pragma unroll
-          for (int a = 0; a < 5; ++a) {
-            JCp[a][j] = u[a];
-            JdP[a][j] = du[a];
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-          double u[5], du[5];
-          J.apply(JCp[a], u);
-          J.apply(JdP[a], du);
-#pragma unroll
-          for (int b = 0; b <= a; ++b) {
-            Sr[a * (a + 1) / 2 + b] = u[b];
-            dPr[a * (a + 1) / 2 + b] = du[b];
-          }
-        }
+        for (int m = 0; m < 21; ++m) Cs[m] -= Cp[m];
+        sandwich5(J, Cs, dPr);
       }
       // Cholesky factor of Sr in place
       bool pd = true;
@@ -1536,12 +1552,12 @@ __global__ __launch_bounds__(256) void k_smooth_bwd(FindParams P, const float *w
       for (int i = 0; i < 5; ++i) {
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
-          double a = Sr[i * (i + 1) / 2 + j];
+          float a = Sr[i * (i + 1) / 2 + j];
 #pragma unroll
-          for (int q = 0; q < j; ++q) a -= Sr[i * (i + 1) / 2 + q] * Sr[j * (j + 1) / 2 + q];
+          for (int q = 0; q < j; ++q) a = fmaf(-Sr[i * (i + 1) / 2 + q], Sr[j * (j + 1) / 2 + q], a);
           if (i == j) {
-            pd = pd && a > 0.0;
-            Sr[i * (i + 1) / 2 + i] = sqrt(a > 0.0 ? a : 1.0);
+            pd = pd && a > 0.f;
+            Sr[i * (i + 1) / 2 + i] = sqrtf(a > 0.f ? a : 1.f);
           } else {
             Sr[i * (i + 1) / 2 + j] = a / Sr[j * (j + 1) / 2 + j];
           }
@@ -1552,24 +1568,24 @@ __global__ __launch_bounds__(256) void k_smooth_bwd(FindParams P, const float *w
         break;
       }
       // u = Sr^-1 J (xs - xp)
-      double d[6], u[5];
+      float d[6], u[5];
 #pragma unroll
       for (int m = 0; m < 6; ++m) d[m] = xs[m] - xp[m];
       d[4] = wrap_phi(d[4]);
       J.apply(d, u);
       chol_solve5(Sr, u);
-      // M = J F C (5 x 6), one column at a time; xs(k) = x(k) + M^T u and
+      // M = J F C (5 x 6), one column at a time: xs(k) = x(k) + M^T u and
       // W = Sr^-1 M
-      double W[5][6];
+      float W[5][6];
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        double col[6], w[5];
+        float col[6], w[5];
 #pragma unroll
         for (int i = 0; i < 6; ++i) col[i] = at(k + 1, kSmFC + i * 6 + j);
         J.apply(col, w);
-        double a = at(k, kSmFilt + j);
+        float a = at(k, kSmFilt + j);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) a += w[q] * u[q];
+        for (int q = 0; q < 5; ++q) a = fmaf(w[q], u[q], a);
         xs[j] = a;
         chol_solve5(Sr, w);
 #pragma unroll
@@ -1579,27 +1595,27 @@ __global__ __launch_bounds__(256) void k_smooth_bwd(FindParams P, const float *w
       // Cs(k) = C(k) + W^T dPr W
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        double t[5];
+        float t[5];
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
-          double v = 0.0;
+          float v = 0.f;
 #pragma unroll
           for (int b = 0; b < 5; ++b)
-            v += dPr[a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a] * W[b][i];
+            v = fmaf(dPr[a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a], W[b][i], v);
           t[a] = v;
         }
 #pragma unroll
         for (int j = i; j < 6; ++j) {
-          double v = at(k, kSmFilt + 6 + tri(i, j));
+          float v = at(k, kSmFilt + 6 + tri(i, j));
 #pragma unroll
-          for (int a = 0; a < 5; ++a) v += t[a] * W[a][j];
+          for (int a = 0; a < 5; ++a) v = fmaf(t[a], W[a][j], v);
           Cs[tri(i, j)] = v;
         }
       }
 #pragma unroll
-      for (int m = 0; m < 6; ++m) op[k * 6 + m] = (float)xs[m];
+      for (int m = 0; m < 6; ++m) op[k * 6 + m] = xs[m];
 #pragma unroll
-      for (int m = 0; m < 21; ++m) oc[k * 21 + m] = (float)Cs[m];
+      for (int m = 0; m < 21; ++m) oc[k * 21 + m] = Cs[m];
     }
   }
   out_n[seed] = n;
