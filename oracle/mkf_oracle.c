@@ -1000,3 +1000,107 @@ int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
   }
   return n;
 }
+
+/* --------------------------------------------------- triplet seeding */
+
+/* Seeds are supplied from outside in the paper (Section 2.2); building them
+ * from the hits is the step the paper leaves to the host framework.
+ * Reading: a seed is a triplet of hits on three barrel layers (innermost
+ * first) whose helix is a plausible track from the beam line.  The circle
+ * through the three transverse points gives the centre c and the radius rho;
+ * the triplet passes if
+ *   pT = kappa |B| rho >= pt_min,
+ *   d0 = | |c| - rho | <= d0_max        (transverse distance to the beam line),
+ *   the hits follow each other along the circle in the turning sense within
+ *   half a turn (0 < psi_ab < psi_ac < pi),
+ *   |z_b - (z_a + (z_c - z_a) s_ab / s_ac)| <= dz_max   (s: arc lengths),
+ *   the point of closest approach to the beam line precedes a within half a
+ *   turn, and there |z0| <= z0_max, z0 = z_a - (z_c - z_a) s_0a / s_ac.
+ * Writes the cut variables (pt, d0, dz, z0, psi_ab, psi_ac, psi_0a) to v
+ * (may be NULL) and, in *margin, the smallest distance of a variable to its
+ * cut relative to the cut's scale (angles relative to pi).  Returns 1 if the
+ * triplet passes. */
+int orc_triplet_params(const orc_cfg *cfg, const orc_seeding *sc, const double a[3],
+                       const double b[3], const double c[3], double v[7], double *margin) {
+  *margin = 0.0;
+  double abx = b[0] - a[0], aby = b[1] - a[1], acx = c[0] - a[0], acy = c[1] - a[1];
+  double cr = abx * acy - aby * acx;
+  if (cr == 0.0) return 0; /* collinear: no circle */
+  double ab2 = abx * abx + aby * aby, ac2 = acx * acx + acy * acy;
+  /* centre relative to a: solves 2 u.ab = |ab|^2, 2 u.ac = |ac|^2 */
+  double ux = (acy * ab2 - aby * ac2) / (2.0 * cr);
+  double uy = (abx * ac2 - acx * ab2) / (2.0 * cr);
+  double cx = a[0] + ux, cy = a[1] + uy;
+  double rho = hypot(ux, uy);
+  double pt = cfg->kappa * fabs(cfg->bz) * rho;
+  double D = hypot(cx, cy);
+  if (D == 0.0) return 0;
+  double d0 = fabs(D - rho);
+  double sgn = cr > 0.0 ? 1.0 : -1.0; /* turning sense of a -> b -> c */
+  double pa = atan2(a[1] - cy, a[0] - cx), pb = atan2(b[1] - cy, b[0] - cx);
+  double pc = atan2(c[1] - cy, c[0] - cx), p0 = atan2(-cy, -cx);
+  double psi_ab = fmod(sgn * (pb - pa) + 4.0 * M_PI, 2.0 * M_PI);
+  double psi_ac = fmod(sgn * (pc - pa) + 4.0 * M_PI, 2.0 * M_PI);
+  double psi_0a = fmod(sgn * (pa - p0) + 4.0 * M_PI, 2.0 * M_PI);
+  double s_ab = rho * psi_ab, s_ac = rho * psi_ac, s_0a = rho * psi_0a;
+  double slope = s_ac > 0.0 ? (c[2] - a[2]) / s_ac : 0.0;
+  double dz = b[2] - (a[2] + slope * s_ab);
+  double z0 = a[2] - slope * s_0a;
+  if (v) {
+    v[0] = pt;
+    v[1] = d0;
+    v[2] = dz;
+    v[3] = z0;
+    v[4] = psi_ab;
+    v[5] = psi_ac;
+    v[6] = psi_0a;
+  }
+  double m[7] = {(pt - sc->pt_min) / sc->pt_min, (sc->d0_max - d0) / sc->d0_max,
+                 (sc->dz_max - fabs(dz)) / sc->dz_max, (sc->z0_max - fabs(z0)) / sc->z0_max,
+                 psi_ab / M_PI, (psi_ac - psi_ab) / M_PI, (M_PI - psi_ac) / M_PI};
+  double mn = m[0];
+  for (int i = 1; i < 7; ++i) mn = fmin(mn, m[i]);
+  mn = fmin(mn, (M_PI - psi_0a) / M_PI);
+  *margin = mn;
+  return mn > 0.0;
+}
+
+/* All triplets of one event that pass (brute force over every hit of the
+ * three seeding layers, a in the caller's order, then b, then c).  Writes up
+ * to cap triplets (event-local hit indices, innermost first) and, for each,
+ * fragile = 1 if a cut variable lies within frag_tol (relative) of its cut;
+ * triplets that fail by less than frag_tol are counted in *n_fragile_out.
+ * Returns the number that pass. */
+int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_hits,
+                          const float *x, const float *y, const float *z, const int32_t *layer,
+                          double frag_tol, int64_t cap, int32_t *out, int32_t *fragile,
+                          int64_t *n_fragile_out) {
+  int64_t n = 0, nf = 0;
+  for (int32_t i = 0; i < n_hits; ++i) {
+    if (layer[i] != sc->layer[0]) continue;
+    const double a[3] = {x[i], y[i], z[i]};
+    for (int32_t j = 0; j < n_hits; ++j) {
+      if (layer[j] != sc->layer[1]) continue;
+      const double b[3] = {x[j], y[j], z[j]};
+      for (int32_t k = 0; k < n_hits; ++k) {
+        if (layer[k] != sc->layer[2]) continue;
+        const double c[3] = {x[k], y[k], z[k]};
+        double margin;
+        int ok = orc_triplet_params(cfg, sc, a, b, c, NULL, &margin);
+        if (!ok) {
+          if (margin > -frag_tol && margin != 0.0) ++nf;
+          continue;
+        }
+        if (n < cap) {
+          out[3 * n] = i;
+          out[3 * n + 1] = j;
+          out[3 * n + 2] = k;
+          fragile[n] = margin < frag_tol;
+        }
+        ++n;
+      }
+    }
+  }
+  *n_fragile_out = nf;
+  return n;
+}

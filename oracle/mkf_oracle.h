@@ -189,6 +189,27 @@ int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
                      const double seed_cov[36], const orc_track *trk, int32_t *surf_layer,
                      double *par_out, double *cov_out);
 
+/* ---- triplet seeding (the paper takes seeds from outside) ---------- */
+
+typedef struct {
+  int32_t layer[3]; /* three barrel layers, innermost first */
+  double pt_min;    /* GeV/c */
+  double d0_max;    /* cm: transverse distance of the circle from the beam line */
+  double z0_max;    /* cm: |z| at the point of closest approach to the beam line */
+  double dz_max;    /* cm: middle hit off the s-z line of the outer two */
+} orc_seeding;
+
+/* Cut variables of one triplet (pt, d0, dz, z0, psi_ab, psi_ac, psi_0a; v
+ * may be NULL) and the smallest relative margin to a cut; 1 if it passes. */
+int orc_triplet_params(const orc_cfg *cfg, const orc_seeding *sc, const double a[3],
+                       const double b[3], const double c[3], double v[7], double *margin);
+
+/* Brute-force triplet seeds of one event; see the definition above. */
+int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_hits,
+                          const float *x, const float *y, const float *z, const int32_t *layer,
+                          double frag_tol, int64_t cap, int32_t *out, int32_t *fragile,
+                          int64_t *n_fragile_out);
+
 #ifdef __cplusplus
 }
 #endif

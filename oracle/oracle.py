@@ -58,6 +58,11 @@ class Track(C.Structure):
                 ("fragile_step", C.c_int32), ("n_steps", C.c_int64)]
 
 
+class Seeding(C.Structure):
+    _fields_ = [("layer", C.c_int32 * 3), ("pt_min", C.c_double), ("d0_max", C.c_double),
+                ("z0_max", C.c_double), ("dz_max", C.c_double)]
+
+
 class Tol(C.Structure):
     _fields_ = [("chi2_rel", C.c_double), ("chi2_abs", C.c_double), ("pos_tol", C.c_double)]
 
@@ -95,6 +100,11 @@ def lib():
                                        _F, _F, _I, _I, C.POINTER(Track), _D, _D, _D, _I]
         L.orc_smooth_track.argtypes = [C.POINTER(Cfg), C.POINTER(Layer), C.c_int32, _F, _F, _F,
                                        _F, _F, C.c_int32, _D, _D, C.POINTER(Track), _I, _D, _D]
+        L.orc_triplet_params.argtypes = [C.POINTER(Cfg), C.POINTER(Seeding), _D, _D, _D, _D, _D]
+        L.orc_triplet_seeds.argtypes = [C.POINTER(Cfg), C.POINTER(Seeding), C.c_int32, _F, _F, _F,
+                                        _I, C.c_double, C.c_int64, _I, _I,
+                                        C.POINTER(C.c_int64)]
+        L.orc_triplet_seeds.restype = C.c_int64
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
         L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
         L.orc_mlp_grad.restype = C.c_double
@@ -363,3 +373,39 @@ def smooth_track(fc, layers, ev, seed_layer, seed_par, seed_cov, trk):
     m = max(n, 0)
     return (int(n), sl[:m].copy(), po.reshape(ns, 6)[:m].copy(),
             Co.reshape(ns, 6, 6)[:m].copy())
+
+
+def make_seeding(sc) -> Seeding:
+    s = Seeding()
+    for i in range(3):
+        s.layer[i] = int(sc.layers[i])
+    s.pt_min, s.d0_max, s.z0_max, s.dz_max = sc.pt_min, sc.d0_max, sc.z0_max, sc.dz_max
+    return s
+
+
+def triplet_params(fc, sc, a, b, c):
+    """Returns (passes, margin, [pt, d0, dz, z0, psi_ab, psi_ac, psi_0a])."""
+    cfg, s = make_cfg(fc), make_seeding(sc)
+    v, m = np.zeros(7), np.zeros(1)
+    ok = lib().orc_triplet_params(C.byref(cfg), C.byref(s), _p(_d(a, 3)), _p(_d(b, 3)),
+                                  _p(_d(c, 3)), _p(v), _p(m))
+    return bool(ok), float(m[0]), v
+
+
+def triplet_seeds(fc, sc, ev, frag_tol=1e-9):
+    """Brute-force triplet seeds of one event: (triplets [n][3] int32,
+    fragile [n] bool, number of near-miss triplets)."""
+    cfg, s = make_cfg(fc), make_seeding(sc)
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z)]
+    layer = np.ascontiguousarray(ev.layer, np.int32)
+    nf = C.c_int64(0)
+    cap = 1 << 16
+    while True:
+        out = np.zeros((cap, 3), np.int32)
+        frag = np.zeros(cap, np.int32)
+        n = lib().orc_triplet_seeds(C.byref(cfg), C.byref(s), int(layer.shape[0]),
+                                    *[_p(a, _F) for a in arrs], _p(layer, _I), frag_tol, cap,
+                                    _p(out, _I), _p(frag, _I), C.byref(nf))
+        if n <= cap:
+            return out[:n].copy(), frag[:n].astype(bool), int(nf.value)
+        cap = int(n)

@@ -67,6 +67,20 @@ class FindConfig:
 
 
 @dataclass(frozen=True)
+class SeedingConfig:
+    """Cuts of the combinatorial triplet seeding (readings; the paper takes
+    seeds from outside): three barrel layers, innermost first; pT above
+    pt_min (GeV/c); the circle within d0_max (cm) of the beam line; the
+    middle hit within dz_max (cm) of the s-z line of the outer two; |z| at
+    the point of closest approach below z0_max (cm)."""
+    layers: Tuple[int, int, int] = (0, 1, 2)
+    pt_min: float = 0.25
+    d0_max: float = 0.1
+    z0_max: float = 20.0
+    dz_max: float = 0.1
+
+
+@dataclass(frozen=True)
 class EventRecipe:
     pt_lo: float = 0.5
     pt_hi: float = 10.0
