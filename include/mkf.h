@@ -122,6 +122,15 @@ typedef struct {
   int64_t sur_rejected;    /* ... rejected (the closed-form crossing was used) */
 } mkf_stats;
 
+/* Cuts of the combinatorial triplet seeding (mkf_make_seeds). */
+typedef struct {
+  int32_t layers[3]; /* three barrel layers, increasing radius */
+  float pt_min;      /* GeV/c */
+  float d0_max;      /* cm: the circle's transverse distance to the beam line */
+  float z0_max;      /* cm: |z| at the point of closest approach to the beam line */
+  float dz_max;      /* cm: middle hit off the s-z line through the outer two */
+} mkf_seeding;
+
 typedef struct mkf_ctx mkf_ctx;
 
 /* Create a context.  cfg is copied.  stream: a hipStream_t (NULL = the
@@ -234,6 +243,24 @@ mkf_status mkf_backward_fit(mkf_ctx *ctx, float *out_par, float *out_cov, float 
  * Device scratch: 364 bytes per surface and seed, held by the context.
  * Asynchronous on the context's stream.  MKF_E_ORDER before a find. */
 mkf_status mkf_smooth(mkf_ctx *ctx, float *out_par, float *out_cov, int32_t *out_n);
+
+/* Combinatorial triplet seeds from the loaded hits (the paper takes seeds
+ * from outside, Section 2.2; this is the step it leaves to the host
+ * framework).  A seed is a triplet of hits a, b, c on sc->layers whose
+ * helix is a plausible track from the beam line: with the circle through
+ * the three transverse points (radius rho, centre c0), kappa |B| rho >=
+ * pt_min; | |c0| - rho | <= d0_max; a, b, c follow each other in the
+ * turning sense within half a turn; |z_b - (z_a + (z_c - z_a) s_ab/s_ac)|
+ * <= dz_max (s: arc lengths); and the s-z line through a and c has |z| <=
+ * z0_max at the point of closest approach to the beam line, which precedes
+ * a within half a turn.  The cuts are evaluated in FP64.  Device outputs:
+ * out_event [capacity], out_hits [capacity][3] (event-local hit indices,
+ * innermost first), ordered by the caller's order of a, then by the hit
+ * index's bin order of b and c; *n_total receives the number of triplets.
+ * If it exceeds capacity nothing is written and MKF_E_CAPACITY returned.
+ * The outputs can go to mkf_seed with MKF_MEM_DEVICE.  Blocks until done. */
+mkf_status mkf_make_seeds(mkf_ctx *ctx, const mkf_seeding *sc, int64_t capacity,
+                          int32_t *out_event, int32_t *out_hits, int64_t *n_total);
 
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);

@@ -1018,8 +1018,9 @@ int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
  *   turn, and there |z0| <= z0_max, z0 = z_a - (z_c - z_a) s_0a / s_ac.
  * Writes the cut variables (pt, d0, dz, z0, psi_ab, psi_ac, psi_0a) to v
  * (may be NULL) and, in *margin, the smallest distance of a variable to its
- * cut relative to the cut's scale (angles relative to pi).  Returns 1 if the
- * triplet passes. */
+ * cut relative to the cut's scale (angles relative to pi); when pT or d0
+ * misses its cut by more than half of it only those two are computed (the
+ * others are NaN in v).  Returns 1 if the triplet passes. */
 int orc_triplet_params(const orc_cfg *cfg, const orc_seeding *sc, const double a[3],
                        const double b[3], const double c[3], double v[7], double *margin) {
   *margin = 0.0;
@@ -1036,6 +1037,17 @@ int orc_triplet_params(const orc_cfg *cfg, const orc_seeding *sc, const double a
   double D = hypot(cx, cy);
   if (D == 0.0) return 0;
   double d0 = fabs(D - rho);
+  {
+    /* far from the pT or d0 cut: fails whatever the rest (saves the
+     * arctangents of most combinations in the brute force) */
+    double m_pt = (pt - sc->pt_min) / sc->pt_min, m_d0 = (sc->d0_max - d0) / sc->d0_max;
+    if (m_pt < -0.5 || m_d0 < -0.5) {
+      *margin = fmin(m_pt, m_d0);
+      if (v)
+        for (int i = 0; i < 7; ++i) v[i] = i == 0 ? pt : (i == 1 ? d0 : NAN);
+      return 0;
+    }
+  }
   double sgn = cr > 0.0 ? 1.0 : -1.0; /* turning sense of a -> b -> c */
   double pa = atan2(a[1] - cy, a[0] - cx), pb = atan2(b[1] - cy, b[0] - cx);
   double pc = atan2(c[1] - cy, c[0] - cx), p0 = atan2(-cy, -cx);
@@ -1066,18 +1078,19 @@ int orc_triplet_params(const orc_cfg *cfg, const orc_seeding *sc, const double a
 }
 
 /* All triplets of one event that pass (brute force over every hit of the
- * three seeding layers, a in the caller's order, then b, then c).  Writes up
+ * three seeding layers, a in the caller's order, then b, then c; only those
+ * starting at hit a_only if a_only >= 0).  Writes up
  * to cap triplets (event-local hit indices, innermost first) and, for each,
  * fragile = 1 if a cut variable lies within frag_tol (relative) of its cut;
  * triplets that fail by less than frag_tol are counted in *n_fragile_out.
  * Returns the number that pass. */
 int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_hits,
                           const float *x, const float *y, const float *z, const int32_t *layer,
-                          double frag_tol, int64_t cap, int32_t *out, int32_t *fragile,
-                          int64_t *n_fragile_out) {
+                          int32_t a_only, double frag_tol, int64_t cap, int32_t *out,
+                          int32_t *fragile, int64_t *n_fragile_out) {
   int64_t n = 0, nf = 0;
   for (int32_t i = 0; i < n_hits; ++i) {
-    if (layer[i] != sc->layer[0]) continue;
+    if (layer[i] != sc->layer[0] || (a_only >= 0 && i != a_only)) continue;
     const double a[3] = {x[i], y[i], z[i]};
     for (int32_t j = 0; j < n_hits; ++j) {
       if (layer[j] != sc->layer[1]) continue;

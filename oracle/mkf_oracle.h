@@ -207,8 +207,8 @@ int orc_triplet_params(const orc_cfg *cfg, const orc_seeding *sc, const double a
 /* Brute-force triplet seeds of one event; see the definition above. */
 int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_hits,
                           const float *x, const float *y, const float *z, const int32_t *layer,
-                          double frag_tol, int64_t cap, int32_t *out, int32_t *fragile,
-                          int64_t *n_fragile_out);
+                          int32_t a_only, double frag_tol, int64_t cap, int32_t *out,
+                          int32_t *fragile, int64_t *n_fragile_out);
 
 #ifdef __cplusplus
 }

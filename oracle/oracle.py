@@ -102,7 +102,7 @@ def lib():
                                        _F, _F, C.c_int32, _D, _D, C.POINTER(Track), _I, _D, _D]
         L.orc_triplet_params.argtypes = [C.POINTER(Cfg), C.POINTER(Seeding), _D, _D, _D, _D, _D]
         L.orc_triplet_seeds.argtypes = [C.POINTER(Cfg), C.POINTER(Seeding), C.c_int32, _F, _F, _F,
-                                        _I, C.c_double, C.c_int64, _I, _I,
+                                        _I, C.c_int32, C.c_double, C.c_int64, _I, _I,
                                         C.POINTER(C.c_int64)]
         L.orc_triplet_seeds.restype = C.c_int64
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
@@ -392,9 +392,10 @@ def triplet_params(fc, sc, a, b, c):
     return bool(ok), float(m[0]), v
 
 
-def triplet_seeds(fc, sc, ev, frag_tol=1e-9):
-    """Brute-force triplet seeds of one event: (triplets [n][3] int32,
-    fragile [n] bool, number of near-miss triplets)."""
+def triplet_seeds(fc, sc, ev, frag_tol=1e-9, a_only=-1):
+    """Brute-force triplet seeds of one event (only those starting at hit
+    a_only if >= 0): (triplets [n][3] int32, fragile [n] bool, number of
+    near-miss triplets)."""
     cfg, s = make_cfg(fc), make_seeding(sc)
     arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z)]
     layer = np.ascontiguousarray(ev.layer, np.int32)
@@ -404,7 +405,8 @@ def triplet_seeds(fc, sc, ev, frag_tol=1e-9):
         out = np.zeros((cap, 3), np.int32)
         frag = np.zeros(cap, np.int32)
         n = lib().orc_triplet_seeds(C.byref(cfg), C.byref(s), int(layer.shape[0]),
-                                    *[_p(a, _F) for a in arrs], _p(layer, _I), frag_tol, cap,
+                                    *[_p(a, _F) for a in arrs], _p(layer, _I), int(a_only),
+                                    frag_tol, cap,
                                     _p(out, _I), _p(frag, _I), C.byref(nf))
         if n <= cap:
             return out[:n].copy(), frag[:n].astype(bool), int(nf.value)

@@ -73,6 +73,7 @@ struct mkf_ctx {
   DevBuf d_order, d_pstate, d_pinfo, d_pevent, d_pplan;
   DevBuf d_bf_tmp;  // backward fit: state between its FP64 and FP32 parts
   DevBuf d_sm_wk, d_sm_n;  // smoothing: forward-pass states per surface, surface counts
+  DevBuf d_tr_cnt, d_tr_off, d_tr_tmp;  // triplet seeding: counts, offsets, scan scratch
   std::vector<int32_t> h_order, h_plen, h_ok;
   std::vector<int64_t> active_at_step;  // seeds (in processing order) with plan_len > step
   int max_plan_len = 0;
@@ -104,7 +105,7 @@ struct mkf_ctx {
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
                      &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
-                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n};
+                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n, &d_tr_cnt, &d_tr_off, &d_tr_tmp};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -842,6 +843,55 @@ mkf_status mkf_smooth(mkf_ctx *c, float *out_par, float *out_cov, int32_t *out_n
   launch_smooth(c->stream, P, c->d_seed_hits.as<int>(), c->d_sm_wk.as<float>(),
                 c->d_sm_n.as<int>(), out_par, out_cov, out_n);
   HIP_TRY(c, hipGetLastError());
+  return MKF_OK;
+}
+
+mkf_status mkf_make_seeds(mkf_ctx *c, const mkf_seeding *sc, int64_t capacity,
+                          int32_t *out_event, int32_t *out_hits, int64_t *n_total) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kHits) return fail(c, MKF_E_ORDER, "load_hits first");
+  if (!sc || !n_total || capacity < 0) return fail(c, MKF_E_ARG, "NULL argument");
+  if (capacity > 0 && (!out_event || !out_hits)) return fail(c, MKF_E_ARG, "NULL output array");
+  for (int k = 0; k < 3; ++k) {
+    const int L = sc->layers[k];
+    if (L < 0 || L >= c->n_layers || c->layers[L].kind != MKF_BARREL)
+      return fail(c, MKF_E_ARG, "seeding layer %d is not a barrel layer", L);
+    if (k > 0 && !(c->layers[L].pos > c->layers[sc->layers[k - 1]].pos))
+      return fail(c, MKF_E_ARG, "seeding layers must have increasing radii");
+  }
+  if (!(sc->pt_min > 0.f) || !(sc->d0_max > 0.f) || !(sc->z0_max > 0.f) || !(sc->dz_max > 0.f))
+    return fail(c, MKF_E_ARG, "seeding cuts must be positive");
+  if (c->cfg.bz == 0.f) return fail(c, MKF_E_ARG, "triplet seeding needs a field");
+  *n_total = 0;
+  const int64_t n = c->n_hits;
+  if (n == 0) return MKF_OK;
+  DevSeeding ds{};
+  for (int k = 0; k < 3; ++k) ds.layer[k] = sc->layers[k];
+  ds.pt_min = sc->pt_min;
+  ds.d0_max = sc->d0_max;
+  ds.z0_max = sc->z0_max;
+  ds.dz_max = sc->dz_max;
+  HIP_TRY(c, c->d_tr_cnt.ensure(sizeof(int) * (size_t)n));
+  HIP_TRY(c, c->d_tr_off.ensure(sizeof(int) * (size_t)(n + 1)));
+  HIP_TRY(c, c->d_tr_tmp.ensure(sizeof(int) * (size_t)(4 * (n / 2048 + 4) + 64)));
+  FindParams P = params(c);
+  launch_triplets(c->stream, P, ds, n, false, c->d_tr_cnt.as<int>(), nullptr, nullptr, nullptr);
+  HIP_TRY(c, hipGetLastError());
+  launch_scan(c->stream, c->d_tr_cnt.as<int>(), c->d_tr_off.as<int>(), n, c->d_tr_tmp.as<int>(),
+              nullptr);
+  HIP_TRY(c, hipGetLastError());
+  int total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, c->d_tr_off.as<int>() + n, sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (total < 0) return fail(c, MKF_E_CAPACITY, "more than 2^31 triplets");
+  *n_total = total;
+  if (total > capacity)
+    return fail(c, MKF_E_CAPACITY, "%d triplets, capacity %lld", total, (long long)capacity);
+  launch_triplets(c->stream, P, ds, n, true, c->d_tr_cnt.as<int>(), c->d_tr_off.as<int>(),
+                  out_event, out_hits);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MKF_OK;
 }
 

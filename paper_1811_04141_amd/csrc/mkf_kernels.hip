@@ -957,6 +957,147 @@ __device__ __forceinline__ int bin_of(const DevLayer &L, float x, float y, float
   return L.bin_base + qb * L.nphi + pb;
 }
 
+// ------------------------------------------------------ triplet seeding
+//
+// The paper takes seeds from outside (Section 2.2); this builds them from
+// the hits.  A seed is a triplet of hits a, b, c on three barrel layers
+// (innermost first) whose helix is a plausible track from the beam line:
+// with the circle through the three transverse points (centre c0, radius
+// rho), pT = kappa |B| rho >= pt_min; the circle passes within d0_max of the
+// beam line; a, b, c follow each other in the turning sense within half a
+// turn; b lies within dz_max of the s-z line through a and c; and that line
+// has |z| <= z0_max at the point of closest approach to the beam line, which
+// precedes a within half a turn.  The cuts are evaluated in FP64.
+//
+// One thread per hit of the first layer walks the second layer's hits in an
+// azimuth window (every z bin), drops pairs whose straight-line z at the beam
+// line is far outside z0_max, and walks the third layer's hits in an azimuth
+// and z window around the pair's extrapolation.  The windows only bound the
+// search (their margins cover curvature, d0 and dz); the cuts decide.
+
+// exact cuts of one triplet (FP64)
+__device__ __forceinline__ bool triplet_passes(const DevCfg &cfg, const DevSeeding &sc, double ax,
+                                               double ay, double az, double bx, double by,
+                                               double bz, double cx, double cy, double cz) {
+  const double ux0 = bx - ax, uy0 = by - ay, vx0 = cx - ax, vy0 = cy - ay;
+  const double cr = ux0 * vy0 - uy0 * vx0;
+  if (cr == 0.0) return false;
+  const double u2 = ux0 * ux0 + uy0 * uy0, v2 = vx0 * vx0 + vy0 * vy0;
+  const double ox = ax + (vy0 * u2 - uy0 * v2) / (2.0 * cr);
+  const double oy = ay + (ux0 * v2 - vx0 * u2) / (2.0 * cr);
+  const double rho = sqrt((ox - ax) * (ox - ax) + (oy - ay) * (oy - ay));
+  // kappa |B| = |mkb|
+  if (fabs((double)cfg.mkb) * rho < (double)sc.pt_min) return false;
+  const double dist = sqrt(ox * ox + oy * oy);
+  if (dist == 0.0 || fabs(dist - rho) > (double)sc.d0_max) return false;
+  const double sg = cr > 0.0 ? 1.0 : -1.0;
+  const double two_pi = 6.283185307179586;
+  const double qa = atan2(ay - oy, ax - ox), qb = atan2(by - oy, bx - ox);
+  const double qc = atan2(cy - oy, cx - ox), q0 = atan2(-oy, -ox);
+  auto turn = [&](double from, double to) {
+    double t = sg * (to - from);
+    if (t < 0.0) t += two_pi;
+    if (t < 0.0) t += two_pi;
+    return t;
+  };
+  const double pab = turn(qa, qb), pac = turn(qa, qc), p0a = turn(q0, qa);
+  const double pi = 3.141592653589793;
+  if (!(pab > 0.0 && pac > pab && pac < pi && p0a < pi)) return false;
+  const double slope = (cz - az) / (rho * pac);
+  const double dz = bz - (az + slope * rho * pab);
+  if (fabs(dz) > (double)sc.dz_max) return false;
+  const double z0 = az - slope * rho * p0a;
+  return fabs(z0) <= (double)sc.z0_max;
+}
+
+// the bin rows [qlo, qhi] x azimuth window [phi - dphi, phi + dphi] of one
+// layer (two azimuth segments where it wraps); fn(hit record) per hit
+template <class Fn>
+__device__ __forceinline__ void walk_window(const FindParams &P, const DevLayer &L, int ev, float phi,
+                                            float dphi, int qlo, int qhi, Fn fn) {
+  const int nphi = L.nphi;
+  int s0lo = 0, s0hi = nphi - 1, s1lo = 1, s1hi = 0;
+  if (dphi < kPi) {
+    const int blo = (int)floorf((phi - dphi + kPi) * L.phi_scale);
+    const int bhi = (int)floorf((phi + dphi + kPi) * L.phi_scale);
+    if (bhi - blo + 1 < nphi) {
+      if (blo < 0) {
+        s0lo = blo + nphi; s1lo = 0; s1hi = bhi;
+      } else if (bhi >= nphi) {
+        s0lo = blo; s1lo = 0; s1hi = bhi - nphi;
+      } else {
+        s0lo = blo; s0hi = bhi;
+      }
+    }
+  }
+  const int base = ev * P.bins_per_event + L.bin_base;
+  for (int qb = qlo; qb <= qhi; ++qb) {
+    const int row = base + qb * nphi;
+    for (int sg = 0; sg < 2; ++sg) {
+      const int lo = sg == 0 ? s0lo : s1lo, hi = sg == 0 ? s0hi : s1hi;
+      if (lo > hi) continue;
+      const int h0 = P.bin_start[row + lo], h1 = P.bin_start[row + hi + 1];
+      for (int k = h0; k < h1; ++k) fn(P.sorted[k]);
+    }
+  }
+}
+
+// azimuth change between radii r0 < r1 of a circle of radius >= rho_min
+// passing within d0 of the beam line, with room for rounding
+__device__ __forceinline__ float bend_window(float r0, float r1, float rho_min, float d0) {
+  const float s0 = fminf(1.f, r0 / (2.f * rho_min)), s1 = fminf(1.f, r1 / (2.f * rho_min));
+  return asinf(s1) - asinf(s0) + d0 / r0 + d0 / r1 + 2e-3f;
+}
+
+template <bool kWrite>
+__global__ __launch_bounds__(256) void k_triplets(FindParams P, DevSeeding sc, int64_t n_hits,
+                                                  int *counts, const int *offsets,
+                                                  int *out_event, int *out_hits) {
+  __shared__ DevLayer sl[kMaxLayers];
+  stage_layers(P, sl);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_hits) return;
+  int n = 0;
+  if (P.hlayer[i] == sc.layer[0]) {
+    const int e = event_of(P.ev_off, P.n_events, i);
+    const int ia = (int)(i - P.ev_off[e]);
+    const float ax = P.hx[i], ay = P.hy[i], az = P.hz[i];
+    const DevLayer &L1 = sl[sc.layer[1]], &L2 = sl[sc.layer[2]];
+    const float ra = sqrtf(fmaf(ax, ax, ay * ay));
+    const float rho_min = sc.pt_min / fabsf(P.cfg.mkb);
+    const float R0 = sl[sc.layer[0]].pos, R1 = L1.pos, R2 = L2.pos;
+    const float dphi1 = bend_window(R0, R1, rho_min, sc.d0_max);
+    const float dphi2 = bend_window(R1, R2, rho_min, sc.d0_max);
+    int pos = kWrite ? offsets[i] : 0;
+    walk_window(P, L1, e, atan2f(ay, ax), dphi1, 0, L1.nq - 1, [&](const HitRec &hb) {
+      const float rb = sqrtf(fmaf(hb.x, hb.x, hb.y * hb.y));
+      const float Z = hb.z - az;
+      const float lever = ra / (rb - ra);
+      // straight-line z at the beam line, against z0_max with room for the
+      // arc-versus-radius differences (d0, bending) and dz
+      const float z0e = az - Z * lever;
+      if (fabsf(z0e) > sc.z0_max + 1.f + (0.1f * fabsf(Z) + sc.dz_max) * (lever + 1.f)) return;
+      const float k = (R2 - ra) / (rb - ra);
+      const float zp = az + Z * k;
+      const float hw = (0.1f * fabsf(Z) + 2.f * sc.dz_max) * k + 0.5f;
+      const int qlo = clampi((int)floorf((zp - hw - L2.q_lo) * L2.q_scale), 0, L2.nq - 1);
+      const int qhi = clampi((int)floorf((zp + hw - L2.q_lo) * L2.q_scale), 0, L2.nq - 1);
+      walk_window(P, L2, e, atan2f(hb.y, hb.x), dphi2, qlo, qhi, [&](const HitRec &hc) {
+        if (!triplet_passes(P.cfg, sc, ax, ay, az, hb.x, hb.y, hb.z, hc.x, hc.y, hc.z)) return;
+        if (kWrite) {
+          out_event[pos + n] = e;
+          out_hits[3 * (size_t)(pos + n)] = ia;
+          out_hits[3 * (size_t)(pos + n) + 1] = hb.orig;
+          out_hits[3 * (size_t)(pos + n) + 2] = hc.orig;
+        }
+        ++n;
+      });
+    });
+  }
+  if (!kWrite) counts[i] = n;
+}
+
 __global__ __launch_bounds__(256) void k_hit_bins(FindParams P, int n_events, int64_t n_hits,
                                                   const int *layer, int *hit_bin, int *counts) {
   __shared__ DevLayer sl[kMaxLayers];
@@ -1771,6 +1912,17 @@ void launch_smooth(hipStream_t s, const FindParams &P, const int *seed_hits, flo
                      seed_hits, wk, n_surf);
   hipLaunchKernelGGL(k_smooth_bwd, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, wk,
                      n_surf, out_par, out_cov, out_n);
+}
+
+void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc, int64_t n_hits,
+                     bool write, int *counts, const int *offsets, int *out_event, int *out_hits) {
+  if (n_hits == 0) return;
+  if (write)
+    hipLaunchKernelGGL(k_triplets<true>, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P, sc,
+                       n_hits, counts, offsets, out_event, out_hits);
+  else
+    hipLaunchKernelGGL(k_triplets<false>, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P, sc,
+                       n_hits, counts, offsets, out_event, out_hits);
 }
 
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,

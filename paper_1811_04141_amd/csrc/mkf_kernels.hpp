@@ -86,6 +86,15 @@ constexpr __host__ __device__ int persistent_rec_words(int max_plan, int g, int 
   return (max_plan > 0 ? max_plan : 1) * seeds * g + seeds * kFinWords;
 }
 
+// combinatorial triplet seeding: three barrel layers and the cuts
+struct DevSeeding {
+  int layer[3];
+  float pt_min, d0_max, z0_max, dz_max;
+};
+// counts[i]: triplets whose first hit is hit i (counting pass); with
+// offsets, writes them (event, three event-local hit indices)
+void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc, int64_t n_hits,
+                     bool write, int *counts, const int *offsets, int *out_event, int *out_hits);
 void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
                      int *hit_bin, int *counts);
 void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, int *tmp_b);

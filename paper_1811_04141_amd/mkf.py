@@ -24,7 +24,8 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_get_stats", "mkf_set_tuning",
+           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_get_stats",
+           "mkf_set_tuning",
            "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
 
@@ -60,6 +61,19 @@ TRACK_DTYPE = np.dtype([("seed_id", "<i4"), ("status", "<i4"), ("n_hits", "<i4")
                         ("par", "<f4", 6), ("cov", "<f4", 21), ("plan", "i1", MAX_PLAN),
                         ("hit", "<i4", MAX_PLAN)], align=True)
 assert TRACK_DTYPE.itemsize == C.sizeof(Track)
+
+
+class Seeding(C.Structure):
+    _fields_ = [("layers", C.c_int32 * 3), ("pt_min", C.c_float), ("d0_max", C.c_float),
+                ("z0_max", C.c_float), ("dz_max", C.c_float)]
+
+
+def make_seeding(sc):
+    s = Seeding()
+    for i in range(3):
+        s.layers[i] = int(sc.layers[i])
+    s.pt_min, s.d0_max, s.z0_max, s.dz_max = sc.pt_min, sc.d0_max, sc.z0_max, sc.dz_max
+    return s
 
 
 class Stats(C.Structure):
@@ -103,6 +117,7 @@ def _load():
         "mkf_fit": ([P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P], I32),
         "mkf_backward_fit": ([P, P, P, P, P], I32),
         "mkf_smooth": ([P, P, P, P], I32),
+        "mkf_make_seeds": ([P, C.POINTER(Seeding), I64, P, P, C.POINTER(I64)], I32),
         "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
         "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
@@ -249,6 +264,18 @@ class Context:
         order): out_par [n][MAX_PLAN + 1][6], out_cov [n][MAX_PLAN + 1][21],
         out_n [n] (surfaces per track)."""
         self._check(lib.mkf_smooth(self.h, _ptr(out_par), _ptr(out_cov), _ptr(out_n)))
+
+    def make_seeds(self, seeding, capacity, out_event, out_hits):
+        """Triplet seeds into device arrays out_event [capacity], out_hits
+        [capacity][3]; returns their number (raises on MKF_E_CAPACITY, whose
+        message holds the number needed)."""
+        n = C.c_int64(0)
+        st = lib.mkf_make_seeds(self.h, C.byref(make_seeding(seeding)), int(capacity),
+                                _ptr(out_event), _ptr(out_hits), C.byref(n))
+        if st == MKF_E_CAPACITY:
+            raise MkfError(st, f"{n.value} triplets, capacity {capacity}")
+        self._check(st)
+        return int(n.value)
 
     def set_tuning(self, waves_per_simd, blocks_per_cu):
         self._check(lib.mkf_set_tuning(self.h, C.byref(Tuning(waves_per_simd, blocks_per_cu))))
