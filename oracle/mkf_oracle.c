@@ -1117,3 +1117,50 @@ int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_h
   *n_fragile_out = nf;
   return n;
 }
+
+/* -------------------------------------------------- duplicate removal */
+
+/* Removal of duplicate tracks, which the paper lists as not yet done
+ * (Introduction; Section 3: duplicates from several seeds per particle).
+ * Reading: the hits of a track are its three seed hits and its found hits.
+ * Track u ranks before track t if it has more hits; with as many, a smaller
+ * chi2; with the same chi2, a lexicographically smaller seed triplet.  t is a
+ * duplicate if some track ranking before it shares at least frac of the
+ * hits of the shorter of the two.  hits: n x stride event-local indices
+ * (n_hits[t] used), seed: n x 3.  dup[t] = 1 for duplicates.  fragile[t] =
+ * 1 if the decision involves two tracks with as many hits and chi2 within
+ * chi2_tol_rel * chi2 + chi2_tol_abs, whose order rounding could swap.
+ * Returns the number of duplicates. */
+int32_t orc_duplicates(int32_t n, int32_t stride, const int32_t *n_hits, const int32_t *hits,
+                       const double *chi2, const int32_t *seed, double frac, double chi2_tol_rel,
+                       double chi2_tol_abs, int32_t *dup, int32_t *fragile) {
+  int32_t nd = 0;
+  for (int32_t t = 0; t < n; ++t) {
+    dup[t] = 0;
+    fragile[t] = 0;
+    for (int32_t u = 0; u < n; ++u) {
+      if (u == t) continue;
+      int shared = 0;
+      for (int i = 0; i < n_hits[t]; ++i)
+        for (int j = 0; j < n_hits[u]; ++j) shared += hits[t * stride + i] == hits[u * stride + j];
+      int mn = n_hits[t] < n_hits[u] ? n_hits[t] : n_hits[u];
+      if (shared == 0 || (double)shared < frac * (double)mn) continue;
+      int before;
+      if (n_hits[u] != n_hits[t]) {
+        before = n_hits[u] > n_hits[t];
+      } else {
+        if (fabs(chi2[u] - chi2[t]) <= chi2_tol_rel * fabs(chi2[t]) + chi2_tol_abs) fragile[t] = 1;
+        if (chi2[u] != chi2[t]) {
+          before = chi2[u] < chi2[t];
+        } else {
+          int k = 0;
+          while (k < 3 && seed[3 * u + k] == seed[3 * t + k]) ++k;
+          before = k < 3 && seed[3 * u + k] < seed[3 * t + k];
+        }
+      }
+      if (before) dup[t] = 1;
+    }
+    nd += dup[t];
+  }
+  return nd;
+}

@@ -210,6 +210,15 @@ int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_h
                           int32_t a_only, double frag_tol, int64_t cap, int32_t *out,
                           int32_t *fragile, int64_t *n_fragile_out);
 
+/* ---- duplicate-track removal ---------------------------------------- */
+
+/* t is a duplicate if a track ranking before it (more hits; then smaller
+ * chi2; then smaller seed triplet) shares at least frac of the hits of the
+ * shorter of the two.  Returns the number of duplicates. */
+int32_t orc_duplicates(int32_t n, int32_t stride, const int32_t *n_hits, const int32_t *hits,
+                       const double *chi2, const int32_t *seed, double frac, double chi2_tol_rel,
+                       double chi2_tol_abs, int32_t *dup, int32_t *fragile);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,6 +105,9 @@ def lib():
                                         _I, C.c_int32, C.c_double, C.c_int64, _I, _I,
                                         C.POINTER(C.c_int64)]
         L.orc_triplet_seeds.restype = C.c_int64
+        L.orc_duplicates.argtypes = [C.c_int32, C.c_int32, _I, _I, _D, _I, C.c_double, C.c_double,
+                                     C.c_double, _I, _I]
+        L.orc_duplicates.restype = C.c_int32
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
         L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
         L.orc_mlp_grad.restype = C.c_double
@@ -411,3 +414,29 @@ def triplet_seeds(fc, sc, ev, frag_tol=1e-9, a_only=-1):
         if n <= cap:
             return out[:n].copy(), frag[:n].astype(bool), int(nf.value)
         cap = int(n)
+
+
+def track_hit_sets(tracks, seeds):
+    """Hit sets (seed hits and found hits) of find_event results."""
+    return [list(s) + [int(h) for h in t["hit"] if h >= 0] if t["seed_ok"] else []
+            for t, s in zip(tracks, seeds)]
+
+
+def duplicates(hit_sets, chi2, seeds, frac=0.5, chi2_tol=(1e-3, 1e-2)):
+    """Duplicate flags of tracks given their hit sets, chi2 and seed
+    triplets: (dup [n] bool, fragile [n] bool)."""
+    n = len(hit_sets)
+    stride = max([len(h) for h in hit_sets] + [1])
+    H = np.full((max(n, 1), stride), -1, np.int32)
+    nh = np.zeros(max(n, 1), np.int32)
+    for i, h in enumerate(hit_sets):
+        H[i, :len(h)] = h
+        nh[i] = len(h)
+    c2 = _d(np.asarray(chi2, float).reshape(-1) if n else np.zeros(1))
+    sd = np.ascontiguousarray(np.asarray(seeds, np.int32).reshape(-1, 3) if n
+                              else np.zeros((1, 3), np.int32))
+    dup = np.zeros(max(n, 1), np.int32)
+    frag = np.zeros(max(n, 1), np.int32)
+    lib().orc_duplicates(n, stride, _p(nh, _I), _p(H, _I), _p(c2), _p(sd, _I), frac,
+                         chi2_tol[0], chi2_tol[1], _p(dup, _I), _p(frag, _I))
+    return dup[:n].astype(bool), frag[:n].astype(bool)
