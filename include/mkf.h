@@ -262,6 +262,20 @@ mkf_status mkf_smooth(mkf_ctx *ctx, float *out_par, float *out_cov, int32_t *out
 mkf_status mkf_make_seeds(mkf_ctx *ctx, const mkf_seeding *sc, int64_t capacity,
                           int32_t *out_event, int32_t *out_hits, int64_t *n_total);
 
+/* Duplicate removal for the tracks of the last mkf_find (not yet done in
+ * the paper: Introduction; Section 3 traces its duplicates to several seeds
+ * per particle).  The hits of a track are its three seed hits and its found
+ * hits.  Track u ranks before track t if it has more hits; with as many, a
+ * smaller chi2; with the same chi2, a lexicographically smaller seed
+ * triplet (event-local hit indices).  t is a duplicate if a track ranking
+ * before it shares at least frac (0 < frac <= 1) of the hits of the shorter
+ * of the two; a track ranking before t need not be kept itself.  Device
+ * output out_dup [n_seeds] (seed order): 1 for a duplicate, 0 otherwise
+ * (also for a seed whose fit failed); *n_dup receives their number.
+ * Device scratch of ~150 B per seed and 12 B per hit, held by the context.
+ * Blocks until done. */
+mkf_status mkf_find_duplicates(mkf_ctx *ctx, float frac, int32_t *out_dup, int64_t *n_dup);
+
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);
 

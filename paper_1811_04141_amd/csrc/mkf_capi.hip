@@ -74,6 +74,7 @@ struct mkf_ctx {
   DevBuf d_bf_tmp;  // backward fit: state between its FP64 and FP32 parts
   DevBuf d_sm_wk, d_sm_n;  // smoothing: forward-pass states per surface, surface counts
   DevBuf d_tr_cnt, d_tr_off, d_tr_tmp;  // triplet seeding: counts, offsets, scan scratch
+  DevBuf d_dup_h, d_dup_n, d_dup_cnt, d_dup_off, d_dup_fill, d_dup_list, d_dup_tmp, d_dup_total;
   std::vector<int32_t> h_order, h_plen, h_ok;
   std::vector<int64_t> active_at_step;  // seeds (in processing order) with plan_len > step
   int max_plan_len = 0;
@@ -105,7 +106,8 @@ struct mkf_ctx {
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
                      &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
-                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n, &d_tr_cnt, &d_tr_off, &d_tr_tmp};
+                     &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n, &d_tr_cnt, &d_tr_off, &d_tr_tmp, &d_dup_h, &d_dup_n, &d_dup_cnt, &d_dup_off,
+                     &d_dup_fill, &d_dup_list, &d_dup_tmp, &d_dup_total};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -892,6 +894,44 @@ mkf_status mkf_make_seeds(mkf_ctx *c, const mkf_seeding *sc, int64_t capacity,
                   out_event, out_hits);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MKF_OK;
+}
+
+mkf_status mkf_find_duplicates(mkf_ctx *c, float frac, int32_t *out_dup, int64_t *n_dup) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kFound) return fail(c, MKF_E_ORDER, "find first");
+  if (!n_dup || (c->n_seeds > 0 && !out_dup)) return fail(c, MKF_E_ARG, "NULL argument");
+  if (!(frac > 0.f && frac <= 1.f)) return fail(c, MKF_E_ARG, "frac must lie in (0, 1]");
+  *n_dup = 0;
+  if (c->n_seeds == 0) return MKF_OK;
+  const size_t N = (size_t)c->n_seeds, H = (size_t)std::max<int64_t>(c->n_hits, 1);
+  HIP_TRY(c, c->d_dup_h.ensure(sizeof(int) * kDupStride * N));
+  HIP_TRY(c, c->d_dup_n.ensure(sizeof(int) * N));
+  HIP_TRY(c, c->d_dup_cnt.ensure(sizeof(int) * H));
+  HIP_TRY(c, c->d_dup_off.ensure(sizeof(int) * (H + 1)));
+  HIP_TRY(c, c->d_dup_fill.ensure(sizeof(int) * H));
+  HIP_TRY(c, c->d_dup_list.ensure(sizeof(int) * (kDupStride - 1) * N));
+  HIP_TRY(c, c->d_dup_tmp.ensure(sizeof(int) * (4 * (H / 2048 + 4) + 64)));
+  HIP_TRY(c, c->d_dup_total.ensure(sizeof(int)));
+  FindParams P = params(c);
+  launch_fill_i32(c->stream, c->d_dup_cnt.as<int>(), (int64_t)H, 0);
+  launch_fill_i32(c->stream, c->d_dup_fill.as<int>(), (int64_t)H, 0);
+  launch_fill_i32(c->stream, c->d_dup_total.as<int>(), 1, 0);
+  launch_dup_prep(c->stream, P, c->d_seed_hits.as<int>(), c->d_dup_h.as<int>(),
+                  c->d_dup_n.as<int>(), c->d_dup_cnt.as<int>());
+  launch_scan(c->stream, c->d_dup_cnt.as<int>(), c->d_dup_off.as<int>(), (int64_t)H,
+              c->d_dup_tmp.as<int>(), nullptr);
+  launch_dup_fill(c->stream, P, c->d_dup_h.as<int>(), c->d_dup_n.as<int>(),
+                  c->d_dup_off.as<int>(), c->d_dup_fill.as<int>(), c->d_dup_list.as<int>());
+  launch_dup_decide(c->stream, P, c->d_seed_hits.as<int>(), c->d_dup_h.as<int>(),
+                    c->d_dup_n.as<int>(), c->d_dup_off.as<int>(), c->d_dup_list.as<int>(), frac,
+                    out_dup, c->d_dup_total.as<int>());
+  HIP_TRY(c, hipGetLastError());
+  int total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, c->d_dup_total.ptr, sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *n_dup = total;
   return MKF_OK;
 }
 

@@ -1098,6 +1098,115 @@ __global__ __launch_bounds__(256) void k_triplets(FindParams P, DevSeeding sc, i
   if (!kWrite) counts[i] = n;
 }
 
+// ---------------------------------------------------- duplicate removal
+//
+// Removal of duplicate tracks (the paper lists it as not yet done,
+// Introduction and Section 3).  The hits of a track are its three seed hits
+// and its found hits.  Track u ranks before t if it has more hits; with as
+// many, a smaller chi2; with the same chi2, a lexicographically smaller seed
+// triplet.  t is a duplicate if a track ranking before it shares at least
+// frac of the hits of the shorter of the two.  Tracks that share a hit are
+// found through a hit -> tracks table (CSR over all hits of all events).
+
+// per track: its hits as global indices, sorted, and their use counts
+__global__ __launch_bounds__(256) void k_dup_prep(FindParams P, const int *seed_hits, int *hbuf,
+                                                  int *hn, int *cnt) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const int info = P.pinfo[pos];
+  int n = 0;
+  if ((info >> 8) & 1) {
+    const int plen = info & 0xFF;
+    const int *hit = reinterpret_cast<const int *>(P.out + (size_t)pos * kOutWords + kOutHit);
+    const int64_t base = P.ev_off[P.pevent[pos]];
+    const int *sh = seed_hits + (size_t)P.order[pos] * 3;
+    int *h = hbuf + (size_t)pos * kDupStride;
+    auto insert = [&](int v) {  // insertion into the sorted prefix
+      int j = n;
+      while (j > 0 && h[j - 1] > v) {
+        h[j] = h[j - 1];
+        --j;
+      }
+      h[j] = v;
+      ++n;
+    };
+    for (int k = 0; k < 3; ++k) insert((int)(base + sh[k]));
+    for (int s = 0; s < plen; ++s)
+      if (hit[s] >= 0) insert((int)(base + hit[s]));
+    for (int k = 0; k < n; ++k) atomicAdd(&cnt[h[k]], 1);
+  }
+  hn[pos] = n;
+}
+
+__global__ __launch_bounds__(256) void k_dup_fill(FindParams P, const int *hbuf, const int *hn,
+                                                  const int *off, int *fill, int *list) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= P.n_seeds) return;
+  const int *h = hbuf + (size_t)pos * kDupStride;
+  for (int k = 0; k < hn[pos]; ++k) list[off[h[k]] + atomicAdd(&fill[h[k]], 1)] = (int)pos;
+}
+
+__global__ __launch_bounds__(256) void k_dup_decide(FindParams P, const int *seed_hits,
+                                                    const int *hbuf, const int *hn, const int *off,
+                                                    const int *list, float frac, int *out_dup,
+                                                    int *n_dup) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.n_seeds) return;
+  const int nt = hn[t];
+  const int seed_t = P.order[t];
+  bool dup = false;
+  if (nt > 0) {
+    const int *ht = hbuf + (size_t)t * kDupStride;
+    const float chi_t = P.out[(size_t)t * kOutWords + kOutChi2];
+    const int *st = seed_hits + (size_t)seed_t * 3;
+    for (int k = 0; k < nt && !dup; ++k) {
+      const int g = ht[k];
+      for (int j = off[g]; j < off[g + 1] && !dup; ++j) {
+        const int u = list[j];
+        if (u == t) continue;
+        // shared hits, and the first of them in t's list: each partner is
+        // weighed once, at the first hit the two share
+        const int *hu = hbuf + (size_t)u * kDupStride;
+        const int nu = hn[u];
+        int a = 0, b = 0, shared = 0, first = -1;
+        while (a < nt && b < nu) {
+          const int x = ht[a], y = hu[b];
+          if (x == y) {
+            if (first < 0) first = a;
+            ++shared;
+            ++a;
+            ++b;
+          } else if (x < y) {
+            ++a;
+          } else {
+            ++b;
+          }
+        }
+        if (first != k) continue;
+        const int mn = nt < nu ? nt : nu;
+        if ((double)shared < (double)frac * (double)mn) continue;
+        bool before;
+        if (nu != nt) {
+          before = nu > nt;
+        } else {
+          const float chi_u = P.out[(size_t)u * kOutWords + kOutChi2];
+          if (chi_u != chi_t) {
+            before = chi_u < chi_t;
+          } else {
+            const int *su = seed_hits + (size_t)P.order[u] * 3;
+            int q = 0;
+            while (q < 3 && su[q] == st[q]) ++q;
+            before = q < 3 && su[q] < st[q];
+          }
+        }
+        dup = before;
+      }
+    }
+  }
+  out_dup[seed_t] = dup ? 1 : 0;
+  if (dup) atomicAdd(n_dup, 1);
+}
+
 __global__ __launch_bounds__(256) void k_hit_bins(FindParams P, int n_events, int64_t n_hits,
                                                   const int *layer, int *hit_bin, int *counts) {
   __shared__ DevLayer sl[kMaxLayers];
@@ -1923,6 +2032,28 @@ void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc, i
   else
     hipLaunchKernelGGL(k_triplets<false>, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P, sc,
                        n_hits, counts, offsets, out_event, out_hits);
+}
+
+void launch_dup_prep(hipStream_t s, const FindParams &P, const int *seed_hits, int *hbuf, int *hn,
+                     int *cnt) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_dup_prep, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, seed_hits,
+                     hbuf, hn, cnt);
+}
+
+void launch_dup_fill(hipStream_t s, const FindParams &P, const int *hbuf, const int *hn,
+                     const int *off, int *fill, int *list) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_dup_fill, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, hbuf, hn,
+                     off, fill, list);
+}
+
+void launch_dup_decide(hipStream_t s, const FindParams &P, const int *seed_hits, const int *hbuf,
+                       const int *hn, const int *off, const int *list, float frac, int *out_dup,
+                       int *n_dup) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_dup_decide, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     seed_hits, hbuf, hn, off, list, frac, out_dup, n_dup);
 }
 
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,

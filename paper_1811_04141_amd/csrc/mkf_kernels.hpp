@@ -95,6 +95,16 @@ struct DevSeeding {
 // offsets, writes them (event, three event-local hit indices)
 void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc, int64_t n_hits,
                      bool write, int *counts, const int *offsets, int *out_event, int *out_hits);
+// duplicate-track removal: per track its sorted hits (hbuf [n_seeds][kDupStride],
+// hn), the tracks on every hit (CSR: cnt, off, fill, list), the decision
+constexpr int kDupStride = 36;
+void launch_dup_prep(hipStream_t s, const FindParams &P, const int *seed_hits, int *hbuf, int *hn,
+                     int *cnt);
+void launch_dup_fill(hipStream_t s, const FindParams &P, const int *hbuf, const int *hn,
+                     const int *off, int *fill, int *list);
+void launch_dup_decide(hipStream_t s, const FindParams &P, const int *seed_hits, const int *hbuf,
+                       const int *hn, const int *off, const int *list, float frac, int *out_dup,
+                       int *n_dup);
 void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
                      int *hit_bin, int *counts);
 void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, int *tmp_b);

@@ -24,7 +24,8 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_get_stats",
+           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_find_duplicates",
+           "mkf_get_stats",
            "mkf_set_tuning",
            "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
@@ -118,6 +119,7 @@ def _load():
         "mkf_backward_fit": ([P, P, P, P, P], I32),
         "mkf_smooth": ([P, P, P, P], I32),
         "mkf_make_seeds": ([P, C.POINTER(Seeding), I64, P, P, C.POINTER(I64)], I32),
+        "mkf_find_duplicates": ([P, C.c_float, P, C.POINTER(I64)], I32),
         "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
         "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
@@ -275,6 +277,13 @@ class Context:
         if st == MKF_E_CAPACITY:
             raise MkfError(st, f"{n.value} triplets, capacity {capacity}")
         self._check(st)
+        return int(n.value)
+
+    def find_duplicates(self, frac, out_dup):
+        """Duplicate flags of the last find's tracks into a device int32
+        array [n_seeds] (seed order); returns their number."""
+        n = C.c_int64(0)
+        self._check(lib.mkf_find_duplicates(self.h, float(frac), _ptr(out_dup), C.byref(n)))
         return int(n.value)
 
     def set_tuning(self, waves_per_simd, blocks_per_cu):
