@@ -435,7 +435,7 @@ static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
  * The state starts at the first hit with a wide diagonal prior, less its
  * extent along the first seed layer's normal (the state lies on that layer),
  * and is filtered through the three hits (propagate, scatter, update),
- * ending on the third seed layer.  The layer plan (the paper's per-region list of layers to
+ * ending on the third seed layer; chi2 sums the three updates' chi2.  The layer plan (the paper's per-region list of layers to
  * traverse, Section 2.1) is read per seed: every non-seed layer the seed
  * helix crosses inside its widened extent in the remaining half turn,
  * ordered by path length. */
@@ -470,6 +470,7 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
   double p[6] = {x1, y1, z1, ipt, phi1, theta};
   double C[36];
   surface_prior(cfg, p, layers[hl[0]].kind, C);
+  double chi2 = 0.0;
 
   for (int k = 0; k < 3; ++k) {
     const orc_layer *Lr = &layers[hl[k]];
@@ -485,9 +486,11 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
     double c2;
     if (!orc_update_hit(p, C, Lr->kind, &h[3 * k], hv[2 * k], hv[2 * k + 1], &c2))
       return 0;
+    chi2 += c2;
   }
   memcpy(out->par, p, sizeof(p));
   memcpy(out->cov, C, sizeof(C));
+  out->chi2 = chi2;
 
   int n = 0;
   for (int i = 0; i < n_layers; ++i) {
@@ -1163,4 +1166,60 @@ int32_t orc_duplicates(int32_t n, int32_t stride, const int32_t *n_hits, const i
     nd += dup[t];
   }
   return nd;
+}
+
+/* ------------------------------------------------------ seed cleaning */
+
+/* Seed cleaning (Section 2.2: several seeds built from hits of the same
+ * outgoing particle are reduced to one, using the identity of their hits
+ * and their fitted pT, eta and phi).  Reading: seeds s and t of one event
+ * are instances of one particle if they share at least one hit and their
+ * fitted states (on the third seed layer) agree: |q/pT_s - q/pT_t| <=
+ * tol_ipt max(|q/pT_s|, |q/pT_t|), |eta_s - eta_t| <= tol_eta and |phi_s -
+ * phi_t| <= tol_phi (wrapped).  Seed u ranks before t if its fit chi2 is
+ * smaller; with the same chi2, if its hit triplet is lexicographically
+ * smaller.  t is kept if its fit succeeded and no seed ranking before it is
+ * an instance of the same particle.  trip: n x 3 event-local hit indices of
+ * one event; par: n x 6 fitted states; ok: fit succeeded.  fragile[t] = 1 if
+ * the decision involves a closeness test within frag_rel of its tolerance
+ * or two chi2 within frag_rel of each other.  Returns the number kept. */
+int32_t orc_clean_seeds(int32_t n, const int32_t *trip, const int32_t *ok, const double *par,
+                        const double *chi2, double tol_ipt, double tol_eta, double tol_phi,
+                        double frag_rel, int32_t *keep, int32_t *fragile) {
+  int32_t nk = 0;
+  for (int32_t t = 0; t < n; ++t) {
+    keep[t] = ok[t] ? 1 : 0;
+    fragile[t] = 0;
+    if (!ok[t]) continue;
+    const double eta_t = -log(tan(0.5 * par[6 * t + 5]));
+    for (int32_t u = 0; u < n; ++u) {
+      if (u == t || !ok[u]) continue;
+      int share = 0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) share |= trip[3 * t + i] == trip[3 * u + j];
+      if (!share) continue;
+      const double eta_u = -log(tan(0.5 * par[6 * u + 5]));
+      const double a = par[6 * t + 3], b = par[6 * u + 3];
+      const double m_ipt = tol_ipt * fmax(fabs(a), fabs(b)) - fabs(a - b);
+      const double m_eta = tol_eta - fabs(eta_t - eta_u);
+      const double m_phi = tol_phi - fabs(wrap_phi(par[6 * t + 4] - par[6 * u + 4]));
+      if (fabs(m_ipt) <= frag_rel * tol_ipt * fmax(fabs(a), fabs(b)) ||
+          fabs(m_eta) <= frag_rel * tol_eta || fabs(m_phi) <= frag_rel * tol_phi)
+        fragile[t] = 1;
+      if (m_ipt < 0.0 || m_eta < 0.0 || m_phi < 0.0) continue;
+      int before;
+      if (fabs(chi2[u] - chi2[t]) <= frag_rel * fmax(fabs(chi2[u]), fabs(chi2[t])))
+        fragile[t] = 1;
+      if (chi2[u] != chi2[t]) {
+        before = chi2[u] < chi2[t];
+      } else {
+        int k = 0;
+        while (k < 3 && trip[3 * u + k] == trip[3 * t + k]) ++k;
+        before = k < 3 && trip[3 * u + k] < trip[3 * t + k];
+      }
+      if (before) keep[t] = 0;
+    }
+    nk += keep[t];
+  }
+  return nk;
 }

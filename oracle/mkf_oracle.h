@@ -115,6 +115,7 @@ typedef struct {
   int32_t plan[ORC_MAX_PLAN];
   double plan_l[ORC_MAX_PLAN];
   int32_t plan_fragile; /* a crossing lies within tol of a widened edge */
+  double chi2;          /* sum of the three hit updates' chi2 */
 } orc_seed_out;
 
 /* h: 3 hits x (x,y,z); hv: 3 hits x (var_u, var_v); hl: their layers.
@@ -218,6 +219,15 @@ int64_t orc_triplet_seeds(const orc_cfg *cfg, const orc_seeding *sc, int32_t n_h
 int32_t orc_duplicates(int32_t n, int32_t stride, const int32_t *n_hits, const int32_t *hits,
                        const double *chi2, const int32_t *seed, double frac, double chi2_tol_rel,
                        double chi2_tol_abs, int32_t *dup, int32_t *fragile);
+
+/* ---- seed cleaning (Section 2.2) ------------------------------------ */
+
+/* Keeps a seed unless a seed ranking before it (smaller fit chi2, then
+ * smaller triplet) shares a hit with it and agrees in q/pT, eta and phi
+ * within the tolerances.  Returns the number kept. */
+int32_t orc_clean_seeds(int32_t n, const int32_t *trip, const int32_t *ok, const double *par,
+                        const double *chi2, double tol_ipt, double tol_eta, double tol_phi,
+                        double frag_rel, int32_t *keep, int32_t *fragile);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,8 @@ class Cfg(C.Structure):
 class SeedOut(C.Structure):
     _fields_ = [("ok", C.c_int32), ("par", C.c_double * 6), ("cov", C.c_double * 36),
                 ("plan_len", C.c_int32), ("plan", C.c_int32 * MAX_PLAN),
-                ("plan_l", C.c_double * MAX_PLAN), ("plan_fragile", C.c_int32)]
+                ("plan_l", C.c_double * MAX_PLAN), ("plan_fragile", C.c_int32),
+                ("chi2", C.c_double)]
 
 
 class Track(C.Structure):
@@ -108,6 +109,9 @@ def lib():
         L.orc_duplicates.argtypes = [C.c_int32, C.c_int32, _I, _I, _D, _I, C.c_double, C.c_double,
                                      C.c_double, _I, _I]
         L.orc_duplicates.restype = C.c_int32
+        L.orc_clean_seeds.argtypes = [C.c_int32, _I, _I, _D, _D, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, _I, _I]
+        L.orc_clean_seeds.restype = C.c_int32
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
         L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
         L.orc_mlp_grad.restype = C.c_double
@@ -261,7 +265,8 @@ def seed(fc, layers, h, hv, hl, pos_tol=0.0):
     n = out.plan_len
     return {"ok": bool(out.ok), "par": np.array(out.par[:]),
             "cov": np.array(out.cov[:]).reshape(6, 6), "plan": np.array(out.plan[:n], np.int32),
-            "plan_l": np.array(out.plan_l[:n]), "plan_fragile": bool(out.plan_fragile)}
+            "plan_l": np.array(out.plan_l[:n]), "plan_fragile": bool(out.plan_fragile),
+            "chi2": float(out.chi2)}
 
 
 DEFAULT_TOL = (1e-3, 1e-2, 1e-3)  # chi2 rel, chi2 abs, cm
@@ -440,3 +445,22 @@ def duplicates(hit_sets, chi2, seeds, frac=0.5, chi2_tol=(1e-3, 1e-2)):
     lib().orc_duplicates(n, stride, _p(nh, _I), _p(H, _I), _p(c2), _p(sd, _I), frac,
                          chi2_tol[0], chi2_tol[1], _p(dup, _I), _p(frag, _I))
     return dup[:n].astype(bool), frag[:n].astype(bool)
+
+
+def clean_seeds(trip, ok, par, chi2, tol_ipt, tol_eta, tol_phi, frag_rel=1e-4):
+    """Seed cleaning of one event's seeds: (keep [n] bool, fragile [n] bool)."""
+    n = len(trip)
+    m = max(n, 1)
+    T = np.zeros((m, 3), np.int32)
+    T[:n] = np.asarray(trip, np.int32).reshape(-1, 3)
+    O_ = np.zeros(m, np.int32)
+    O_[:n] = np.asarray(ok, np.int32)
+    Pm = np.zeros((m, 6))
+    Pm[:n] = np.asarray(par, float).reshape(-1, 6)
+    c2 = np.zeros(m)
+    c2[:n] = np.asarray(chi2, float)
+    keep = np.zeros(m, np.int32)
+    frag = np.zeros(m, np.int32)
+    lib().orc_clean_seeds(n, _p(T, _I), _p(O_, _I), _p(Pm), _p(c2), tol_ipt, tol_eta, tol_phi,
+                          frag_rel, _p(keep, _I), _p(frag, _I))
+    return keep[:n].astype(bool), frag[:n].astype(bool)

@@ -1,5 +1,6 @@
 """Seeded synthetic inputs (geometry, events, seeds) shared by the tests, the
 benchmark and the smoke check.  Input side only: no part of the method."""
-from .workloads import (BARREL, DISK, KAPPA, EventRecipe, FindConfig, Layer, SeedingConfig, Workload,
+from .workloads import (BARREL, DISK, KAPPA, CleaningConfig, EventRecipe, FindConfig, Layer, SeedingConfig,
+                        Workload,
                         barrel_endcap, batched_uneven, dense, layer_arrays, small_barrel)
 from .events import Event, EventBatch, generate, generate_event, make_batch, simulate_tracks

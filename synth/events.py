@@ -13,7 +13,7 @@ Random numbers come from numpy's Philox counter-based generator, keyed by
 own.
 """
 from dataclasses import dataclass
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -237,12 +237,17 @@ def _noise(rng, layers, counts, frac):
             np.concatenate(vus), np.concatenate(vvs), np.concatenate(ls))
 
 
-def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None) -> Event:
+def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None,
+                   phi_range: Optional[Tuple[float, float]] = None) -> Event:
+    """One seeded event.  phi_range confines the tracks' initial azimuth (a
+    dense, jet-like event: the hit density of many more tracks in a sector,
+    at the cost of few)."""
     rng = event_rng(w.master_seed, event)
     lo, hi = w.n_tracks
     if n_tracks is None:
         n_tracks = lo if lo == hi else int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
-    init, trk, lay, st = simulate_tracks(rng, n_tracks, w.layers, w.find.bz, w.recipe)
+    phi = None if phi_range is None else rng.uniform(phi_range[0], phi_range[1], n_tracks)
+    init, trk, lay, st = simulate_tracks(rng, n_tracks, w.layers, w.find.bz, w.recipe, phi=phi)
     # 2% (or as configured) independent loss of hits
     if w.recipe.hit_ineff > 0.0:
         keep = rng.random(trk.shape[0]) >= w.recipe.hit_ineff

@@ -81,6 +81,16 @@ class SeedingConfig:
 
 
 @dataclass(frozen=True)
+class CleaningConfig:
+    """Seed cleaning (readings): seeds sharing a hit are instances of one
+    particle if their fitted q/pT agree within tol_ipt (relative), eta
+    within tol_eta and phi within tol_phi (rad)."""
+    tol_ipt: float = 0.1
+    tol_eta: float = 0.02
+    tol_phi: float = 0.02
+
+
+@dataclass(frozen=True)
 class EventRecipe:
     pt_lo: float = 0.5
     pt_hi: float = 10.0
