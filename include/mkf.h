@@ -131,6 +131,13 @@ typedef struct {
   float dz_max;      /* cm: middle hit off the s-z line through the outer two */
 } mkf_seeding;
 
+/* Tolerances of the seed cleaning (mkf_clean_seeds). */
+typedef struct {
+  float tol_ipt; /* q/pT, relative to the larger of the two */
+  float tol_eta;
+  float tol_phi; /* rad */
+} mkf_cleaning;
+
 typedef struct mkf_ctx mkf_ctx;
 
 /* Create a context.  cfg is copied.  stream: a hipStream_t (NULL = the
@@ -169,9 +176,10 @@ mkf_status mkf_seed(mkf_ctx *ctx, int64_t n_seeds, const int32_t *seed_event,
 
 /* Seed states after the triplet fit (host outputs, each may be NULL):
  * par [n_seeds][6], cov [n_seeds][21], ok [n_seeds], plan_len [n_seeds],
- * plan [n_seeds][MKF_MAX_PLAN] (layer ids).  Blocks until done. */
+ * plan [n_seeds][MKF_MAX_PLAN] (layer ids), chi2 [n_seeds] (sum of the
+ * three hit updates' chi2).  Blocks until done. */
 mkf_status mkf_get_seed_states(mkf_ctx *ctx, float *par, float *cov, int32_t *ok,
-                               int32_t *plan_len, int8_t *plan);
+                               int32_t *plan_len, int8_t *plan, float *chi2);
 
 /* Clone-engine track finding over all seeds (the timed hot path). */
 mkf_status mkf_find(mkf_ctx *ctx);
@@ -275,6 +283,21 @@ mkf_status mkf_make_seeds(mkf_ctx *ctx, const mkf_seeding *sc, int64_t capacity,
  * Device scratch of ~150 B per seed and 12 B per hit, held by the context.
  * Blocks until done. */
 mkf_status mkf_find_duplicates(mkf_ctx *ctx, float frac, int32_t *out_dup, int64_t *n_dup);
+
+/* Seed cleaning of the last mkf_seed's seeds (Section 2.2: several seeds
+ * built from hits of the same outgoing particle are reduced to one, using
+ * the identity of their hits and their fitted pT, eta and phi).  Seeds of
+ * one event sharing a hit are instances of one particle if their fitted
+ * states (on the third seed layer) agree: |q/pT_s - q/pT_t| <= tol_ipt
+ * max(|q/pT_s|, |q/pT_t|), |eta_s - eta_t| <= tol_eta, |phi_s - phi_t| <=
+ * tol_phi.  Seed u ranks before t if its fit chi2 is smaller; with the same
+ * chi2, if its hit triplet is lexicographically smaller.  t is kept if its
+ * fit succeeded and no seed ranking before it is an instance of the same
+ * particle.  Device output out_keep [n_seeds] (seed order, 1 = keep);
+ * *n_keep receives their number.  The kept seeds can go back to mkf_seed.
+ * Blocks until done. */
+mkf_status mkf_clean_seeds(mkf_ctx *ctx, const mkf_cleaning *cc, int32_t *out_keep,
+                           int64_t *n_keep);
 
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);

@@ -70,6 +70,7 @@ struct mkf_ctx {
   // seeds
   int64_t n_seeds = 0;
   DevBuf d_seed_event, d_seed_hits, d_seed_state, d_seed_ok, d_plan_len, d_plan, d_plan_l;
+  DevBuf d_seed_chi2;
   DevBuf d_order, d_pstate, d_pinfo, d_pevent, d_pplan;
   DevBuf d_bf_tmp;  // backward fit: state between its FP64 and FP32 parts
   DevBuf d_sm_wk, d_sm_n;  // smoothing: forward-pass states per surface, surface counts
@@ -107,7 +108,7 @@ struct mkf_ctx {
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
                      &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
                      &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n, &d_tr_cnt, &d_tr_off, &d_tr_tmp, &d_dup_h, &d_dup_n, &d_dup_cnt, &d_dup_off,
-                     &d_dup_fill, &d_dup_list, &d_dup_tmp, &d_dup_total};
+                     &d_dup_fill, &d_dup_list, &d_dup_tmp, &d_dup_total, &d_seed_chi2};
     for (DevBuf *b : all) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -520,12 +521,13 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   HIP_TRY(c, c->d_plan.ensure(kMaxPlan * N));
   HIP_TRY(c, c->d_plan_l.ensure(sizeof(double) * kMaxPlan * N));
   HIP_TRY(c, c->d_order.ensure(4 * N));
+  HIP_TRY(c, c->d_seed_chi2.ensure(4 * N));
   c->n_seeds = n_seeds;
   FindParams P = params(c);
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   launch_seed(c->stream, P, c->d_seed_hits.as<int>(), c->d_seed_state.as<float>(),
               c->d_seed_ok.as<int>(), c->d_plan_len.as<int>(), c->d_plan.as<int8_t>(),
-              c->d_plan_l.as<double>());
+              c->d_plan_l.as<double>(), c->d_seed_chi2.as<float>());
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
   // processing order: longest plans first (the persistent form takes tiles
@@ -633,7 +635,7 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
 }
 
 mkf_status mkf_get_seed_states(mkf_ctx *c, float *par, float *cov, int32_t *ok,
-                               int32_t *plan_len, int8_t *plan) {
+                               int32_t *plan_len, int8_t *plan, float *chi2) {
   if (!c) return MKF_E_ARG;
   if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
   const size_t n = (size_t)c->n_seeds, N = std::max<size_t>(n, 1);
@@ -646,6 +648,8 @@ mkf_status mkf_get_seed_states(mkf_ctx *c, float *par, float *cov, int32_t *ok,
     HIP_TRY(c, hipMemcpyAsync(plan_len, c->d_plan_len.ptr, 4 * n, hipMemcpyDeviceToHost, c->stream));
   if (plan)
     HIP_TRY(c, hipMemcpyAsync(plan, c->d_plan.ptr, kMaxPlan * n, hipMemcpyDeviceToHost, c->stream));
+  if (chi2)
+    HIP_TRY(c, hipMemcpyAsync(chi2, c->d_seed_chi2.ptr, 4 * n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (size_t i = 0; i < n; ++i) {
     if (par)
@@ -932,6 +936,47 @@ mkf_status mkf_find_duplicates(mkf_ctx *c, float frac, int32_t *out_dup, int64_t
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   *n_dup = total;
+  return MKF_OK;
+}
+
+mkf_status mkf_clean_seeds(mkf_ctx *c, const mkf_cleaning *cc, int32_t *out_keep,
+                           int64_t *n_keep) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
+  if (!cc || !n_keep || (c->n_seeds > 0 && !out_keep)) return fail(c, MKF_E_ARG, "NULL argument");
+  if (!(cc->tol_ipt >= 0.f) || !(cc->tol_eta >= 0.f) || !(cc->tol_phi >= 0.f))
+    return fail(c, MKF_E_ARG, "tolerances must not be negative");
+  *n_keep = 0;
+  if (c->n_seeds == 0) return MKF_OK;
+  const size_t N = (size_t)c->n_seeds, H = (size_t)std::max<int64_t>(c->n_hits, 1);
+  // the duplicate-removal scratch serves here too (3 hits per seed)
+  HIP_TRY(c, c->d_dup_h.ensure(sizeof(int) * 3 * N));
+  HIP_TRY(c, c->d_dup_cnt.ensure(sizeof(int) * H));
+  HIP_TRY(c, c->d_dup_off.ensure(sizeof(int) * (H + 1)));
+  HIP_TRY(c, c->d_dup_fill.ensure(sizeof(int) * H));
+  HIP_TRY(c, c->d_dup_list.ensure(sizeof(int) * 3 * N));
+  HIP_TRY(c, c->d_dup_tmp.ensure(sizeof(int) * (4 * (H / 2048 + 4) + 64)));
+  HIP_TRY(c, c->d_dup_total.ensure(sizeof(int)));
+  FindParams P = params(c);
+  DevCleaning dc{cc->tol_ipt, cc->tol_eta, cc->tol_phi};
+  launch_fill_i32(c->stream, c->d_dup_cnt.as<int>(), (int64_t)H, 0);
+  launch_fill_i32(c->stream, c->d_dup_fill.as<int>(), (int64_t)H, 0);
+  launch_fill_i32(c->stream, c->d_dup_total.as<int>(), 1, 0);
+  launch_clean_prep(c->stream, P, c->d_seed_hits.as<int>(), c->d_dup_h.as<int>(),
+                    c->d_dup_cnt.as<int>());
+  launch_scan(c->stream, c->d_dup_cnt.as<int>(), c->d_dup_off.as<int>(), (int64_t)H,
+              c->d_dup_tmp.as<int>(), nullptr);
+  launch_clean_fill(c->stream, P, c->d_dup_h.as<int>(), c->d_dup_off.as<int>(),
+                    c->d_dup_fill.as<int>(), c->d_dup_list.as<int>());
+  launch_clean_decide(c->stream, P, c->d_seed_hits.as<int>(), c->d_seed_chi2.as<float>(),
+                      c->d_dup_h.as<int>(), c->d_dup_off.as<int>(), c->d_dup_list.as<int>(), dc,
+                      out_keep, c->d_dup_total.as<int>());
+  HIP_TRY(c, hipGetLastError());
+  int total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, c->d_dup_total.ptr, sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *n_keep = total;
   return MKF_OK;
 }
 

@@ -840,7 +840,7 @@ __global__ __launch_bounds__(256) void k_permute_seeds(FindParams P, float *psta
 
 __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits,
                                               float *seed_state, int *seed_ok, int *plan_len,
-                                              int8_t *plan, double *plan_l) {
+                                              int8_t *plan, double *plan_l, float *seed_chi2) {
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
   __syncthreads();
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
   const double ms_var = (double)P.cfg.ms_var;
   int ok = 0;
   int n = 0;
-  double p[6], c[21];
+  double p[6], c[21], chi2 = 0.0;
   do {
     const double ax = hx[1] - hx[0], ay = hy[1] - hy[0];
     const double bx = hx[2] - hx[0], by = hy[2] - hy[0];
@@ -889,6 +889,7 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     const double theta = atan2(rho * fabs(dpsi), hz[2] - hz[0]);
     p[0] = hx[0]; p[1] = hy[0]; p[2] = hz[0]; p[3] = ipt; p[4] = phi1; p[5] = theta;
     surface_prior(P.cfg, p, sl[hl[0]].kind, c);
+    chi2 = 0.0;
     bool good = true;
     for (int k = 0; k < 3 && good; ++k) {
       const DevLayer &L = sl[hl[k]];
@@ -909,6 +910,7 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
         good = false;
         break;
       }
+      chi2 += chi2_of(f, hvu[k], hvv[k], u, v);
       kf_update(p, c, f, L.kind, hvu[k], hvv[k], u, v);
     }
     if (!good) break;
@@ -933,6 +935,7 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     }
   } while (false);
   seed_ok[i] = ok;
+  seed_chi2[i] = ok ? (float)chi2 : 0.f;
   plan_len[i] = ok ? n : 0;
   for (int k = 0; k < 6; ++k) seed_state[k * N + i] = ok ? (float)p[k] : 0.f;
   for (int k = 0; k < 21; ++k) seed_state[(6 + k) * N + i] = ok ? (float)c[k] : 0.f;
@@ -1205,6 +1208,98 @@ __global__ __launch_bounds__(256) void k_dup_decide(FindParams P, const int *see
   }
   out_dup[seed_t] = dup ? 1 : 0;
   if (dup) atomicAdd(n_dup, 1);
+}
+
+// -------------------------------------------------------- seed cleaning
+//
+// Seed cleaning (Section 2.2: seeds built from hits of the same outgoing
+// particle are reduced to one, using the identity of their hits and their
+// fitted pT, eta and phi).  Seeds sharing a hit are instances of one
+// particle if their fitted q/pT agree within tol_ipt (relative to the
+// larger), eta within tol_eta and phi within tol_phi.  Seed u ranks before t
+// if its fit chi2 is smaller; with the same chi2, if its hit triplet is
+// lexicographically smaller.  t is kept if its fit succeeded and no seed
+// ranking before it is an instance of the same particle.  Seeds sharing a
+// hit are found through a hit -> seeds table, as for duplicate tracks.
+
+__global__ __launch_bounds__(256) void k_clean_prep(FindParams P, const int *seed_hits, int *hbuf,
+                                                    int *cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n_seeds) return;
+  int h[3] = {-1, -1, -1};
+  if (P.seed_ok[i]) {
+    const int64_t base = P.ev_off[P.seed_event[i]];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) h[k] = (int)(base + seed_hits[3 * i + k]);
+    // sort three
+    if (h[0] > h[1]) { const int t = h[0]; h[0] = h[1]; h[1] = t; }
+    if (h[1] > h[2]) { const int t = h[1]; h[1] = h[2]; h[2] = t; }
+    if (h[0] > h[1]) { const int t = h[0]; h[0] = h[1]; h[1] = t; }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) atomicAdd(&cnt[h[k]], 1);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) hbuf[3 * i + k] = h[k];
+}
+
+__global__ __launch_bounds__(256) void k_clean_fill(FindParams P, const int *hbuf, const int *off,
+                                                    int *fill, int *list) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n_seeds || hbuf[3 * i] < 0) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int g = hbuf[3 * i + k];
+    list[off[g] + atomicAdd(&fill[g], 1)] = (int)i;
+  }
+}
+
+__device__ __forceinline__ float eta_of(float theta) { return -logf(tanf(0.5f * theta)); }
+
+__global__ __launch_bounds__(256) void k_clean_decide(FindParams P, const int *seed_hits,
+                                                      const float *seed_chi2, const int *hbuf,
+                                                      const int *off, const int *list,
+                                                      DevCleaning cc, int *out_keep,
+                                                      int *n_keep) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.n_seeds) return;
+  bool keep = P.seed_ok[t] != 0;
+  if (keep) {
+    const size_t N = (size_t)P.n_seeds;
+    const float ipt_t = P.seed_state[3 * N + t], phi_t = P.seed_state[4 * N + t];
+    const float eta_t = eta_of(P.seed_state[5 * N + t]);
+    const float chi_t = seed_chi2[t];
+    const int *ht = hbuf + 3 * t;
+    for (int k = 0; k < 3 && keep; ++k) {
+      const int g = ht[k];
+      for (int j = off[g]; j < off[g + 1] && keep; ++j) {
+        const int u = list[j];
+        if (u == t) continue;
+        // weigh each partner once, at the first hit the two share
+        const int *hu = hbuf + 3 * (size_t)u;
+        int first = -1;
+        for (int a = 0; a < 3 && first < 0; ++a)
+          if (ht[a] == hu[0] || ht[a] == hu[1] || ht[a] == hu[2]) first = a;
+        if (first != k) continue;
+        const float ipt_u = P.seed_state[3 * N + u];
+        if (fabsf(ipt_t - ipt_u) > cc.tol_ipt * fmaxf(fabsf(ipt_t), fabsf(ipt_u))) continue;
+        if (fabsf(eta_t - eta_of(P.seed_state[5 * N + u])) > cc.tol_eta) continue;
+        if (fabsf(wrap_phi(phi_t - P.seed_state[4 * N + u])) > cc.tol_phi) continue;
+        const float chi_u = seed_chi2[u];
+        bool before;
+        if (chi_u != chi_t) {
+          before = chi_u < chi_t;
+        } else {
+          const int *su = seed_hits + 3 * (size_t)u, *st = seed_hits + 3 * t;
+          int q = 0;
+          while (q < 3 && su[q] == st[q]) ++q;
+          before = q < 3 && su[q] < st[q];
+        }
+        if (before) keep = false;
+      }
+    }
+  }
+  out_keep[t] = keep ? 1 : 0;
+  if (keep) atomicAdd(n_keep, 1);
 }
 
 __global__ __launch_bounds__(256) void k_hit_bins(FindParams P, int n_events, int64_t n_hits,
@@ -1933,10 +2028,10 @@ void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, 
 }
 
 void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
-                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l) {
+                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l, float *seed_chi2) {
   if (P.n_seeds == 0) return;
   hipLaunchKernelGGL(k_seed, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, seed_hits,
-                     seed_state, seed_ok, plan_len, plan, plan_l);
+                     seed_state, seed_ok, plan_len, plan, plan_l, seed_chi2);
 }
 
 void launch_find_init(hipStream_t s, const FindParams &P) {
@@ -2054,6 +2149,28 @@ void launch_dup_decide(hipStream_t s, const FindParams &P, const int *seed_hits,
   if (P.n_seeds == 0) return;
   hipLaunchKernelGGL(k_dup_decide, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
                      seed_hits, hbuf, hn, off, list, frac, out_dup, n_dup);
+}
+
+void launch_clean_prep(hipStream_t s, const FindParams &P, const int *seed_hits, int *hbuf,
+                       int *cnt) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_clean_prep, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     seed_hits, hbuf, cnt);
+}
+
+void launch_clean_fill(hipStream_t s, const FindParams &P, const int *hbuf, const int *off,
+                       int *fill, int *list) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_clean_fill, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, hbuf,
+                     off, fill, list);
+}
+
+void launch_clean_decide(hipStream_t s, const FindParams &P, const int *seed_hits,
+                         const float *seed_chi2, const int *hbuf, const int *off,
+                         const int *list, const DevCleaning &cc, int *out_keep, int *n_keep) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_clean_decide, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P,
+                     seed_hits, seed_chi2, hbuf, off, list, cc, out_keep, n_keep);
 }
 
 void launch_validate_hits(hipStream_t s, int64_t n, const float *x, const float *y,

@@ -105,13 +105,24 @@ void launch_dup_fill(hipStream_t s, const FindParams &P, const int *hbuf, const 
 void launch_dup_decide(hipStream_t s, const FindParams &P, const int *seed_hits, const int *hbuf,
                        const int *hn, const int *off, const int *list, float frac, int *out_dup,
                        int *n_dup);
+// seed cleaning: tolerances, and the seeds' sorted global hits (hbuf [n_seeds][3])
+struct DevCleaning {
+  float tol_ipt, tol_eta, tol_phi;
+};
+void launch_clean_prep(hipStream_t s, const FindParams &P, const int *seed_hits, int *hbuf,
+                       int *cnt);
+void launch_clean_fill(hipStream_t s, const FindParams &P, const int *hbuf, const int *off,
+                       int *fill, int *list);
+void launch_clean_decide(hipStream_t s, const FindParams &P, const int *seed_hits,
+                         const float *seed_chi2, const int *hbuf, const int *off,
+                         const int *list, const DevCleaning &cc, int *out_keep, int *n_keep);
 void launch_hit_bins(hipStream_t s, const FindParams &P, int64_t n_hits, const int *layer,
                      int *hit_bin, int *counts);
 void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, int *tmp_b);
 void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const int *hit_bin,
                     int *fill, HitRec *sorted, HitRec *byorig);
 void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
-                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l);
+                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l, float *seed_chi2);
 void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int *pinfo,
                           int *pevent, int8_t *pplan);
 void launch_find_init(hipStream_t s, const FindParams &P);

@@ -24,7 +24,8 @@ HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
-           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_find_duplicates",
+           "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_clean_seeds",
+           "mkf_find_duplicates",
            "mkf_get_stats",
            "mkf_set_tuning",
            "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
@@ -77,6 +78,10 @@ def make_seeding(sc):
     return s
 
 
+class Cleaning(C.Structure):
+    _fields_ = [("tol_ipt", C.c_float), ("tol_eta", C.c_float), ("tol_phi", C.c_float)]
+
+
 class Stats(C.Structure):
     _fields_ = [("n_seeds", C.c_int64), ("n_seeds_ok", C.c_int64), ("n_steps", C.c_int64),
                 ("max_plan_len", C.c_int32), ("n_launches", C.c_int32), ("find_ms", C.c_float),
@@ -111,7 +116,7 @@ def _load():
         "mkf_load_geometry": ([P, C.POINTER(Layer), I32], I32),
         "mkf_load_hits": ([P, I32, P, P, P, P, P, P, P, I32], I32),
         "mkf_seed": ([P, I64, P, P, I32], I32),
-        "mkf_get_seed_states": ([P, P, P, P, P, P], I32),
+        "mkf_get_seed_states": ([P, P, P, P, P, P, P], I32),
         "mkf_find": ([P], I32),
         "mkf_get_tracks": ([P, P, I64, C.POINTER(I64)], I32),
         "mkf_propagate": ([P, I64, P, P, P, P, P, P, P], I32),
@@ -120,6 +125,7 @@ def _load():
         "mkf_smooth": ([P, P, P, P], I32),
         "mkf_make_seeds": ([P, C.POINTER(Seeding), I64, P, P, C.POINTER(I64)], I32),
         "mkf_find_duplicates": ([P, C.c_float, P, C.POINTER(I64)], I32),
+        "mkf_clean_seeds": ([P, C.POINTER(Cleaning), P, C.POINTER(I64)], I32),
         "mkf_get_stats": ([P, C.POINTER(Stats)], I32),
         "mkf_set_tuning": ([P, C.POINTER(Tuning)], I32),
         "mkf_get_tuning": ([P, C.POINTER(Tuning)], I32),
@@ -229,9 +235,10 @@ class Context:
         ok = np.zeros(n, np.int32)
         plen = np.zeros(n, np.int32)
         plan = np.zeros((n, MAX_PLAN), np.int8)
+        chi2 = np.zeros(n, np.float32)
         self._check(lib.mkf_get_seed_states(self.h, _ptr(par), _ptr(cov), _ptr(ok), _ptr(plen),
-                                            _ptr(plan)))
-        return par, cov, ok, plen, plan
+                                            _ptr(plan), _ptr(chi2)))
+        return par, cov, ok, plen, plan, chi2
 
     def find(self):
         self._check(lib.mkf_find(self.h))
@@ -277,6 +284,14 @@ class Context:
         if st == MKF_E_CAPACITY:
             raise MkfError(st, f"{n.value} triplets, capacity {capacity}")
         self._check(st)
+        return int(n.value)
+
+    def clean_seeds(self, cleaning, out_keep):
+        """Seed cleaning of the loaded seeds into a device int32 array
+        [n_seeds] (seed order, 1 = keep); returns the number kept."""
+        cc = Cleaning(cleaning.tol_ipt, cleaning.tol_eta, cleaning.tol_phi)
+        n = C.c_int64(0)
+        self._check(lib.mkf_clean_seeds(self.h, C.byref(cc), _ptr(out_keep), C.byref(n)))
         return int(n.value)
 
     def find_duplicates(self, frac, out_dup):

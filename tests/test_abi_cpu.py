@@ -61,6 +61,7 @@ def test_host_side_argument_errors():
     assert lib.mkf_smooth(None, None, None, None) == mkf.MKF_E_ARG
     assert lib.mkf_make_seeds(None, None, 0, None, None, None) == mkf.MKF_E_ARG
     assert lib.mkf_find_duplicates(None, 0.5, None, None) == mkf.MKF_E_ARG
+    assert lib.mkf_clean_seeds(None, None, None, None) == mkf.MKF_E_ARG
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):

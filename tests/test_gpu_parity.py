@@ -114,7 +114,7 @@ def test_seed_states_match_oracle(mkf, wname):
     ctx.load_geometry(w.layers)
     ctx.load_hits(b.ev_off, dev(b.x), dev(b.y), dev(b.z), dev(b.var_u), dev(b.var_v), dev(b.layer))
     ctx.seed(dev(b.seed_event), dev(b.seed_hits))
-    par, cov, ok, plen, plan = ctx.get_seed_states(b.seed_hits.shape[0])
+    par, cov, ok, plen, plan, chi2 = ctx.get_seed_states(b.seed_hits.shape[0])
     ctx.close()
     bad = 0
     for s in range(b.seed_hits.shape[0]):
@@ -128,6 +128,7 @@ def test_seed_states_match_oracle(mkf, wname):
         good, rel = PT.par_ok(par[s], r["par"])
         assert good, (s, rel)
         assert PT.cov_ok(mkf.unpack_cov(cov[s]), r["cov"]), s
+        assert PT.chi2_ok(chi2[s], r["chi2"]), (s, chi2[s], r["chi2"])
         if list(plan[s, :plen[s]]) != list(r["plan"]):
             assert r["plan_fragile"], (s, plan[s, :plen[s]], r["plan"])
             bad += 1
