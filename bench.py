@@ -106,8 +106,9 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
     """Throughput of the other hot-path kernels, each from HIP events on the
     context stream around one launch after a warm-up: the search-free fit
     (131,072 tracks x 26 layers), the backward fit and the smoothing of the
-    benchmark workload's found tracks, and the surrogate network's inference
-    and gradient (2^20 samples from its training sampler)."""
+    benchmark workload's found tracks, triplet seeding with cleaning, find and
+    duplicate removal on it, and the surrogate network's inference and
+    gradient (2^20 samples from its training sampler)."""
     import numpy as np
     import torch
 
@@ -172,6 +173,48 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
                                                f"{nsurf} surfaces"}
         del sm
         ctx2.close()
+        # combinatorial triplet seeding, seed cleaning, the find from all the
+        # triplet seeds and duplicate removal on the same workload (each call
+        # between HIP events on the context stream; the seeding and removal
+        # calls wait on the host for their counts inside that span)
+        from synth import CleaningConfig, SeedingConfig
+        ctx3 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+        ctx3.load_geometry(w.layers)
+        ctx3.load_hits(batch.ev_off, *hits)
+        cap = 8 << 20
+        sev = torch.zeros(cap, dtype=torch.int32, device=dev)
+        shit = torch.zeros((cap, 3), dtype=torch.int32, device=dev)
+        nt = [0]
+
+        def mk():
+            nt[0] = ctx3.make_seeds(SeedingConfig(), cap, sev, shit)
+
+        ms_seed = timed(mk)
+        ctx3.seed(sev[:nt[0]], shit[:nt[0]])
+        keep = torch.zeros(nt[0], dtype=torch.int32, device=dev)
+        nk = [0]
+
+        def cl():
+            nk[0] = ctx3.clean_seeds(CleaningConfig(), keep)
+
+        ms_clean = timed(cl)
+        ctx3.find()
+        ctx3.find()
+        find_ms = ctx3.stats()["find_ms"]
+        dup = torch.zeros(nt[0], dtype=torch.int32, device=dev)
+        nd = [0]
+
+        def dd():
+            nd[0] = ctx3.find_duplicates(0.5, dup)
+
+        ms_dup = timed(dd)
+        out["triplet_seeding_pipeline"] = {
+            "workload": f"{w.name}, seeds from every triplet of layers 0-2",
+            "triplets": nt[0], "make_seeds_ms": ms_seed, "clean_seeds_ms": ms_clean,
+            "kept_after_cleaning": nk[0], "find_ms_all_triplet_seeds": find_ms,
+            "duplicates": nd[0], "find_duplicates_ms": ms_dup}
+        del sev, shit, keep, dup
+        ctx3.close()
         m = 1 << 20
         x = torch.zeros((m, 8), device=dev)
         t = torch.zeros((m, 7), device=dev)

@@ -263,8 +263,8 @@ mkf_status mkf_smooth(mkf_ctx *ctx, float *out_par, float *out_cov, int32_t *out
  * z0_max at the point of closest approach to the beam line, which precedes
  * a within half a turn.  The cuts are evaluated in FP64.  Device outputs:
  * out_event [capacity], out_hits [capacity][3] (event-local hit indices,
- * innermost first), ordered by the caller's order of a, then by the hit
- * index's bin order of b and c; *n_total receives the number of triplets.
+ * innermost first), ordered by event, then by the hit index's bin order of
+ * a, b and c; *n_total receives the number of triplets.
  * If it exceeds capacity nothing is written and MKF_E_CAPACITY returned.
  * The outputs can go to mkf_seed with MKF_MEM_DEVICE.  Blocks until done. */
 mkf_status mkf_make_seeds(mkf_ctx *ctx, const mkf_seeding *sc, int64_t capacity,

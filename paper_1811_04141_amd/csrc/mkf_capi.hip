@@ -868,6 +868,7 @@ mkf_status mkf_make_seeds(mkf_ctx *c, const mkf_seeding *sc, int64_t capacity,
   if (!(sc->pt_min > 0.f) || !(sc->d0_max > 0.f) || !(sc->z0_max > 0.f) || !(sc->dz_max > 0.f))
     return fail(c, MKF_E_ARG, "seeding cuts must be positive");
   if (c->cfg.bz == 0.f) return fail(c, MKF_E_ARG, "triplet seeding needs a field");
+  if (c->n_events > 65535) return fail(c, MKF_E_CAPACITY, "triplet seeding takes <= 65535 events");
   *n_total = 0;
   const int64_t n = c->n_hits;
   if (n == 0) return MKF_OK;
@@ -881,7 +882,11 @@ mkf_status mkf_make_seeds(mkf_ctx *c, const mkf_seeding *sc, int64_t capacity,
   HIP_TRY(c, c->d_tr_off.ensure(sizeof(int) * (size_t)(n + 1)));
   HIP_TRY(c, c->d_tr_tmp.ensure(sizeof(int) * (size_t)(4 * (n / 2048 + 4) + 64)));
   FindParams P = params(c);
-  launch_triplets(c->stream, P, ds, n, false, c->d_tr_cnt.as<int>(), nullptr, nullptr, nullptr);
+  int64_t max_ev = 0;
+  for (int e = 0; e < c->n_events; ++e) max_ev = std::max(max_ev, c->ev_off[e + 1] - c->ev_off[e]);
+  launch_fill_i32(c->stream, c->d_tr_cnt.as<int>(), n, 0);
+  launch_triplets(c->stream, P, ds, max_ev, false, c->d_tr_cnt.as<int>(), nullptr, nullptr,
+                  nullptr);
   HIP_TRY(c, hipGetLastError());
   launch_scan(c->stream, c->d_tr_cnt.as<int>(), c->d_tr_off.as<int>(), n, c->d_tr_tmp.as<int>(),
               nullptr);
@@ -894,7 +899,7 @@ mkf_status mkf_make_seeds(mkf_ctx *c, const mkf_seeding *sc, int64_t capacity,
   *n_total = total;
   if (total > capacity)
     return fail(c, MKF_E_CAPACITY, "%d triplets, capacity %lld", total, (long long)capacity);
-  launch_triplets(c->stream, P, ds, n, true, c->d_tr_cnt.as<int>(), c->d_tr_off.as<int>(),
+  launch_triplets(c->stream, P, ds, max_ev, true, c->d_tr_cnt.as<int>(), c->d_tr_off.as<int>(),
                   out_event, out_hits);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));

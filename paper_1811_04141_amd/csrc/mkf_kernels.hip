@@ -1052,53 +1052,55 @@ __device__ __forceinline__ float bend_window(float r0, float r1, float rho_min, 
   return asinf(s1) - asinf(s0) + d0 / r0 + d0 / r1 + 2e-3f;
 }
 
+// One thread per first-layer hit, taken in the hit index's order within
+// its event (blockIdx.y), so that neighbouring lanes walk neighbouring
+// windows; counts and offsets are indexed by that sorted position.
 template <bool kWrite>
-__global__ __launch_bounds__(256) void k_triplets(FindParams P, DevSeeding sc, int64_t n_hits,
-                                                  int *counts, const int *offsets,
-                                                  int *out_event, int *out_hits) {
+__global__ __launch_bounds__(256) void k_triplets(FindParams P, DevSeeding sc, int *counts,
+                                                  const int *offsets, int *out_event,
+                                                  int *out_hits) {
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_hits) return;
+  const int e = blockIdx.y;
+  const DevLayer &L0 = sl[sc.layer[0]], &L1 = sl[sc.layer[1]], &L2 = sl[sc.layer[2]];
+  const int first = e * P.bins_per_event + L0.bin_base;
+  const int idx = P.bin_start[first] + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P.bin_start[first + L0.nq * L0.nphi]) return;
+  const HitRec ha = P.sorted[idx];
+  const float ax = ha.x, ay = ha.y, az = ha.z;
+  const float ra = sqrtf(fmaf(ax, ax, ay * ay));
+  const float rho_min = sc.pt_min / fabsf(P.cfg.mkb);
+  const float R0 = L0.pos, R1 = L1.pos, R2 = L2.pos;
+  const float dphi1 = bend_window(R0, R1, rho_min, sc.d0_max);
+  const float dphi2 = bend_window(R1, R2, rho_min, sc.d0_max);
+  const int pos = kWrite ? offsets[idx] : 0;
   int n = 0;
-  if (P.hlayer[i] == sc.layer[0]) {
-    const int e = event_of(P.ev_off, P.n_events, i);
-    const int ia = (int)(i - P.ev_off[e]);
-    const float ax = P.hx[i], ay = P.hy[i], az = P.hz[i];
-    const DevLayer &L1 = sl[sc.layer[1]], &L2 = sl[sc.layer[2]];
-    const float ra = sqrtf(fmaf(ax, ax, ay * ay));
-    const float rho_min = sc.pt_min / fabsf(P.cfg.mkb);
-    const float R0 = sl[sc.layer[0]].pos, R1 = L1.pos, R2 = L2.pos;
-    const float dphi1 = bend_window(R0, R1, rho_min, sc.d0_max);
-    const float dphi2 = bend_window(R1, R2, rho_min, sc.d0_max);
-    int pos = kWrite ? offsets[i] : 0;
-    walk_window(P, L1, e, atan2f(ay, ax), dphi1, 0, L1.nq - 1, [&](const HitRec &hb) {
-      const float rb = sqrtf(fmaf(hb.x, hb.x, hb.y * hb.y));
-      const float Z = hb.z - az;
-      const float lever = ra / (rb - ra);
-      // straight-line z at the beam line, against z0_max with room for the
-      // arc-versus-radius differences (d0, bending) and dz
-      const float z0e = az - Z * lever;
-      if (fabsf(z0e) > sc.z0_max + 1.f + (0.1f * fabsf(Z) + sc.dz_max) * (lever + 1.f)) return;
-      const float k = (R2 - ra) / (rb - ra);
-      const float zp = az + Z * k;
-      const float hw = (0.1f * fabsf(Z) + 2.f * sc.dz_max) * k + 0.5f;
-      const int qlo = clampi((int)floorf((zp - hw - L2.q_lo) * L2.q_scale), 0, L2.nq - 1);
-      const int qhi = clampi((int)floorf((zp + hw - L2.q_lo) * L2.q_scale), 0, L2.nq - 1);
-      walk_window(P, L2, e, atan2f(hb.y, hb.x), dphi2, qlo, qhi, [&](const HitRec &hc) {
-        if (!triplet_passes(P.cfg, sc, ax, ay, az, hb.x, hb.y, hb.z, hc.x, hc.y, hc.z)) return;
-        if (kWrite) {
-          out_event[pos + n] = e;
-          out_hits[3 * (size_t)(pos + n)] = ia;
-          out_hits[3 * (size_t)(pos + n) + 1] = hb.orig;
-          out_hits[3 * (size_t)(pos + n) + 2] = hc.orig;
-        }
-        ++n;
-      });
+  walk_window(P, L1, e, atan2f(ay, ax), dphi1, 0, L1.nq - 1, [&](const HitRec &hb) {
+    const float rb = sqrtf(fmaf(hb.x, hb.x, hb.y * hb.y));
+    const float Z = hb.z - az;
+    const float lever = ra / (rb - ra);
+    // straight-line z at the beam line, against z0_max with room for the
+    // arc-versus-radius differences (d0, bending) and dz
+    const float z0e = az - Z * lever;
+    if (fabsf(z0e) > sc.z0_max + 1.f + (0.1f * fabsf(Z) + sc.dz_max) * (lever + 1.f)) return;
+    const float k = (R2 - ra) / (rb - ra);
+    const float zp = az + Z * k;
+    const float hw = (0.1f * fabsf(Z) + 2.f * sc.dz_max) * k + 0.5f;
+    const int qlo = clampi((int)floorf((zp - hw - L2.q_lo) * L2.q_scale), 0, L2.nq - 1);
+    const int qhi = clampi((int)floorf((zp + hw - L2.q_lo) * L2.q_scale), 0, L2.nq - 1);
+    walk_window(P, L2, e, atan2f(hb.y, hb.x), dphi2, qlo, qhi, [&](const HitRec &hc) {
+      if (!triplet_passes(P.cfg, sc, ax, ay, az, hb.x, hb.y, hb.z, hc.x, hc.y, hc.z)) return;
+      if (kWrite) {
+        out_event[pos + n] = e;
+        out_hits[3 * (size_t)(pos + n)] = ha.orig;
+        out_hits[3 * (size_t)(pos + n) + 1] = hb.orig;
+        out_hits[3 * (size_t)(pos + n) + 2] = hc.orig;
+      }
+      ++n;
     });
-  }
-  if (!kWrite) counts[i] = n;
+  });
+  if (!kWrite) counts[idx] = n;
 }
 
 // ---------------------------------------------------- duplicate removal
@@ -2118,15 +2120,17 @@ void launch_smooth(hipStream_t s, const FindParams &P, const int *seed_hits, flo
                      n_surf, out_par, out_cov, out_n);
 }
 
-void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc, int64_t n_hits,
-                     bool write, int *counts, const int *offsets, int *out_event, int *out_hits) {
-  if (n_hits == 0) return;
+void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc,
+                     int64_t max_event_hits, bool write, int *counts, const int *offsets,
+                     int *out_event, int *out_hits) {
+  if (max_event_hits == 0 || P.n_events == 0) return;
+  const dim3 grid(blocks_for(max_event_hits, 256), (unsigned)P.n_events);
   if (write)
-    hipLaunchKernelGGL(k_triplets<true>, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P, sc,
-                       n_hits, counts, offsets, out_event, out_hits);
+    hipLaunchKernelGGL(k_triplets<true>, grid, dim3(256), 0, s, P, sc, counts, offsets, out_event,
+                       out_hits);
   else
-    hipLaunchKernelGGL(k_triplets<false>, dim3(blocks_for(n_hits, 256)), dim3(256), 0, s, P, sc,
-                       n_hits, counts, offsets, out_event, out_hits);
+    hipLaunchKernelGGL(k_triplets<false>, grid, dim3(256), 0, s, P, sc, counts, offsets,
+                       out_event, out_hits);
 }
 
 void launch_dup_prep(hipStream_t s, const FindParams &P, const int *seed_hits, int *hbuf, int *hn,

@@ -91,10 +91,13 @@ struct DevSeeding {
   int layer[3];
   float pt_min, d0_max, z0_max, dz_max;
 };
-// counts[i]: triplets whose first hit is hit i (counting pass); with
-// offsets, writes them (event, three event-local hit indices)
-void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc, int64_t n_hits,
-                     bool write, int *counts, const int *offsets, int *out_event, int *out_hits);
+// counts[i]: triplets whose first hit is the hit at binned position i
+// (counting pass; the other positions are left alone); with offsets, writes
+// them (event, three event-local hit indices).  max_event_hits bounds the
+// hits of one event.
+void launch_triplets(hipStream_t s, const FindParams &P, const DevSeeding &sc,
+                     int64_t max_event_hits, bool write, int *counts, const int *offsets,
+                     int *out_event, int *out_hits);
 // duplicate-track removal: per track its sorted hits (hbuf [n_seeds][kDupStride],
 // hn), the tracks on every hit (CSR: cnt, off, fill, list), the decision
 constexpr int kDupStride = 36;
