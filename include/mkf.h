@@ -75,6 +75,14 @@ typedef struct {
   float var_v_max;   /*   search windows are sized with them               */
   int32_t n_phi_bins; /* hit index bins in phi (1..4096) */
   int32_t n_q_bins;   /* hit index bins in z (barrel) or r (disk) (1..1024) */
+  float stereo;       /* stereo layer: the strips' measuring direction is
+                         turned by this angle (|stereo| < pi/2) from u towards
+                         v; a hit's var_u lies along it, var_v across it, and
+                         var_u_max, var_v_max bound the turned covariance's
+                         u-u and v-v terms.  0: var_u, var_v along u, v */
+  float hole_lo;      /* no sensors for hole_lo < q < hole_hi (q: z on a  */
+  float hole_hi;      /*   barrel, r on a disk); a crossing there is outside
+                           the layer (a skip).  hole_lo >= hole_hi: none */
 } mkf_layer;
 
 /* Method settings.  The paper states none of these values; the defaults

@@ -189,6 +189,9 @@ int orc_propagate(const double p[6], const double C[36], const orc_layer *Lr,
     double q = Lr->kind == 0 ? pp[2] : hypot(pp[0], pp[1]);
     if (q < Lr->ext_lo - edge_margin || q > Lr->ext_hi + edge_margin)
       return ORC_OUT_OF_EXTENT;
+    /* a hole (hole_lo < q < hole_hi, shrunk by the same margin) has no
+     * sensors: a crossing there is outside the layer */
+    if (q > Lr->hole_lo + edge_margin && q < Lr->hole_hi - edge_margin) return ORC_OUT_OF_EXTENT;
   }
   if (l_out) *l_out = l;
   memcpy(p_out, pp, sizeof(pp));
@@ -317,11 +320,24 @@ static void inv_small(int m, const double *S, double *Si) {
   }
 }
 
+/* A hit measures along the layer's strip frame, turned by the stereo angle
+ * a from the local (u, v) frame: w = cos(a) u + sin(a) v is measured with
+ * variance var_u, the orthogonal direction with var_v (the Section 2.1
+ * layer description's stereo layers; a = 0 for the others).  In (u, v):
+ * V = R^T diag(var_u, var_v) R, R = [[c, s], [-s, c]]. */
+static void hit_cov(double stereo, double var_u, double var_v, double V[4]) {
+  double c = cos(stereo), s = sin(stereo);
+  V[0] = c * c * var_u + s * s * var_v;
+  V[1] = V[2] = c * s * (var_u - var_v);
+  V[3] = s * s * var_u + c * c * var_v;
+}
+
 int orc_chi2(const double p[6], const double C[36], int kind,
-             const double hit[3], double var_u, double var_v, double *chi2) {
+             const double hit[3], double var_u, double var_v, double stereo, double *chi2) {
   double r[2], H[12], S[4], Si[4], PHt[12];
   if (!orc_measure(p, kind, hit, r, H)) return 0;
-  double V[4] = {var_u, 0.0, 0.0, var_v};
+  double V[4];
+  hit_cov(stereo, var_u, var_v, V);
   residual_cov(C, 2, H, V, S, PHt);
   inv_small(2, S, Si);
   *chi2 = r[0] * (Si[0] * r[0] + Si[1] * r[1]) + r[1] * (Si[2] * r[0] + Si[3] * r[1]);
@@ -384,10 +400,11 @@ void orc_kf_update(double p[6], double C[36], int m, const double *H,
 }
 
 int orc_update_hit(double p[6], double C[36], int kind, const double hit[3],
-                   double var_u, double var_v, double *chi2) {
+                   double var_u, double var_v, double stereo, double *chi2) {
   double r[2], H[12];
   if (!orc_measure(p, kind, hit, r, H)) return 0;
-  double V[4] = {var_u, 0.0, 0.0, var_v};
+  double V[4];
+  hit_cov(stereo, var_u, var_v, V);
   orc_kf_update(p, C, 2, H, r, V, 0, chi2);
   p[4] = wrap_phi(p[4]);
   return 1;
@@ -424,7 +441,10 @@ static void surface_prior(const orc_cfg *cfg, const double p[6], int kind, doubl
 
 static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
   double q = Lr->kind == 0 ? pp[2] : hypot(pp[0], pp[1]);
-  return fmin(fabs(q - (Lr->ext_lo - m)), fabs(q - (Lr->ext_hi + m)));
+  double d = fmin(fabs(q - (Lr->ext_lo - m)), fabs(q - (Lr->ext_hi + m)));
+  if (Lr->hole_hi - Lr->hole_lo > 2.0 * m)
+    d = fmin(d, fmin(fabs(q - (Lr->hole_lo + m)), fabs(q - (Lr->hole_hi - m))));
+  return d;
 }
 
 /* Seed from three hits (seeds are supplied from outside, Section 2.2):
@@ -484,7 +504,7 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
     }
     orc_add_ms(p, cfg->ms_sigma, C);
     double c2;
-    if (!orc_update_hit(p, C, Lr->kind, &h[3 * k], hv[2 * k], hv[2 * k + 1], &c2))
+    if (!orc_update_hit(p, C, Lr->kind, &h[3 * k], hv[2 * k], hv[2 * k + 1], Lr->stereo, &c2))
       return 0;
     chi2 += c2;
   }
@@ -643,7 +663,7 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
         int32_t hi = lay_idx[k];
         double hh[3] = {x[hi], y[hi], z[hi]};
         double c2;
-        if (!orc_chi2(pc, Cc, Lr->kind, hh, vu[hi], vv[hi], &c2)) continue;
+        if (!orc_chi2(pc, Cc, Lr->kind, hh, vu[hi], vv[hi], Lr->stereo, &c2)) continue;
         if (fabs(c2 - cfg->chi2_cut) <= tol_of(tol, cfg->chi2_cut)) mark(&out->fragile_step, s);
         if (c2 < cfg->chi2_cut) {
           ext_t e = {cands[c].n_hits + 1, cands[c].chi2 + c2, c, hi, EXT_HIT, hi, c2};
@@ -678,7 +698,7 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
         } else {
           double hh[3] = {x[e->hit], y[e->hit], z[e->hit]};
           double c2;
-          orc_update_hit(dst->p, dst->C, Lr->kind, hh, vu[e->hit], vv[e->hit], &c2);
+          orc_update_hit(dst->p, dst->C, Lr->kind, hh, vu[e->hit], vv[e->hit], Lr->stereo, &c2);
           dst->n_hits += 1;
           dst->chi2 = e->chi2_sum;
           dst->hist[s] = e->hit;
@@ -770,7 +790,8 @@ int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36], i
       return -(k + 1);
     orc_add_ms(pp, cfg->ms_sigma, Cp);
     double c2;
-    if (!orc_update_hit(pp, Cp, kinds[k], &hits[3 * k], var_u[k], var_v[k], &c2)) return -(k + 1);
+    if (!orc_update_hit(pp, Cp, kinds[k], &hits[3 * k], var_u[k], var_v[k], 0.0, &c2))
+      return -(k + 1);
     sum += c2;
     memcpy(p, pp, sizeof(p));
     memcpy(C, Cp, sizeof(C));
@@ -856,7 +877,8 @@ int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
     if (hit[k] >= 0) {
       const double h[3] = {x[hit[k]], y[hit[k]], z[hit[k]]};
       double c2;
-      if (!orc_update_hit(p, C, Lr->kind, h, var_u[hit[k]], var_v[hit[k]], &c2)) return -(k + 1);
+      if (!orc_update_hit(p, C, Lr->kind, h, var_u[hit[k]], var_v[hit[k]], Lr->stereo, &c2))
+        return -(k + 1);
       sum += c2;
       ++nu;
     }
@@ -952,7 +974,8 @@ int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
     if (code >= 0) {
       const double h[3] = {x[code], y[code], z[code]};
       double c2;
-      if (!orc_update_hit(pp, Cp, Lr->kind, h, var_u[code], var_v[code], &c2)) return -1;
+      if (!orc_update_hit(pp, Cp, Lr->kind, h, var_u[code], var_v[code], Lr->stereo, &c2))
+        return -1;
     }
     memcpy(xf[n], pp, sizeof(pp));
     memcpy(Cf[n], Cp, sizeof(Cp));

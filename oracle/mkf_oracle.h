@@ -45,6 +45,8 @@ typedef struct {
   double pos;    /* radius R (barrel) or signed z position Z (disk) */
   double ext_lo; /* barrel: lowest z; disk: inner radius */
   double ext_hi; /* barrel: highest z; disk: outer radius */
+  double stereo; /* strip frame turned by this angle from (u, v); 0: none */
+  double hole_lo, hole_hi; /* no sensors for hole_lo < q < hole_hi (q as ext) */
 } orc_layer;
 
 typedef struct {
@@ -90,9 +92,11 @@ void orc_add_ms(const double p[6], double sigma, double C[36]);
 int orc_measure(const double p[6], int kind, const double hit[3],
                 double r[2], double H[12]);
 
-/* chi2 = r^T (H C H^T + V)^-1 r.  Returns 0 if incompatible (hemisphere). */
+/* chi2 = r^T (H C H^T + V)^-1 r, V the hit covariance: var_u along the
+ * layer's strip direction, turned by stereo from u, var_v across it.
+ * Returns 0 if incompatible (hemisphere). */
 int orc_chi2(const double p[6], const double C[36], int kind,
-             const double hit[3], double var_u, double var_v, double *chi2);
+             const double hit[3], double var_u, double var_v, double stereo, double *chi2);
 
 /* General linear Kalman update with an m-dimensional measurement
  * (m <= 2): K = C H^T S^-1, p += K r, C -= K S K^T (symmetrised).
@@ -101,9 +105,10 @@ void orc_kf_update(double p[6], double C[36], int m, const double *H,
                    const double *r, const double *V, int joseph,
                    double *chi2);
 
-/* Hit update at a layer: measure + orc_kf_update + wrap phi. */
+/* Hit update at a layer: measure + orc_kf_update + wrap phi (V as in
+ * orc_chi2). */
 int orc_update_hit(double p[6], double C[36], int kind, const double hit[3],
-                   double var_u, double var_v, double *chi2);
+                   double var_u, double var_v, double stereo, double *chi2);
 
 /* ---- seeding, plan, find, fit --------------------------------------- */
 

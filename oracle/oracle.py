@@ -35,7 +35,14 @@ def build(force: bool = False) -> str:
 
 class Layer(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos", C.c_double), ("ext_lo", C.c_double),
-                ("ext_hi", C.c_double)]
+                ("ext_hi", C.c_double), ("stereo", C.c_double), ("hole_lo", C.c_double),
+                ("hole_hi", C.c_double)]
+
+
+def _layer(l):
+    return Layer(int(l.kind), float(l.pos), float(l.ext_lo), float(l.ext_hi),
+                 float(getattr(l, "stereo", 0.0)), float(getattr(l, "hole_lo", 0.0)),
+                 float(getattr(l, "hole_hi", 0.0)))
 
 
 class Cfg(C.Structure):
@@ -86,9 +93,10 @@ def lib():
                                     C.c_double, C.c_int, _D, _D, _D, _D]
         L.orc_add_ms.argtypes = [_D, C.c_double, _D]
         L.orc_measure.argtypes = [_D, C.c_int, _D, _D, _D]
-        L.orc_chi2.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, _D]
+        L.orc_chi2.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, C.c_double, _D]
         L.orc_kf_update.argtypes = [_D, _D, C.c_int, _D, _D, _D, C.c_int, _D]
-        L.orc_update_hit.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, _D]
+        L.orc_update_hit.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, C.c_double,
+                                     _D]
         L.orc_seed.argtypes = [C.POINTER(Cfg), C.POINTER(Layer), C.c_int32, _D, _D, _I,
                                C.c_double, C.POINTER(SeedOut)]
         L.orc_find_event.argtypes = [C.POINTER(Cfg), C.POINTER(Tol), C.POINTER(Layer), C.c_int32,
@@ -164,7 +172,7 @@ def _p(a, t=_D):
 def make_layers(layers) -> "C.Array":
     arr = (Layer * len(layers))()
     for i, l in enumerate(layers):
-        arr[i] = Layer(int(l.kind), float(l.pos), float(l.ext_lo), float(l.ext_hi))
+        arr[i] = _layer(l)
     return arr
 
 
@@ -205,7 +213,7 @@ def propagate(p, Cm, layer, bz, kappa, l_min=1e-4, edge_margin=0.0, check_extent
     """Returns (status, p', C', F, l)."""
     p = _d(p, 6)
     Cm = _d(Cm, 36) if Cm is not None else None
-    lay = Layer(int(layer.kind), float(layer.pos), float(layer.ext_lo), float(layer.ext_hi))
+    lay = _layer(layer)
     po, Co, Fo, lo = np.zeros(6), np.zeros(36), np.zeros(36), np.zeros(1)
     st = lib().orc_propagate(_p(p), _p(Cm) if Cm is not None else None, C.byref(lay), bz, kappa,
                              l_min, edge_margin, int(check_extent), _p(po),
@@ -227,10 +235,10 @@ def measure(p, kind, hit):
     return bool(ok), r, H.reshape(2, 6)
 
 
-def chi2(p, Cm, kind, hit, var_u, var_v):
+def chi2(p, Cm, kind, hit, var_u, var_v, stereo=0.0):
     p, Cm, hit = _d(p, 6), _d(Cm, 36), _d(hit, 3)
     out = np.zeros(1)
-    ok = lib().orc_chi2(_p(p), _p(Cm), int(kind), _p(hit), var_u, var_v, _p(out))
+    ok = lib().orc_chi2(_p(p), _p(Cm), int(kind), _p(hit), var_u, var_v, stereo, _p(out))
     return float(out[0]) if ok else None
 
 
@@ -245,12 +253,12 @@ def kf_update(p, Cm, H, r, V, joseph=False):
     return p, Cm.reshape(6, 6), float(c2[0])
 
 
-def update_hit(p, Cm, kind, hit, var_u, var_v):
+def update_hit(p, Cm, kind, hit, var_u, var_v, stereo=0.0):
     p = _d(p, 6).copy()
     Cm = _d(Cm, 36).copy()
     hit = _d(hit, 3)
     c2 = np.zeros(1)
-    ok = lib().orc_update_hit(_p(p), _p(Cm), int(kind), _p(hit), var_u, var_v, _p(c2))
+    ok = lib().orc_update_hit(_p(p), _p(Cm), int(kind), _p(hit), var_u, var_v, stereo, _p(c2))
     return bool(ok), p, Cm.reshape(6, 6), float(c2[0])
 
 

@@ -373,6 +373,10 @@ mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_laye
       return fail(c, MKF_E_GEOMETRY, "layer %d: variance bounds must be > 0", i);
     if (L.n_phi_bins < 1 || L.n_phi_bins > 4096 || L.n_q_bins < 1 || L.n_q_bins > 1024)
       return fail(c, MKF_E_GEOMETRY, "layer %d: bin counts out of range", i);
+    if (!finite_f(L.stereo) || !(std::fabs(L.stereo) < 1.5707f))
+      return fail(c, MKF_E_GEOMETRY, "layer %d: stereo angle must lie in (-pi/2, pi/2)", i);
+    if (!finite_f(L.hole_lo) || !finite_f(L.hole_hi))
+      return fail(c, MKF_E_GEOMETRY, "layer %d: bad hole", i);
     DevLayer &d = dl[i];
     d.kind = L.kind;
     d.pos = L.pos;
@@ -386,6 +390,10 @@ mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_laye
     d.q_lo = L.ext_lo;
     d.q_scale = (float)L.n_q_bins / (L.ext_hi - L.ext_lo);
     d.phi_scale = (float)L.n_phi_bins / kTwoPi;
+    d.cs = L.stereo == 0.f ? 1.f : std::cos(L.stereo);
+    d.sn = L.stereo == 0.f ? 0.f : std::sin(L.stereo);
+    d.hole_lo = L.hole_lo < L.hole_hi ? L.hole_lo : 0.f;
+    d.hole_hi = L.hole_lo < L.hole_hi ? L.hole_hi : 0.f;
     base += L.n_phi_bins * L.n_q_bins;
   }
   HIP_TRY(c, c->d_layers.ensure(sizeof(DevLayer) * kMaxLayers));

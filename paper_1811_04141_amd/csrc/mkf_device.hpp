@@ -36,6 +36,8 @@ struct DevLayer {
   float q_lo;       // q bin = floor((q - q_lo) * q_scale)
   float q_scale;
   float phi_scale;  // nphi / (2 pi)
+  float cs, sn;     // cos, sin of the stereo angle
+  float hole_lo, hole_hi;  // no sensors for hole_lo < q < hole_hi
 };
 
 struct DevCfg {
@@ -252,6 +254,8 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   if (check_extent) {
     const T q = L.kind == 0 ? z1 : sqrt_t(fma_t(x1, x1, y1 * y1));
     if (q < T(L.lo) - edge_margin || q > T(L.hi) + edge_margin) return kOutOfExtent;
+    // a hole (shrunk by the same margin) has no sensors
+    if (q > T(L.hole_lo) + edge_margin && q < T(L.hole_hi) - edge_margin) return kOutOfExtent;
   }
   o.p[0] = x1;
   o.p[1] = y1;
@@ -443,14 +447,24 @@ __device__ __forceinline__ bool residual(const T *p, const FrameT<T> &f, int kin
   return true;
 }
 
+// Hit covariance in the local (u, v) frame from the variances along and
+// across the strips of a layer whose strips measure in a direction turned by
+// the stereo angle (cos cs, sin sn) from u: V = R^T diag(vw, vp) R.
 template <typename T>
-__device__ __forceinline__ T chi2_of(const FrameT<T> &f, T vu, T vv, T u, T v) {
-  const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
+__device__ __forceinline__ void hit_cov(T cs, T sn, T vw, T vp, T &vuu, T &vvv, T &vuv) {
+  vuu = fma_t(cs * cs, vw, sn * sn * vp);
+  vvv = fma_t(sn * sn, vw, cs * cs * vp);
+  vuv = cs * sn * (vw - vp);
+}
+
+template <typename T>
+__device__ __forceinline__ T chi2_of(const FrameT<T> &f, T vu, T vv, T vuv, T u, T v) {
+  const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv + vuv;
   const T det = fma_t(suu, svv, -suv * suv);
   return (svv * u * u - T(2) * suv * u * v + suu * v * v) / det;
 }
 
-// Kalman update with the hit (u, v residual, variances vu, vv): K = C H^T
+// Kalman update with the hit (u, v residual, covariance vu, vv, vuv): K = C H^T
 // S^-1, p += K r, and the covariance in Joseph form,
 //   C' = (I - K H) C (I - K H)^T + K V K^T = C - K (CH^T)^T - B K^T,
 // with B = C H^T - K (H C H^T + V), which is zero in exact arithmetic and
@@ -460,7 +474,7 @@ __device__ __forceinline__ T chi2_of(const FrameT<T> &f, T vu, T vv, T u, T v) {
 // because its result is a small difference of large terms.
 template <typename T>
 __device__ __forceinline__ void kf_update(T *p, T *c, const FrameT<T> &f, int kind, T vu, T vv,
-                                          T u, T v) {
+                                          T vuv, T u, T v) {
   T PHu[6], PHv[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -469,7 +483,7 @@ __device__ __forceinline__ void kf_update(T *p, T *c, const FrameT<T> &f, int ki
     PHu[i] = fma_t(f.tx, ci0, f.ty * ci1);
     PHv[i] = kind == 0 ? c[i <= 2 ? tri(i, 2) : tri(2, i)] : fma_t(f.rx, ci0, f.ry * ci1);
   }
-  const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
+  const T suu = f.suu + vu, svv = f.svv + vv, suv = f.suv + vuv;
   const T inv_det = T(1) / fma_t(suu, svv, -suv * suv);
   const T iuu = svv * inv_det, ivv = suu * inv_det, iuv = -suv * inv_det;
   T Ku[6], Kv[6], Bu[6], Bv[6];

@@ -226,8 +226,9 @@ __device__ __forceinline__ float window_azimuth(float y, float x) {
 
 // chi2 of a window hit, with the hardware reciprocal (1 ulp) in place of a
 // correctly rounded division; both forms of the find score hits with it
-__device__ __forceinline__ float chi2_hit(const Frame &f, float vu, float vv, float u, float v) {
-  const float suu = f.suu + vu, svv = f.svv + vv, suv = f.suv;
+__device__ __forceinline__ float chi2_hit(const Frame &f, float vu, float vv, float vuv, float u,
+                                          float v) {
+  const float suu = f.suu + vu, svv = f.svv + vv, suv = f.suv + vuv;
   const float det = fmaf(suu, svv, -suv * suv);
   return (svv * u * u - 2.f * suv * u * v + suu * v * v) * __builtin_amdgcn_rcpf(det);
 }
@@ -285,22 +286,22 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
       const int h0 = P.bin_start[row + lo];
       const int h1 = P.bin_start[row + hi + 1];
       const float4 *hits = reinterpret_cast<const float4 *>(P.sorted);
-      const float2 *hits2 = reinterpret_cast<const float2 *>(P.sorted);
+      const float4 *hits2 = reinterpret_cast<const float4 *>(P.sorted);
       for (int k = h0; k < h1; k += 4) {
         float4 a[4];
-        float2 b[4];  // (var_v, index); the record's padding is not read
+        float4 b[4];  // (var_v, index, covariance uv, -)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int kk = min(k + j, h1 - 1);
           a[j] = hits[2 * kk];
-          b[j] = hits2[4 * kk + 2];
+          b[j] = hits2[2 * kk + 1];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (k + j >= h1) break;
           float u, v;
           if (!residual(pr.p, f, L.kind, a[j].x, a[j].y, a[j].z, u, v)) continue;
-          const float c2 = fmaxf(chi2_hit(f, a[j].w, b[j].x, u, v), 0.f);
+          const float c2 = fmaxf(chi2_hit(f, a[j].w, b[j].x, b[j].z, u, v), 0.f);
           if (c2 < cut) {
             insert_sorted(lst, ext_key(nh + 1, chi2_base + c2, slot,
                                        (unsigned)__float_as_int(b[j].y)));
@@ -376,12 +377,11 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   // the kept hit's record is requested first, so that its latency overlaps
   // the state exchange below
   const unsigned order = mine != kKeyMax ? (unsigned)(mine & 0x7FFFFFu) : kOrderNone;
-  float4 ha = make_float4(0.f, 0.f, 0.f, 0.f);
-  float hvv = 0.f;
+  float4 ha = make_float4(0.f, 0.f, 0.f, 0.f), hb = ha;
   if (order != kOrderNone) {
     const float4 *hr = reinterpret_cast<const float4 *>(P.byorig + ev_base + order);
     ha = hr[0];
-    hvv = reinterpret_cast<const float *>(hr + 1)[0];
+    hb = hr[1];  // (vv, index, vuv, -)
   }
 
   // children read their parent's propagated state (or, for a skip, its
@@ -405,12 +405,12 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
     const bool pok = (pmeta >> 16) & 1;
     int hitcode;
     if (order != kOrderNone) {
-      const float hx = ha.x, hy = ha.y, hz = ha.z, vu = ha.w, vv = hvv;
+      const float hx = ha.x, hy = ha.y, hz = ha.z, vu = ha.w, vv = hb.x, vuv = hb.z;
       Frame f;
       make_frame(np, np + 6, L.kind, f);
       float u, v;
       residual(np, f, L.kind, hx, hy, hz, u, v);
-      kf_update(np, np + 6, f, L.kind, vu, vv, u, v);
+      kf_update(np, np + 6, f, L.kind, vu, vv, vuv, u, v);
       ++nh;
       hitcode = (int)order;
     } else if (pok) {
@@ -910,8 +910,10 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
         good = false;
         break;
       }
-      chi2 += chi2_of(f, hvu[k], hvv[k], u, v);
-      kf_update(p, c, f, L.kind, hvu[k], hvv[k], u, v);
+      double vuu, vvv, vuv;
+      hit_cov((double)L.cs, (double)L.sn, hvu[k], hvv[k], vuu, vvv, vuv);
+      chi2 += chi2_of(f, vuu, vvv, vuv, u, v);
+      kf_update(p, c, f, L.kind, vuu, vvv, vuv, u, v);
     }
     if (!good) break;
     ok = 1;
@@ -1329,10 +1331,9 @@ __global__ __launch_bounds__(256) void k_hit_scatter(FindParams P, int n_events,
   h.x = P.hx[i];
   h.y = P.hy[i];
   h.z = P.hz[i];
-  h.vu = P.hvu[i];
-  h.vv = P.hvv[i];
+  const DevLayer &L = P.layers[P.hlayer[i]];
+  hit_cov(L.cs, L.sn, P.hvu[i], P.hvv[i], h.vu, h.vv, h.vuv);
   h.orig = (int)(i - P.ev_off[e]);
-  h.pad0 = 0;
   h.pad1 = 0;
   sorted[slot] = h;
   byorig[i] = h;
@@ -1451,8 +1452,8 @@ __global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
       break;
     }
     const float hvu = vu[j], hvv = vv[j];
-    chi2 += fmaxf(chi2_of(f, hvu, hvv, u, v), 0.f);
-    kf_update(pr.p, pr.c, f, L.kind, hvu, hvv, u, v);
+    chi2 += fmaxf(chi2_of(f, hvu, hvv, 0.f, u, v), 0.f);
+    kf_update(pr.p, pr.c, f, L.kind, hvu, hvv, 0.f, u, v);
 #pragma unroll
     for (int k = 0; k < 6; ++k) p[k] = pr.p[k];
 #pragma unroll
@@ -1524,8 +1525,8 @@ __device__ __forceinline__ bool backfit_surface(const FindParams &P, const DevLa
     make_frame(p, c, L.kind, f);
     T u, v;
     if (!residual(p, f, L.kind, T(h.x), T(h.y), T(h.z), u, v)) return false;
-    chi2 += fmaxf((float)chi2_of(f, T(h.vu), T(h.vv), u, v), 0.f);
-    kf_update(p, c, f, L.kind, T(h.vu), T(h.vv), u, v);
+    chi2 += fmaxf((float)chi2_of(f, T(h.vu), T(h.vv), T(h.vuv), u, v), 0.f);
+    kf_update(p, c, f, L.kind, T(h.vu), T(h.vv), T(h.vuv), u, v);
   }
   return true;
 }
@@ -1759,7 +1760,7 @@ __global__ __launch_bounds__(256) void k_smooth_fwd(FindParams P, const int *see
           n = -1;
           break;
         }
-        kf_update(pr.p, pr.c, f, L.kind, h.vu, h.vv, u, v);
+        kf_update(pr.p, pr.c, f, L.kind, h.vu, h.vv, h.vuv, u, v);
       }
 #pragma unroll
       for (int m = 0; m < 6; ++m) p[m] = pr.p[m];

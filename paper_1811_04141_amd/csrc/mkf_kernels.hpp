@@ -12,11 +12,14 @@
 namespace mkf {
 
 // Hit as stored in the binned index: one 32-byte record, two 16-byte loads.
+// A hit with its covariance in the layer's local (u, v) frame (vu, vv,
+// vuv: the caller's variances turned by the layer's stereo angle).
 struct alignas(16) HitRec {
   float x, y, z, vu;
   float vv;
   int orig;  // event-local index in the caller's order
-  int pad0, pad1;
+  float vuv;
+  int pad1;
 };
 
 // Candidate buffers between layer steps (layer-synchronous form), SoA by

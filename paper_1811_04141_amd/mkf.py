@@ -41,7 +41,8 @@ class MkfError(RuntimeError):
 class Layer(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos", C.c_float), ("ext_lo", C.c_float),
                 ("ext_hi", C.c_float), ("var_u_max", C.c_float), ("var_v_max", C.c_float),
-                ("n_phi_bins", C.c_int32), ("n_q_bins", C.c_int32)]
+                ("n_phi_bins", C.c_int32), ("n_q_bins", C.c_int32), ("stereo", C.c_float),
+                ("hole_lo", C.c_float), ("hole_hi", C.c_float)]
 
 
 class Config(C.Structure):
@@ -177,7 +178,9 @@ def make_layers(layers):
     arr = (Layer * len(layers))()
     for i, l in enumerate(layers):
         arr[i] = Layer(int(l.kind), float(l.pos), float(l.ext_lo), float(l.ext_hi),
-                       float(l.var_u_max), float(l.var_v_max), int(l.n_phi_bins), int(l.n_q_bins))
+                       float(l.var_u_max), float(l.var_v_max), int(l.n_phi_bins), int(l.n_q_bins),
+                       float(getattr(l, "stereo", 0.0)), float(getattr(l, "hole_lo", 0.0)),
+                       float(getattr(l, "hole_hi", 0.0)))
     return arr
 
 

@@ -188,7 +188,9 @@ def simulate_tracks(rng, n, layers, bz, recipe, pt=None, eta=None, phi=None, q=N
 
 
 def _smear(rng, layers, lay, st):
-    """Smeared hit positions on their layer surfaces and their variances."""
+    """Smeared hit positions on their layer surfaces and their variances
+    (along and across the strips; on a layer without stereo angle these are
+    u = r-phi and v = z or r)."""
     n = lay.shape[0]
     kind = np.array([layers[k].kind for k in lay]) if n else np.zeros(0, int)
     posv = np.array([layers[k].pos for k in lay]) if n else np.zeros(0)
@@ -198,14 +200,27 @@ def _smear(rng, layers, lay, st):
     e_u = rng.normal(0.0, SIGMA_RPHI, n)
     e_v = rng.normal(0.0, 1.0, n)
     is_b = kind == BARREL
-    # barrel: along the cylinder in r-phi, and in z
-    rb = np.where(is_b, posv, r + e_v * SIGMA_R)
-    phib = phi + e_u / np.where(is_b, posv, r)
+    sig_v = np.where(is_b, SIGMA_Z, SIGMA_R)
+    du, dv = e_u, e_v * sig_v
+    vu = np.full(n, SIGMA_RPHI ** 2)
+    vv = sig_v ** 2
+    stereo = np.array([layers[k].stereo for k in lay]) if n else np.zeros(0)
+    st_m = stereo != 0.0
+    if np.any(st_m):
+        # strips turned by a: the error e_u lies along w = (cos a, sin a) in
+        # (u, v), the error across them (sigma_perp) along (-sin a, cos a)
+        sp = np.array([layers[k].sigma_perp for k in lay])
+        c, s = np.cos(stereo), np.sin(stereo)
+        ep = e_v * sp
+        du = np.where(st_m, c * e_u - s * ep, du)
+        dv = np.where(st_m, s * e_u + c * ep, dv)
+        vv = np.where(st_m, sp ** 2, vv)
+    # barrel: along the cylinder in r-phi, and in z; disk: r-phi and r
+    rb = np.where(is_b, posv, r + dv)
+    phib = phi + du / np.where(is_b, posv, r)
     hx = rb * np.cos(phib)
     hy = rb * np.sin(phib)
-    hz = np.where(is_b, z + e_v * SIGMA_Z, posv)
-    vu = np.full(n, SIGMA_RPHI ** 2)
-    vv = np.where(is_b, SIGMA_Z ** 2, SIGMA_R ** 2)
+    hz = np.where(is_b, z + dv, posv)
     return hx, hy, hz, vu, vv
 
 
@@ -224,6 +239,13 @@ def _noise(rng, layers, counts, frac):
             r = np.sqrt(rng.uniform(layer.ext_lo ** 2, layer.ext_hi ** 2, m))
             z = np.full(m, layer.pos)
             vv = np.full(m, SIGMA_R ** 2)
+        if layer.stereo != 0.0:
+            vv = np.full(m, layer.sigma_perp ** 2)
+        if layer.hole_lo < layer.hole_hi:
+            q = z if layer.kind == BARREL else r
+            keep = ~((q > layer.hole_lo) & (q < layer.hole_hi))
+            phi, r, z, vv = phi[keep], r[keep], z[keep], vv[keep]
+            m = int(keep.sum())
         xs.append(r * np.cos(phi))
         ys.append(r * np.sin(phi))
         zs.append(z)
@@ -251,6 +273,14 @@ def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None,
     # 2% (or as configured) independent loss of hits
     if w.recipe.hit_ineff > 0.0:
         keep = rng.random(trk.shape[0]) >= w.recipe.hit_ineff
+        trk, lay, st = trk[keep], lay[keep], st[keep]
+    # crossings inside a layer's hole leave no hit
+    if any(L.hole_lo < L.hole_hi for L in w.layers):
+        hl = np.array([L.hole_lo for L in w.layers])[lay]
+        hh = np.array([L.hole_hi for L in w.layers])[lay]
+        isb = np.array([L.kind == BARREL for L in w.layers])[lay]
+        q = np.where(isb, st[:, 2], np.hypot(st[:, 0], st[:, 1]))
+        keep = ~((q > hl) & (q < hh))
         trk, lay, st = trk[keep], lay[keep], st[keep]
     hx, hy, hz, vu, vv = _smear(rng, w.layers, lay, st)
     counts = np.bincount(lay, minlength=len(w.layers))

@@ -22,10 +22,17 @@ class Layer:
     pos: float         # radius (barrel) or signed z (disk), cm
     ext_lo: float      # barrel: lowest z; disk: inner radius
     ext_hi: float      # barrel: highest z; disk: outer radius
-    var_u_max: float   # largest hit variance along u on this layer, cm^2
-    var_v_max: float   # largest hit variance along v on this layer, cm^2
+    var_u_max: float   # bound on the hit covariance's u-u term on this layer, cm^2
+    var_v_max: float   # bound on its v-v term, cm^2
     n_phi_bins: int = 256
     n_q_bins: int = 16
+    # stereo layer: strips measuring along a direction turned by `stereo`
+    # (rad) from u towards v, with resolution sigma_perp (cm) across them
+    stereo: float = 0.0
+    sigma_perp: float = 0.0
+    # no sensors for hole_lo < q < hole_hi (q: z on a barrel, r on a disk)
+    hole_lo: float = 0.0
+    hole_hi: float = 0.0
 
 
 BARREL_RADII = (4.0, 7.0, 11.0, 16.0, 25.0, 34.0, 43.0, 52.0, 61.0, 70.0)
@@ -111,6 +118,36 @@ class Workload:
     n_events: int
     n_tracks: Tuple[int, int]   # (lo, hi); lo == hi means fixed, else log-uniform
     master_seed: int
+
+
+def stereo_layer(layer: Layer, angle: float, sigma_perp: float) -> Layer:
+    """The layer with strips turned by `angle`: a hit measures along them
+    with SIGMA_RPHI and across them with sigma_perp; the covariance bounds
+    are those of the turned covariance."""
+    c, s = np.cos(angle), np.sin(angle)
+    vw, vp = SIGMA_RPHI ** 2, sigma_perp ** 2
+    return replace(layer, stereo=angle, sigma_perp=sigma_perp,
+                   var_u_max=c * c * vw + s * s * vp, var_v_max=s * s * vw + c * c * vp)
+
+
+def cms_like(n_events: int = 10, n_tracks: int = 2000) -> Workload:
+    """The realistic recipe on a geometry with the generality of the
+    paper's layer description (Section 2.1): barrel layers 4 and 6 (R = 25,
+    43 cm) are stereo layers (strips turned by 0.1 rad, 1.5 cm across),
+    barrel layer 5 (R = 34 cm) has no sensors for |z| < 2 cm, and every
+    disk has a ring without sensors at 50 < r < 55 cm."""
+    bl = barrel_layers()
+    bl[4] = stereo_layer(bl[4], 0.1, 1.5)
+    bl[6] = stereo_layer(bl[6], 0.1, 1.5)
+    bl[5] = replace(bl[5], hole_lo=-2.0, hole_hi=2.0)
+    dl = [replace(d, hole_lo=50.0, hole_hi=55.0) for d in disk_layers()]
+    return Workload(
+        name=f"cms_like_{n_events}x{n_tracks}",
+        layers=tuple(bl + dl),
+        recipe=EventRecipe(pt_lo=0.3, pt_hi=10.0, eta_max=2.4, ms_sigma=0.001,
+                           hit_ineff=0.02, noise_frac=0.3),
+        find=FindConfig(),
+        n_events=n_events, n_tracks=(n_tracks, n_tracks), master_seed=0x5EED0007)
 
 
 def small_barrel() -> Workload:

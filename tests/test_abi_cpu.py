@@ -33,8 +33,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     from paper_1811_04141_amd import mkf
-    # mkf_layer: 8 x 4 bytes; mkf_config: 6 floats, 2 ints, 6 floats, flags
-    assert C.sizeof(mkf.Layer) == 32
+    # mkf_layer: 11 x 4 bytes; mkf_config: 6 floats, 2 ints, 6 floats, flags
+    assert C.sizeof(mkf.Layer) == 44
     assert C.sizeof(mkf.Config) == 4 * (6 + 2 + 6 + 1)
     assert C.sizeof(mkf.Track) == 4 * 5 + 4 + 4 * 27 + 32 + 4 * 32
 
