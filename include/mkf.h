@@ -139,6 +139,20 @@ typedef struct {
   float dz_max;      /* cm: middle hit off the s-z line through the outer two */
 } mkf_seeding;
 
+/* Steering of one tracking region (Section 2.1: each region has a list of
+ * the layers the find traverses, five eta regions sufficing for CMS).  A
+ * seed whose pseudorapidity eta = -ln tan(theta / 2), of the seed fit,
+ * lies in [eta_lo, eta_hi) follows the first such region's list in the
+ * given order, less its own three layers; a listed layer its candidates do
+ * not reach inside the extent is a skip.  A seed in no region gets an
+ * empty plan. */
+#define MKF_MAX_REGIONS 8
+typedef struct {
+  float eta_lo, eta_hi;
+  int32_t n_layers;              /* 0..MKF_MAX_PLAN */
+  int32_t layers[MKF_MAX_PLAN];  /* layer ids, distinct, in visiting order */
+} mkf_region;
+
 /* Tolerances of the seed cleaning (mkf_clean_seeds). */
 typedef struct {
   float tol_ipt; /* q/pT, relative to the larger of the two */
@@ -162,6 +176,14 @@ const char *mkf_last_error(const mkf_ctx *ctx);
 /* Detector description (Section 2.1): n_layers records, host memory.
  * Replaces any previous geometry and invalidates loaded hits. */
 mkf_status mkf_load_geometry(mkf_ctx *ctx, const mkf_layer *layers, int32_t n_layers);
+
+/* Region steering (Section 2.1): n_regions (0..MKF_MAX_REGIONS) records,
+ * host memory, copied.  Layer ids refer to the loaded geometry, so load it
+ * first.  Takes effect at the next mkf_seed; n_regions = 0 returns to
+ * plans read from each seed's helix (every layer it crosses, by path
+ * length).  Loading a geometry clears it.  MKF_E_ARG for a bad record,
+ * MKF_E_ORDER without geometry. */
+mkf_status mkf_load_steering(mkf_ctx *ctx, const mkf_region *regions, int32_t n_regions);
 
 /* Hits of n_events events (hits and seeds are supplied from outside,
  * Section 2.2).  Event e owns hits [ev_off[e], ev_off[e+1]) of the arrays;

@@ -455,10 +455,12 @@ static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
  * The state starts at the first hit with a wide diagonal prior, less its
  * extent along the first seed layer's normal (the state lies on that layer),
  * and is filtered through the three hits (propagate, scatter, update),
- * ending on the third seed layer; chi2 sums the three updates' chi2.  The layer plan (the paper's per-region list of layers to
- * traverse, Section 2.1) is read per seed: every non-seed layer the seed
- * helix crosses inside its widened extent in the remaining half turn,
- * ordered by path length. */
+ * ending on the third seed layer; chi2 sums the three updates' chi2.
+ * The layer plan is the paper's per-region list of layers to traverse
+ * (Section 2.1).  With region steering it is the list of the region holding
+ * the seed's pseudorapidity, less the seed layers; without, it is read per
+ * seed: every non-seed layer the seed helix crosses inside its widened
+ * extent in the remaining half turn, ordered by path length. */
 int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
              const double h[9], const double hv[6], const int32_t hl[3],
              double pos_tol, orc_seed_out *out) {
@@ -513,6 +515,26 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
   out->chi2 = chi2;
 
   int n = 0;
+  if (cfg->n_regions > 0) {
+    /* region steering: the region's list, less the seed layers; a layer the
+     * track does not reach inside its extent becomes a skip in the find */
+    double eta = -log(tan(0.5 * p[5]));
+    const orc_region *R = NULL;
+    for (int r = 0; r < cfg->n_regions; ++r) {
+      const orc_region *g = &cfg->regions[r];
+      if (fabs(eta - g->eta_lo) <= ORC_ETA_TOL || fabs(eta - g->eta_hi) <= ORC_ETA_TOL)
+        out->plan_fragile = 1;
+      if (R == NULL && eta >= g->eta_lo && eta < g->eta_hi) R = g;
+    }
+    for (int k = 0; R != NULL && k < R->n_layers && n < ORC_MAX_PLAN; ++k) {
+      int i = R->layers[k];
+      if (i == hl[0] || i == hl[1] || i == hl[2]) continue;
+      out->plan[n++] = i;
+    }
+    out->plan_len = n;
+    out->ok = 1;
+    return 1;
+  }
   for (int i = 0; i < n_layers; ++i) {
     if (i == hl[0] || i == hl[1] || i == hl[2]) continue;
     double pp[6], l;

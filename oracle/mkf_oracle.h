@@ -29,6 +29,7 @@ extern "C" {
 #define ORC_KAPPA 0.299792458e-2
 
 #define ORC_MAX_PLAN 32
+#define ORC_ETA_TOL 1e-6
 
 /* Outcome of a propagation. */
 #define ORC_OK 0
@@ -49,6 +50,15 @@ typedef struct {
   double hole_lo, hole_hi; /* no sensors for hole_lo < q < hole_hi (q as ext) */
 } orc_layer;
 
+/* A tracking region's steering (Section 2.1): seeds whose pseudorapidity
+ * (of the seed fit's theta) lies in [eta_lo, eta_hi) follow its layer list,
+ * in the order given. */
+typedef struct {
+  double eta_lo, eta_hi;
+  int32_t n_layers;
+  int32_t layers[ORC_MAX_PLAN];
+} orc_region;
+
 typedef struct {
   double bz;          /* field along +z, tesla */
   double kappa;       /* curvature constant (normally ORC_KAPPA) */
@@ -59,6 +69,9 @@ typedef struct {
   int32_t n_cand;     /* candidates kept per seed */
   int32_t max_holes;  /* misses allowed per candidate */
   double init_var[6]; /* diagonal seed prior variances */
+  /* region steering; n_regions = 0: every seed's plan from its own helix */
+  const orc_region *regions;
+  int32_t n_regions;
 } orc_cfg;
 
 /* ---- single-state primitives (exposed for the tests) ---------------- */
@@ -124,7 +137,9 @@ typedef struct {
 } orc_seed_out;
 
 /* h: 3 hits x (x,y,z); hv: 3 hits x (var_u, var_v); hl: their layers.
- * pos_tol: distance to a widened edge below which the plan is flagged. */
+ * pos_tol: distance to a widened edge below which the plan is flagged.
+ * With region steering the plan is the seed's region's layer list less the
+ * seed layers, flagged if eta lies within ORC_ETA_TOL of a region bound. */
 int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
              const double h[9], const double hv[6], const int32_t hl[3],
              double pos_tol, orc_seed_out *out);

@@ -45,10 +45,16 @@ def _layer(l):
                  float(getattr(l, "hole_hi", 0.0)))
 
 
+class Region(C.Structure):
+    _fields_ = [("eta_lo", C.c_double), ("eta_hi", C.c_double), ("n_layers", C.c_int32),
+                ("layers", C.c_int32 * MAX_PLAN)]
+
+
 class Cfg(C.Structure):
     _fields_ = [("bz", C.c_double), ("kappa", C.c_double), ("chi2_cut", C.c_double),
                 ("ms_sigma", C.c_double), ("edge_margin", C.c_double), ("l_min", C.c_double),
-                ("n_cand", C.c_int32), ("max_holes", C.c_int32), ("init_var", C.c_double * 6)]
+                ("n_cand", C.c_int32), ("max_holes", C.c_int32), ("init_var", C.c_double * 6),
+                ("regions", C.POINTER(Region)), ("n_regions", C.c_int32)]
 
 
 class SeedOut(C.Structure):
@@ -176,13 +182,26 @@ def make_layers(layers) -> "C.Array":
     return arr
 
 
-def make_cfg(fc) -> Cfg:
+def make_cfg(fc, steering=None) -> Cfg:
+    """steering: a sequence of regions (eta_lo, eta_hi, layers); the bounds
+    are taken at FP32, as the library receives them."""
     c = Cfg()
     c.bz, c.kappa, c.chi2_cut = fc.bz, fc.kappa, fc.chi2_cut
     c.ms_sigma, c.edge_margin, c.l_min = fc.ms_sigma, fc.edge_margin, fc.l_min
     c.n_cand, c.max_holes = fc.n_cand, fc.max_holes
     for i in range(6):
         c.init_var[i] = fc.init_var[i]
+    if steering:
+        arr = (Region * len(steering))()
+        for r, g in zip(arr, steering):
+            r.eta_lo, r.eta_hi = float(np.float32(g.eta_lo)), float(np.float32(g.eta_hi))
+            if len(g.layers) > MAX_PLAN:
+                raise ValueError("region layer list longer than the plan")
+            r.n_layers = len(g.layers)
+            for k, L in enumerate(g.layers):
+                r.layers[k] = int(L)
+        c.regions, c.n_regions = arr, len(steering)
+        c._keep = arr
     return c
 
 
@@ -262,8 +281,8 @@ def update_hit(p, Cm, kind, hit, var_u, var_v, stereo=0.0):
     return bool(ok), p, Cm.reshape(6, 6), float(c2[0])
 
 
-def seed(fc, layers, h, hv, hl, pos_tol=0.0):
-    cfg = make_cfg(fc)
+def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None):
+    cfg = make_cfg(fc, steering)
     lay = make_layers(layers)
     h, hv = _d(h, 9), _d(hv, 6)
     hl = np.ascontiguousarray(hl, np.int32)
@@ -280,10 +299,10 @@ def seed(fc, layers, h, hv, hl, pos_tol=0.0):
 DEFAULT_TOL = (1e-3, 1e-2, 1e-3)  # chi2 rel, chi2 abs, cm
 
 
-def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL):
-    """Clone-engine finding for the seeds of one event (all seeds if None).
-    Returns a list of dicts, one per seed."""
-    cfg = make_cfg(fc)
+def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None):
+    """Clone-engine finding for the seeds of one event (all seeds if None),
+    with region steering if given.  Returns a list of dicts, one per seed."""
+    cfg = make_cfg(fc, steering)
     lay = make_layers(layers)
     t = Tol(*tol)
     seeds = ev.seeds if seeds is None else seeds

@@ -59,6 +59,8 @@ struct mkf_ctx {
   DevLayer layers[kMaxLayers]{};
   int bins_per_event = 0;
   DevBuf d_layers;
+  int n_regions = 0;  // region steering (0: plans from each seed's helix)
+  DevBuf d_regions;
 
   // hits
   int n_events = 0;
@@ -100,7 +102,7 @@ struct mkf_ctx {
 
   // fit scratch (host-side inputs are staged here)
   ~mkf_ctx() {
-    DevBuf *all[] = {&d_layers, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
+    DevBuf *all[] = {&d_layers, &d_regions, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
                      &d_hit_bin, &d_counts, &d_fill, &d_bin_start, &d_scan_tmp, &d_sorted,
                      &d_byorig, &d_bad, &d_seed_event, &d_seed_hits, &d_seed_state, &d_seed_ok,
                      &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_pstate, &d_pinfo,
@@ -402,7 +404,40 @@ mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_laye
   std::memcpy(c->layers, dl, sizeof(dl));
   c->n_layers = n_layers;
   c->bins_per_event = base;
+  c->n_regions = 0;
   c->stage = kGeometry;
+  return MKF_OK;
+}
+
+mkf_status mkf_load_steering(mkf_ctx *c, const mkf_region *regions, int32_t n_regions) {
+  if (!c) return MKF_E_ARG;
+  if (c->stage < kGeometry) return fail(c, MKF_E_ORDER, "load_geometry first");
+  if (n_regions < 0 || n_regions > MKF_MAX_REGIONS || (n_regions > 0 && !regions))
+    return fail(c, MKF_E_ARG, "need 0..%d regions", MKF_MAX_REGIONS);
+  DevRegion dr[kMaxRegions]{};
+  for (int r = 0; r < n_regions; ++r) {
+    const mkf_region &g = regions[r];
+    if (std::isnan(g.eta_lo) || std::isnan(g.eta_hi) || !(g.eta_lo < g.eta_hi))
+      return fail(c, MKF_E_ARG, "region %d: need eta_lo < eta_hi", r);
+    if (g.n_layers < 0 || g.n_layers > MKF_MAX_PLAN)
+      return fail(c, MKF_E_ARG, "region %d: need 0..%d layers", r, MKF_MAX_PLAN);
+    bool seen[kMaxLayers] = {};
+    for (int k = 0; k < g.n_layers; ++k) {
+      const int L = g.layers[k];
+      if (L < 0 || L >= c->n_layers)
+        return fail(c, MKF_E_ARG, "region %d: layer id %d not in the geometry", r, L);
+      if (seen[L]) return fail(c, MKF_E_ARG, "region %d: layer %d listed twice", r, L);
+      seen[L] = true;
+      dr[r].layers[k] = (int8_t)L;
+    }
+    dr[r].eta_lo = g.eta_lo;
+    dr[r].eta_hi = g.eta_hi;
+    dr[r].n = g.n_layers;
+  }
+  HIP_TRY(c, c->d_regions.ensure(sizeof(dr)));
+  HIP_TRY(c, hipMemcpyAsync(c->d_regions.ptr, dr, sizeof(dr), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->n_regions = n_regions;
   return MKF_OK;
 }
 
@@ -535,7 +570,8 @@ mkf_status mkf_seed(mkf_ctx *c, int64_t n_seeds, const int32_t *seed_event,
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   launch_seed(c->stream, P, c->d_seed_hits.as<int>(), c->d_seed_state.as<float>(),
               c->d_seed_ok.as<int>(), c->d_plan_len.as<int>(), c->d_plan.as<int8_t>(),
-              c->d_plan_l.as<double>(), c->d_seed_chi2.as<float>());
+              c->d_plan_l.as<double>(), c->d_seed_chi2.as<float>(),
+              c->n_regions > 0 ? c->d_regions.as<DevRegion>() : nullptr, c->n_regions);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
   // processing order: longest plans first (the persistent form takes tiles

@@ -834,13 +834,16 @@ __global__ __launch_bounds__(256) void k_permute_seeds(FindParams P, float *psta
 // transverse points gives the centre and radius, the turning sense the
 // charge, the tangent at the first hit phi, and the z rise over the arc
 // theta.  A wide diagonal prior at the first hit is filtered through the
-// three hits.  The layer plan (the paper's per-region list of layers to
-// traverse, Section 2.1) is built per seed: every other layer the seed
-// helix crosses inside its widened extent, by increasing path length.
+// three hits.  The layer plan is the paper's per-region list of layers to
+// traverse (Section 2.1): with region steering, the list of the region that
+// holds the seed's pseudorapidity, less the seed layers; without, it is built
+// per seed: every other layer the seed helix crosses inside its widened
+// extent, by increasing path length.
 
 __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits,
                                               float *seed_state, int *seed_ok, int *plan_len,
-                                              int8_t *plan, double *plan_l, float *seed_chi2) {
+                                              int8_t *plan, double *plan_l, float *seed_chi2,
+                                              const DevRegion *regions, int n_regions) {
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
   __syncthreads();
@@ -917,6 +920,20 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     }
     if (!good) break;
     ok = 1;
+    if (n_regions > 0) {
+      const double eta = -log(tan(0.5 * p[5]));
+      int r = 0;
+      while (r < n_regions && !(eta >= regions[r].eta_lo && eta < regions[r].eta_hi)) ++r;
+      if (r < n_regions) {
+        const DevRegion &g = regions[r];
+        for (int k = 0; k < g.n && n < kMaxPlan; ++k) {
+          const int L = g.layers[k];
+          if (L == hl[0] || L == hl[1] || L == hl[2]) continue;
+          plan[i * kMaxPlan + n++] = (int8_t)L;
+        }
+      }
+      break;
+    }
     // plan: insertion by path length (ties by layer id) into global scratch
     for (int L = 0; L < P.n_layers; ++L) {
       if (L == hl[0] || L == hl[1] || L == hl[2]) continue;
@@ -2031,10 +2048,11 @@ void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, 
 }
 
 void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
-                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l, float *seed_chi2) {
+                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l, float *seed_chi2,
+                 const DevRegion *regions, int n_regions) {
   if (P.n_seeds == 0) return;
   hipLaunchKernelGGL(k_seed, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P, seed_hits,
-                     seed_state, seed_ok, plan_len, plan, plan_l, seed_chi2);
+                     seed_state, seed_ok, plan_len, plan, plan_l, seed_chi2, regions, n_regions);
 }
 
 void launch_find_init(hipStream_t s, const FindParams &P) {

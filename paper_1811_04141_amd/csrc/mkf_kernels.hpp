@@ -22,6 +22,15 @@ struct alignas(16) HitRec {
   int pad1;
 };
 
+// Steering of one tracking region: seeds with eta_lo <= eta < eta_hi
+// follow `layers` (less their seed layers) in this order.
+constexpr int kMaxRegions = MKF_MAX_REGIONS;
+struct DevRegion {
+  double eta_lo, eta_hi;
+  int n;
+  int8_t layers[kMaxPlan];
+};
+
 // Candidate buffers between layer steps (layer-synchronous form), SoA by
 // field over n_seeds * kGroup slots so that a wavefront reads 64
 // consecutive floats per field.
@@ -128,7 +137,8 @@ void launch_scan(hipStream_t s, const int *in, int *out, int64_t n, int *tmp_a, 
 void launch_scatter(hipStream_t s, const FindParams &P, int64_t n_hits, const int *hit_bin,
                     int *fill, HitRec *sorted, HitRec *byorig);
 void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float *seed_state,
-                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l, float *seed_chi2);
+                 int *seed_ok, int *plan_len, int8_t *plan, double *plan_l, float *seed_chi2,
+                 const DevRegion *regions, int n_regions);
 void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int *pinfo,
                           int *pevent, int8_t *pplan);
 void launch_find_init(hipStream_t s, const FindParams &P);

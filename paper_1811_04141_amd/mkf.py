@@ -20,9 +20,11 @@ F_BATCHED, F_GRAPH, F_SURROGATE = 1, 2, 4
 MLP_NPARAM = 5191  # W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]
 MAX_LAYERS = MAX_PLAN = 32
 MAX_CAND = 8
+MAX_REGIONS = 8
 HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
-EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry", "mkf_load_hits",
+EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry",
+           "mkf_load_steering", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
            "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_clean_seeds",
            "mkf_find_duplicates",
@@ -79,6 +81,23 @@ def make_seeding(sc):
     return s
 
 
+class Region(C.Structure):
+    _fields_ = [("eta_lo", C.c_float), ("eta_hi", C.c_float), ("n_layers", C.c_int32),
+                ("layers", C.c_int32 * MAX_PLAN)]
+
+
+def make_regions(regions):
+    """Region records from objects with eta_lo, eta_hi and layers."""
+    arr = (Region * max(1, len(regions)))()
+    for r, g in zip(arr, regions):
+        if len(g.layers) > MAX_PLAN:
+            raise ValueError("a region lists more than %d layers" % MAX_PLAN)
+        r.eta_lo, r.eta_hi, r.n_layers = g.eta_lo, g.eta_hi, len(g.layers)
+        for k, L in enumerate(g.layers):
+            r.layers[k] = int(L)
+    return arr
+
+
 class Cleaning(C.Structure):
     _fields_ = [("tol_ipt", C.c_float), ("tol_eta", C.c_float), ("tol_phi", C.c_float)]
 
@@ -115,6 +134,7 @@ def _load():
         "mkf_destroy": ([P], None),
         "mkf_last_error": ([P], C.c_char_p),
         "mkf_load_geometry": ([P, C.POINTER(Layer), I32], I32),
+        "mkf_load_steering": ([P, C.POINTER(Region), I32], I32),
         "mkf_load_hits": ([P, I32, P, P, P, P, P, P, P, I32], I32),
         "mkf_seed": ([P, I64, P, P, I32], I32),
         "mkf_get_seed_states": ([P, P, P, P, P, P, P], I32),
@@ -218,6 +238,11 @@ class Context:
 
     def load_geometry(self, layers):
         self._check(lib.mkf_load_geometry(self.h, make_layers(layers), len(layers)))
+
+    def load_steering(self, regions):
+        """Region steering for the next seed(); an empty sequence returns to
+        plans from each seed's helix."""
+        self._check(lib.mkf_load_steering(self.h, make_regions(regions), len(regions)))
 
     def load_hits(self, ev_off, x, y, z, var_u, var_v, layer):
         ev_off = np.ascontiguousarray(ev_off, np.int64)

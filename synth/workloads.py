@@ -130,6 +130,35 @@ def stereo_layer(layer: Layer, angle: float, sigma_perp: float) -> Layer:
                    var_u_max=c * c * vw + s * s * vp, var_v_max=s * s * vw + c * c * vp)
 
 
+@dataclass(frozen=True)
+class Region:
+    """A tracking region's steering: seeds with eta_lo <= eta < eta_hi
+    follow `layers` (layer ids) in this order."""
+    eta_lo: float
+    eta_hi: float
+    layers: Tuple[int, ...]
+
+
+def five_regions(eta_barrel: float = 0.9, eta_endcap: float = 1.7,
+                 n_barrel: int = len(BARREL_RADII), n_disks: int = len(DISK_Z),
+                 endcap_barrel: int = 7) -> Tuple[Region, ...]:
+    """Five eta regions (barrel, -z/+z transition, -z/+z endcap) on the
+    layer order of barrel_layers() + disk_layers(): barrel layers by radius,
+    then the side's disks by |z|.  The disks start beyond the barrel's end,
+    so an outgoing track meets the layers in this order.  The endcap lists
+    hold the first `endcap_barrel` barrel layers only."""
+    barrel = tuple(range(n_barrel))
+    plus = tuple(range(n_barrel, n_barrel + n_disks))
+    minus = tuple(range(n_barrel + n_disks, n_barrel + 2 * n_disks))
+    inner = barrel[:endcap_barrel]
+    big = float(np.finfo(np.float32).max)
+    return (Region(-big, -eta_endcap, inner + minus),
+            Region(-eta_endcap, -eta_barrel, barrel + minus),
+            Region(-eta_barrel, eta_barrel, barrel),
+            Region(eta_barrel, eta_endcap, barrel + plus),
+            Region(eta_endcap, big, inner + plus))
+
+
 def cms_like(n_events: int = 10, n_tracks: int = 2000) -> Workload:
     """The realistic recipe on a geometry with the generality of the
     paper's layer description (Section 2.1): barrel layers 4 and 6 (R = 25,
