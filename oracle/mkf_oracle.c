@@ -262,6 +262,68 @@ void orc_add_ms(const double p[6], double sigma, double C[36]) {
   C[5 * 6 + 5] += s2;
 }
 
+/* Bethe's mean mass stopping power (PDG form: K Z/A / beta^2 *
+ * (ln(2 m_e c^2 b^2 g^2 T_max / I^2) / 2 - beta^2)) for silicon, without
+ * the density-effect and shell corrections. */
+double orc_bethe_si(double bg, double mass) {
+  const double K = 0.307075e-3;   /* GeV cm^2 / mol */
+  const double ZA = 0.49848;      /* mol / g */
+  const double I = 173e-9;        /* GeV */
+  const double me = 0.51099895e-3; /* GeV */
+  double bg2 = bg * bg, b2 = bg2 / (1.0 + bg2), g = sqrt(1.0 + bg2), r = me / mass;
+  double tmax = 2.0 * me * bg2 / (1.0 + 2.0 * g * r + r * r);
+  return K * ZA / b2 * (0.5 * log(2.0 * me * bg2 * tmax / (I * I)) - b2);
+}
+
+void orc_material_effects(const orc_cfg *cfg, int kind, double p[6], double C[36], int dir,
+                          double M[36]) {
+  if (M) {
+    memset(M, 0, 36 * sizeof(double));
+    for (int i = 0; i < 6; ++i) M[i * 6 + i] = 1.0;
+  }
+  const orc_material *m = cfg->material;
+  if (!m) {
+    orc_add_ms(p, cfg->ms_sigma, C);
+    return;
+  }
+  double r = hypot(p[0], p[1]);
+  int ir = (int)floor(r / m->r_max * m->n_r);
+  int iz = (int)floor((p[2] + m->z_max) / (2.0 * m->z_max) * m->n_z);
+  ir = ir < 0 ? 0 : (ir >= m->n_r ? m->n_r - 1 : ir);
+  iz = iz < 0 ? 0 : (iz >= m->n_z ? m->n_z - 1 : iz);
+  double t0 = m->x_x0[iz * m->n_r + ir], xi0 = m->xi[iz * m->n_r + ir];
+  double st = sin(p[5]), ct = cos(p[5]);
+  /* cosine of the angle between the direction and the surface normal */
+  double cosa = kind == 0 ? st * (cos(p[4]) * p[0] + sin(p[4]) * p[1]) / r : ct;
+  double k = fabs(cosa) * m->k_max > 1.0 ? 1.0 / fabs(cosa) : m->k_max;
+  double pm = 1.0 / (fabs(p[3]) * st);
+  double beta = pm / sqrt(pm * pm + m->mass * m->mass);
+  double t = t0 * k;
+  if (t > 0.0) {
+    double f = 1.0 + 0.038 * log(t);
+    if (f < 0.0) f = 0.0;
+    orc_add_ms(p, 0.0136 / (beta * pm) * sqrt(t) * f, C);
+  }
+  double x = xi0 * k;
+  if (x > 0.0) {
+    double dp = x * orc_bethe_si(pm / m->mass, m->mass) / beta;
+    if (dp > 0.5 * pm) dp = 0.5 * pm;
+    double ratio = 1.0 / (1.0 - dir * dp / pm); /* |p| / |p'| */
+    double J[36];
+    memset(J, 0, sizeof(J));
+    for (int i = 0; i < 6; ++i) J[i * 6 + i] = 1.0;
+    J[3 * 6 + 3] = ratio * ratio;
+    J[3 * 6 + 5] = dir * dp * p[3] * fabs(p[3]) * ct * ratio * ratio;
+    p[3] *= ratio;
+    double JC[36], Jt[36];
+    matmul6(J, C, JC);
+    transpose6(J, Jt);
+    matmul6(JC, Jt, C);
+    symmetrize6(C);
+    if (M) memcpy(M, J, sizeof(J));
+  }
+}
+
 /* ------------------------------------------------------- measurement */
 
 /* Local 2-D frame at the predicted point: t = (-y', x')/r' along the
@@ -504,7 +566,7 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
       memcpy(p, pp, sizeof(pp));
       memcpy(C, Cp, sizeof(Cp));
     }
-    orc_add_ms(p, cfg->ms_sigma, C);
+    orc_material_effects(cfg, Lr->kind, p, C, 1, NULL);
     double c2;
     if (!orc_update_hit(p, C, Lr->kind, &h[3 * k], hv[2 * k], hv[2 * k + 1], Lr->stereo, &c2))
       return 0;
@@ -680,7 +742,7 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
         ext[ne++] = e;
         continue;
       }
-      orc_add_ms(pc, cfg->ms_sigma, Cc);
+      orc_material_effects(cfg, Lr->kind, pc, Cc, 1, NULL);
       for (int k = lay_off[L]; k < lay_off[L + 1]; ++k) {
         int32_t hi = lay_idx[k];
         double hh[3] = {x[hi], y[hi], z[hi]};
@@ -810,7 +872,7 @@ int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36], i
     double pp[6], Cp[36];
     if (orc_propagate(p, C, &Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL) != ORC_OK)
       return -(k + 1);
-    orc_add_ms(pp, cfg->ms_sigma, Cp);
+    orc_material_effects(cfg, kinds[k], pp, Cp, 1, NULL);
     double c2;
     if (!orc_update_hit(pp, Cp, kinds[k], &hits[3 * k], var_u[k], var_v[k], 0.0, &c2))
       return -(k + 1);
@@ -895,7 +957,7 @@ int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
       memcpy(p, pp, sizeof(pp));
       memcpy(C, Cp, sizeof(Cp));
     }
-    orc_add_ms(p, cfg->ms_sigma, C);
+    orc_material_effects(cfg, Lr->kind, p, C, -1, NULL);
     if (hit[k] >= 0) {
       const double h[3] = {x[hit[k]], y[hit[k]], z[hit[k]]};
       double c2;
@@ -990,7 +1052,10 @@ int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
     if (orc_propagate(xf[n - 1], Cf[n - 1], Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp,
                       F[n], NULL) != ORC_OK)
       return -1;
-    orc_add_ms(pp, cfg->ms_sigma, Cp);
+    double Mm[36], MF[36];
+    orc_material_effects(cfg, Lr->kind, pp, Cp, 1, Mm);
+    matmul6(Mm, F[n], MF);
+    memcpy(F[n], MF, sizeof(MF));
     memcpy(xp[n], pp, sizeof(pp));
     memcpy(Cpr[n], Cp, sizeof(Cp));
     if (code >= 0) {

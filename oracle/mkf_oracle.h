@@ -59,6 +59,21 @@ typedef struct {
   int32_t layers[ORC_MAX_PLAN];
 } orc_region;
 
+/* Material map (Section 2.1: radiation and interaction lengths in 2-D r-z
+ * arrays, indexed at each crossing).  Bin (iz, ir) covers
+ * r in [ir, ir + 1) * r_max / n_r and z in -z_max + [iz, iz + 1) * 2 z_max / n_z
+ * (crossings outside take the nearest edge bin) and holds the layer's
+ * thickness there at normal incidence, in radiation lengths (x_x0) and as
+ * mass thickness in g/cm^2 (xi, for the mean ionisation loss). */
+typedef struct {
+  int32_t n_r, n_z;
+  double r_max, z_max;
+  double mass;        /* particle mass hypothesis, GeV */
+  double k_max;       /* cap on the path factor 1 / |cos(incidence)| */
+  const double *x_x0; /* [n_z][n_r] */
+  const double *xi;   /* [n_z][n_r] */
+} orc_material;
+
 typedef struct {
   double bz;          /* field along +z, tesla */
   double kappa;       /* curvature constant (normally ORC_KAPPA) */
@@ -72,6 +87,8 @@ typedef struct {
   /* region steering; n_regions = 0: every seed's plan from its own helix */
   const orc_region *regions;
   int32_t n_regions;
+  /* material map; NULL: the constant scattering angle ms_sigma per layer */
+  const orc_material *material;
 } orc_cfg;
 
 /* ---- single-state primitives (exposed for the tests) ---------------- */
@@ -98,6 +115,22 @@ int orc_propagate(const double p[6], const double C[36], const orc_layer *L,
 
 /* Multiple-scattering noise for state p with angle sigma, added to C. */
 void orc_add_ms(const double p[6], double sigma, double C[36]);
+
+/* Mean ionisation loss in silicon (Bethe, no density or shell correction),
+ * GeV cm^2 / g, for a particle of the given mass at beta*gamma = bg. */
+double orc_bethe_si(double bg, double mass);
+
+/* Effects of the material of one crossed layer of the given kind on the
+ * state p, C at the crossing.  Without a material map: scattering with
+ * cfg->ms_sigma.  With one: the Highland scattering angle of the path's
+ * radiation lengths at the momentum before the loss, then the mean
+ * ionisation loss of the path's mass thickness, |p| -> |p| - dir * dp
+ * (dir = +1 moving forward, -1 for the backward fit, which regains it),
+ * dp = dE / beta, at most half of |p|.  M (may be NULL) receives the
+ * Jacobian of the state change (identity but the q/pT row, with dp held
+ * fixed); C becomes M (C + Q) M^T. */
+void orc_material_effects(const orc_cfg *cfg, int kind, double p[6], double C[36], int dir,
+                          double M[36]);
 
 /* Local measurement of a hit at the predicted state: residual r[2],
  * projection H (2x6) and hit variances.  Returns 0 if the hit lies in the

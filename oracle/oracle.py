@@ -50,11 +50,18 @@ class Region(C.Structure):
                 ("layers", C.c_int32 * MAX_PLAN)]
 
 
+class Material(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_z", C.c_int32), ("r_max", C.c_double),
+                ("z_max", C.c_double), ("mass", C.c_double), ("k_max", C.c_double),
+                ("x_x0", C.POINTER(C.c_double)), ("xi", C.POINTER(C.c_double))]
+
+
 class Cfg(C.Structure):
     _fields_ = [("bz", C.c_double), ("kappa", C.c_double), ("chi2_cut", C.c_double),
                 ("ms_sigma", C.c_double), ("edge_margin", C.c_double), ("l_min", C.c_double),
                 ("n_cand", C.c_int32), ("max_holes", C.c_int32), ("init_var", C.c_double * 6),
-                ("regions", C.POINTER(Region)), ("n_regions", C.c_int32)]
+                ("regions", C.POINTER(Region)), ("n_regions", C.c_int32),
+                ("material", C.POINTER(Material))]
 
 
 class SeedOut(C.Structure):
@@ -98,6 +105,9 @@ def lib():
         L.orc_propagate.argtypes = [_D, _D, C.POINTER(Layer), C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_int, _D, _D, _D, _D]
         L.orc_add_ms.argtypes = [_D, C.c_double, _D]
+        L.orc_bethe_si.argtypes = [C.c_double, C.c_double]
+        L.orc_bethe_si.restype = C.c_double
+        L.orc_material_effects.argtypes = [C.POINTER(Cfg), C.c_int, _D, _D, C.c_int, _D]
         L.orc_measure.argtypes = [_D, C.c_int, _D, _D, _D]
         L.orc_chi2.argtypes = [_D, _D, C.c_int, _D, C.c_double, C.c_double, C.c_double, _D]
         L.orc_kf_update.argtypes = [_D, _D, C.c_int, _D, _D, _D, C.c_int, _D]
@@ -182,9 +192,27 @@ def make_layers(layers) -> "C.Array":
     return arr
 
 
-def make_cfg(fc, steering=None) -> Cfg:
+def make_material(mm):
+    """Material record from a map with n_r, n_z, r_max, z_max, mass, k_max
+    and the [n_z][n_r] tables x_x0, xi (taken at FP32, as the library
+    receives them)."""
+    m = Material()
+    m.n_r, m.n_z = int(mm.n_r), int(mm.n_z)
+    m.r_max, m.z_max = float(np.float32(mm.r_max)), float(np.float32(mm.z_max))
+    m.mass, m.k_max = float(np.float32(mm.mass)), float(np.float32(mm.k_max))
+    t = np.ascontiguousarray(np.asarray(mm.x_x0, np.float32), np.float64).reshape(-1)
+    x = np.ascontiguousarray(np.asarray(mm.xi, np.float32), np.float64).reshape(-1)
+    if t.size != m.n_r * m.n_z or x.size != m.n_r * m.n_z:
+        raise ValueError("material tables must hold n_z x n_r bins")
+    m.x_x0, m.xi = _p(t), _p(x)
+    m._keep = (t, x)
+    return m
+
+
+def make_cfg(fc, steering=None, material=None) -> Cfg:
     """steering: a sequence of regions (eta_lo, eta_hi, layers); the bounds
-    are taken at FP32, as the library receives them."""
+    are taken at FP32, as the library receives them.  material: a material
+    map (make_material), or None for the constant scattering angle."""
     c = Cfg()
     c.bz, c.kappa, c.chi2_cut = fc.bz, fc.kappa, fc.chi2_cut
     c.ms_sigma, c.edge_margin, c.l_min = fc.ms_sigma, fc.edge_margin, fc.l_min
@@ -202,6 +230,10 @@ def make_cfg(fc, steering=None) -> Cfg:
                 r.layers[k] = int(L)
         c.regions, c.n_regions = arr, len(steering)
         c._keep = arr
+    if material is not None:
+        m = make_material(material)
+        c.material = C.pointer(m)
+        c._keep_m = m
     return c
 
 
@@ -247,6 +279,22 @@ def add_ms(p, sigma, Cm):
     return out.reshape(6, 6)
 
 
+def bethe_si(bg, mass):
+    """Mean ionisation loss in silicon, GeV cm^2 / g."""
+    return float(lib().orc_bethe_si(float(bg), float(mass)))
+
+
+def material_effects(fc, material, kind, p, Cm, direction=1):
+    """Effects of one crossed layer's material on (p, Cm).  Returns (p,
+    Cm 6x6, M 6x6)."""
+    cfg = make_cfg(fc, material=material)
+    p = _d(p, 6).copy()
+    Cm = _d(Cm, 36).copy()
+    M = np.zeros(36)
+    lib().orc_material_effects(C.byref(cfg), int(kind), _p(p), _p(Cm), int(direction), _p(M))
+    return p, Cm.reshape(6, 6), M.reshape(6, 6)
+
+
 def measure(p, kind, hit):
     p, hit = _d(p, 6), _d(hit, 3)
     r, H = np.zeros(2), np.zeros(12)
@@ -281,8 +329,8 @@ def update_hit(p, Cm, kind, hit, var_u, var_v, stereo=0.0):
     return bool(ok), p, Cm.reshape(6, 6), float(c2[0])
 
 
-def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None):
-    cfg = make_cfg(fc, steering)
+def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None, material=None):
+    cfg = make_cfg(fc, steering, material)
     lay = make_layers(layers)
     h, hv = _d(h, 9), _d(hv, 6)
     hl = np.ascontiguousarray(hl, np.int32)
@@ -299,10 +347,11 @@ def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None):
 DEFAULT_TOL = (1e-3, 1e-2, 1e-3)  # chi2 rel, chi2 abs, cm
 
 
-def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None):
+def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None, material=None):
     """Clone-engine finding for the seeds of one event (all seeds if None),
-    with region steering if given.  Returns a list of dicts, one per seed."""
-    cfg = make_cfg(fc, steering)
+    with region steering and a material map if given.  Returns a list of
+    dicts, one per seed."""
+    cfg = make_cfg(fc, steering, material)
     lay = make_layers(layers)
     t = Tol(*tol)
     seeds = ev.seeds if seeds is None else seeds
@@ -326,8 +375,8 @@ def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None):
     return res
 
 
-def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v):
-    cfg = make_cfg(fc)
+def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v, material=None):
+    cfg = make_cfg(fc, material=material)
     p0, C0 = _d(p0, 6), _d(C0, 36)
     kinds = np.ascontiguousarray(kinds, np.int32)
     n = kinds.shape[0]
@@ -350,11 +399,11 @@ def flip(p, Cm=None):
     return p, Cm.reshape(6, 6)
 
 
-def backward_fit(fc, layers, ev, seed_hits, trk):
+def backward_fit(fc, layers, ev, seed_hits, trk, material=None):
     """Backward fit of one found track of event ev (a find_event result
     dict, or any dict with seed_ok, plan, hit, par).  Returns (status, par,
     cov 6x6, chi2, n_updates)."""
-    cfg = make_cfg(fc)
+    cfg = make_cfg(fc, material=material)
     lay = make_layers(layers)
     t = Track()
     t.seed_ok = int(bool(trk["seed_ok"]))
@@ -390,11 +439,11 @@ def _track_struct(trk):
     return t
 
 
-def smooth_track(fc, layers, ev, seed_layer, seed_par, seed_cov, trk):
+def smooth_track(fc, layers, ev, seed_layer, seed_par, seed_cov, trk, material=None):
     """RTS smoothing of one found track of event ev, starting from the seed
     state (seed_par, seed_cov 6x6) on seed_layer.  Returns (n, layers [n],
     par [n][6], cov [n][6][6]); n <= 0 on failure."""
-    cfg = make_cfg(fc)
+    cfg = make_cfg(fc, material=material)
     lay = make_layers(layers)
     t = _track_struct(trk)
     arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z, ev.var_u, ev.var_v)]

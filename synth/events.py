@@ -39,6 +39,8 @@ class Event:
     # (position on the surface, q/pT, phi, theta after the scattering kick)
     truth_state: np.ndarray  # (n_hits, 6); NaN rows for noise
     track_hits: List[np.ndarray]  # per track: event-local hit indices in order
+    # per track: the initial state (vertex, q/pT, phi, theta), float64
+    track_init: Optional[np.ndarray] = None
 
     @property
     def n_hits(self) -> int:
@@ -90,11 +92,53 @@ def _next_crossings(cx, cy, rho, sgn, x, y, z, cot, budget, kinds, poss, eps):
     return out
 
 
+_ME = 0.51099895e-3      # electron mass, GeV
+_K_BETHE = 0.307075e-3  # GeV cm^2 / mol
+_SI_ZA, _SI_I = 0.49848, 173e-9
+
+
+def _si_loss_rate(p, mass):
+    """Mean ionisation loss rate in silicon, GeV cm^2/g, at momentum p
+    (Bethe-Bloch without density effect)."""
+    bg2 = (p / mass) ** 2
+    g = np.sqrt(1.0 + bg2)
+    b2 = bg2 / (1.0 + bg2)
+    ratio = _ME / mass
+    wmax = 2.0 * _ME * bg2 / (1.0 + 2.0 * g * ratio + ratio * ratio)
+    return _K_BETHE * _SI_ZA / b2 * (0.5 * np.log(2.0 * _ME * bg2 * wmax / _SI_I ** 2) - b2)
+
+
+def _material_kick(rng, mat, is_b, x, y, z, ph, th, p_tot):
+    """Scattering angle (Highland, at the momentum before the loss) and
+    mean ionisation loss of the material crossed at (x, y, z) by tracks of
+    direction (ph, th) and momentum p_tot.  Returns (angle sigma, new p)."""
+    r = np.hypot(x, y)
+    ir = np.clip(np.floor(r / mat.r_max * mat.n_r).astype(int), 0, mat.n_r - 1)
+    iz = np.clip(np.floor((z + mat.z_max) / (2.0 * mat.z_max) * mat.n_z).astype(int), 0,
+                 mat.n_z - 1)
+    t0 = np.asarray(mat.x_x0, np.float64)[iz, ir]
+    xi0 = np.asarray(mat.xi, np.float64)[iz, ir]
+    # incidence: track direction against the surface normal
+    dx, dy, dz = np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)
+    cos_in = np.where(is_b, (dx * x + dy * y) / r, dz)
+    path = np.minimum(1.0 / np.maximum(np.abs(cos_in), 1e-300), mat.k_max)
+    energy = np.sqrt(p_tot ** 2 + mat.mass ** 2)
+    beta = p_tot / energy
+    t = t0 * path
+    with np.errstate(divide="ignore"):
+        corr = np.maximum(1.0 + 0.038 * np.log(np.where(t > 0, t, 1.0)), 0.0)
+    sigma = np.where(t > 0, 0.0136 / (beta * p_tot) * np.sqrt(t) * corr, 0.0)
+    dp = np.minimum(xi0 * path * _si_loss_rate(p_tot, mat.mass) / beta, 0.5 * p_tot)
+    return sigma, p_tot - np.where(xi0 > 0, dp, 0.0)
+
+
 def simulate_tracks(rng, n, layers, bz, recipe, pt=None, eta=None, phi=None, q=None,
-                    vertex=None, max_iter=64):
+                    vertex=None, max_iter=64, material=None):
     """Simulate n tracks; returns per-crossing records (track, layer, true
     position, state after the layer) in crossing order, plus the initial
-    parameters."""
+    parameters.  With a material map, each crossed layer scatters the track
+    by the Highland angle of its material and takes its mean ionisation
+    loss (in place of the recipe's constant angle)."""
     if q is None:
         q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
     if pt is None:
@@ -167,7 +211,16 @@ def simulate_tracks(rng, n, layers, bz, recipe, pt=None, eta=None, phi=None, q=N
         if sel.size:
             t = idx[sel]
             # scattering on the crossed layer, after the hit is made
-            if recipe.ms_sigma > 0.0:
+            if material is not None:
+                p_tot = ptc[t] / np.sin(th[t])
+                sig, p_new = _material_kick(rng, material, is_b[sel], x[t], y[t], z[t], ph[t],
+                                            th[t], p_tot)
+                dth = rng.normal(0.0, 1.0, t.size) * sig
+                dal = rng.normal(0.0, 1.0, t.size) * sig
+                ph[t] = _wrap(ph[t] + dal / np.sin(th[t]))
+                th[t] = th[t] + dth
+                ptc[t] = p_new * np.sin(th[t])
+            elif recipe.ms_sigma > 0.0:
                 dth = rng.normal(0.0, recipe.ms_sigma, t.size)
                 dal = rng.normal(0.0, recipe.ms_sigma, t.size)
                 p_tot = ptc[t] / np.sin(th[t])
@@ -269,7 +322,8 @@ def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None,
     if n_tracks is None:
         n_tracks = lo if lo == hi else int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
     phi = None if phi_range is None else rng.uniform(phi_range[0], phi_range[1], n_tracks)
-    init, trk, lay, st = simulate_tracks(rng, n_tracks, w.layers, w.find.bz, w.recipe, phi=phi)
+    init, trk, lay, st = simulate_tracks(rng, n_tracks, w.layers, w.find.bz, w.recipe, phi=phi,
+                                         material=w.material)
     # 2% (or as configured) independent loss of hits
     if w.recipe.hit_ineff > 0.0:
         keep = rng.random(trk.shape[0]) >= w.recipe.hit_ineff
@@ -312,7 +366,7 @@ def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None,
             seed_track.append(t)
     seeds = np.array(seeds, np.int32).reshape(-1, 3)
     return Event(X, Y, Zc, VU, VV, LAY, TRK, seeds, np.array(seed_track, np.int32),
-                 TS, track_hits)
+                 TS, track_hits, init)
 
 
 @dataclass

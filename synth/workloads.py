@@ -7,7 +7,7 @@ CMS-2017 geometry, Section 3) is not available, so seeded synthetic events of
 the shapes below stand in for it.
 """
 from dataclasses import dataclass, field, replace
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -109,6 +109,36 @@ class EventRecipe:
     noise_frac: float = 0.0
 
 
+PION_MASS = 0.13957  # GeV
+
+
+@dataclass(frozen=True)
+class MaterialMap:
+    """Material in r-z (the paper's 2-D radiation and interaction length
+    arrays, Section 2.1): bin (iz, ir) covers r in [ir, ir + 1) r_max / n_r
+    and z in -z_max + [iz, iz + 1) 2 z_max / n_z (outside: the nearest edge
+    bin) and holds the thickness of the layer crossed there, at normal
+    incidence, in radiation lengths (x_x0) and in g/cm^2 (xi)."""
+    n_r: int
+    n_z: int
+    r_max: float
+    z_max: float
+    x_x0: np.ndarray = field(compare=False)   # [n_z][n_r]
+    xi: np.ndarray = field(compare=False)     # [n_z][n_r]
+    mass: float = PION_MASS
+    k_max: float = 10.0
+
+
+def material_map(r_max: float, z_max: float, n_r: int, n_z: int, x_x0: float, xi: float,
+                 outer_z: float = 50.0, outer_factor: float = 1.5) -> MaterialMap:
+    """A map with x_x0 and xi everywhere, times outer_factor where the bin
+    lies beyond |z| = outer_z (thicker services at the barrel's ends)."""
+    zc = -z_max + (np.arange(n_z) + 0.5) * (2.0 * z_max / n_z)
+    f = np.where(np.abs(zc) > outer_z, outer_factor, 1.0)[:, None] * np.ones((1, n_r))
+    return MaterialMap(n_r, n_z, r_max, z_max, (x_x0 * f).astype(np.float32),
+                       (xi * f).astype(np.float32))
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
@@ -118,6 +148,9 @@ class Workload:
     n_events: int
     n_tracks: Tuple[int, int]   # (lo, hi); lo == hi means fixed, else log-uniform
     master_seed: int
+    # material map (replaces the recipe's and the settings' constant
+    # scattering angle), or None
+    material: Optional[MaterialMap] = None
 
 
 def stereo_layer(layer: Layer, angle: float, sigma_perp: float) -> Layer:
@@ -177,6 +210,29 @@ def cms_like(n_events: int = 10, n_tracks: int = 2000) -> Workload:
                            hit_ineff=0.02, noise_frac=0.3),
         find=FindConfig(),
         n_events=n_events, n_tracks=(n_tracks, n_tracks), master_seed=0x5EED0007)
+
+
+def barrel_material(n_tracks: int = 300) -> Workload:
+    """The small barrel's 10 cylinders with heavy material (3% of a
+    radiation length and 0.5 g/cm^2 per layer at normal incidence, 1.5x
+    beyond |z| = 50 cm), pT 0.5-2 GeV/c: ionisation loss of the order of
+    the momentum resolution.  No noise, no inefficiency."""
+    return Workload(
+        name=f"barrel10_material_1x{n_tracks}",
+        layers=tuple(barrel_layers()),
+        recipe=EventRecipe(pt_lo=0.5, pt_hi=2.0),
+        find=FindConfig(),
+        n_events=1, n_tracks=(n_tracks, n_tracks), master_seed=0x5EED0009,
+        material=material_map(80.0, 100.0, 16, 8, 0.03, 0.5))
+
+
+def cms_like_material(n_events: int = 10, n_tracks: int = 2000) -> Workload:
+    """The CMS-like geometry with a silicon-like material map (1.5% of a
+    radiation length and 0.1 g/cm^2 per layer, 1.5x beyond |z| = 50 cm) in
+    place of the constant scattering angle."""
+    w = cms_like(n_events, n_tracks)
+    return replace(w, name=f"cms_like_material_{n_events}x{n_tracks}",
+                   material=material_map(120.0, 300.0, 24, 30, 0.015, 0.1))
 
 
 def small_barrel() -> Workload:

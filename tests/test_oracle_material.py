@@ -1,0 +1,202 @@
+"""Pins of the oracle's material effects (Section 2.1: multiple scattering
+and energy loss from radiation and interaction lengths in r-z arrays):
+Bethe's minimum ionisation in silicon, the Highland angle at one radiation
+length, the path factor of an inclined crossing, the backward fit's regained
+loss, and on simulated events with heavy material, unbiased pulls of the
+find, the backward fit and the smoother against the simulated truth (and a
+clear bias when the loss is left out).  CPU only."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import (PION_MASS, FindConfig, MaterialMap, barrel_material, generate_event)
+import parity as PT
+
+FC = FindConfig()
+
+
+def one_bin(x_x0, xi, k_max=10.0):
+    return MaterialMap(1, 1, 200.0, 300.0, np.full((1, 1), x_x0, np.float32),
+                       np.full((1, 1), xi, np.float32), PION_MASS, k_max)
+
+
+def barrel_state(p_t, dphi, theta=np.pi / 2):
+    """On a barrel at (25, 0, 0), moving at dphi from the radial direction."""
+    return np.array([25.0, 0.0, 0.0, 1.0 / p_t, dphi, theta])
+
+
+def test_bethe_minimum_ionisation_in_silicon():
+    """The minimum of the mean loss in silicon is 1.66 MeV cm^2/g near
+    beta*gamma = 3.5 (PDG; the density effect, left out here, lowers it by a
+    few per cent)."""
+    bg = np.exp(np.linspace(np.log(0.5), np.log(100.0), 600))
+    v = np.array([O.bethe_si(b, PION_MASS) for b in bg]) * 1e3
+    i = int(np.argmin(v))
+    assert 1.60 < v[i] < 1.75 and 2.5 < bg[i] < 4.5
+    # falls as 1/beta^2 below the minimum, rises logarithmically above
+    assert v[0] > 3.0 * v[i] and v[-1] > 1.3 * v[i]
+
+
+def test_highland_at_one_radiation_length():
+    """At one radiation length the logarithmic term vanishes: the angle is
+    13.6 MeV / (beta p), added as in the constant-angle case."""
+    for p_t in (0.5, 1.0, 5.0):
+        p, Cm, M = O.material_effects(FC, one_bin(1.0, 0.0), 0, barrel_state(p_t, 0.0),
+                                      np.zeros((6, 6)))
+        beta = p_t / np.hypot(p_t, float(np.float32(PION_MASS)))  # the map is FP32
+        s = 0.0136 / (beta * p_t)
+        want = O.add_ms(barrel_state(p_t, 0.0), s, np.zeros((6, 6)))
+        assert np.allclose(Cm, want, rtol=1e-12, atol=0.0)
+        assert Cm[5, 5] == pytest.approx(s * s, rel=1e-12)
+        assert np.array_equal(M, np.eye(6)) and p[3] == 1.0 / p_t
+
+
+def test_inclined_crossing_doubles_the_path():
+    """A crossing at 60 degrees from the normal goes through twice the
+    material: twice the loss, and the scattering of two radiation lengths;
+    a grazing crossing is capped at k_max times."""
+    lossy = one_bin(0.0, 0.5)
+    dp = []
+    for dphi in (0.0, np.pi / 3):
+        p, _, _ = O.material_effects(FC, lossy, 0, barrel_state(1.0, dphi), np.zeros((6, 6)))
+        dp.append(1.0 - 1.0 / p[3])
+    assert dp[0] > 0 and dp[1] == pytest.approx(2.0 * dp[0], rel=1e-12)
+    _, C1, _ = O.material_effects(FC, one_bin(1.0, 0.0), 0, barrel_state(1.0, np.pi / 3),
+                                  np.zeros((6, 6)))
+    _, C2, _ = O.material_effects(FC, one_bin(2.0, 0.0), 0, barrel_state(1.0, 0.0),
+                                  np.zeros((6, 6)))
+    assert np.allclose(C1, C2, rtol=1e-12, atol=0.0)
+    # disk: the normal is z; at theta = 60 degrees the path doubles too, so
+    # 0.5 g/cm^2 there takes what 1 g/cm^2 takes at normal incidence on a
+    # barrel, at the same |p|
+    th = np.pi / 3
+    pd, _, _ = O.material_effects(FC, lossy, 1,
+                                  np.array([30.0, 0.0, 150.0, 1.0 / np.sin(th), 0.0, th]),
+                                  np.zeros((6, 6)))
+    pb, _, _ = O.material_effects(FC, one_bin(0.0, 1.0), 0, barrel_state(1.0, 0.0),
+                                  np.zeros((6, 6)))
+    assert 1.0 - 1.0 / (pd[3] * np.sin(th)) == pytest.approx(1.0 - 1.0 / pb[3], rel=1e-12)
+    # grazing: cos = 1e-4 would give k = 1e4; the cap keeps k_max = 10
+    pg, _, _ = O.material_effects(FC, lossy, 0, barrel_state(1.0, np.pi / 2 - 1e-4),
+                                  np.zeros((6, 6)))
+    assert 1.0 - 1.0 / pg[3] == pytest.approx(10.0 * dp[0], rel=1e-9)
+
+
+def test_backward_regains_the_loss():
+    """Forward then backward through the same material returns |p| to
+    second order in dp/p, and the two Jacobians multiply to the identity to
+    that order."""
+    lossy = one_bin(0.0, 0.5)
+    s0 = np.array([25.0, 0.0, 3.0, -1.3, 0.2, 1.1])
+    p1, _, M1 = O.material_effects(FC, lossy, 0, s0, np.zeros((6, 6)), direction=1)
+    p2, _, M2 = O.material_effects(FC, lossy, 0, p1, np.zeros((6, 6)), direction=-1)
+    rel = abs(p1[3] / s0[3] - 1.0)
+    assert 1e-4 < rel < 1e-2
+    assert abs(p2[3] / s0[3] - 1.0) < 5 * rel * rel
+    assert np.allclose(M2 @ M1, np.eye(6), atol=20 * rel * rel)
+
+
+@pytest.fixture(scope="module")
+def heavy():
+    w = barrel_material()
+    return w, generate_event(w, 0)
+
+
+def pulls(w, ev, mat):
+    res = O.find_event(w.find, w.layers, ev, material=mat)
+    fwd, bwd, smo = [], [], []
+    for s, r in enumerate(res):
+        if not r["seed_ok"]:
+            continue
+        tid = ev.seed_track[s]
+        if len(r["hit"]) and r["hit"][-1] >= 0:
+            t = ev.truth_state[r["hit"][-1]]
+            d = r["par"] - t
+            d[4] = np.arctan2(np.sin(d[4]), np.cos(d[4]))
+            fwd.append([(abs(r["par"][3]) - abs(t[3])) / np.sqrt(r["cov"][3, 3]),
+                        d[4] / np.sqrt(r["cov"][4, 4]), d[5] / np.sqrt(r["cov"][5, 5])])
+        st, p, Cm, _, _ = O.backward_fit(w.find, w.layers, ev, ev.seeds[s], r, material=mat)
+        if st == 1:
+            bwd.append((abs(p[3]) - abs(ev.track_init[tid][3])) / np.sqrt(Cm[3, 3]))
+        sh = ev.seeds[s]
+        h = np.array([[ev.x[i], ev.y[i], ev.z[i]] for i in sh], float).ravel()
+        hv = np.array([[ev.var_u[i], ev.var_v[i]] for i in sh], float).ravel()
+        sd = O.seed(w.find, w.layers, h, hv, [int(ev.layer[i]) for i in sh], material=mat)
+        m, lay, sp, sc = O.smooth_track(w.find, w.layers, ev, int(ev.layer[sh[2]]), sd["par"],
+                                        sd["cov"], r, material=mat)
+        codes = {int(L): int(c) for L, c in zip(r["plan"], r["hit"])}
+        codes[int(ev.layer[sh[2]])] = int(sh[2])
+        for q in range(max(m, 0)):
+            c = codes.get(int(lay[q]), -1)
+            if c >= 0:
+                smo.append((abs(sp[q][3]) - abs(ev.truth_state[c][3])) / np.sqrt(sc[q][3, 3]))
+    return np.array(fwd), np.array(bwd), np.array(smo)
+
+
+def test_pulls_against_the_simulated_truth(heavy):
+    """300 tracks of 0.5-2 GeV/c through 3% of a radiation length and
+    0.5 g/cm^2 per layer: the find's |q/pT|, phi and theta at the last hit,
+    the backward fit's |q/pT| at the vertex side of the first layer and the
+    smoothed |q/pT| on every hit layer have pulls of mean ~0 and width ~1."""
+    w, ev = heavy
+    fwd, bwd, smo = pulls(w, ev, w.material)
+    assert len(fwd) > 250 and len(bwd) > 280 and len(smo) > 2000
+    for col in range(3):
+        assert abs(fwd[:, col].mean()) < 0.2 and 0.85 < fwd[:, col].std() < 1.15, col
+    assert abs(bwd.mean()) < 0.2 and 0.85 < bwd.std() < 1.15
+    assert abs(smo.mean()) < 0.2 and 0.8 < smo.std() < 1.2
+
+
+def test_leaving_out_the_loss_biases_the_momentum(heavy):
+    """The same events with the map's mass thickness set to zero (scattering
+    only): the found |q/pT| comes out too small and the backward fit's too
+    large by half a standard deviation or more."""
+    w, ev = heavy
+    fwd, bwd, _ = pulls(w, ev, replace(w.material, xi=np.zeros_like(w.material.xi)))
+    assert fwd[:, 0].mean() < -0.35 and bwd.mean() > 0.35
+
+
+def test_smoothed_states_follow_the_loss_without_scattering():
+    """Energy loss only (no radiation lengths, 3 g/cm^2 per layer: a few
+    per cent of the momentum): the smoothed states of a track are one
+    trajectory, each carried to the next surface and through its material
+    (state and covariance, with the loss's Jacobian) being the next one, up
+    to linearisation.  Without the loss's Jacobian in the smoother's
+    transport the smoother has nothing to absorb the mismatch and fails
+    by orders of magnitude."""
+    w = barrel_material()
+    mat = replace(w.material, x_x0=np.zeros_like(w.material.x_x0),
+                  xi=np.full_like(w.material.xi, 3.0))
+    ev = generate_event(replace(w, material=mat), 1, n_tracks=60)
+    res = O.find_event(w.find, w.layers, ev, material=mat)
+    n_cmp, worst_cov, worst_d, worst_loss = 0, 0.0, 0.0, 0.0
+    for s, r in enumerate(res):
+        if not r["seed_ok"]:
+            continue
+        sh = ev.seeds[s]
+        h = np.array([[ev.x[i], ev.y[i], ev.z[i]] for i in sh], float).ravel()
+        hv = np.array([[ev.var_u[i], ev.var_v[i]] for i in sh], float).ravel()
+        sd = O.seed(w.find, w.layers, h, hv, [int(ev.layer[i]) for i in sh], material=mat)
+        m, lay, par, cov = O.smooth_track(w.find, w.layers, ev, int(ev.layer[sh[2]]), sd["par"],
+                                          sd["cov"], r, material=mat)
+        for k in range(m - 1):
+            L = w.layers[lay[k + 1]]
+            st, q, Q, _, _ = O.propagate(par[k], cov[k], L, w.find.bz, w.find.kappa,
+                                         check_extent=False)
+            assert st == O.OK
+            q, Q, _ = O.material_effects(w.find, mat, L.kind, q, Q)
+            worst_loss = max(worst_loss, abs(q[3] / par[k][3] - 1.0))
+            d = q - par[k + 1]
+            d[4] = np.arctan2(np.sin(d[4]), np.cos(d[4]))
+            sig = np.sqrt(np.maximum(np.diag(cov[k + 1]), 1e-30))
+            worst_d = max(worst_d, float(np.max(np.abs(d[2:]) / sig[2:])))
+            worst_cov = max(worst_cov, PT.cov_err(Q, cov[k + 1]))
+            n_cmp += 1
+    assert n_cmp > 300 and worst_loss > 0.01
+    # measured: worst 0.46 sigma and 4.5e-3 (the loss's dependence on the
+    # direction and |p|, which its Jacobian holds fixed, enters at second
+    # order); leaving the Jacobian out of the smoother's transport gives
+    # ~1e12 sigma, as nothing else there absorbs it without scattering
+    assert worst_d < 1.0 and worst_cov < 1e-2, (worst_d, worst_cov)
