@@ -153,6 +153,25 @@ typedef struct {
   int32_t layers[MKF_MAX_PLAN];  /* layer ids, distinct, in visiting order */
 } mkf_region;
 
+/* Material map (Section 2.1: multiple scattering and energy loss from
+ * two-dimensional arrays of radiation and interaction lengths indexed in
+ * r-z).  Bin (iz, ir) covers r in [ir, ir + 1) r_max / n_r and z in
+ * -z_max + [iz, iz + 1) 2 z_max / n_z (a crossing outside takes the nearest
+ * edge bin) and gives the thickness of the layer crossed there at normal
+ * incidence: x_x0 in radiation lengths, xi in g/cm^2.  At each crossing the
+ * path factor 1/|cos| of the incidence (at most k_max) scales both; the
+ * Highland angle of the path's radiation lengths at the momentum before the
+ * loss replaces ms_sigma, and the mean ionisation loss in silicon (Bethe,
+ * no density correction) at the path's mass thickness lowers |p| by
+ * dE/beta (at most half of |p|; the backward fit regains it). */
+typedef struct {
+  int32_t n_r, n_z;  /* bins, 1..4096 each, at most 2^22 in all */
+  float r_max;       /* cm, > 0 */
+  float z_max;       /* cm, > 0 */
+  float mass;        /* particle mass hypothesis, GeV, > 0 */
+  float k_max;       /* cap on the path factor, >= 1 */
+} mkf_material_info;
+
 /* Tolerances of the seed cleaning (mkf_clean_seeds). */
 typedef struct {
   float tol_ipt; /* q/pT, relative to the larger of the two */
@@ -176,6 +195,16 @@ const char *mkf_last_error(const mkf_ctx *ctx);
 /* Detector description (Section 2.1): n_layers records, host memory.
  * Replaces any previous geometry and invalidates loaded hits. */
 mkf_status mkf_load_geometry(mkf_ctx *ctx, const mkf_layer *layers, int32_t n_layers);
+
+/* Material map: info and the host tables x_x0 [n_z][n_r] (0..1) and
+ * xi [n_z][n_r] (0..100 g/cm^2), copied.  info == NULL returns to the
+ * constant angle ms_sigma.  Used by every later call that fits: mkf_seed,
+ * mkf_find, mkf_fit, mkf_backward_fit, mkf_smooth (seed states already made
+ * keep the material they were fitted with).  MKF_E_ARG for bad values.
+ * The surrogate form (MKF_F_SURROGATE) has no material variant: mkf_find
+ * returns MKF_E_ARG while a map is loaded. */
+mkf_status mkf_load_material(mkf_ctx *ctx, const mkf_material_info *info, const float *x_x0,
+                             const float *xi);
 
 /* Region steering (Section 2.1): n_regions (0..MKF_MAX_REGIONS) records,
  * host memory, copied.  Layer ids refer to the loaded geometry, so load it

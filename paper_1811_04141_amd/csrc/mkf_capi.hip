@@ -61,6 +61,8 @@ struct mkf_ctx {
   DevBuf d_layers;
   int n_regions = 0;  // region steering (0: plans from each seed's helix)
   DevBuf d_regions;
+  DevMat mat{};       // material map (mat.tab == nullptr: constant angle)
+  DevBuf d_mat;
 
   // hits
   int n_events = 0;
@@ -102,7 +104,7 @@ struct mkf_ctx {
 
   // fit scratch (host-side inputs are staged here)
   ~mkf_ctx() {
-    DevBuf *all[] = {&d_layers, &d_regions, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
+    DevBuf *all[] = {&d_layers, &d_regions, &d_mat, &d_ev_off, &d_x, &d_y, &d_z, &d_vu, &d_vv, &d_layer,
                      &d_hit_bin, &d_counts, &d_fill, &d_bin_start, &d_scan_tmp, &d_sorted,
                      &d_byorig, &d_bad, &d_seed_event, &d_seed_hits, &d_seed_state, &d_seed_ok,
                      &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_pstate, &d_pinfo,
@@ -161,6 +163,7 @@ FindParams params(mkf_ctx *c) {
   P.layers = c->d_layers.as<DevLayer>();
   P.n_layers = c->n_layers;
   P.cfg = dev_cfg(c->cfg);
+  P.cfg.mat = c->mat;
   P.n_events = c->n_events;
   P.ev_off = c->d_ev_off.as<int64_t>();
   P.hx = c->d_x.as<float>();
@@ -406,6 +409,51 @@ mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_laye
   c->bins_per_event = base;
   c->n_regions = 0;
   c->stage = kGeometry;
+  return MKF_OK;
+}
+
+mkf_status mkf_load_material(mkf_ctx *c, const mkf_material_info *info, const float *x_x0,
+                             const float *xi) {
+  if (!c) return MKF_E_ARG;
+  if (!info) {
+    c->mat = DevMat{};
+    drop_graph(c);
+    return MKF_OK;
+  }
+  if (info->n_r < 1 || info->n_z < 1 || info->n_r > 4096 || info->n_z > 4096 ||
+      (int64_t)info->n_r * info->n_z > (1 << 22))
+    return fail(c, MKF_E_ARG, "material map: need 1..4096 bins per axis, at most 2^22 in all");
+  if (!finite_f(info->r_max) || !(info->r_max > 0.f) || !finite_f(info->z_max) ||
+      !(info->z_max > 0.f))
+    return fail(c, MKF_E_ARG, "material map: r_max and z_max must be finite and > 0");
+  if (!finite_f(info->mass) || !(info->mass > 0.f) || !finite_f(info->k_max) ||
+      !(info->k_max >= 1.f))
+    return fail(c, MKF_E_ARG, "material map: need mass > 0 and k_max >= 1");
+  if (!x_x0 || !xi) return fail(c, MKF_E_ARG, "material map: NULL table");
+  const size_t n = (size_t)info->n_r * (size_t)info->n_z;
+  std::vector<float2> tab(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!finite_f(x_x0[i]) || !(x_x0[i] >= 0.f) || !(x_x0[i] <= 1.f) || !finite_f(xi[i]) ||
+        !(xi[i] >= 0.f) || !(xi[i] <= 100.f))
+      return fail(c, MKF_E_ARG, "material map: bin %zu out of range (0 <= x/X0 <= 1, 0 <= xi <= 100)",
+                  i);
+    tab[i] = make_float2(x_x0[i], xi[i]);
+  }
+  HIP_TRY(c, c->d_mat.ensure(sizeof(float2) * n));
+  HIP_TRY(c, hipMemcpyAsync(c->d_mat.ptr, tab.data(), sizeof(float2) * n, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  DevMat m{};
+  m.tab = c->d_mat.as<float2>();
+  m.nr = info->n_r;
+  m.nz = info->n_z;
+  m.r_scale = (float)info->n_r / info->r_max;
+  m.z_max = info->z_max;
+  m.z_scale = (float)info->n_z / (2.f * info->z_max);
+  m.mass = info->mass;
+  m.k_max = info->k_max;
+  c->mat = m;
+  drop_graph(c);
   return MKF_OK;
 }
 
@@ -742,6 +790,8 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
 mkf_status mkf_find(mkf_ctx *c) {
   if (!c) return MKF_E_ARG;
   if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
+  if ((c->cfg.flags & MKF_F_SURROGATE) && c->mat.tab)
+    return fail(c, MKF_E_ARG, "the surrogate form has no material-map variant");
   FindParams P = params(c);
   int launches = 0;
   const bool graph = (c->cfg.flags & MKF_F_GRAPH) != 0;
@@ -860,7 +910,9 @@ mkf_status mkf_fit(mkf_ctx *c, int64_t n_tracks, int32_t n_steps, const int8_t *
   if (n_tracks > 0 && n_steps > 0 && (!kind || !pos || !x || !y || !z || !var_u || !var_v))
     return fail(c, MKF_E_ARG, "NULL hit array");
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
-  launch_fit(c->stream, dev_cfg(c->cfg), n_tracks, n_steps, kind, pos, x, y, z, var_u, var_v, len,
+  DevCfg fcfg = dev_cfg(c->cfg);
+  fcfg.mat = c->mat;
+  launch_fit(c->stream, fcfg, n_tracks, n_steps, kind, pos, x, y, z, var_u, var_v, len,
              init_par, init_cov, out_par, out_cov, out_chi2, out_status);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));

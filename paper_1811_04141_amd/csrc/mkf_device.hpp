@@ -40,6 +40,17 @@ struct DevLayer {
   float hole_lo, hole_hi;  // no sensors for hole_lo < q < hole_hi
 };
 
+// Material map in r-z: per bin (x/X0, xi in g/cm^2) at normal incidence.
+struct DevMat {
+  const float2 *tab;  // [nz][nr]; nullptr: constant scattering angle
+  int nr, nz;
+  float r_scale;      // nr / r_max
+  float z_max;
+  float z_scale;      // nz / (2 z_max)
+  float mass;
+  float k_max;
+};
+
 struct DevCfg {
   float mkb;        // -kappa * B: omega = mkb * (q/pT)
   float chi2_cut;
@@ -49,6 +60,7 @@ struct DevCfg {
   int n_cand;
   int max_holes;
   float init_var[6];
+  DevMat mat;
 };
 
 
@@ -63,6 +75,8 @@ __device__ __forceinline__ float rsqrt_t(float a) { return rsqrtf(a); }
 __device__ __forceinline__ double rsqrt_t(double a) { return 1.0 / sqrt(a); }
 __device__ __forceinline__ float atan_t(float a) { return atanf(a); }
 __device__ __forceinline__ double atan_t(double a) { return atan(a); }
+__device__ __forceinline__ float log_t(float a) { return logf(a); }
+__device__ __forceinline__ double log_t(double a) { return log(a); }
 __device__ __forceinline__ float abs_t(float a) { return fabsf(a); }
 __device__ __forceinline__ double abs_t(double a) { return fabs(a); }
 __device__ __forceinline__ float copysign_t(float a, float b) { return copysignf(a, b); }
@@ -402,6 +416,86 @@ __device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c) {
   c[tri(3, 5)] -= a * ms_var;
   c[tri(4, 4)] += ms_var / (sth * sth);
   c[tri(5, 5)] += ms_var;
+}
+
+// Mean ionisation loss rate in silicon (Bethe, no density or shell
+// correction), GeV cm^2/g, at beta*gamma^2 = bg2 for a particle of mass m.
+template <typename T>
+__device__ __forceinline__ T si_loss_rate(T bg2, T m) {
+  const T me = T(0.51099895e-3), r = me / m;
+  const T b2 = bg2 / (T(1) + bg2), g = sqrt_t(T(1) + bg2);
+  const T wmax = T(2) * me * bg2 / (T(1) + T(2) * g * r + r * r);
+  // K Z/A with K = 0.307075e-3 GeV cm^2/mol, Z/A = 0.49848; I = 173 eV
+  return T(0.307075e-3 * 0.49848) / b2 *
+         (T(0.5) * log_t(T(2) * me * bg2 * wmax / T(173e-9 * 173e-9)) - b2);
+}
+
+// Effects of one crossed layer's material on the state at the crossing.
+// Without a map: the constant scattering angle.  With one (the paper's r-z
+// radiation and interaction length arrays, Section 2.1): the bin at the
+// crossing gives the thickness at normal incidence, scaled by the path
+// factor 1/|cos| of the incidence (at most k_max); the Highland angle of
+// those radiation lengths at the momentum before the loss scatters the
+// track; then the mean ionisation loss dp = dE / beta (at most half of |p|)
+// changes |p| by -dir * dp (dir = -1 regains it on the way back).  The loss
+// maps q/pT -> q/pT |p|/|p'| with dp held fixed; its Jacobian (identity but
+// the q/pT row: j33 on q/pT, j35 on theta) multiplies the covariance on both
+// sides and is returned in *j33, *j35.
+template <typename T>
+__device__ __forceinline__ void material(const DevCfg &cfg, int kind, T *p, T *c, T dir,
+                                         T *j33 = nullptr, T *j35 = nullptr) {
+  if (j33) *j33 = T(1);
+  if (j35) *j35 = T(0);
+  const DevMat &M = cfg.mat;
+  if (M.tab == nullptr) {
+    add_ms(p, T(cfg.ms_var), c);
+    return;
+  }
+  const T r = sqrt_t(p[0] * p[0] + p[1] * p[1]);
+  int ir = (int)floor(r * T(M.r_scale));
+  int iz = (int)floor((p[2] + T(M.z_max)) * T(M.z_scale));
+  ir = ir < 0 ? 0 : (ir >= M.nr ? M.nr - 1 : ir);
+  iz = iz < 0 ? 0 : (iz >= M.nz ? M.nz - 1 : iz);
+  const float2 tb = M.tab[iz * M.nr + ir];
+  T sth, cth, sph, cph;
+  sincos_t(p[5], &sth, &cth);
+  sincos_t(p[4], &sph, &cph);
+  const T cosa = kind == 0 ? sth * (cph * p[0] + sph * p[1]) / r : cth;
+  const T k = abs_t(cosa) * T(M.k_max) > T(1) ? T(1) / abs_t(cosa) : T(M.k_max);
+  const T pm = T(1) / (abs_t(p[3]) * sth);
+  const T m = T(M.mass);
+  const T e = sqrt_t(pm * pm + m * m);
+  const T beta = pm / e;
+  const T t = T(tb.x) * k;
+  if (t > T(0)) {
+    T f = T(1) + T(0.038) * log_t(t);
+    f = f < T(0) ? T(0) : f;
+    const T th0 = T(0.0136) / (beta * pm) * sqrt_t(t) * f;
+    add_ms(p, th0 * th0, c);
+  }
+  const T x = T(tb.y) * k;
+  if (x > T(0)) {
+    T dp = x * si_loss_rate(pm * pm / (m * m), m) / beta;
+    dp = dp > T(0.5) * pm ? T(0.5) * pm : dp;
+    const T ratio = T(1) / (T(1) - dir * dp / pm);
+    const T a = ratio * ratio;
+    const T b = dir * dp * p[3] * abs_t(p[3]) * cth * a;
+    p[3] *= ratio;
+    // C <- J C J^T, J = I but row 3 = (0, 0, 0, a, 0, b)
+    const T c33 = c[tri(3, 3)], c35 = c[tri(3, 5)], c55 = c[tri(5, 5)];
+    // (tri takes its row index first: the smaller of the two)
+#pragma unroll
+    for (int mm = 0; mm < 6; ++mm) {
+      if (mm == 3) continue;
+      const int i3 = mm < 3 ? tri(mm, 3) : tri(3, mm);
+      const int i5 = mm < 5 ? tri(mm, 5) : tri(5, mm);
+      c[i3] = a * c[i3] + b * c[i5];
+    }
+    c[tri(3, 5)] = a * c35 + b * c55;
+    c[tri(3, 3)] = a * a * c33 + T(2) * a * b * c35 + b * b * c55;
+    if (j33) *j33 = a;
+    if (j35) *j35 = b;
+  }
 }
 
 // Local frame at the predicted point and the 2x2 predicted covariance

@@ -319,7 +319,7 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
 // lane holds one candidate (or none); on exit it holds the candidate of its
 // rank among the kept extensions.  pos indexes the seed's find buffers
 // (back-pointers keep kGroup = 8 slots per seed for either G).
-template <int G, class Rec>
+template <int G, bool kMat, class Rec>
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
                                            int lane, int slot, const Rec &rec, int ev,
                                            int64_t ev_base, int step, int lid, u64 &fin_key,
@@ -331,7 +331,12 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
     st = propagate<true>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr,
                          l_hint, sur);
   const bool ok = cd.active && st == kOk;
-  if (ok) add_ms(pr.p, P.cfg.ms_var, pr.c);
+  // kMat: the material map's effects (a separate instantiation, so that the
+  // constant-angle form keeps its register allocation)
+  if (ok) {
+    if constexpr (kMat) material(P.cfg, L.kind, pr.p, pr.c, 1.f);
+    else add_ms(pr.p, P.cfg.ms_var, pr.c);
+  }
 
   u64 lst[G];  // this lane's best extensions (G >= n_cand)
 #pragma unroll
@@ -546,6 +551,7 @@ __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
   if (slot == 0) P.fin_key[pos] = kKeyMax;
 }
 
+template <bool kMat>
 __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64_t n_active) {
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
@@ -567,7 +573,7 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   load_cand(P, (size_t)pos * kGroup + slot, cd);
   u64 fin_key = P.fin_key[pos];
   const u64 fk0 = fin_key;
-  group_step<kGroup>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, P.ev_off[ev], step, lid,
+  group_step<kGroup, kMat>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, P.ev_off[ev], step, lid,
                      fin_key);
   store_cand(P, (size_t)pos * kGroup + slot, cd);
   if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
@@ -634,8 +640,9 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
 // (one wave-wide matrix-core inference per layer step, then one exact Newton
 // step per lane, falling back to the closed form when it does not converge).
 // G: lanes per seed (8, or 6 for candidate budgets up to 6).
-template <int kWaves, bool kSurr, int G>
-__global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
+// kMat: with the material map (constant scattering angle otherwise).
+template <int kWaves, bool kSurr, int G, bool kMat>
+__device__ __forceinline__ void find_persistent(const FindParams &P) {
   __shared__ DevLayer sl[kMaxLayers];
   __shared__ unsigned long long block_steps, block_sur[2];
   // surrogate: the network's BF16 weight images and biases, shared by the
@@ -774,7 +781,8 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
       if (in_plan) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
-        group_step<G>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, l_hint, &sur);
+        group_step<G, kMat>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, l_hint,
+                            &sur);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
@@ -810,6 +818,16 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
     atomicAdd(&P.sur_stats[0], block_sur[0]);
     atomicAdd(&P.sur_stats[1], block_sur[1]);
   }
+}
+
+template <int kWaves, bool kSurr, int G>
+__global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
+  find_persistent<kWaves, kSurr, G, false>(P);
+}
+
+template <int kWaves, int G>
+__global__ __launch_bounds__(256, kWaves) void k_find_persistent_mat(FindParams P) {
+  find_persistent<kWaves, false, G, true>(P);
 }
 
 // Gather the seed results into processing order (untimed preparation), so
@@ -866,7 +884,6 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     hl[k] = P.hlayer[g];
   }
   const double mkb = P.cfg.mkb, l_min = P.cfg.l_min, edge = P.cfg.edge_margin;
-  const double ms_var = (double)P.cfg.ms_var;
   int ok = 0;
   int n = 0;
   double p[6], c[21], chi2 = 0.0;
@@ -905,7 +922,7 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
         for (int q = 0; q < 6; ++q) p[q] = pr.p[q];
         for (int q = 0; q < 21; ++q) c[q] = pr.c[q];
       }
-      add_ms(p, ms_var, c);
+      material<double>(P.cfg, L.kind, p, c, 1.0);
       FrameT<double> f;
       make_frame(p, c, L.kind, f);
       double u, v;
@@ -1460,7 +1477,7 @@ __global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
       status = s + 1;
       break;
     }
-    add_ms(pr.p, cfg.ms_var, pr.c);
+    material(cfg, L.kind, pr.p, pr.c, 1.f);
     Frame f;
     make_frame(pr.p, pr.c, L.kind, f);
     float u, v;
@@ -1535,7 +1552,8 @@ __device__ __forceinline__ bool backfit_surface(const FindParams &P, const DevLa
     for (int m = 0; m < 21; ++m) c[m] = pr.c[m];
     flip_state(p, c);
   }
-  add_ms(p, T(P.cfg.ms_var), c);
+  // on the way back the track regains the layer's loss
+  material<T>(P.cfg, L.kind, p, c, T(-1));
   if (code >= 0) {
     const HitRec h = P.byorig[ev_base + code];
     FrameT<T> f;
@@ -1761,7 +1779,11 @@ __global__ __launch_bounds__(256) void k_smooth_fwd(FindParams P, const int *see
         n = -1;
         break;
       }
-      add_ms(pr.p, P.cfg.ms_var, pr.c);
+      float j33, j35;
+      material(P.cfg, L.kind, pr.p, pr.c, 1.f, &j33, &j35);
+      // the transport to the prediction includes the loss's Jacobian
+#pragma unroll
+      for (int m = 0; m < 6; ++m) fc[18 + m] = j33 * fc[18 + m] + j35 * fc[30 + m];
 #pragma unroll
       for (int m = 0; m < 6; ++m) at(n, kSmPred + m) = pr.p[m];
 #pragma unroll
@@ -2064,7 +2086,8 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
   if (n_active == 0) return;
   const unsigned nb = blocks_for(n_active * kGroup, 256);
   const unsigned grid = (nb + kQueues - 1) / kQueues * kQueues;  // whole XCD shares
-  hipLaunchKernelGGL(k_find_step, dim3(grid), dim3(256), 0, s, P, step, n_active);
+  if (P.cfg.mat.tab) hipLaunchKernelGGL(k_find_step<true>, dim3(grid), dim3(256), 0, s, P, step, n_active);
+  else hipLaunchKernelGGL(k_find_step<false>, dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
 template <bool kSurr>
@@ -2083,10 +2106,26 @@ static void launch_persistent_t(hipStream_t s, const FindParams &P, int grid, in
   }
 }
 
+static void launch_persistent_mat(hipStream_t s, const FindParams &P, int grid, int waves) {
+  if (P.cfg.n_cand > 6) {
+    const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 8, Grp<8>::kSeeds);
+    hipLaunchKernelGGL((k_find_persistent_mat<2, 8>), dim3(grid), dim3(256), lds, s, P);
+    return;
+  }
+  const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 6, Grp<6>::kSeeds);
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_find_persistent_mat<1, 6>), dim3(grid), dim3(256), lds, s, P); break;
+    case 3: hipLaunchKernelGGL((k_find_persistent_mat<3, 6>), dim3(grid), dim3(256), lds, s, P); break;
+    case 4: hipLaunchKernelGGL((k_find_persistent_mat<4, 6>), dim3(grid), dim3(256), lds, s, P); break;
+    default: hipLaunchKernelGGL((k_find_persistent_mat<2, 6>), dim3(grid), dim3(256), lds, s, P); break;
+  }
+}
+
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
                             bool surrogate) {
   if (P.n_seeds == 0) return;
-  if (surrogate) launch_persistent_t<true>(s, P, grid_blocks, waves);
+  if (P.cfg.mat.tab) launch_persistent_mat(s, P, grid_blocks, waves);
+  else if (surrogate) launch_persistent_t<true>(s, P, grid_blocks, waves);
   else launch_persistent_t<false>(s, P, grid_blocks, waves);
 }
 

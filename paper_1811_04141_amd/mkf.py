@@ -24,7 +24,7 @@ MAX_REGIONS = 8
 HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry",
-           "mkf_load_steering", "mkf_load_hits",
+           "mkf_load_steering", "mkf_load_material", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
            "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_clean_seeds",
            "mkf_find_duplicates",
@@ -98,6 +98,11 @@ def make_regions(regions):
     return arr
 
 
+class MaterialInfo(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("n_z", C.c_int32), ("r_max", C.c_float),
+                ("z_max", C.c_float), ("mass", C.c_float), ("k_max", C.c_float)]
+
+
 class Cleaning(C.Structure):
     _fields_ = [("tol_ipt", C.c_float), ("tol_eta", C.c_float), ("tol_phi", C.c_float)]
 
@@ -135,6 +140,7 @@ def _load():
         "mkf_last_error": ([P], C.c_char_p),
         "mkf_load_geometry": ([P, C.POINTER(Layer), I32], I32),
         "mkf_load_steering": ([P, C.POINTER(Region), I32], I32),
+        "mkf_load_material": ([P, C.POINTER(MaterialInfo), P, P], I32),
         "mkf_load_hits": ([P, I32, P, P, P, P, P, P, P, I32], I32),
         "mkf_seed": ([P, I64, P, P, I32], I32),
         "mkf_get_seed_states": ([P, P, P, P, P, P, P], I32),
@@ -243,6 +249,20 @@ class Context:
         """Region steering for the next seed(); an empty sequence returns to
         plans from each seed's helix."""
         self._check(lib.mkf_load_steering(self.h, make_regions(regions), len(regions)))
+
+    def load_material(self, mm):
+        """Material map (an object with n_r, n_z, r_max, z_max, mass, k_max
+        and [n_z][n_r] tables x_x0, xi), or None for the constant angle."""
+        if mm is None:
+            self._check(lib.mkf_load_material(self.h, None, None, None))
+            return
+        info = MaterialInfo(int(mm.n_r), int(mm.n_z), float(mm.r_max), float(mm.z_max),
+                            float(mm.mass), float(mm.k_max))
+        t = np.ascontiguousarray(mm.x_x0, np.float32).reshape(-1)
+        x = np.ascontiguousarray(mm.xi, np.float32).reshape(-1)
+        if t.size != info.n_r * info.n_z or x.size != t.size:
+            raise ValueError("material tables must hold n_z x n_r bins")
+        self._check(lib.mkf_load_material(self.h, C.byref(info), t.ctypes.data, x.ctypes.data))
 
     def load_hits(self, ev_off, x, y, z, var_u, var_v, layer):
         ev_off = np.ascontiguousarray(ev_off, np.int64)
