@@ -107,8 +107,9 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
     context stream around one launch after a warm-up: the search-free fit
     (131,072 tracks x 26 layers), the backward fit and the smoothing of the
     benchmark workload's found tracks, triplet seeding with cleaning, find and
-    duplicate removal on it, and the surrogate network's inference and
-    gradient (2^20 samples from its training sampler)."""
+    duplicate removal on it, the find with a material map and with region
+    steering, and the surrogate network's inference and gradient (2^20
+    samples from its training sampler)."""
     import numpy as np
     import torch
 
@@ -215,6 +216,27 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
             "duplicates": nd[0], "find_duplicates_ms": ms_dup}
         del sev, shit, keep, dup
         ctx3.close()
+        # the batched find with a silicon-like material map (1.5% of a
+        # radiation length and 0.1 g/cm^2 per layer, 1.5x beyond |z| = 50 cm)
+        # and with five-region steering, from the same seeds (the autotuned
+        # launch shape of the constant-angle kernel; mkf_get_stats timing)
+        from synth import five_regions, material_map
+        variants = (("find_material_map",
+                     lambda c: c.load_material(material_map(120.0, 300.0, 24, 30, 0.015, 0.1))),
+                    ("find_five_region_steering", lambda c: c.load_steering(five_regions())))
+        for label, setup in variants:
+            c4 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+            c4.load_geometry(w.layers)
+            setup(c4)
+            c4.load_hits(batch.ev_off, *hits)
+            c4.seed(*seeds)
+            c4.find()
+            c4.find()
+            st = c4.stats()
+            c4.close()
+            out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
+                          "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
+                          "unit": "candidate-layer updates/s", "workload": w.name}
         m = 1 << 20
         x = torch.zeros((m, 8), device=dev)
         t = torch.zeros((m, 7), device=dev)

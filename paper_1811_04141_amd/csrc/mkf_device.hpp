@@ -77,6 +77,17 @@ __device__ __forceinline__ float atan_t(float a) { return atanf(a); }
 __device__ __forceinline__ double atan_t(double a) { return atan(a); }
 __device__ __forceinline__ float log_t(float a) { return logf(a); }
 __device__ __forceinline__ double log_t(double a) { return log(a); }
+// for the material corrections (a relative error of ~1e-6 in a correction
+// of ~1e-3 is far below the FP32 state's rounding): hardware reciprocal,
+// logarithm and sine/cosine in FP32, the exact forms in FP64
+__device__ __forceinline__ float div_fast(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+__device__ __forceinline__ double div_fast(double a, double b) { return a / b; }
+__device__ __forceinline__ float log_fast(float a) { return __logf(a); }
+__device__ __forceinline__ double log_fast(double a) { return log(a); }
+__device__ __forceinline__ void sincos_fast(float x, float *s, float *c) { __sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_fast(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ float abs_t(float a) { return fabsf(a); }
 __device__ __forceinline__ double abs_t(double a) { return fabs(a); }
 __device__ __forceinline__ float copysign_t(float a, float b) { return copysignf(a, b); }
@@ -419,15 +430,15 @@ __device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c) {
 }
 
 // Mean ionisation loss rate in silicon (Bethe, no density or shell
-// correction), GeV cm^2/g, at beta*gamma^2 = bg2 for a particle of mass m.
+// correction), GeV cm^2/g, at (beta gamma)^2 = bg2 for a particle of mass m.
 template <typename T>
 __device__ __forceinline__ T si_loss_rate(T bg2, T m) {
-  const T me = T(0.51099895e-3), r = me / m;
-  const T b2 = bg2 / (T(1) + bg2), g = sqrt_t(T(1) + bg2);
-  const T wmax = T(2) * me * bg2 / (T(1) + T(2) * g * r + r * r);
+  const T me = T(0.51099895e-3), r = div_fast(me, m);
+  const T b2 = div_fast(bg2, T(1) + bg2), g = sqrt_t(T(1) + bg2);
+  const T wmax = div_fast(T(2) * me * bg2, T(1) + T(2) * g * r + r * r);
   // K Z/A with K = 0.307075e-3 GeV cm^2/mol, Z/A = 0.49848; I = 173 eV
-  return T(0.307075e-3 * 0.49848) / b2 *
-         (T(0.5) * log_t(T(2) * me * bg2 * wmax / T(173e-9 * 173e-9)) - b2);
+  return div_fast(T(0.307075e-3 * 0.49848), b2) *
+         (T(0.5) * log_fast(T(2) * me * bg2 * wmax * T(1.0 / (173e-9 * 173e-9))) - b2);
 }
 
 // Effects of one crossed layer's material on the state at the crossing.
@@ -440,10 +451,12 @@ __device__ __forceinline__ T si_loss_rate(T bg2, T m) {
 // changes |p| by -dir * dp (dir = -1 regains it on the way back).  The loss
 // maps q/pT -> q/pT |p|/|p'| with dp held fixed; its Jacobian (identity but
 // the q/pT row: j33 on q/pT, j35 on theta) multiplies the covariance on both
-// sides and is returned in *j33, *j35.
+// sides and is returned in *j33, *j35.  tab: the map's table where the
+// caller staged it (nullptr: the map's own).
 template <typename T>
 __device__ __forceinline__ void material(const DevCfg &cfg, int kind, T *p, T *c, T dir,
-                                         T *j33 = nullptr, T *j35 = nullptr) {
+                                         T *j33 = nullptr, T *j35 = nullptr,
+                                         const float2 *tab = nullptr) {
   if (j33) *j33 = T(1);
   if (j35) *j35 = T(0);
   const DevMat &M = cfg.mat;
@@ -456,28 +469,33 @@ __device__ __forceinline__ void material(const DevCfg &cfg, int kind, T *p, T *c
   int iz = (int)floor((p[2] + T(M.z_max)) * T(M.z_scale));
   ir = ir < 0 ? 0 : (ir >= M.nr ? M.nr - 1 : ir);
   iz = iz < 0 ? 0 : (iz >= M.nz ? M.nz - 1 : iz);
-  const float2 tb = M.tab[iz * M.nr + ir];
-  T sth, cth, sph, cph;
+  const float2 tb = (tab ? tab : M.tab)[iz * M.nr + ir];
+  T sth, cth;
   sincos_t(p[5], &sth, &cth);
-  sincos_t(p[4], &sph, &cph);
-  const T cosa = kind == 0 ? sth * (cph * p[0] + sph * p[1]) / r : cth;
-  const T k = abs_t(cosa) * T(M.k_max) > T(1) ? T(1) / abs_t(cosa) : T(M.k_max);
-  const T pm = T(1) / (abs_t(p[3]) * sth);
+  T cosa = cth;
+  if (kind == 0) {
+    T sph, cph;
+    sincos_fast(p[4], &sph, &cph);
+    cosa = div_fast(sth * (cph * p[0] + sph * p[1]), r);
+  }
+  const T k = abs_t(cosa) * T(M.k_max) > T(1) ? div_fast(T(1), abs_t(cosa)) : T(M.k_max);
+  const T pm = div_fast(T(1), abs_t(p[3]) * sth);
   const T m = T(M.mass);
   const T e = sqrt_t(pm * pm + m * m);
-  const T beta = pm / e;
+  const T beta = div_fast(pm, e);
   const T t = T(tb.x) * k;
   if (t > T(0)) {
-    T f = T(1) + T(0.038) * log_t(t);
+    T f = T(1) + T(0.038) * log_fast(t);
     f = f < T(0) ? T(0) : f;
-    const T th0 = T(0.0136) / (beta * pm) * sqrt_t(t) * f;
+    const T th0 = div_fast(T(0.0136), beta * pm) * sqrt_t(t) * f;
     add_ms(p, th0 * th0, c);
   }
   const T x = T(tb.y) * k;
   if (x > T(0)) {
-    T dp = x * si_loss_rate(pm * pm / (m * m), m) / beta;
+    const T im = div_fast(T(1), m);
+    T dp = div_fast(x * si_loss_rate(pm * pm * im * im, m), beta);
     dp = dp > T(0.5) * pm ? T(0.5) * pm : dp;
-    const T ratio = T(1) / (T(1) - dir * dp / pm);
+    const T ratio = div_fast(T(1), T(1) - dir * div_fast(dp, pm));
     const T a = ratio * ratio;
     const T b = dir * dp * p[3] * abs_t(p[3]) * cth * a;
     p[3] *= ratio;

@@ -323,7 +323,8 @@ template <int G, bool kMat, class Rec>
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
                                            int lane, int slot, const Rec &rec, int ev,
                                            int64_t ev_base, int step, int lid, u64 &fin_key,
-                                           float l_hint = 0.f, int *sur = nullptr) {
+                                           float l_hint = 0.f, int *sur = nullptr,
+                                           const float2 *mtab = nullptr) {
   const DevLayer &L = sl[lid];
   Prop pr;
   int st = kNoCrossing;
@@ -334,7 +335,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   // kMat: the material map's effects (a separate instantiation, so that the
   // constant-angle form keeps its register allocation)
   if (ok) {
-    if constexpr (kMat) material(P.cfg, L.kind, pr.p, pr.c, 1.f);
+    if constexpr (kMat) material<float>(P.cfg, L.kind, pr.p, pr.c, 1.f, nullptr, nullptr, mtab);
     else add_ms(pr.p, P.cfg.ms_var, pr.c);
   }
 
@@ -651,6 +652,17 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
   __shared__ __attribute__((aligned(16))) __bf16 sMW[kSurr ? kW1n + kW2n + kW3n : 8];
   __shared__ __attribute__((aligned(16))) float sMB[kSurr ? 64 + 64 + 32 : 4];
   __shared__ __attribute__((aligned(16))) __bf16 sMH[kSurr ? 4 * 64 * kLdH : 8];
+  // material: a table of up to kMatLds bins is read from LDS
+  constexpr int kMatLds = 1024;
+  __shared__ float2 sMat[kMat ? kMatLds : 1];
+  const float2 *mtab = nullptr;
+  if constexpr (kMat) {
+    const int nb = P.cfg.mat.nr * P.cfg.mat.nz;
+    if (nb <= kMatLds) {
+      for (int i = threadIdx.x; i < nb; i += blockDim.x) sMat[i] = P.cfg.mat.tab[i];
+      mtab = sMat;
+    }
+  }
   stage_layers(P, sl);
   MlpWeights mw{};
   if constexpr (kSurr) {
@@ -782,7 +794,7 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
         group_step<G, kMat>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, l_hint,
-                            &sur);
+                            &sur, mtab);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
