@@ -174,17 +174,123 @@ int orc_path_to_disk(const double p[6], double Z, double bz, double kappa,
  *   dl/dp0 = -(n^T D)/(n^T t),  F = D + t (dl/dp0)^T = (I - t n^T/(n^T t)) D.
  * C' = F C F^T then has n as a null direction (rank 5): the state is
  * constrained to the surface. */
+double orc_field_bz(const orc_field *f, double x, double y, double z) {
+  double r2 = x * x + y * y, z2 = z * z;
+  return f->b0 * (1.0 + f->c_r2 * r2 + f->c_z2 * z2 + f->c_z4 * z2 * z2);
+}
+
+/* d(x, y, z, phi)/dl in the axial field */
+static void field_deriv(const orc_field *f, double kappa, double ipt, double cot,
+                        const double y[4], double d[4]) {
+  d[0] = cos(y[3]);
+  d[1] = sin(y[3]);
+  d[2] = cot;
+  d[3] = -kappa * orc_field_bz(f, y[0], y[1], y[2]) * ipt;
+}
+
+/* one classical Runge-Kutta step of transverse length h */
+static void rk4(const orc_field *f, double kappa, double ipt, double cot, const double y[4],
+                double h, double out[4]) {
+  double k1[4], k2[4], k3[4], k4[4], t[4];
+  field_deriv(f, kappa, ipt, cot, y, k1);
+  for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k1[i];
+  field_deriv(f, kappa, ipt, cot, t, k2);
+  for (int i = 0; i < 4; ++i) t[i] = y[i] + 0.5 * h * k2[i];
+  field_deriv(f, kappa, ipt, cot, t, k3);
+  for (int i = 0; i < 4; ++i) t[i] = y[i] + h * k3[i];
+  field_deriv(f, kappa, ipt, cot, t, k4);
+  for (int i = 0; i < 4; ++i) out[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+#define ORC_FIELD_MAX_STEPS 4096
+
+/* Crossing of a layer in the parameterised field: path l and the end
+ * point y = (x, y, z, phi unwrapped). */
+static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, double l_min,
+                          const orc_field *f, double *l_out, double yend[4]) {
+  double cot = cos(p[5]) / sin(p[5]);
+  double y[4] = {p[0], p[1], p[2], p[4]};
+  if (Lr->kind == 1) {
+    if (cos(p[5]) == 0.0) return ORC_NO_CROSSING;
+    double lt = (Lr->pos - p[2]) * sin(p[5]) / cos(p[5]);
+    if (!(lt > l_min)) return ORC_NO_CROSSING;
+    int n = (int)ceil(lt / f->h_max);
+    if (n > ORC_FIELD_MAX_STEPS) return ORC_NO_CROSSING;
+    double h = lt / n;
+    for (int k = 0; k < n; ++k) {
+      rk4(f, kappa, p[3], cot, y, h, y);
+      if (fabs(y[3] - p[4]) >= M_PI) return ORC_NO_CROSSING;
+    }
+    y[2] = Lr->pos;
+    *l_out = lt;
+    memcpy(yend, y, sizeof(y));
+    return ORC_OK;
+  }
+  double R2 = Lr->pos * Lr->pos;
+  double g = y[0] * y[0] + y[1] * y[1] - R2, l = 0.0;
+  for (int k = 0; k < ORC_FIELD_MAX_STEPS; ++k) {
+    double yn[4];
+    rk4(f, kappa, p[3], cot, y, f->h_max, yn);
+    double gn = yn[0] * yn[0] + yn[1] * yn[1] - R2;
+    if ((g < 0.0) != (gn < 0.0) || gn == 0.0) {
+      /* Newton on the step length s from the bracket's start */
+      double s = g == gn ? f->h_max : f->h_max * g / (g - gn), ys[4];
+      for (int it = 0; it < 6; ++it) {
+        rk4(f, kappa, p[3], cot, y, s, ys);
+        double gs = ys[0] * ys[0] + ys[1] * ys[1] - R2;
+        double gp = 2.0 * (ys[0] * cos(ys[3]) + ys[1] * sin(ys[3]));
+        if (gp == 0.0) break;
+        s -= gs / gp;
+      }
+      rk4(f, kappa, p[3], cot, y, s, ys);
+      if (l + s > l_min && fabs(ys[3] - p[4]) < M_PI) {
+        *l_out = l + s;
+        memcpy(yend, ys, sizeof(ys));
+        return ORC_OK;
+      }
+    }
+    if (fabs(yn[3] - p[4]) >= M_PI) return ORC_NO_CROSSING;
+    memcpy(y, yn, sizeof(yn));
+    g = gn;
+    l += f->h_max;
+  }
+  return ORC_NO_CROSSING;
+}
+
 int orc_propagate(const double p[6], const double C[36], const orc_layer *Lr,
                   double bz, double kappa, double l_min, double edge_margin,
                   int check_extent, double p_out[6], double C_out[36],
                   double F_out[36], double *l_out) {
+  return orc_propagate_f(p, C, Lr, bz, kappa, l_min, edge_margin, check_extent, p_out, C_out,
+                         F_out, l_out, NULL);
+}
+
+int orc_propagate_f(const double p[6], const double C[36], const orc_layer *Lr,
+                    double bz, double kappa, double l_min, double edge_margin,
+                    int check_extent, double p_out[6], double C_out[36],
+                    double F_out[36], double *l_out, const orc_field *fld) {
   double l;
-  int st = Lr->kind == 0
-               ? orc_path_to_barrel(p, Lr->pos, bz, kappa, l_min, &l)
-               : orc_path_to_disk(p, Lr->pos, bz, kappa, l_min, &l);
-  if (st != ORC_OK) return st;
   double pp[6];
-  orc_transport(p, l, bz, kappa, pp);
+  double dw = -kappa * bz; /* d omega / d(q/pT) */
+  if (fld) {
+    double y[4];
+    int st = field_crossing(p, Lr, kappa, l_min, fld, &l, y);
+    if (st != ORC_OK) return st;
+    pp[0] = y[0];
+    pp[1] = y[1];
+    pp[2] = y[2];
+    pp[3] = p[3];
+    pp[4] = wrap_phi(y[3]);
+    pp[5] = p[5];
+    /* the helix of the path's mean curvature: omega = turning / l */
+    if (p[3] != 0.0) dw = (y[3] - p[4]) / (l * p[3]);
+  } else {
+    int st = Lr->kind == 0
+                 ? orc_path_to_barrel(p, Lr->pos, bz, kappa, l_min, &l)
+                 : orc_path_to_disk(p, Lr->pos, bz, kappa, l_min, &l);
+    if (st != ORC_OK) return st;
+    orc_transport(p, l, bz, kappa, pp);
+  }
   if (check_extent) {
     double q = Lr->kind == 0 ? pp[2] : hypot(pp[0], pp[1]);
     if (q < Lr->ext_lo - edge_margin || q > Lr->ext_hi + edge_margin)
@@ -197,7 +303,6 @@ int orc_propagate(const double p[6], const double C[36], const orc_layer *Lr,
   memcpy(p_out, pp, sizeof(pp));
   if (!F_out && !C_out) return ORC_OK;
 
-  double dw = -kappa * bz; /* d omega / d(q/pT) */
   double w = dw * p[3];
   double h = 0.5 * w * l;
   double L = l * sinc(h);
@@ -511,7 +616,8 @@ static double edge_distance(const orc_layer *Lr, const double pp[6], double m) {
 
 /* Seed from three hits (seeds are supplied from outside, Section 2.2):
  * the circle through the three transverse points gives the centre and the
- * radius rho; the turning sense gives the charge; pT = kappa |B| rho; phi
+ * radius rho; the turning sense gives the charge; pT = kappa |B| rho (B: a
+ * parameterised field at the middle hit); phi
  * is the tangent at the first hit in the direction of motion; cot(theta)
  * is the z rise over the transverse arc from the first to the third hit.
  * The state starts at the first hit with a wide diagonal prior, less its
@@ -540,9 +646,12 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
   double rho = hypot(ux, uy);
   double turn = (x2 - x1) * (y3 - y2) - (y2 - y1) * (x3 - x2);
   int ccw = turn > 0.0; /* omega > 0 */
-  double pt = cfg->kappa * fabs(cfg->bz) * rho;
+  /* a parameterised field is taken at the middle hit */
+  double bz = cfg->field ? orc_field_bz(cfg->field, x2, y2, h[5]) : cfg->bz;
+  if (bz == 0.0) return 0;
+  double pt = cfg->kappa * fabs(bz) * rho;
   /* omega = -kappa B ipt > 0  <=>  B * ipt < 0 */
-  double ipt = (ccw ? -1.0 : 1.0) * (cfg->bz > 0 ? 1.0 : -1.0) / pt;
+  double ipt = (ccw ? -1.0 : 1.0) * (bz > 0 ? 1.0 : -1.0) / pt;
   double r1x = x1 - cx, r1y = y1 - cy;
   double dirx = ccw ? -r1y : r1y, diry = ccw ? r1x : -r1x;
   double phi1 = atan2(diry, dirx);
@@ -560,8 +669,8 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
     const orc_layer *Lr = &layers[hl[k]];
     if (k > 0) {
       double pp[6], Cp[36];
-      if (orc_propagate(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp,
-                        Cp, NULL, NULL) != ORC_OK)
+      if (orc_propagate_f(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp,
+                          Cp, NULL, NULL, cfg->field) != ORC_OK)
         return 0;
       memcpy(p, pp, sizeof(pp));
       memcpy(C, Cp, sizeof(Cp));
@@ -600,20 +709,16 @@ int orc_seed(const orc_cfg *cfg, const orc_layer *layers, int32_t n_layers,
   for (int i = 0; i < n_layers; ++i) {
     if (i == hl[0] || i == hl[1] || i == hl[2]) continue;
     double pp[6], l;
-    int st = orc_propagate(p, NULL, &layers[i], cfg->bz, cfg->kappa, cfg->l_min,
-                           cfg->edge_margin, 1, pp, NULL, NULL, &l);
+    int st = orc_propagate_f(p, NULL, &layers[i], cfg->bz, cfg->kappa, cfg->l_min,
+                             cfg->edge_margin, 1, pp, NULL, NULL, &l, cfg->field);
     if (st == ORC_NO_CROSSING) continue;
     if (st == ORC_OUT_OF_EXTENT) {
-      double l2;
       /* near the widened edge the FP32 decision may flip */
-      int s2 = layers[i].kind == 0
-                   ? orc_path_to_barrel(p, layers[i].pos, cfg->bz, cfg->kappa, cfg->l_min, &l2)
-                   : orc_path_to_disk(p, layers[i].pos, cfg->bz, cfg->kappa, cfg->l_min, &l2);
-      if (s2 == ORC_OK) {
-        double p2[6];
-        orc_transport(p, l2, cfg->bz, cfg->kappa, p2);
-        if (edge_distance(&layers[i], p2, cfg->edge_margin) <= pos_tol) out->plan_fragile = 1;
-      }
+      double p2[6];
+      if (orc_propagate_f(p, NULL, &layers[i], cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, p2, NULL,
+                          NULL, NULL, cfg->field) == ORC_OK &&
+          edge_distance(&layers[i], p2, cfg->edge_margin) <= pos_tol)
+        out->plan_fragile = 1;
       continue;
     }
     if (edge_distance(&layers[i], pp, cfg->edge_margin) <= pos_tol) out->plan_fragile = 1;
@@ -724,18 +829,15 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
       int ne0 = ne;
       double *pc = &pp[6 * c], *Cc = &Cp[36 * c];
       double l;
-      int st = orc_propagate(cands[c].p, cands[c].C, Lr, cfg->bz, cfg->kappa, cfg->l_min,
-                             cfg->edge_margin, 1, pc, Cc, NULL, &l);
+      int st = orc_propagate_f(cands[c].p, cands[c].C, Lr, cfg->bz, cfg->kappa, cfg->l_min,
+                               cfg->edge_margin, 1, pc, Cc, NULL, &l, cfg->field);
       if (st == ORC_OK && edge_distance(Lr, pc, cfg->edge_margin) <= tol->pos_tol) mark(&out->fragile_step, s);
       if (st == ORC_OUT_OF_EXTENT) {
-        double l2, p2[6];
-        int s2 = Lr->kind == 0
-                     ? orc_path_to_barrel(cands[c].p, Lr->pos, cfg->bz, cfg->kappa, cfg->l_min, &l2)
-                     : orc_path_to_disk(cands[c].p, Lr->pos, cfg->bz, cfg->kappa, cfg->l_min, &l2);
-        if (s2 == ORC_OK) {
-          orc_transport(cands[c].p, l2, cfg->bz, cfg->kappa, p2);
-          if (edge_distance(Lr, p2, cfg->edge_margin) <= tol->pos_tol) mark(&out->fragile_step, s);
-        }
+        double p2[6];
+        if (orc_propagate_f(cands[c].p, NULL, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, p2,
+                            NULL, NULL, NULL, cfg->field) == ORC_OK &&
+            edge_distance(Lr, p2, cfg->edge_margin) <= tol->pos_tol)
+          mark(&out->fragile_step, s);
       }
       if (st != ORC_OK) {
         ext_t e = {cands[c].n_hits, cands[c].chi2, c, 0x7fffffff, EXT_SKIP, ORC_HIT_SKIP, 0.0};
@@ -870,7 +972,8 @@ int orc_fit_track(const orc_cfg *cfg, const double p0[6], const double C0[36], i
   for (int32_t k = 0; k < n; ++k) {
     orc_layer Lr = {kinds[k], pos[k], 0.0, 0.0};
     double pp[6], Cp[36];
-    if (orc_propagate(p, C, &Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL) != ORC_OK)
+    if (orc_propagate_f(p, C, &Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL,
+                        cfg->field) != ORC_OK)
       return -(k + 1);
     orc_material_effects(cfg, kinds[k], pp, Cp, 1, NULL);
     double c2;
@@ -950,8 +1053,8 @@ int orc_backward_fit(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
     if (k > 0) {
       double pp[6], Cp[36];
       orc_flip(p, C);
-      if (orc_propagate(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL) !=
-          ORC_OK)
+      if (orc_propagate_f(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp, NULL, NULL,
+                          cfg->field) != ORC_OK)
         return -(k + 1);
       orc_flip(pp, Cp);
       memcpy(p, pp, sizeof(pp));
@@ -1049,8 +1152,8 @@ int orc_smooth_track(const orc_cfg *cfg, const orc_layer *layers, int32_t n_laye
     if (L < 0 || L >= n_layers) return -1;
     const orc_layer *Lr = &layers[L];
     double pp[6], Cp[36];
-    if (orc_propagate(xf[n - 1], Cf[n - 1], Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp, Cp,
-                      F[n], NULL) != ORC_OK)
+    if (orc_propagate_f(xf[n - 1], Cf[n - 1], Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pp,
+                        Cp, F[n], NULL, cfg->field) != ORC_OK)
       return -1;
     double Mm[36], MF[36];
     orc_material_effects(cfg, Lr->kind, pp, Cp, 1, Mm);

@@ -74,6 +74,17 @@ typedef struct {
   const double *xi;   /* [n_z][n_r] */
 } orc_material;
 
+/* Parameterised field (Section 2.1: a constant or a parameterised field):
+ * Bz(r, z) = b0 (1 + c_r2 r^2 + c_z2 z^2 + c_z4 z^4), tesla, cm; the radial
+ * component is neglected, so pT and theta are constants of the motion and
+ * the azimuth turns at the local curvature omega = -kappa Bz (q/pT).  The
+ * transport integrates (x, y, z, phi) over the transverse path with
+ * fourth-order Runge-Kutta steps of at most h_max. */
+typedef struct {
+  double b0, c_r2, c_z2, c_z4;
+  double h_max;
+} orc_field;
+
 typedef struct {
   double bz;          /* field along +z, tesla */
   double kappa;       /* curvature constant (normally ORC_KAPPA) */
@@ -89,6 +100,8 @@ typedef struct {
   int32_t n_regions;
   /* material map; NULL: the constant scattering angle ms_sigma per layer */
   const orc_material *material;
+  /* parameterised field; NULL: the uniform field bz */
+  const orc_field *field;
 } orc_cfg;
 
 /* ---- single-state primitives (exposed for the tests) ---------------- */
@@ -112,6 +125,21 @@ int orc_propagate(const double p[6], const double C[36], const orc_layer *L,
                   double bz, double kappa, double l_min, double edge_margin,
                   int check_extent, double p_out[6], double C_out[36],
                   double F_out[36], double *l_out);
+
+/* The same in the parameterised field fld (NULL: the uniform bz).  The
+ * crossing is found by Runge-Kutta steps: on a disk, equal steps to the
+ * exact path (Z - z) tan(theta); on a barrel, steps of h_max until r^2 - R^2
+ * changes sign, then Newton iterations on the last step's length.  The
+ * turning must stay below half a turn.  The Jacobian is that of the helix
+ * with the path's mean curvature (the turning over the path length), made
+ * surface-constrained at the end point. */
+int orc_propagate_f(const double p[6], const double C[36], const orc_layer *Lr,
+                    double bz, double kappa, double l_min, double edge_margin,
+                    int check_extent, double p_out[6], double C_out[36],
+                    double F_out[36], double *l_out, const orc_field *fld);
+
+/* Bz of the parameterised field at (x, y, z). */
+double orc_field_bz(const orc_field *fld, double x, double y, double z);
 
 /* Multiple-scattering noise for state p with angle sigma, added to C. */
 void orc_add_ms(const double p[6], double sigma, double C[36]);

@@ -56,12 +56,17 @@ class Material(C.Structure):
                 ("x_x0", C.POINTER(C.c_double)), ("xi", C.POINTER(C.c_double))]
 
 
+class Field(C.Structure):
+    _fields_ = [("b0", C.c_double), ("c_r2", C.c_double), ("c_z2", C.c_double),
+                ("c_z4", C.c_double), ("h_max", C.c_double)]
+
+
 class Cfg(C.Structure):
     _fields_ = [("bz", C.c_double), ("kappa", C.c_double), ("chi2_cut", C.c_double),
                 ("ms_sigma", C.c_double), ("edge_margin", C.c_double), ("l_min", C.c_double),
                 ("n_cand", C.c_int32), ("max_holes", C.c_int32), ("init_var", C.c_double * 6),
                 ("regions", C.POINTER(Region)), ("n_regions", C.c_int32),
-                ("material", C.POINTER(Material))]
+                ("material", C.POINTER(Material)), ("field", C.POINTER(Field))]
 
 
 class SeedOut(C.Structure):
@@ -104,6 +109,9 @@ def lib():
         L.orc_path_to_disk.argtypes = L.orc_path_to_barrel.argtypes
         L.orc_propagate.argtypes = [_D, _D, C.POINTER(Layer), C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_int, _D, _D, _D, _D]
+        L.orc_propagate_f.argtypes = L.orc_propagate.argtypes + [C.POINTER(Field)]
+        L.orc_field_bz.argtypes = [C.POINTER(Field), C.c_double, C.c_double, C.c_double]
+        L.orc_field_bz.restype = C.c_double
         L.orc_add_ms.argtypes = [_D, C.c_double, _D]
         L.orc_bethe_si.argtypes = [C.c_double, C.c_double]
         L.orc_bethe_si.restype = C.c_double
@@ -209,7 +217,14 @@ def make_material(mm):
     return m
 
 
-def make_cfg(fc, steering=None, material=None) -> Cfg:
+def make_field(fd):
+    """Field record from an object with b0, c_r2, c_z2, c_z4, h_max (taken at
+    FP32, as the library receives them)."""
+    return Field(*[float(np.float32(getattr(fd, k))) for k in ("b0", "c_r2", "c_z2", "c_z4",
+                                                                  "h_max")])
+
+
+def make_cfg(fc, steering=None, material=None, field=None) -> Cfg:
     """steering: a sequence of regions (eta_lo, eta_hi, layers); the bounds
     are taken at FP32, as the library receives them.  material: a material
     map (make_material), or None for the constant scattering angle."""
@@ -234,6 +249,10 @@ def make_cfg(fc, steering=None, material=None) -> Cfg:
         m = make_material(material)
         c.material = C.pointer(m)
         c._keep_m = m
+    if field is not None:
+        f = make_field(field)
+        c.field = C.pointer(f)
+        c._keep_f = f
     return c
 
 
@@ -260,16 +279,22 @@ def path_to_disk(p, Z, bz, kappa, l_min=1e-4):
     return float(l[0]) if st == OK else None
 
 
-def propagate(p, Cm, layer, bz, kappa, l_min=1e-4, edge_margin=0.0, check_extent=True):
-    """Returns (status, p', C', F, l)."""
+def propagate(p, Cm, layer, bz, kappa, l_min=1e-4, edge_margin=0.0, check_extent=True,
+              field=None):
+    """Returns (status, p', C', F, l); in the parameterised field if given."""
     p = _d(p, 6)
     Cm = _d(Cm, 36) if Cm is not None else None
     lay = _layer(layer)
     po, Co, Fo, lo = np.zeros(6), np.zeros(36), np.zeros(36), np.zeros(1)
-    st = lib().orc_propagate(_p(p), _p(Cm) if Cm is not None else None, C.byref(lay), bz, kappa,
-                             l_min, edge_margin, int(check_extent), _p(po),
-                             _p(Co) if Cm is not None else None, _p(Fo), _p(lo))
+    fld = C.byref(make_field(field)) if field is not None else None
+    st = lib().orc_propagate_f(_p(p), _p(Cm) if Cm is not None else None, C.byref(lay), bz, kappa,
+                               l_min, edge_margin, int(check_extent), _p(po),
+                               _p(Co) if Cm is not None else None, _p(Fo), _p(lo), fld)
     return st, po, Co.reshape(6, 6), Fo.reshape(6, 6), float(lo[0])
+
+
+def field_bz(field, x, y, z):
+    return float(lib().orc_field_bz(C.byref(make_field(field)), float(x), float(y), float(z)))
 
 
 def add_ms(p, sigma, Cm):
@@ -329,8 +354,8 @@ def update_hit(p, Cm, kind, hit, var_u, var_v, stereo=0.0):
     return bool(ok), p, Cm.reshape(6, 6), float(c2[0])
 
 
-def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None, material=None):
-    cfg = make_cfg(fc, steering, material)
+def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None, material=None, field=None):
+    cfg = make_cfg(fc, steering, material, field)
     lay = make_layers(layers)
     h, hv = _d(h, 9), _d(hv, 6)
     hl = np.ascontiguousarray(hl, np.int32)
@@ -347,11 +372,12 @@ def seed(fc, layers, h, hv, hl, pos_tol=0.0, steering=None, material=None):
 DEFAULT_TOL = (1e-3, 1e-2, 1e-3)  # chi2 rel, chi2 abs, cm
 
 
-def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None, material=None):
+def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None, material=None,
+               field=None):
     """Clone-engine finding for the seeds of one event (all seeds if None),
     with region steering and a material map if given.  Returns a list of
     dicts, one per seed."""
-    cfg = make_cfg(fc, steering, material)
+    cfg = make_cfg(fc, steering, material, field)
     lay = make_layers(layers)
     t = Tol(*tol)
     seeds = ev.seeds if seeds is None else seeds
@@ -375,8 +401,8 @@ def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None, mater
     return res
 
 
-def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v, material=None):
-    cfg = make_cfg(fc, material=material)
+def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v, material=None, field=None):
+    cfg = make_cfg(fc, material=material, field=field)
     p0, C0 = _d(p0, 6), _d(C0, 36)
     kinds = np.ascontiguousarray(kinds, np.int32)
     n = kinds.shape[0]
@@ -399,11 +425,11 @@ def flip(p, Cm=None):
     return p, Cm.reshape(6, 6)
 
 
-def backward_fit(fc, layers, ev, seed_hits, trk, material=None):
+def backward_fit(fc, layers, ev, seed_hits, trk, material=None, field=None):
     """Backward fit of one found track of event ev (a find_event result
     dict, or any dict with seed_ok, plan, hit, par).  Returns (status, par,
     cov 6x6, chi2, n_updates)."""
-    cfg = make_cfg(fc, material=material)
+    cfg = make_cfg(fc, material=material, field=field)
     lay = make_layers(layers)
     t = Track()
     t.seed_ok = int(bool(trk["seed_ok"]))
@@ -439,11 +465,12 @@ def _track_struct(trk):
     return t
 
 
-def smooth_track(fc, layers, ev, seed_layer, seed_par, seed_cov, trk, material=None):
+def smooth_track(fc, layers, ev, seed_layer, seed_par, seed_cov, trk, material=None,
+                 field=None):
     """RTS smoothing of one found track of event ev, starting from the seed
     state (seed_par, seed_cov 6x6) on seed_layer.  Returns (n, layers [n],
     par [n][6], cov [n][6][6]); n <= 0 on failure."""
-    cfg = make_cfg(fc, material=material)
+    cfg = make_cfg(fc, material=material, field=field)
     lay = make_layers(layers)
     t = _track_struct(trk)
     arrs = [np.ascontiguousarray(a, np.float32) for a in (ev.x, ev.y, ev.z, ev.var_u, ev.var_v)]

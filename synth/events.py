@@ -132,8 +132,130 @@ def _material_kick(rng, mat, is_b, x, y, z, ph, th, p_tot):
     return sigma, p_tot - np.where(xi0 > 0, dp, 0.0)
 
 
+def _bz(field, x, y, z):
+    r2, z2 = x * x + y * y, z * z
+    return field.b0 * (1.0 + field.c_r2 * r2 + field.c_z2 * z2 + field.c_z4 * z2 * z2)
+
+
+def _rk4(field, ipt, cot, x, y, z, ph, h):
+    """One Runge-Kutta step of transverse length h (arrays) of the motion in
+    the axial field: pT and theta constant, phi turning at -KAPPA Bz q/pT."""
+    def d(x, y, z, ph):
+        return np.cos(ph), np.sin(ph), cot, -KAPPA * _bz(field, x, y, z) * ipt
+    k1 = d(x, y, z, ph)
+    k2 = d(*(v + 0.5 * h * k for v, k in zip((x, y, z, ph), k1)))
+    k3 = d(*(v + 0.5 * h * k for v, k in zip((x, y, z, ph), k2)))
+    k4 = d(*(v + h * k for v, k in zip((x, y, z, ph), k3)))
+    return tuple(v + h / 6.0 * (a + 2.0 * b + 2.0 * c + e)
+                 for v, a, b, c, e in zip((x, y, z, ph), k1, k2, k3, k4))
+
+
+def _simulate_field(rng, q, pt, theta, phi, vx, vy, vz, layers, recipe, field, material,
+                    step=0.25):
+    """Truth in a parameterised field: all tracks advance together in
+    Runge-Kutta steps of `step` cm of transverse path; a step that crosses
+    a layer is cut at the crossing (a disk's exactly, a barrel's by Newton
+    iterations on the cut step), where the hit is recorded and the layer's
+    scattering and loss applied.  A track stops after half a turn or when
+    it leaves the detector."""
+    n = q.shape[0]
+    kinds = np.array([l.kind for l in layers])
+    poss = np.array([l.pos for l in layers], float)
+    lo = np.array([l.ext_lo for l in layers])
+    hi = np.array([l.ext_hi for l in layers])
+    is_b = kinds == BARREL
+    r_out = max(max(poss[is_b], default=0.0), max(hi[~is_b], default=0.0)) + 5.0
+    z_out = max(np.abs(poss[~is_b]).max(initial=0.0), np.abs(hi[is_b]).max(initial=0.0)) + 5.0
+    x, y, z, ph = vx.copy(), vy.copy(), vz.copy(), phi.copy()
+    th, ptc = theta.copy(), pt.copy()
+    ph0 = phi.copy()
+    alive = np.ones(n, bool)
+    recs = []
+    for _ in range(200000):
+        idx = np.nonzero(alive)[0]
+        if idx.size == 0:
+            break
+        ipt = q[idx] / ptc[idx]
+        cot = np.cos(th[idx]) / np.sin(th[idx])
+        x0, y0, z0, p0 = x[idx], y[idx], z[idx], ph[idx]
+        x1, y1, z1, p1 = _rk4(field, ipt, cot, x0, y0, z0, p0, step)
+        # fraction of the step to each layer's crossing (inf: none)
+        frac = np.full((idx.size, len(layers)), np.inf)
+        for k, L in enumerate(layers):
+            if L.kind == BARREL:
+                g0 = x0 * x0 + y0 * y0 - L.pos ** 2
+                g1 = x1 * x1 + y1 * y1 - L.pos ** 2
+                hit = (g0 != 0.0) & ((g0 < 0.0) != (g1 < 0.0))
+                frac[hit, k] = (g0 / (g0 - g1))[hit]
+            else:
+                d0, d1 = z0 - L.pos, z1 - L.pos
+                hit = (d0 != 0.0) & ((d0 < 0.0) != (d1 < 0.0))
+                frac[hit, k] = (d0 / (d0 - d1))[hit]
+        k = np.argmin(frac, axis=1)
+        f = frac[np.arange(idx.size), k]
+        cross = np.isfinite(f)
+        # no crossing: take the whole step
+        nc = ~cross
+        x[idx[nc]], y[idx[nc]], z[idx[nc]], ph[idx[nc]] = x1[nc], y1[nc], z1[nc], p1[nc]
+        if cross.any():
+            c = np.nonzero(cross)[0]
+            t = idx[c]
+            kk = k[c]
+            s = f[c] * step
+            bar = is_b[kk]
+            # disks: z is linear in the path, so the fraction is exact;
+            # barrels: Newton on the cut step length
+            for _it in range(4):
+                xs, ys, zs, ps = _rk4(field, ipt[c], cot[c], x0[c], y0[c], z0[c], p0[c], s)
+                g = xs * xs + ys * ys - poss[kk] ** 2
+                gp = 2.0 * (xs * np.cos(ps) + ys * np.sin(ps))
+                s = np.where(bar & (gp != 0.0), s - g / np.where(gp != 0.0, gp, 1.0), s)
+            xs, ys, zs, ps = _rk4(field, ipt[c], cot[c], x0[c], y0[c], z0[c], p0[c], s)
+            rr = np.hypot(xs, ys)
+            xs = np.where(bar, xs * poss[kk] / rr, xs)
+            ys = np.where(bar, ys * poss[kk] / rr, ys)
+            zs = np.where(bar, zs, poss[kk])
+            # step just past the surface so that it is not found again
+            x[t], y[t], z[t], ph[t] = xs, ys, zs, ps
+            qv = np.where(bar, zs, np.hypot(xs, ys))
+            inside = (qv >= lo[kk]) & (qv <= hi[kk])
+            sel = np.nonzero(inside)[0]
+            if sel.size:
+                tt = t[sel]
+                if material is not None:
+                    p_tot = ptc[tt] / np.sin(th[tt])
+                    sig, p_new = _material_kick(rng, material, bar[sel], x[tt], y[tt], z[tt],
+                                                ph[tt], th[tt], p_tot)
+                    dth = rng.normal(0.0, 1.0, tt.size) * sig
+                    dal = rng.normal(0.0, 1.0, tt.size) * sig
+                    ph[tt] = ph[tt] + dal / np.sin(th[tt])
+                    th[tt] = th[tt] + dth
+                    ptc[tt] = p_new * np.sin(th[tt])
+                elif recipe.ms_sigma > 0.0:
+                    dth = rng.normal(0.0, recipe.ms_sigma, tt.size)
+                    dal = rng.normal(0.0, recipe.ms_sigma, tt.size)
+                    p_tot = ptc[tt] / np.sin(th[tt])
+                    ph[tt] = ph[tt] + dal / np.sin(th[tt])
+                    th[tt] = th[tt] + dth
+                    ptc[tt] = p_tot * np.sin(th[tt])
+                state = np.stack([x[tt], y[tt], z[tt], q[tt] / ptc[tt], _wrap(ph[tt]), th[tt]],
+                                 axis=1)
+                recs.append((tt, kk[sel].astype(np.int32), state))
+            # nudge past the surface along the direction
+            x[t] += 1e-7 * np.cos(ph[t])
+            y[t] += 1e-7 * np.sin(ph[t])
+            z[t] += 1e-7 * np.cos(th[t]) / np.sin(th[t])
+        gone = ((np.abs(ph[idx] - ph0[idx]) >= np.pi) | (np.hypot(x[idx], y[idx]) > r_out) |
+                (np.abs(z[idx]) > z_out))
+        alive[idx[gone]] = False
+    if recs:
+        return (np.concatenate([r[0] for r in recs]), np.concatenate([r[1] for r in recs]),
+                np.concatenate([r[2] for r in recs]))
+    return np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros((0, 6))
+
+
 def simulate_tracks(rng, n, layers, bz, recipe, pt=None, eta=None, phi=None, q=None,
-                    vertex=None, max_iter=64, material=None):
+                    vertex=None, max_iter=64, material=None, field=None):
     """Simulate n tracks; returns per-crossing records (track, layer, true
     position, state after the layer) in crossing order, plus the initial
     parameters.  With a material map, each crossed layer scatters the track
@@ -155,6 +277,10 @@ def simulate_tracks(rng, n, layers, bz, recipe, pt=None, eta=None, phi=None, q=N
         vx, vy, vz = vertex
     theta = 2.0 * np.arctan(np.exp(-eta))
     init = np.stack([vx, vy, vz, q / pt, phi, theta], axis=1)
+    if field is not None:
+        trk, lay, st = _simulate_field(rng, q, pt, theta, phi, vx, vy, vz, layers, recipe, field,
+                                       material)
+        return init, trk, lay, st
 
     kinds = [l.kind for l in layers]
     poss = [l.pos for l in layers]
@@ -323,7 +449,7 @@ def generate_event(w: Workload, event: int, n_tracks: Optional[int] = None,
         n_tracks = lo if lo == hi else int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
     phi = None if phi_range is None else rng.uniform(phi_range[0], phi_range[1], n_tracks)
     init, trk, lay, st = simulate_tracks(rng, n_tracks, w.layers, w.find.bz, w.recipe, phi=phi,
-                                         material=w.material)
+                                         material=w.material, field=w.field)
     # 2% (or as configured) independent loss of hits
     if w.recipe.hit_ineff > 0.0:
         keep = rng.random(trk.shape[0]) >= w.recipe.hit_ineff

@@ -140,6 +140,19 @@ def material_map(r_max: float, z_max: float, n_r: int, n_z: int, x_x0: float, xi
 
 
 @dataclass(frozen=True)
+class FieldMap:
+    """Parameterised field: Bz(r, z) = b0 (1 + c_r2 r^2 + c_z2 z^2 +
+    c_z4 z^4) tesla (r, z in cm), the radial component neglected; the
+    transport takes Runge-Kutta steps of at most h_max cm of transverse
+    path."""
+    b0: float
+    c_r2: float = 0.0
+    c_z2: float = 0.0
+    c_z4: float = 0.0
+    h_max: float = 5.0
+
+
+@dataclass(frozen=True)
 class Workload:
     name: str
     layers: Tuple[Layer, ...]
@@ -151,6 +164,8 @@ class Workload:
     # material map (replaces the recipe's and the settings' constant
     # scattering angle), or None
     material: Optional[MaterialMap] = None
+    # parameterised field (replaces the settings' uniform bz), or None
+    field: Optional[FieldMap] = None
 
 
 def stereo_layer(layer: Layer, angle: float, sigma_perp: float) -> Layer:
@@ -233,6 +248,20 @@ def cms_like_material(n_events: int = 10, n_tracks: int = 2000) -> Workload:
     w = cms_like(n_events, n_tracks)
     return replace(w, name=f"cms_like_material_{n_events}x{n_tracks}",
                    material=material_map(120.0, 300.0, 24, 30, 0.015, 0.1))
+
+
+def solenoid_field() -> FieldMap:
+    """A solenoid-like axial field: 3.8 T at the centre, 5% lower at the
+    barrel's ends (|z| = 100 cm), 45% lower at the last disks (|z| = 280
+    cm), 1% lower at r = 100 cm."""
+    return FieldMap(b0=3.8, c_r2=-1e-6, c_z2=-4.9e-6, c_z4=-1.1e-11)
+
+
+def barrel_endcap_field(n_events: int = 10, n_tracks: int = 2000) -> Workload:
+    """The realistic barrel + endcap recipe in the solenoid-like field."""
+    w = barrel_endcap(n_events, n_tracks)
+    return replace(w, name=f"barrel10_disk18_field_{n_events}x{n_tracks}",
+                   master_seed=0x5EED000B, field=solenoid_field())
 
 
 def small_barrel() -> Workload:
