@@ -172,6 +172,22 @@ typedef struct {
   float k_max;       /* cap on the path factor, >= 1 */
 } mkf_material_info;
 
+/* Parameterised field (Section 2.1: a constant or a parameterised field,
+ * selectable per propagation): Bz(r, z) = b0 (1 + c_r2 r^2 + c_z2 z^2 +
+ * c_z4 z^4) tesla (r, z in cm); the radial component is neglected, so pT and
+ * theta are constants of the motion and the azimuth turns at the local
+ * curvature.  Crossings come from fourth-order Runge-Kutta steps of at most
+ * h_max cm of transverse path (a disk's path is exact; a barrel's last step
+ * is cut by Newton iterations), within half a turn and 1000 cm; the
+ * transport Jacobian is the helix's with the path's mean curvature. */
+typedef struct {
+  float b0;          /* T, != 0 */
+  float c_r2;        /* cm^-2 */
+  float c_z2;        /* cm^-2 */
+  float c_z4;        /* cm^-4 */
+  float h_max;       /* cm, 0.01..100 */
+} mkf_field;
+
 /* Tolerances of the seed cleaning (mkf_clean_seeds). */
 typedef struct {
   float tol_ipt; /* q/pT, relative to the larger of the two */
@@ -205,6 +221,14 @@ mkf_status mkf_load_geometry(mkf_ctx *ctx, const mkf_layer *layers, int32_t n_la
  * returns MKF_E_ARG while a map is loaded. */
 mkf_status mkf_load_material(mkf_ctx *ctx, const mkf_material_info *info, const float *x_x0,
                              const float *xi);
+
+/* Parameterised field: f copied; NULL returns to the uniform cfg.bz.  Used
+ * by every later call that propagates: mkf_seed (the seed momentum takes the
+ * field at the middle hit; plans), mkf_find, mkf_fit, mkf_backward_fit,
+ * mkf_smooth, mkf_propagate.  Not by mkf_make_seeds (its cuts take the
+ * uniform cfg.bz) nor the surrogate, whose form mkf_find refuses while a
+ * field is loaded.  MKF_E_ARG for bad values. */
+mkf_status mkf_load_field(mkf_ctx *ctx, const mkf_field *f);
 
 /* Region steering (Section 2.1): n_regions (0..MKF_MAX_REGIONS) records,
  * host memory, copied.  Layer ids refer to the loaded geometry, so load it

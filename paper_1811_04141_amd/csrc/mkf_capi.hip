@@ -63,6 +63,7 @@ struct mkf_ctx {
   DevBuf d_regions;
   DevMat mat{};       // material map (mat.tab == nullptr: constant angle)
   DevBuf d_mat;
+  DevField field{};   // parameterised field (field.on == 0: uniform bz)
 
   // hits
   int n_events = 0;
@@ -164,6 +165,7 @@ FindParams params(mkf_ctx *c) {
   P.n_layers = c->n_layers;
   P.cfg = dev_cfg(c->cfg);
   P.cfg.mat = c->mat;
+  P.cfg.field = c->field;
   P.n_events = c->n_events;
   P.ev_off = c->d_ev_off.as<int64_t>();
   P.hx = c->d_x.as<float>();
@@ -453,6 +455,30 @@ mkf_status mkf_load_material(mkf_ctx *c, const mkf_material_info *info, const fl
   m.mass = info->mass;
   m.k_max = info->k_max;
   c->mat = m;
+  drop_graph(c);
+  return MKF_OK;
+}
+
+mkf_status mkf_load_field(mkf_ctx *c, const mkf_field *f) {
+  if (!c) return MKF_E_ARG;
+  if (!f) {
+    c->field = DevField{};
+    drop_graph(c);
+    return MKF_OK;
+  }
+  if (!finite_f(f->b0) || f->b0 == 0.f || !finite_f(f->c_r2) || !finite_f(f->c_z2) ||
+      !finite_f(f->c_z4))
+    return fail(c, MKF_E_ARG, "field: coefficients must be finite and b0 != 0");
+  if (!finite_f(f->h_max) || !(f->h_max >= 0.01f) || !(f->h_max <= 100.f))
+    return fail(c, MKF_E_ARG, "field: h_max must lie in [0.01, 100] cm");
+  DevField d{};
+  d.on = 1;
+  d.kb0 = -c->cfg.kappa * f->b0;
+  d.c_r2 = f->c_r2;
+  d.c_z2 = f->c_z2;
+  d.c_z4 = f->c_z4;
+  d.h_max = f->h_max;
+  c->field = d;
   drop_graph(c);
   return MKF_OK;
 }
@@ -790,8 +816,8 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
 mkf_status mkf_find(mkf_ctx *c) {
   if (!c) return MKF_E_ARG;
   if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
-  if ((c->cfg.flags & MKF_F_SURROGATE) && c->mat.tab)
-    return fail(c, MKF_E_ARG, "the surrogate form has no material-map variant");
+  if ((c->cfg.flags & MKF_F_SURROGATE) && (c->mat.tab || c->field.on))
+    return fail(c, MKF_E_ARG, "the surrogate form has no material-map or field variant");
   FindParams P = params(c);
   int launches = 0;
   const bool graph = (c->cfg.flags & MKF_F_GRAPH) != 0;
@@ -912,6 +938,7 @@ mkf_status mkf_fit(mkf_ctx *c, int64_t n_tracks, int32_t n_steps, const int8_t *
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   DevCfg fcfg = dev_cfg(c->cfg);
   fcfg.mat = c->mat;
+  fcfg.field = c->field;
   launch_fit(c->stream, fcfg, n_tracks, n_steps, kind, pos, x, y, z, var_u, var_v, len,
              init_par, init_cov, out_par, out_cov, out_chi2, out_status);
   HIP_TRY(c, hipGetLastError());

@@ -51,6 +51,14 @@ struct DevMat {
   float k_max;
 };
 
+// Parameterised axial field: omega = kb0 (1 + c_r2 r^2 + c_z2 z^2 +
+// c_z4 z^4) (q/pT), kb0 = -kappa b0; Runge-Kutta steps of at most h_max.
+struct DevField {
+  int on;
+  float kb0, c_r2, c_z2, c_z4;
+  float h_max;
+};
+
 struct DevCfg {
   float mkb;        // -kappa * B: omega = mkb * (q/pT)
   float chi2_cut;
@@ -61,6 +69,7 @@ struct DevCfg {
   int max_holes;
   float init_var[6];
   DevMat mat;
+  DevField field;
 };
 
 
@@ -183,6 +192,102 @@ struct PropT {
 };
 using Prop = PropT<float>;
 
+// -kappa Bz at (x, y, z) of the parameterised field
+template <typename T>
+__device__ __forceinline__ T field_mkb(const DevField &f, T x, T y, T z) {
+  const T r2 = x * x + y * y, z2 = z * z;
+  return T(f.kb0) * (T(1) + T(f.c_r2) * r2 + T(f.c_z2) * z2 + T(f.c_z4) * z2 * z2);
+}
+
+// One classical Runge-Kutta step of transverse length h of (x, y, z, phi)
+// in the axial field (pT and theta constant; phi turns at the local
+// curvature).
+template <typename T>
+__device__ __forceinline__ void rk4_field(const DevField &f, T ipt, T cot, const T *y, T h,
+                                          T *out) {
+  T k[4][4], t[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const T a = st == 0 ? T(0) : (st == 3 ? h : T(0.5) * h);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = st == 0 ? y[i] : fma_t(a, k[st - 1][i], y[i]);
+    T sp, cp;
+    sincos_t(t[3], &sp, &cp);
+    k[st][0] = cp;
+    k[st][1] = sp;
+    k[st][2] = cot;
+    k[st][3] = field_mkb(f, t[0], t[1], t[2]) * ipt;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    out[i] = y[i] + h / T(6) * (k[0][i] + T(2) * k[1][i] + T(2) * k[2][i] + k[3][i]);
+}
+
+constexpr float kFieldMaxPath = 1000.f;  // cm of transverse path searched
+
+// Crossing of layer L in the parameterised field: on a disk, equal steps to
+// the exact path (Z - z) tan(theta); on a barrel, steps of h_max until
+// r^2 - R^2 changes sign, then Newton iterations on the last step's length.
+// The turning stays below half a turn, the path below kFieldMaxPath.
+// y: the end point (x, y, z, phi unwrapped).
+template <typename T>
+__device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T sth, T cth,
+                                               const DevLayer &L, T l_min, T &l, T *y) {
+  const T cot = cth / sth;
+  y[0] = p[0];
+  y[1] = p[1];
+  y[2] = p[2];
+  y[3] = p[4];
+  const T pos = T(L.pos);
+  const T h_max = T(f.h_max);
+  if (L.kind == 1) {
+    if (cth == T(0)) return false;
+    const T lt = (pos - p[2]) * sth / cth;
+    if (!(lt > l_min) || lt > T(kFieldMaxPath)) return false;
+    const int n = (int)ceil(lt / h_max);
+    const T h = lt / T(n);
+    for (int k = 0; k < n; ++k) {
+      rk4_field(f, p[3], cot, y, h, y);
+      if (abs_t(y[3] - p[4]) >= Consts<T>::pi()) return false;
+    }
+    y[2] = pos;
+    l = lt;
+    return true;
+  }
+  const T R2 = pos * pos;
+  T g = y[0] * y[0] + y[1] * y[1] - R2, lacc = T(0);
+  for (;;) {
+    T yn[4];
+    rk4_field(f, p[3], cot, y, h_max, yn);
+    const T gn = yn[0] * yn[0] + yn[1] * yn[1] - R2;
+    if ((g < T(0)) != (gn < T(0)) || gn == T(0)) {
+      T s = g == gn ? h_max : h_max * g / (g - gn), ys[4];
+      for (int it = 0; it < 6; ++it) {
+        rk4_field(f, p[3], cot, y, s, ys);
+        T sp, cp;
+        sincos_t(ys[3], &sp, &cp);
+        const T gs = ys[0] * ys[0] + ys[1] * ys[1] - R2;
+        const T gp = T(2) * (ys[0] * cp + ys[1] * sp);
+        if (gp == T(0)) break;
+        s -= gs / gp;
+      }
+      rk4_field(f, p[3], cot, y, s, ys);
+      if (lacc + s > l_min && abs_t(ys[3] - p[4]) < Consts<T>::pi()) {
+        l = lacc + s;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = ys[i];
+        return true;
+      }
+    }
+    if (abs_t(yn[3] - p[4]) >= Consts<T>::pi()) return false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = yn[i];
+    g = gn;
+    lacc += h_max;
+    if (lacc > T(kFieldMaxPath)) return false;
+  }
+}
+
 // Exact helix transport by l, surface polish, extent test, and the
 // surface-constrained covariance transport C' = F C F^T with
 // F = (I - t n^T / (n^T t)) D (D: d p'/d p at fixed l; t = d p'/dl; n: the
@@ -201,12 +306,18 @@ using Prop = PropT<float>;
 //
 // kWantFC: fc receives F C, 6x6 row-major (the cross-covariance of the
 // start and end states, which smoothing needs).
+//
+// fld (if given and on): the parameterised field.  The crossing and the end
+// point come from Runge-Kutta steps (field_crossing); the Jacobian is the
+// helix's with the path's mean curvature (the turning over the path), whose
+// end direction is the stepped one.
 template <bool kWantCov, typename T, bool kWantFC = false>
 __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__restrict__ c,
                                          const DevLayer &L, T mkb, T l_min, bool check_extent,
                                          T edge_margin, PropT<T> &o, T l_hint = T(0),
-                                         int *sur = nullptr, T *fc = nullptr) {
-  const T w = mkb * p[3];
+                                         int *sur = nullptr, T *fc = nullptr,
+                                         const DevField *fld = nullptr) {
+  T w = mkb * p[3];
   T sphi, cphi;
   sincos_t(p[4], &sphi, &cphi);
   T sth, cth;
@@ -215,7 +326,13 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   const T pos = T(L.pos);
   T l;
   bool hinted = false;
-  if (L.kind == 0) {
+  const bool stepped = fld != nullptr && fld->on;
+  T yf[4];
+  if (stepped) {
+    if (!field_crossing(*fld, p, sth, cth, L, l_min, l, yf)) return kNoCrossing;
+    w = (yf[3] - p[4]) / l;
+    mkb = p[3] != T(0) ? w / p[3] : mkb;
+  } else if (L.kind == 0) {
     if (l_hint > T(0)) {
       T hs, hc;
       const T hh = T(0.5) * w * l_hint;
@@ -257,6 +374,11 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   T x1 = fma_t(Lc, cpsi, p[0]);
   T y1 = fma_t(Lc, spsi, p[1]);
   T z1 = fma_t(l, cot, p[2]);
+  if (stepped) {  // the stepped end point, on the mean-curvature helix's end direction
+    x1 = yf[0];
+    y1 = yf[1];
+    z1 = yf[2];
+  }
   // one Newton step along the track removes the rounding of the closed form
   // (a kept surrogate path has had its Newton step already)
   if (L.kind == 0 && !hinted) {

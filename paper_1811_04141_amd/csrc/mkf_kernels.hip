@@ -329,11 +329,12 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   Prop pr;
   int st = kNoCrossing;
   if (cd.active)
-    st = propagate<true>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr,
-                         l_hint, sur);
+    st = propagate<true, float>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr,
+                         l_hint, sur, nullptr, kMat ? &P.cfg.field : nullptr);
   const bool ok = cd.active && st == kOk;
-  // kMat: the material map's effects (a separate instantiation, so that the
-  // constant-angle form keeps its register allocation)
+  // kMat: the material map's effects and the parameterised field (a separate
+  // instantiation, so that the constant-angle uniform-field form keeps its
+  // register allocation)
   if (ok) {
     if constexpr (kMat) material<float>(P.cfg, L.kind, pr.p, pr.c, 1.f, nullptr, nullptr, mtab);
     else add_ms(pr.p, P.cfg.ms_var, pr.c);
@@ -641,7 +642,8 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
 // (one wave-wide matrix-core inference per layer step, then one exact Newton
 // step per lane, falling back to the closed form when it does not converge).
 // G: lanes per seed (8, or 6 for candidate budgets up to 6).
-// kMat: with the material map (constant scattering angle otherwise).
+// kMat: with the material map and/or the parameterised field (constant
+// scattering angle and uniform field otherwise).
 template <int kWaves, bool kSurr, int G, bool kMat>
 __device__ __forceinline__ void find_persistent(const FindParams &P) {
   __shared__ DevLayer sl[kMaxLayers];
@@ -658,7 +660,7 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
   const float2 *mtab = nullptr;
   if constexpr (kMat) {
     const int nb = P.cfg.mat.nr * P.cfg.mat.nz;
-    if (nb <= kMatLds) {
+    if (P.cfg.mat.tab && nb <= kMatLds) {
       for (int i = threadIdx.x; i < nb; i += blockDim.x) sMat[i] = P.cfg.mat.tab[i];
       mtab = sMat;
     }
@@ -911,8 +913,11 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     const double rho = sqrt(ux * ux + uy * uy);
     const double turn = (hx[1] - hx[0]) * (hy[2] - hy[1]) - (hy[1] - hy[0]) * (hx[2] - hx[1]);
     const bool ccw = turn > 0.0;  // omega > 0
-    // omega = mkb * ipt and |omega| = 1/rho
-    const double ipt = (ccw ? 1.0 : -1.0) / (mkb * rho);
+    // omega = mkb * ipt and |omega| = 1/rho; a parameterised field is taken
+    // at the middle hit
+    const double mkb_s = P.cfg.field.on ? field_mkb(P.cfg.field, hx[1], hy[1], hz[1]) : mkb;
+    if (mkb_s == 0.0) break;
+    const double ipt = (ccw ? 1.0 : -1.0) / (mkb_s * rho);
     const double r1x = hx[0] - cx, r1y = hy[0] - cy;
     const double dirx = ccw ? -r1y : r1y, diry = ccw ? r1x : -r1x;
     const double phi1 = atan2(diry, dirx);
@@ -927,7 +932,8 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
       const DevLayer &L = sl[hl[k]];
       if (k > 0) {
         PropT<double> pr;
-        if (propagate<true, double>(p, c, L, mkb, l_min, false, 0.0, pr) != kOk) {
+        if (propagate<true, double>(p, c, L, mkb, l_min, false, 0.0, pr, 0.0, nullptr, nullptr,
+                                    &P.cfg.field) != kOk) {
           good = false;
           break;
         }
@@ -967,7 +973,8 @@ __global__ __launch_bounds__(256) void k_seed(FindParams P, const int *seed_hits
     for (int L = 0; L < P.n_layers; ++L) {
       if (L == hl[0] || L == hl[1] || L == hl[2]) continue;
       PropT<double> pr;
-      if (propagate<false, double>(p, nullptr, sl[L], mkb, l_min, true, edge, pr) != kOk)
+      if (propagate<false, double>(p, nullptr, sl[L], mkb, l_min, true, edge, pr, 0.0, nullptr,
+                                   nullptr, &P.cfg.field) != kOk)
         continue;
       if (n >= kMaxPlan) break;
       const double lf = pr.l;
@@ -1450,8 +1457,9 @@ __global__ __launch_bounds__(256) void k_propagate(FindParams P, int64_t n, cons
   Prop pr;
   const int st = (lid < 0 || lid >= P.n_layers)
                      ? 3
-                     : propagate<true>(p, c, sl[lid], P.cfg.mkb, P.cfg.l_min, true,
-                                       P.cfg.edge_margin, pr);
+                     : propagate<true, float>(p, c, sl[lid], P.cfg.mkb, P.cfg.l_min, true,
+                                       P.cfg.edge_margin, pr, 0.f, nullptr, nullptr,
+                                       &P.cfg.field);
   out_status[i] = st;
   for (int k = 0; k < 6; ++k) out_par[i * 6 + k] = st == kOk ? pr.p[k] : 0.f;
   for (int k = 0; k < 21; ++k) out_cov[i * 21 + k] = st == kOk ? pr.c[k] : 0.f;
@@ -1485,7 +1493,8 @@ __global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
     L.lo = 0.f;
     L.hi = 0.f;
     Prop pr;
-    if (propagate<true>(p, c, L, cfg.mkb, cfg.l_min, false, 0.f, pr) != kOk) {
+    if (propagate<true, float>(p, c, L, cfg.mkb, cfg.l_min, false, 0.f, pr, 0.f, nullptr, nullptr,
+                        &cfg.field) != kOk) {
       status = s + 1;
       break;
     }
@@ -1556,7 +1565,8 @@ __device__ __forceinline__ bool backfit_surface(const FindParams &P, const DevLa
   } else {
     flip_state(p, c);
     PropT<T> pr;
-    if (propagate<true, T>(p, c, L, T(P.cfg.mkb), T(P.cfg.l_min), false, T(0), pr) != kOk)
+    if (propagate<true, T>(p, c, L, T(P.cfg.mkb), T(P.cfg.l_min), false, T(0), pr, T(0), nullptr,
+                           nullptr, &P.cfg.field) != kOk)
       return false;
 #pragma unroll
     for (int m = 0; m < 6; ++m) p[m] = pr.p[m];
@@ -1787,7 +1797,7 @@ __global__ __launch_bounds__(256) void k_smooth_fwd(FindParams P, const int *see
       Prop pr;
       float fc[36];
       if (propagate<true, float, true>(p, c, L, P.cfg.mkb, P.cfg.l_min, false, 0.f, pr, 0.f,
-                                       nullptr, fc) != kOk) {
+                                       nullptr, fc, &P.cfg.field) != kOk) {
         n = -1;
         break;
       }
@@ -2098,7 +2108,8 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
   if (n_active == 0) return;
   const unsigned nb = blocks_for(n_active * kGroup, 256);
   const unsigned grid = (nb + kQueues - 1) / kQueues * kQueues;  // whole XCD shares
-  if (P.cfg.mat.tab) hipLaunchKernelGGL(k_find_step<true>, dim3(grid), dim3(256), 0, s, P, step, n_active);
+  if (P.cfg.mat.tab || P.cfg.field.on)
+    hipLaunchKernelGGL(k_find_step<true>, dim3(grid), dim3(256), 0, s, P, step, n_active);
   else hipLaunchKernelGGL(k_find_step<false>, dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
@@ -2136,7 +2147,7 @@ static void launch_persistent_mat(hipStream_t s, const FindParams &P, int grid, 
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
                             bool surrogate) {
   if (P.n_seeds == 0) return;
-  if (P.cfg.mat.tab) launch_persistent_mat(s, P, grid_blocks, waves);
+  if (P.cfg.mat.tab || P.cfg.field.on) launch_persistent_mat(s, P, grid_blocks, waves);
   else if (surrogate) launch_persistent_t<true>(s, P, grid_blocks, waves);
   else launch_persistent_t<false>(s, P, grid_blocks, waves);
 }

@@ -24,7 +24,7 @@ MAX_REGIONS = 8
 HIT_MISS, HIT_SKIP, HIT_NONE = -1, -2, -3
 
 EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry",
-           "mkf_load_steering", "mkf_load_material", "mkf_load_hits",
+           "mkf_load_steering", "mkf_load_material", "mkf_load_field", "mkf_load_hits",
            "mkf_seed", "mkf_get_seed_states", "mkf_find", "mkf_get_tracks", "mkf_propagate",
            "mkf_fit", "mkf_backward_fit", "mkf_smooth", "mkf_make_seeds", "mkf_clean_seeds",
            "mkf_find_duplicates",
@@ -103,6 +103,11 @@ class MaterialInfo(C.Structure):
                 ("z_max", C.c_float), ("mass", C.c_float), ("k_max", C.c_float)]
 
 
+class Field(C.Structure):
+    _fields_ = [("b0", C.c_float), ("c_r2", C.c_float), ("c_z2", C.c_float),
+                ("c_z4", C.c_float), ("h_max", C.c_float)]
+
+
 class Cleaning(C.Structure):
     _fields_ = [("tol_ipt", C.c_float), ("tol_eta", C.c_float), ("tol_phi", C.c_float)]
 
@@ -141,6 +146,7 @@ def _load():
         "mkf_load_geometry": ([P, C.POINTER(Layer), I32], I32),
         "mkf_load_steering": ([P, C.POINTER(Region), I32], I32),
         "mkf_load_material": ([P, C.POINTER(MaterialInfo), P, P], I32),
+        "mkf_load_field": ([P, C.POINTER(Field)], I32),
         "mkf_load_hits": ([P, I32, P, P, P, P, P, P, P, I32], I32),
         "mkf_seed": ([P, I64, P, P, I32], I32),
         "mkf_get_seed_states": ([P, P, P, P, P, P, P], I32),
@@ -263,6 +269,15 @@ class Context:
         if t.size != info.n_r * info.n_z or x.size != t.size:
             raise ValueError("material tables must hold n_z x n_r bins")
         self._check(lib.mkf_load_material(self.h, C.byref(info), t.ctypes.data, x.ctypes.data))
+
+    def load_field(self, fd):
+        """Parameterised field (an object with b0, c_r2, c_z2, c_z4, h_max), or
+        None for the uniform field of the settings."""
+        if fd is None:
+            self._check(lib.mkf_load_field(self.h, None))
+            return
+        f = Field(float(fd.b0), float(fd.c_r2), float(fd.c_z2), float(fd.c_z4), float(fd.h_max))
+        self._check(lib.mkf_load_field(self.h, C.byref(f)))
 
     def load_hits(self, ev_off, x, y, z, var_u, var_v, layer):
         ev_off = np.ascontiguousarray(ev_off, np.int64)

@@ -40,6 +40,7 @@ def test_struct_layouts_match_header():
     # mkf_region: eta bounds, a count and MKF_MAX_PLAN layer ids
     assert C.sizeof(mkf.Region) == 4 * 3 + 4 * 32
     assert C.sizeof(mkf.MaterialInfo) == 4 * 6
+    assert C.sizeof(mkf.Field) == 4 * 5
 
 
 def test_host_side_argument_errors():
@@ -67,6 +68,7 @@ def test_host_side_argument_errors():
     assert lib.mkf_clean_seeds(None, None, None, None) == mkf.MKF_E_ARG
     assert lib.mkf_load_steering(None, None, 0) == mkf.MKF_E_ARG
     assert lib.mkf_load_material(None, None, None, None) == mkf.MKF_E_ARG
+    assert lib.mkf_load_field(None, None) == mkf.MKF_E_ARG
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
