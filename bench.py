@@ -108,8 +108,9 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
     (131,072 tracks x 26 layers), the backward fit and the smoothing of the
     benchmark workload's found tracks, triplet seeding with cleaning, find and
     duplicate removal on it, the find with a material map and with region
-    steering, and the surrogate network's inference and gradient (2^20
-    samples from its training sampler)."""
+    steering, the find in a parameterised field (events simulated in it),
+    and the surrogate network's inference and gradient (2^20 samples from
+    its training sampler)."""
     import numpy as np
     import torch
 
@@ -237,6 +238,32 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
             out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
                           "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
                           "unit": "candidate-layer updates/s", "workload": w.name}
+        # the batched find in the solenoid-like parameterised field (Runge-Kutta
+        # crossings) on events of the benchmark's sizes simulated in that
+        # field, against the uniform-field find on the same events
+        from synth import barrel_endcap_field, generate as gen
+        wf = barrel_endcap_field(w.n_events, w.n_tracks[0])
+        bf = gen(wf, workers=min(16, os.cpu_count() or 1))
+        fh = [T(a) for a in (bf.x, bf.y, bf.z, bf.var_u, bf.var_v, bf.layer)]
+        fs = (T(bf.seed_event), T(bf.seed_hits))
+        for label, fld in (("find_parameterised_field", wf.field),
+                           ("find_uniform_field_same_events", None)):
+            c5 = mkf.Context(wf.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+            c5.load_geometry(wf.layers)
+            c5.load_field(fld)
+            c5.load_hits(bf.ev_off, *fh)
+            c5.seed(*fs)
+            c5.find()
+            c5.find()
+            st = c5.stats()
+            n = int(bf.seed_hits.shape[0])
+            tr = c5.get_tracks(n)
+            c5.close()
+            out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
+                          "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
+                          "unit": "candidate-layer updates/s", "workload": wf.name,
+                          "mean_hits_per_track": float(tr["n_hits"].mean())}
+        del fh, fs, bf
         m = 1 << 20
         x = torch.zeros((m, 8), device=dev)
         t = torch.zeros((m, 7), device=dev)
