@@ -203,6 +203,7 @@ static void rk4(const orc_field *f, double kappa, double ipt, double cot, const 
 }
 
 #define ORC_FIELD_MAX_STEPS 4096
+#define ORC_FIELD_MAX_PATH 1000.0 /* cm of transverse path searched */
 
 /* Crossing of a layer in the parameterised field: path l and the end
  * point y = (x, y, z, phi unwrapped). */
@@ -213,7 +214,7 @@ static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, 
   if (Lr->kind == 1) {
     if (cos(p[5]) == 0.0) return ORC_NO_CROSSING;
     double lt = (Lr->pos - p[2]) * sin(p[5]) / cos(p[5]);
-    if (!(lt > l_min)) return ORC_NO_CROSSING;
+    if (!(lt > l_min) || lt > ORC_FIELD_MAX_PATH) return ORC_NO_CROSSING;
     int n = (int)ceil(lt / f->h_max);
     if (n > ORC_FIELD_MAX_STEPS) return ORC_NO_CROSSING;
     double h = lt / n;
@@ -235,7 +236,7 @@ static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, 
     if ((g < 0.0) != (gn < 0.0) || gn == 0.0) {
       /* Newton on the step length s from the bracket's start */
       double s = g == gn ? f->h_max : f->h_max * g / (g - gn), ys[4];
-      for (int it = 0; it < 6; ++it) {
+      for (int it = 0; it < 3; ++it) {
         rk4(f, kappa, p[3], cot, y, s, ys);
         double gs = ys[0] * ys[0] + ys[1] * ys[1] - R2;
         double gp = 2.0 * (ys[0] * cos(ys[3]) + ys[1] * sin(ys[3]));
@@ -253,6 +254,7 @@ static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, 
     memcpy(y, yn, sizeof(yn));
     g = gn;
     l += f->h_max;
+    if (l > ORC_FIELD_MAX_PATH) return ORC_NO_CROSSING;
   }
   return ORC_NO_CROSSING;
 }

@@ -129,8 +129,8 @@ int orc_propagate(const double p[6], const double C[36], const orc_layer *L,
 /* The same in the parameterised field fld (NULL: the uniform bz).  The
  * crossing is found by Runge-Kutta steps: on a disk, equal steps to the
  * exact path (Z - z) tan(theta); on a barrel, steps of h_max until r^2 - R^2
- * changes sign, then Newton iterations on the last step's length.  The
- * turning must stay below half a turn.  The Jacobian is that of the helix
+ * changes sign, then three Newton iterations on the last step's length.  The
+ * turning must stay below half a turn and the path below 1000 cm.  The Jacobian is that of the helix
  * with the path's mean curvature (the turning over the path length), made
  * surface-constrained at the end point. */
 int orc_propagate_f(const double p[6], const double C[36], const orc_layer *Lr,

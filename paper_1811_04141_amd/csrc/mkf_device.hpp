@@ -227,7 +227,7 @@ constexpr float kFieldMaxPath = 1000.f;  // cm of transverse path searched
 
 // Crossing of layer L in the parameterised field: on a disk, equal steps to
 // the exact path (Z - z) tan(theta); on a barrel, steps of h_max until
-// r^2 - R^2 changes sign, then Newton iterations on the last step's length.
+// r^2 - R^2 changes sign, then three Newton iterations on the last step's length.
 // The turning stays below half a turn, the path below kFieldMaxPath.
 // y: the end point (x, y, z, phi unwrapped).
 template <typename T>
@@ -262,7 +262,7 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
     const T gn = yn[0] * yn[0] + yn[1] * yn[1] - R2;
     if ((g < T(0)) != (gn < T(0)) || gn == T(0)) {
       T s = g == gn ? h_max : h_max * g / (g - gn), ys[4];
-      for (int it = 0; it < 6; ++it) {
+      for (int it = 0; it < 3; ++it) {
         rk4_field(f, p[3], cot, y, s, ys);
         T sp, cp;
         sincos_t(ys[3], &sp, &cp);
