@@ -188,6 +188,7 @@ struct PropT {
   T p[6];
   T c[21];
   T l;
+  T sth, cth;  // sin, cos of theta (unchanged by the transport)
   int status;
 };
 using Prop = PropT<float>;
@@ -411,6 +412,8 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   o.p[4] = wrap_phi(fma_t(w, l, p[4]));
   o.p[5] = p[5];
   o.l = l;
+  o.sth = sth;
+  o.cth = cth;
   o.status = kOk;
   if (!kWantCov) return kOk;
 
@@ -539,6 +542,17 @@ __device__ __forceinline__ void surface_prior(const DevCfg &cfg, const T *p, int
 // Scattering noise of one crossed layer, added to the (q/pT, phi, theta)
 // block: two independent deflections of variance sigma^2 perpendicular to
 // the momentum with |p| fixed.
+// (sth, cth: sin and cos of theta, where the caller has them)
+template <typename T>
+__device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c, T sth, T cth) {
+  if (ms_var == T(0)) return;
+  const T a = p[3] * cth / sth;
+  c[tri(3, 3)] += a * a * ms_var;
+  c[tri(3, 5)] -= a * ms_var;
+  c[tri(4, 4)] += ms_var / (sth * sth);
+  c[tri(5, 5)] += ms_var;
+}
+
 template <typename T>
 __device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c) {
   if (ms_var == T(0)) return;

@@ -337,7 +337,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   // register allocation)
   if (ok) {
     if constexpr (kMat) material<float>(P.cfg, L.kind, pr.p, pr.c, 1.f, nullptr, nullptr, mtab);
-    else add_ms(pr.p, P.cfg.ms_var, pr.c);
+    else add_ms(pr.p, P.cfg.ms_var, pr.c, pr.sth, pr.cth);
   }
 
   u64 lst[G];  // this lane's best extensions (G >= n_cand)
