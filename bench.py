@@ -91,8 +91,12 @@ def cpu_baseline(w, batch, seconds, workers):
         out = [_oracle_share(jobs[0])]
     else:
         import multiprocessing as mp
-        with mp.get_context("spawn").Pool(n) as pool:
+        pool = mp.get_context("spawn").Pool(n)
+        try:
             out = pool.map(_oracle_share, jobs, chunksize=1)
+        finally:
+            pool.close()  # the workers exit on their own
+            pool.join()
     steps = sum(o[0] for o in out)
     t = max(o[1] for o in out)
     seeds = sum(o[2] for o in out)
@@ -239,11 +243,18 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
                           "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
                           "unit": "candidate-layer updates/s", "workload": w.name}
         # the batched find in the solenoid-like parameterised field (Runge-Kutta
-        # crossings) on events of the benchmark's sizes simulated in that
-        # field, against the uniform-field find on the same events
-        from synth import barrel_endcap_field, generate as gen
-        wf = barrel_endcap_field(w.n_events, w.n_tracks[0])
-        bf = gen(wf, workers=min(16, os.cpu_count() or 1))
+        # crossings) on 20 events of 5,000 tracks simulated in that field
+        # (generated here, in this process), against the uniform-field find
+        # on the same events
+        from synth import barrel_endcap_field, generate_event, make_batch
+        wf = barrel_endcap_field(20, w.n_tracks[0])
+        evs = []
+        for e in range(wf.n_events):
+            evs.append(generate_event(wf, e))
+            if e % 5 == 4:
+                log(f"field events generated: {e + 1}/{wf.n_events}")
+        bf = make_batch(evs)
+        del evs
         fh = [T(a) for a in (bf.x, bf.y, bf.z, bf.var_u, bf.var_v, bf.layer)]
         fs = (T(bf.seed_event), T(bf.seed_hits))
         for label, fld in (("find_parameterised_field", wf.field),

@@ -539,8 +539,13 @@ def generate(w: Workload, events=None, workers: int = 1) -> EventBatch:
     events = list(events)
     if workers > 1 and len(events) > 1:
         import multiprocessing as mp
-        with mp.get_context("spawn").Pool(workers) as pool:
+        pool = mp.get_context("spawn").Pool(workers)
+        try:
             evs = pool.map(_gen_one, [(w, e) for e in events], chunksize=1)
+        finally:
+            # let the workers exit on their own (no terminate signal)
+            pool.close()
+            pool.join()
     else:
         evs = [generate_event(w, e) for e in events]
     return make_batch(evs)
