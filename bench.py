@@ -243,15 +243,15 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
                           "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
                           "unit": "candidate-layer updates/s", "workload": w.name}
         # the batched find in the solenoid-like parameterised field (Runge-Kutta
-        # crossings) on 20 events of 5,000 tracks simulated in that field
-        # (generated here, in this process), against the uniform-field find
-        # on the same events
+        # crossings) on events of the benchmark's sizes simulated in that field
+        # (generated here, in this process: ~1.6 s per event), against the
+        # uniform-field find on the same events
         from synth import barrel_endcap_field, generate_event, make_batch
-        wf = barrel_endcap_field(20, w.n_tracks[0])
+        wf = barrel_endcap_field(w.n_events, w.n_tracks[0])
         evs = []
         for e in range(wf.n_events):
             evs.append(generate_event(wf, e))
-            if e % 5 == 4:
+            if e % 10 == 9:
                 log(f"field events generated: {e + 1}/{wf.n_events}")
         bf = make_batch(evs)
         del evs
