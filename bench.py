@@ -223,8 +223,8 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         ctx3.close()
         # the batched find with a silicon-like material map (1.5% of a
         # radiation length and 0.1 g/cm^2 per layer, 1.5x beyond |z| = 50 cm)
-        # and with five-region steering, from the same seeds (the autotuned
-        # launch shape of the constant-angle kernel; mkf_get_stats timing)
+        # and with five-region steering, from the same seeds (each autotuned;
+        # mkf_get_stats timing)
         from synth import five_regions, material_map
         variants = (("find_material_map",
                      lambda c: c.load_material(material_map(120.0, 300.0, 24, 30, 0.015, 0.1))),
@@ -235,13 +235,15 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
             setup(c4)
             c4.load_hits(batch.ev_off, *hits)
             c4.seed(*seeds)
+            tun4 = c4.autotune(repeats=2)
             c4.find()
             c4.find()
             st = c4.stats()
             c4.close()
             out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
                           "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
-                          "unit": "candidate-layer updates/s", "workload": w.name}
+                          "unit": "candidate-layer updates/s", "workload": w.name,
+                          "tuning": tun4}
         # the batched find in the solenoid-like parameterised field (Runge-Kutta
         # crossings) on events of the benchmark's sizes simulated in that field
         # (generated here, in this process: ~1.6 s per event), against the
@@ -264,6 +266,7 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
             c5.load_field(fld)
             c5.load_hits(bf.ev_off, *fh)
             c5.seed(*fs)
+            tun5 = c5.autotune(repeats=2)
             c5.find()
             c5.find()
             st = c5.stats()
@@ -273,7 +276,7 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
             out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
                           "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
                           "unit": "candidate-layer updates/s", "workload": wf.name,
-                          "mean_hits_per_track": float(tr["n_hits"].mean())}
+                          "mean_hits_per_track": float(tr["n_hits"].mean()), "tuning": tun5}
         del fh, fs, bf
         m = 1 << 20
         x = torch.zeros((m, 8), device=dev)

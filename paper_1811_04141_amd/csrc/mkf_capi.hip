@@ -1135,12 +1135,15 @@ mkf_status mkf_autotune(mkf_ctx *c, int32_t repeats, const char *cache_path, mkf
   if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
   if (!(c->cfg.flags & MKF_F_BATCHED)) return fail(c, MKF_E_ARG, "autotune needs MKF_F_BATCHED");
   if (repeats < 1) return fail(c, MKF_E_ARG, "repeats must be >= 1");
-  // workload key: architecture, compute units, candidate budget, sizes
+  // workload key: architecture, compute units, kernel form, candidate
+  // budget, sizes
   int lg = 0;
   while (((int64_t)1 << (lg + 1)) <= c->n_seeds) ++lg;
+  const char *form = (c->mat.tab || c->field.on) ? "extended"
+                     : (c->cfg.flags & MKF_F_SURROGATE) ? "surrogate" : "plain";
   char key[256];
-  snprintf(key, sizeof key, "%s cu%d cand%d seeds2^%d events%d layers%d",
-           c->arch.empty() ? "unknown" : c->arch.c_str(), c->n_cu, c->cfg.n_cand, lg,
+  snprintf(key, sizeof key, "%s cu%d %s cand%d seeds2^%d events%d layers%d",
+           c->arch.empty() ? "unknown" : c->arch.c_str(), c->n_cu, form, c->cfg.n_cand, lg,
            c->n_events, c->n_layers);
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "r")) {

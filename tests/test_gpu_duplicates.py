@@ -13,7 +13,7 @@ from synth import SeedingConfig, barrel_endcap, generate, generate_event, make_b
 
 pytestmark = pytest.mark.gpu
 
-WORKERS = 8  # event generation processes (the GPU machine has 16 CPUs)
+WORKERS = 8  # event generation processes (sized for a 16-CPU host)
 FRAC = 0.5
 
 torch = pytest.importorskip("torch")

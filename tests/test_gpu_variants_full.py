@@ -13,7 +13,7 @@ import parity as PT
 
 pytestmark = pytest.mark.gpu
 
-WORKERS = 8  # event generation processes (the GPU machine has 16 CPUs)
+WORKERS = 8  # event generation processes (sized for a 16-CPU host)
 MATERIAL = material_map(120.0, 300.0, 24, 30, 0.015, 0.1)
 
 torch = pytest.importorskip("torch")
