@@ -196,6 +196,9 @@ using Prop = PropT<float>;
 // -kappa Bz at (x, y, z) of the parameterised field
 template <typename T>
 __device__ __forceinline__ T field_mkb(const DevField &f, T x, T y, T z) {
+  // contraction within each expression only: the same rounding in every
+  // kernel that inlines this
+#pragma clang fp contract(on)
   const T r2 = x * x + y * y, z2 = z * z;
   return T(f.kb0) * (T(1) + T(f.c_r2) * r2 + T(f.c_z2) * z2 + T(f.c_z4) * z2 * z2);
 }
@@ -206,6 +209,7 @@ __device__ __forceinline__ T field_mkb(const DevField &f, T x, T y, T z) {
 template <typename T>
 __device__ __forceinline__ void rk4_field(const DevField &f, T ipt, T cot, const T *y, T h,
                                           T *out) {
+#pragma clang fp contract(on)
   T k[4][4], t[4];
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
@@ -234,6 +238,7 @@ constexpr float kFieldMaxPath = 1000.f;  // cm of transverse path searched
 template <typename T>
 __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T sth, T cth,
                                                const DevLayer &L, T l_min, T &l, T *y) {
+#pragma clang fp contract(on)
   const T cot = cth / sth;
   y[0] = p[0];
   y[1] = p[1];
@@ -569,6 +574,9 @@ __device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c) {
 // correction), GeV cm^2/g, at (beta gamma)^2 = bg2 for a particle of mass m.
 template <typename T>
 __device__ __forceinline__ T si_loss_rate(T bg2, T m) {
+  // contraction within each expression only: the same rounding in every
+  // kernel that inlines this
+#pragma clang fp contract(on)
   const T me = T(0.51099895e-3), r = div_fast(me, m);
   const T b2 = div_fast(bg2, T(1) + bg2), g = sqrt_t(T(1) + bg2);
   const T wmax = div_fast(T(2) * me * bg2, T(1) + T(2) * g * r + r * r);
@@ -593,6 +601,7 @@ template <typename T>
 __device__ __forceinline__ void material(const DevCfg &cfg, int kind, T *p, T *c, T dir,
                                          T *j33 = nullptr, T *j35 = nullptr,
                                          const float2 *tab = nullptr) {
+#pragma clang fp contract(on)
   if (j33) *j33 = T(1);
   if (j35) *j35 = T(0);
   const DevMat &M = cfg.mat;

@@ -96,8 +96,9 @@ def test_no_seeds_and_empty_plans(mkf):
 
 def test_longest_region_list_both_forms(mkf):
     """32 cylinders, one region listing all of them: plans of 29 layers.
-    With the extensions loaded the two forms are not bitwise equal; they
-    take the same hits and both match the oracle."""
+    With the extensions loaded the two forms are bitwise equal too (the
+    material and field arithmetic contracts within expressions only, so
+    every kernel that inlines it rounds alike) and match the oracle."""
     radii = np.linspace(3.0, 100.0, 32)
     layers = [Layer(BARREL, float(r), -200.0, 200.0, SIGMA_RPHI ** 2, SIGMA_Z ** 2) for r in radii]
     w = Workload(name="barrel32_1x400", layers=tuple(layers),
@@ -109,16 +110,12 @@ def test_longest_region_list_both_forms(mkf):
     a, sa, _, _ = run(mkf, w, b, st, flags=0)
     c, sc, _, _ = run(mkf, w, b, st, flags=mkf.F_BATCHED)
     assert a["plan_len"].max() == 29
-    assert sa["n_steps"] == sc["n_steps"]
-    same = np.mean([np.array_equal(x["hit"], y["hit"]) for x, y in zip(a, c)])
-    say("same hits in both forms", same)
-    assert same >= 0.99
+    assert sa["n_steps"] == sc["n_steps"] and a.tobytes() == c.tobytes()
     ev = b.events[0]
     rng = np.random.default_rng(5)
     pick = np.sort(rng.choice(len(ev.seeds), 100, replace=False))
     ref = O.find_event(w.find, w.layers, ev, seeds=ev.seeds[pick], steering=st,
                        material=ONE_BIN, field=FIELD)
-    for tr in (a, c):
-        out = PT.compare_tracks(tr[pick], ref, mkf.unpack_cov)
-        say({k: (v if k != "fail" else len(v)) for k, v in out.items()})
-        assert not out["fail"] and out["equal"] >= 0.9 * out["n"]
+    out = PT.compare_tracks(a[pick], ref, mkf.unpack_cov)
+    say({k: (v if k != "fail" else len(v)) for k, v in out.items()})
+    assert not out["fail"] and out["equal"] >= 0.9 * out["n"]
