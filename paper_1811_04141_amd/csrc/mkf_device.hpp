@@ -203,12 +203,12 @@ __device__ __forceinline__ T field_mkb(const DevField &f, T x, T y, T z) {
   return T(f.kb0) * (T(1) + T(f.c_r2) * r2 + T(f.c_z2) * z2 + T(f.c_z4) * z2 * z2);
 }
 
-// One classical Runge-Kutta step of transverse length h of (x, y, z, phi)
-// in the axial field (pT and theta constant; phi turns at the local
-// curvature).
+// The increment d of one classical Runge-Kutta step of transverse length h
+// of (x, y, z, phi) in the axial field (pT and theta constant; phi turns at
+// the local curvature).
 template <typename T>
 __device__ __forceinline__ void rk4_field(const DevField &f, T ipt, T cot, const T *y, T h,
-                                          T *out) {
+                                          T *d) {
 #pragma clang fp contract(on)
   T k[4][4], t[4];
 #pragma unroll
@@ -225,7 +225,21 @@ __device__ __forceinline__ void rk4_field(const DevField &f, T ipt, T cot, const
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
-    out[i] = y[i] + h / T(6) * (k[0][i] + T(2) * k[1][i] + T(2) * k[2][i] + k[3][i]);
+    d[i] = h / T(6) * (k[0][i] + T(2) * k[1][i] + T(2) * k[2][i] + k[3][i]);
+}
+
+// Compensated (Kahan) accumulation of the steps: y holds the sum rounded,
+// cmp the part rounded away (the sum is y - cmp), so that many short steps
+// in FP32 do not accumulate the position's rounding.
+template <typename T>
+__device__ __forceinline__ void rk_accumulate(T *y, T *cmp, const T *d) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T t = d[i] - cmp[i];
+    const T s = y[i] + t;
+    cmp[i] = (s - y[i]) - t;
+    y[i] = s;
+  }
 }
 
 constexpr float kFieldMaxPath = 1000.f;  // cm of transverse path searched
@@ -252,24 +266,38 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
     if (!(lt > l_min) || lt > T(kFieldMaxPath)) return false;
     const int n = (int)ceil(lt / h_max);
     const T h = lt / T(n);
+    T cmp[4] = {T(0), T(0), T(0), T(0)}, d[4];
     for (int k = 0; k < n; ++k) {
-      rk4_field(f, p[3], cot, y, h, y);
+      rk4_field(f, p[3], cot, y, h, d);
+      rk_accumulate(y, cmp, d);
       if (abs_t(y[3] - p[4]) >= Consts<T>::pi()) return false;
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] -= cmp[i];
     y[2] = pos;
     l = lt;
     return true;
   }
   const T R2 = pos * pos;
   T g = y[0] * y[0] + y[1] * y[1] - R2, lacc = T(0);
+  T cmp[4] = {T(0), T(0), T(0), T(0)}, d[4];
+  int nstep = 0;
   for (;;) {
-    T yn[4];
-    rk4_field(f, p[3], cot, y, h_max, yn);
+    T yn[4], cn[4];
+    rk4_field(f, p[3], cot, y, h_max, d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      yn[i] = y[i];
+      cn[i] = cmp[i];
+    }
+    rk_accumulate(yn, cn, d);
     const T gn = yn[0] * yn[0] + yn[1] * yn[1] - R2;
     if ((g < T(0)) != (gn < T(0)) || gn == T(0)) {
       T s = g == gn ? h_max : h_max * g / (g - gn), ys[4];
       for (int it = 0; it < 3; ++it) {
-        rk4_field(f, p[3], cot, y, s, ys);
+        rk4_field(f, p[3], cot, y, s, d);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ys[i] = y[i] + (d[i] - cmp[i]);
         T sp, cp;
         sincos_t(ys[3], &sp, &cp);
         const T gs = ys[0] * ys[0] + ys[1] * ys[1] - R2;
@@ -277,7 +305,9 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
         if (gp == T(0)) break;
         s -= gs / gp;
       }
-      rk4_field(f, p[3], cot, y, s, ys);
+      rk4_field(f, p[3], cot, y, s, d);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ys[i] = y[i] + (d[i] - cmp[i]);
       if (lacc + s > l_min && abs_t(ys[3] - p[4]) < Consts<T>::pi()) {
         l = lacc + s;
 #pragma unroll
@@ -287,9 +317,12 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
     }
     if (abs_t(yn[3] - p[4]) >= Consts<T>::pi()) return false;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) y[i] = yn[i];
+    for (int i = 0; i < 4; ++i) {
+      y[i] = yn[i];
+      cmp[i] = cn[i];
+    }
     g = gn;
-    lacc += h_max;
+    lacc = T(++nstep) * h_max;  // the path so far, without accumulated rounding
     if (lacc > T(kFieldMaxPath)) return false;
   }
 }

@@ -119,3 +119,42 @@ def test_longest_region_list_both_forms(mkf):
     out = PT.compare_tracks(a[pick], ref, mkf.unpack_cov)
     say({k: (v if k != "fail" else len(v)) for k, v in out.items()})
     assert not out["fail"] and out["equal"] >= 0.9 * out["n"]
+
+
+def test_largest_material_map_and_fine_field_steps(mkf):
+    """A 2048 x 2047-bin material map with a different thickness in every bin
+    (above what the persistent find stages in LDS, so it reads the table
+    from HBM) and field steps of 0.05 cm, on the small barrel event, in both
+    find forms: equal to each other and to the oracle.  A crossing on a bin
+    edge may take either bin (FP32 against FP64), so the map's radial edges
+    are kept off the layer radii (at least 5e-4 cm away): 2047 bins over
+    200 cm rather than 2048, which would put an edge at R = 25 cm."""
+    from dataclasses import replace
+    w = small_barrel()
+    ev = generate_event(w, 0)
+    nr, nz = 2047, 2048
+    rng = np.random.default_rng(11)
+    big = MaterialMap(nr, nz, 200.0, 300.0,
+                      rng.uniform(0.005, 0.03, (nz, nr)).astype(np.float32),
+                      rng.uniform(0.05, 0.3, (nz, nr)).astype(np.float32), PION_MASS, 10.0)
+    edges = np.array([L.pos for L in w.layers]) * nr / 200.0
+    assert np.all(np.abs(edges - np.round(edges)) * 200.0 / nr > 5e-4)
+    fine = replace(FIELD, h_max=0.05)
+    b = make_batch([ev])
+    out = []
+    for flags in (0, mkf.F_BATCHED):
+        ctx = mkf.Context(w.find, flags=flags)
+        ctx.load_geometry(w.layers)
+        ctx.load_material(big)
+        ctx.load_field(fine)
+        ctx.load_hits(b.ev_off, dev(b.x), dev(b.y), dev(b.z), dev(b.var_u), dev(b.var_v),
+                      dev(b.layer))
+        ctx.seed(dev(b.seed_event), dev(b.seed_hits))
+        ctx.find()
+        out.append(ctx.get_tracks(b.seed_hits.shape[0]))
+        ctx.close()
+    assert out[0].tobytes() == out[1].tobytes()
+    ref = O.find_event(w.find, w.layers, ev, material=big, field=fine)
+    res = PT.compare_tracks(out[1], ref, mkf.unpack_cov)
+    say({k: (v if k != "fail" else len(v)) for k, v in res.items()})
+    assert not res["fail"] and res["equal"] >= 0.95 * res["n"]
