@@ -780,6 +780,35 @@ static void mark(int32_t *fragile, int32_t step) {
   if (*fragile < 0 || step < *fragile) *fragile = step;
 }
 
+/* Distance of the crossing p to the nearest edge of its material bin across
+ * which the thickness changes (INFINITY without a map or such an edge): there
+ * the bin, and so the material, is a decision that rounding may flip. */
+static double material_edge_distance(const orc_cfg *cfg, const double p[6]) {
+  const orc_material *m = cfg->material;
+  if (!m) return INFINITY;
+  double r = hypot(p[0], p[1]);
+  double fr = r / m->r_max * m->n_r, fz = (p[2] + m->z_max) / (2.0 * m->z_max) * m->n_z;
+  int ir = (int)floor(fr), iz = (int)floor(fz);
+  ir = ir < 0 ? 0 : (ir >= m->n_r ? m->n_r - 1 : ir);
+  iz = iz < 0 ? 0 : (iz >= m->n_z ? m->n_z - 1 : iz);
+  double best = INFINITY;
+  /* the edges at ir, ir + 1 (radial) and iz, iz + 1 (in z) */
+  for (int side = 0; side < 2; ++side) {
+    int jr = ir + (side ? 1 : -1), jz = iz + (side ? 1 : -1);
+    if (jr >= 0 && jr < m->n_r) {
+      int a = iz * m->n_r + ir, b = iz * m->n_r + jr;
+      if (m->x_x0[a] != m->x_x0[b] || m->xi[a] != m->xi[b])
+        best = fmin(best, fabs(fr - (ir + side)) * m->r_max / m->n_r);
+    }
+    if (jz >= 0 && jz < m->n_z) {
+      int a = iz * m->n_r + ir, b = jz * m->n_r + ir;
+      if (m->x_x0[a] != m->x_x0[b] || m->xi[a] != m->xi[b])
+        best = fmin(best, fabs(fz - (iz + side)) * 2.0 * m->z_max / m->n_z);
+    }
+  }
+  return best;
+}
+
 static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
                      int32_t n_layers, const int32_t *lay_off, const int32_t *lay_idx,
                      const float *x, const float *y, const float *z, const float *vu,
@@ -846,6 +875,7 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
         ext[ne++] = e;
         continue;
       }
+      if (material_edge_distance(cfg, pc) <= tol->pos_tol) mark(&out->fragile_step, s);
       orc_material_effects(cfg, Lr->kind, pc, Cc, 1, NULL);
       for (int k = lay_off[L]; k < lay_off[L + 1]; ++k) {
         int32_t hi = lay_idx[k];

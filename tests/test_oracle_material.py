@@ -200,3 +200,34 @@ def test_smoothed_states_follow_the_loss_without_scattering():
     # order); leaving the Jacobian out of the smoother's transport gives
     # ~1e12 sigma, as nothing else there absorbs it without scattering
     assert worst_d < 1.0 and worst_cov < 1e-2, (worst_d, worst_cov)
+
+
+def test_bin_edge_crossings_are_flagged_fragile():
+    """A crossing within the position tolerance of a material bin edge across
+    which the thickness changes is a decision rounding may flip: the find
+    flags the step.  A map whose radial edge lies on the R = 25 cm layer
+    flags every track reaching it; the same map with equal bins flags none."""
+    from synth import small_barrel
+    w = small_barrel()
+    ev = generate_event(w, 0, n_tracks=40)
+    # 8 radial bins over 200 cm: an edge at 25 cm
+    t = np.full((4, 8), 0.02, np.float32)
+    x = np.full((4, 8), 0.2, np.float32)
+    uniform = MaterialMap(8, 4, 200.0, 300.0, t, x, PION_MASS, 10.0)
+    t2 = t.copy()
+    t2[:, 1:] = 0.03
+    stepped = MaterialMap(8, 4, 200.0, 300.0, t2, x, PION_MASS, 10.0)
+    a = O.find_event(w.find, w.layers, ev, material=uniform)
+    b = O.find_event(w.find, w.layers, ev, material=stepped)
+    def flagged_by_25(res):
+        n = f = 0
+        for r in res:
+            if r["seed_ok"] and 4 in r["plan"]:
+                k = int(np.nonzero(r["plan"] == 4)[0][0])
+                n += 1
+                f += 0 <= r["fragile_step"] <= k
+        return n, f
+    n, f = flagged_by_25(b)
+    assert n > 30 and f == n
+    n, f = flagged_by_25(a)
+    assert f < 0.5 * n
