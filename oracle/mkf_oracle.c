@@ -202,11 +202,15 @@ static void rk4(const orc_field *f, double kappa, double ipt, double cot, const 
   for (int i = 0; i < 4; ++i) out[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
 }
 
-#define ORC_FIELD_MAX_STEPS 4096
 #define ORC_FIELD_MAX_PATH 1000.0 /* cm of transverse path searched */
+#define ORC_NEWTON_TOL 1e-12      /* cm: Newton stops once its correction is below this */
+#define ORC_NEWTON_MAX 50
 
 /* Crossing of a layer in the parameterised field: path l and the end
- * point y = (x, y, z, phi unwrapped). */
+ * point y = (x, y, z, phi unwrapped).  The search is bounded by the path
+ * (ORC_FIELD_MAX_PATH) and the half turn only, whatever the step size.  On
+ * a barrel the last step's length s solves r(s)^2 = R^2 for the Runge-Kutta
+ * step from the bracket's start, by Newton's method run to convergence. */
 static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, double l_min,
                           const orc_field *f, double *l_out, double yend[4]) {
   double cot = cos(p[5]) / sin(p[5]);
@@ -216,7 +220,6 @@ static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, 
     double lt = (Lr->pos - p[2]) * sin(p[5]) / cos(p[5]);
     if (!(lt > l_min) || lt > ORC_FIELD_MAX_PATH) return ORC_NO_CROSSING;
     int n = (int)ceil(lt / f->h_max);
-    if (n > ORC_FIELD_MAX_STEPS) return ORC_NO_CROSSING;
     double h = lt / n;
     for (int k = 0; k < n; ++k) {
       rk4(f, kappa, p[3], cot, y, h, y);
@@ -229,19 +232,22 @@ static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, 
   }
   double R2 = Lr->pos * Lr->pos;
   double g = y[0] * y[0] + y[1] * y[1] - R2, l = 0.0;
-  for (int k = 0; k < ORC_FIELD_MAX_STEPS; ++k) {
+  for (long k = 0;; ++k) {
     double yn[4];
     rk4(f, kappa, p[3], cot, y, f->h_max, yn);
     double gn = yn[0] * yn[0] + yn[1] * yn[1] - R2;
     if ((g < 0.0) != (gn < 0.0) || gn == 0.0) {
-      /* Newton on the step length s from the bracket's start */
+      /* Newton on the step length s from the bracket's start, from the
+       * secant's guess */
       double s = g == gn ? f->h_max : f->h_max * g / (g - gn), ys[4];
-      for (int it = 0; it < 3; ++it) {
+      for (int it = 0; it < ORC_NEWTON_MAX; ++it) {
         rk4(f, kappa, p[3], cot, y, s, ys);
         double gs = ys[0] * ys[0] + ys[1] * ys[1] - R2;
         double gp = 2.0 * (ys[0] * cos(ys[3]) + ys[1] * sin(ys[3]));
         if (gp == 0.0) break;
-        s -= gs / gp;
+        double ds = gs / gp;
+        s -= ds;
+        if (fabs(ds) <= ORC_NEWTON_TOL) break;
       }
       rk4(f, kappa, p[3], cot, y, s, ys);
       if (l + s > l_min && fabs(ys[3] - p[4]) < M_PI) {
@@ -253,10 +259,9 @@ static int field_crossing(const double p[6], const orc_layer *Lr, double kappa, 
     if (fabs(yn[3] - p[4]) >= M_PI) return ORC_NO_CROSSING;
     memcpy(y, yn, sizeof(yn));
     g = gn;
-    l += f->h_max;
+    l = (double)(k + 1) * f->h_max;
     if (l > ORC_FIELD_MAX_PATH) return ORC_NO_CROSSING;
   }
-  return ORC_NO_CROSSING;
 }
 
 int orc_propagate(const double p[6], const double C[36], const orc_layer *Lr,

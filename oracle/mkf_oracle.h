@@ -129,10 +129,11 @@ int orc_propagate(const double p[6], const double C[36], const orc_layer *L,
 /* The same in the parameterised field fld (NULL: the uniform bz).  The
  * crossing is found by Runge-Kutta steps: on a disk, equal steps to the
  * exact path (Z - z) tan(theta); on a barrel, steps of h_max until r^2 - R^2
- * changes sign, then three Newton iterations on the last step's length.  The
- * turning must stay below half a turn and the path below 1000 cm.  The Jacobian is that of the helix
- * with the path's mean curvature (the turning over the path length), made
- * surface-constrained at the end point. */
+ * changes sign, then Newton iterations on the last step's length until the
+ * correction falls below 1e-12 cm.  The turning must stay below half a turn
+ * and the path below 1000 cm, whatever the step size.  The Jacobian is that
+ * of the helix with the path's mean curvature (the turning over the path
+ * length), made surface-constrained at the end point. */
 int orc_propagate_f(const double p[6], const double C[36], const orc_layer *Lr,
                     double bz, double kappa, double l_min, double edge_margin,
                     int check_extent, double p_out[6], double C_out[36],

@@ -165,3 +165,57 @@ def test_pulls_in_the_solenoid_like_field(field_event):
     assert abs(bwd.mean()) < 0.2 and 0.85 < bwd.std() < 1.15, (bwd.mean(), bwd.std())
     fwd_u, _, hits_u = abs_ipt_pulls(w, ev, None)
     assert fwd_u.std() > 2.0 and hits_u < 0.97 * hits
+
+
+def test_barrel_crossing_lies_on_the_cylinder_for_any_step():
+    """The last step's length is solved to convergence: whatever the step
+    size, from the smallest the library accepts (0.01 cm) to the largest
+    (100 cm, where one Runge-Kutta step spans the whole path and its
+    secant guess is far off), the end point of the stepped path lies on
+    r = R to rounding."""
+    rng = np.random.default_rng(64)
+    f = solenoid_field()
+    L = Layer(BARREL, 70.0, -300, 300, 1e-5, 1e-4)
+    n = 0
+    for p in states(rng, 10):
+        for h in (0.01, 0.5, 20.0, 100.0):
+            st, q, _, _, l = O.propagate(p, None, L, BZ, KAPPA, check_extent=False,
+                                         field=replace(f, h_max=h))
+            assert st == O.OK, (p, h)
+            assert abs(np.hypot(q[0], q[1]) - 70.0) < 1e-10 * 70.0, (h, np.hypot(q[0], q[1]))
+            n += 1
+    assert n == 40
+
+
+def test_smallest_step_reaches_a_crossing_sixty_cm_away():
+    """At the smallest step the library accepts (0.01 cm) the search runs as
+    far as at any other step (1000 cm of path, half a turn): a barrel
+    crossing ~66 cm away (6,600 steps) and a disk 150 cm away are found;
+    in a uniform field they equal the closed-form crossings, and in the
+    solenoid-like field they equal the 0.25 cm-step crossings to the
+    Runge-Kutta truncation."""
+    rng = np.random.default_rng(65)
+    f = solenoid_field()
+    barrel = Layer(BARREL, 70.0, -300, 300, 1e-5, 1e-4)
+    disk = Layer(DISK, 150.0, 0, 300, 1e-5, 1e-4)
+    n = 0
+    for _ in range(6):
+        a = rng.uniform(-np.pi, np.pi)
+        pt = rng.uniform(2.0, 8.0)
+        p = np.array([4.0 * np.cos(a), 4.0 * np.sin(a), rng.uniform(-5, 5),
+                      rng.choice([-1, 1]) / pt, a + rng.uniform(-0.1, 0.1), 0.9])
+        for L in (barrel, disk):
+            st0, q0, _, _, l0 = O.propagate(p, None, L, float(np.float32(BZ)), KAPPA,
+                                            check_extent=False)
+            st, q, _, _, l = O.propagate(p, None, L, BZ, KAPPA, check_extent=False,
+                                         field=FieldMap(b0=BZ, h_max=0.01))
+            assert st0 == O.OK and st == O.OK and l > 60.0, (st0, st, l)
+            assert np.abs(q[:3] - q0[:3]).max() < 1e-8 and abs(l - l0) < 1e-8
+            st1, q1, _, _, l1 = O.propagate(p, None, L, BZ, KAPPA, check_extent=False,
+                                            field=replace(f, h_max=0.01))
+            st2, q2, _, _, l2 = O.propagate(p, None, L, BZ, KAPPA, check_extent=False,
+                                            field=replace(f, h_max=0.25))
+            assert st1 == O.OK and st2 == O.OK
+            assert np.abs(q1[:3] - q2[:3]).max() < 1e-8 and abs(l1 - l2) < 1e-8
+            n += 1
+    assert n == 12
