@@ -814,11 +814,22 @@ static double material_edge_distance(const orc_cfg *cfg, const double p[6]) {
   return best;
 }
 
+/* Candidate histories at one step of a seed's find (orc_find_prefixes). */
+typedef struct {
+  int32_t step, cap, n;
+  int32_t *hist; /* [cap][ORC_MAX_PLAN] */
+} snap_t;
+
+static void snap_add(snap_t *sn, const cand_t *c) {
+  if (sn->n < sn->cap) memcpy(&sn->hist[(size_t)sn->n * ORC_MAX_PLAN], c->hist, sizeof(c->hist));
+  sn->n++;
+}
+
 static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
                      int32_t n_layers, const int32_t *lay_off, const int32_t *lay_idx,
                      const float *x, const float *y, const float *z, const float *vu,
                      const float *vv, const int32_t *layer, const int32_t *sh,
-                     orc_track *out) {
+                     orc_track *out, snap_t *snap) {
   memset(out, 0, sizeof(*out));
   out->fragile_step = -1;
   double h[9], hv[6];
@@ -837,7 +848,10 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
   out->seed_ok = 1;
   out->plan_len = so.plan_len;
   memcpy(out->plan, so.plan, sizeof(so.plan));
-  if (so.plan_fragile) out->fragile_step = 0;
+  if (so.plan_fragile) {
+    out->fragile_step = 0;
+    out->plan_fragile = 1;
+  }
 
   int nc = cfg->n_cand;
   cand_t *cands = (cand_t *)calloc((size_t)nc, sizeof(cand_t));
@@ -855,6 +869,10 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
   for (int k = 0; k < ORC_MAX_PLAN; ++k) cands[0].hist[k] = ORC_HIT_NONE;
 
   for (int s = 0; s < so.plan_len; ++s) {
+    if (snap && snap->step == s) {
+      for (int c = 0; c < n; ++c) snap_add(snap, &cands[c]);
+      for (int c = 0; c < n_fin; ++c) snap_add(snap, &fin[c]);
+    }
     const orc_layer *Lr = &layers[so.plan[s]];
     int32_t L = so.plan[s];
     int32_t nh = lay_off[L + 1] - lay_off[L];
@@ -935,6 +953,10 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
     n = keep;
   }
 
+  if (snap && snap->step >= so.plan_len) {
+    for (int c = 0; c < n; ++c) snap_add(snap, &cands[c]);
+    for (int c = 0; c < n_fin; ++c) snap_add(snap, &fin[c]);
+  }
   /* best over final candidates (by rank) then retired ones (in order) */
   const cand_t *bc = NULL, *sc = NULL;
   for (int i = 0; i < n + n_fin; ++i) {
@@ -963,14 +985,10 @@ static void find_one(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *la
   free(Cp);
 }
 
-int orc_find_event(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
-                   int32_t n_layers, int32_t n_hits, const float *x, const float *y,
-                   const float *z, const float *var_u, const float *var_v,
-                   const int32_t *layer, int32_t n_seeds, const int32_t *seed_hits,
-                   orc_track *out) {
-  if (cfg->n_cand < 1) return -1;
-  /* hits of each layer in original order (the brute-force scan below
-   * visits every hit of the layer) */
+/* Hits of each layer in original order (the brute-force scans visit every
+ * hit of a layer): *off [n_layers + 1], *idx [n_hits].  -1 for a bad layer. */
+static int layer_lists(int32_t n_layers, int32_t n_hits, const int32_t *layer, int32_t **off_out,
+                       int32_t **idx_out) {
   int32_t *off = (int32_t *)calloc((size_t)n_layers + 1, sizeof(int32_t));
   int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_hits > 0 ? n_hits : 1));
   for (int32_t i = 0; i < n_hits; ++i) {
@@ -984,13 +1002,172 @@ int orc_find_event(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *laye
   for (int32_t L = 0; L < n_layers; ++L) off[L + 1] += off[L];
   int32_t *fill = (int32_t *)calloc((size_t)n_layers, sizeof(int32_t));
   for (int32_t i = 0; i < n_hits; ++i) idx[off[layer[i]] + fill[layer[i]]++] = i;
+  free(fill);
+  *off_out = off;
+  *idx_out = idx;
+  return 0;
+}
+
+int orc_find_event(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                   int32_t n_layers, int32_t n_hits, const float *x, const float *y,
+                   const float *z, const float *var_u, const float *var_v,
+                   const int32_t *layer, int32_t n_seeds, const int32_t *seed_hits,
+                   orc_track *out) {
+  if (cfg->n_cand < 1) return -1;
+  int32_t *off, *idx;
+  if (layer_lists(n_layers, n_hits, layer, &off, &idx)) return -1;
   for (int32_t s = 0; s < n_seeds; ++s)
     find_one(cfg, tol, layers, n_layers, off, idx, x, y, z, var_u, var_v, layer,
-             &seed_hits[3 * s], &out[s]);
+             &seed_hits[3 * s], &out[s], NULL);
   free(off);
   free(idx);
-  free(fill);
   return 0;
+}
+
+int32_t orc_find_prefixes(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                          int32_t n_layers, int32_t n_hits, const float *x, const float *y,
+                          const float *z, const float *var_u, const float *var_v,
+                          const int32_t *layer, const int32_t seed_hits[3], int32_t step,
+                          int32_t cap, int32_t *hist) {
+  if (cfg->n_cand < 1 || step < 0 || cap < 0) return -1;
+  int32_t *off, *idx;
+  if (layer_lists(n_layers, n_hits, layer, &off, &idx)) return -1;
+  snap_t sn = {step, cap, 0, hist};
+  orc_track t;
+  find_one(cfg, tol, layers, n_layers, off, idx, x, y, z, var_u, var_v, layer, seed_hits, &t,
+           &sn);
+  free(off);
+  free(idx);
+  return sn.n;
+}
+
+/* Whether some hit of layer L is clearly compatible with the predicted
+ * state (chi2 below cut - tol); *near_cut is set if one lies within tol of
+ * the cut. */
+static int any_compatible(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *Lr,
+                          const int32_t *lay_off, const int32_t *lay_idx, int32_t L,
+                          const double pc[6], const double Cc[36], const float *x,
+                          const float *y, const float *z, const float *vu, const float *vv,
+                          int *near_cut) {
+  int any = 0;
+  for (int k = lay_off[L]; k < lay_off[L + 1]; ++k) {
+    int32_t hi = lay_idx[k];
+    double hh[3] = {x[hi], y[hi], z[hi]}, c2;
+    if (!orc_chi2(pc, Cc, Lr->kind, hh, vu[hi], vv[hi], Lr->stereo, &c2)) continue;
+    if (fabs(c2 - cfg->chi2_cut) <= tol_of(tol, cfg->chi2_cut)) *near_cut = 1;
+    else if (c2 < cfg->chi2_cut) any = 1;
+  }
+  return any;
+}
+
+int orc_follow_path(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                    int32_t n_layers, int32_t n_hits, const float *x, const float *y,
+                    const float *z, const float *var_u, const float *var_v,
+                    const int32_t *layer, const int32_t seed_hits[3], int32_t plan_len,
+                    const int32_t *plan, const int32_t *hist, orc_path *out) {
+  memset(out, 0, sizeof(*out));
+  out->bad_step = -1;
+  double h[9], hv[6];
+  int32_t hl[3];
+  for (int k = 0; k < 3; ++k) {
+    int32_t i = seed_hits[k];
+    if (i < 0 || i >= n_hits) return -1;
+    h[3 * k] = x[i];
+    h[3 * k + 1] = y[i];
+    h[3 * k + 2] = z[i];
+    hv[2 * k] = var_u[i];
+    hv[2 * k + 1] = var_v[i];
+    hl[k] = layer[i];
+  }
+  orc_seed_out so;
+  if (!orc_seed(cfg, layers, n_layers, h, hv, hl, tol->pos_tol, &so)) return -1;
+  if (so.plan_len != plan_len) return -1;
+  for (int s = 0; s < plan_len; ++s)
+    if (so.plan[s] != plan[s]) return -1;
+  int32_t *off, *idx;
+  if (layer_lists(n_layers, n_hits, layer, &off, &idx)) return -1;
+  double p[6], C[36];
+  memcpy(p, so.par, sizeof(p));
+  memcpy(C, so.cov, sizeof(C));
+  int32_t nh = 3, nm = 0, retired = 0;
+  double chi = 0.0;
+#define FOLLOW_BAD(s_)       \
+  do {                       \
+    out->bad_step = (s_);    \
+    goto done;               \
+  } while (0)
+  for (int s = 0; s < plan_len; ++s) {
+    const orc_layer *Lr = &layers[plan[s]];
+    int32_t L = plan[s], e = hist[s];
+    if (retired) {
+      if (e != ORC_HIT_NONE) FOLLOW_BAD(s);
+      continue;
+    }
+    double pc[6], Cc[36];
+    int st = orc_propagate_f(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, cfg->edge_margin, 1, pc,
+                             Cc, NULL, NULL, cfg->field);
+    double p2[6];
+    int near_edge =
+        (st == ORC_OK && edge_distance(Lr, pc, cfg->edge_margin) <= tol->pos_tol) ||
+        (st == ORC_OUT_OF_EXTENT &&
+         orc_propagate_f(p, NULL, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, p2, NULL, NULL,
+                         NULL, cfg->field) == ORC_OK &&
+         edge_distance(Lr, p2, cfg->edge_margin) <= tol->pos_tol);
+    out->n_edge += near_edge;
+    if (e == ORC_HIT_SKIP) {
+      if (st == ORC_OK && !near_edge) FOLLOW_BAD(s);
+      continue; /* the state stays where it was */
+    }
+    if (st != ORC_OK) {
+      if (!near_edge) FOLLOW_BAD(s);
+      /* a crossing within tolerance of an edge that the other side took
+       * as inside: continue from the unwidened crossing */
+      if (orc_propagate_f(p, C, Lr, cfg->bz, cfg->kappa, cfg->l_min, 0.0, 0, pc, Cc, NULL, NULL,
+                          cfg->field) != ORC_OK)
+        FOLLOW_BAD(s);
+    }
+    if (material_edge_distance(cfg, pc) <= tol->pos_tol) out->n_edge++;
+    orc_material_effects(cfg, Lr->kind, pc, Cc, 1, NULL);
+    int near_cut = 0;
+    if (e == ORC_HIT_NONE) {
+      /* retired here: nothing was compatible and no miss was left */
+      if (nm < cfg->max_holes) FOLLOW_BAD(s);
+      if (any_compatible(cfg, tol, Lr, off, idx, L, pc, Cc, x, y, z, var_u, var_v, &near_cut))
+        FOLLOW_BAD(s);
+      out->n_near_cut += near_cut;
+      retired = 1;
+      continue;
+    }
+    if (e == ORC_HIT_MISS) {
+      if (nm >= cfg->max_holes) FOLLOW_BAD(s);
+      nm += 1;
+      memcpy(p, pc, sizeof(p));
+      memcpy(C, Cc, sizeof(C));
+      continue;
+    }
+    if (e < 0 || e >= n_hits || layer[e] != L) FOLLOW_BAD(s);
+    double hh[3] = {x[e], y[e], z[e]}, c2;
+    if (!orc_chi2(pc, Cc, Lr->kind, hh, var_u[e], var_v[e], Lr->stereo, &c2)) FOLLOW_BAD(s);
+    if (c2 >= cfg->chi2_cut + tol_of(tol, cfg->chi2_cut)) FOLLOW_BAD(s);
+    if (c2 >= cfg->chi2_cut) out->n_near_cut++;
+    out->max_chi2 = fmax(out->max_chi2, c2);
+    double c2u; /* the update's own chi2 (the find sums the test's, c2) */
+    orc_update_hit(pc, Cc, Lr->kind, hh, var_u[e], var_v[e], Lr->stereo, &c2u);
+    memcpy(p, pc, sizeof(p));
+    memcpy(C, Cc, sizeof(C));
+    nh += 1;
+    chi += c2;
+  }
+#undef FOLLOW_BAD
+done:
+  out->n_hits = nh;
+  out->n_miss = nm;
+  out->chi2 = chi;
+  memcpy(out->par, p, sizeof(p));
+  memcpy(out->cov, C, sizeof(C));
+  free(off);
+  free(idx);
+  return out->bad_step < 0 ? 0 : 1;
 }
 
 /* ------------------------------------------------------------- fitting */

@@ -219,6 +219,7 @@ typedef struct {
    * -1 if no decision was fragile. */
   int32_t fragile_step;
   int64_t n_steps; /* candidate-layer steps taken for this seed */
+  int32_t plan_fragile; /* the plan itself holds a fragile decision */
 } orc_track;
 
 typedef struct {
@@ -235,6 +236,44 @@ int orc_find_event(const orc_cfg *cfg, const orc_tol *tol,
                    const float *var_u, const float *var_v,
                    const int32_t *layer, int32_t n_seeds,
                    const int32_t *seed_hits, orc_track *out);
+
+/* Parity bookkeeping for a seed whose result differs from another
+ * implementation's.  The histories (ORC_MAX_PLAN entries each) of the
+ * candidates alive when the find reaches plan step `step` (those kept at
+ * step - 1, in rank order), then of those retired before it; at step >=
+ * plan_len the final candidates and every retired one.  Up to cap are
+ * written to hist; returns their number (-1 on bad input).  Before the
+ * first fragile step every decision is clear, so another implementation's
+ * candidates there must be exactly these. */
+int32_t orc_find_prefixes(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                          int32_t n_layers, int32_t n_hits, const float *x, const float *y,
+                          const float *z, const float *var_u, const float *var_v,
+                          const int32_t *layer, const int32_t seed_hits[3], int32_t step,
+                          int32_t cap, int32_t *hist);
+
+typedef struct {
+  int32_t bad_step;   /* first step whose decision is invalid, -1 if none */
+  int32_t n_hits, n_miss;
+  double chi2;        /* sum of the hits' chi2 tests, as the find sums them */
+  double max_chi2;    /* largest hit chi2 */
+  int32_t n_near_cut; /* decisions within the chi2 tolerance of the cut */
+  int32_t n_edge;     /* crossings within pos_tol of an extent or material edge */
+  double par[6], cov[36];
+} orc_path;
+
+/* Follow a given history (hit index, ORC_HIT_MISS, ORC_HIT_SKIP or
+ * ORC_HIT_NONE per plan step) of a seed with the find's filter and check
+ * each decision: a hit lies on the step's layer with chi2 below cut + tol;
+ * a miss needs a crossing and a hole left; a skip, no crossing inside the
+ * widened extent; retiring (NONE from then on), a crossing, no hole left and
+ * no hit clearly below the cut.  Crossing decisions within pos_tol of an
+ * edge are accepted either way.  Returns 0 if every decision is valid, 1 if
+ * not (out->bad_step), -1 if the seed fit fails or the plan differs. */
+int orc_follow_path(const orc_cfg *cfg, const orc_tol *tol, const orc_layer *layers,
+                    int32_t n_layers, int32_t n_hits, const float *x, const float *y,
+                    const float *z, const float *var_u, const float *var_v,
+                    const int32_t *layer, const int32_t seed_hits[3], int32_t plan_len,
+                    const int32_t *plan, const int32_t *hist, orc_path *out);
 
 /* Kalman fit of one track through n hits on given surfaces (no search,
  * no extent test).  kinds/pos describe each hit's surface. */

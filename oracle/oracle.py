@@ -81,7 +81,14 @@ class Track(C.Structure):
                 ("plan_len", C.c_int32), ("plan", C.c_int32 * MAX_PLAN),
                 ("hit", C.c_int32 * MAX_PLAN), ("par", C.c_double * 6),
                 ("cov", C.c_double * 36), ("chi2", C.c_double),
-                ("fragile_step", C.c_int32), ("n_steps", C.c_int64)]
+                ("fragile_step", C.c_int32), ("n_steps", C.c_int64),
+                ("plan_fragile", C.c_int32)]
+
+
+class Path(C.Structure):
+    _fields_ = [("bad_step", C.c_int32), ("n_hits", C.c_int32), ("n_miss", C.c_int32),
+                ("chi2", C.c_double), ("max_chi2", C.c_double), ("n_near_cut", C.c_int32),
+                ("n_edge", C.c_int32), ("par", C.c_double * 6), ("cov", C.c_double * 36)]
 
 
 class Seeding(C.Structure):
@@ -126,6 +133,13 @@ def lib():
         L.orc_find_event.argtypes = [C.POINTER(Cfg), C.POINTER(Tol), C.POINTER(Layer), C.c_int32,
                                      C.c_int32, _F, _F, _F, _F, _F, _I, C.c_int32, _I,
                                      C.POINTER(Track)]
+        L.orc_find_prefixes.argtypes = [C.POINTER(Cfg), C.POINTER(Tol), C.POINTER(Layer),
+                                        C.c_int32, C.c_int32, _F, _F, _F, _F, _F, _I, _I,
+                                        C.c_int32, C.c_int32, _I]
+        L.orc_find_prefixes.restype = C.c_int32
+        L.orc_follow_path.argtypes = [C.POINTER(Cfg), C.POINTER(Tol), C.POINTER(Layer),
+                                      C.c_int32, C.c_int32, _F, _F, _F, _F, _F, _I, _I,
+                                      C.c_int32, _I, _I, C.POINTER(Path)]
         L.orc_fit_track.argtypes = [C.POINTER(Cfg), _D, _D, C.c_int32, _I, _D, _D, _D, _D, _D,
                                     _D, _D]
         L.orc_flip.argtypes = [_D, _D]
@@ -391,14 +405,55 @@ def find_event(fc, layers, ev, seeds=None, tol=DEFAULT_TOL, steering=None, mater
     if rc != 0:
         raise ValueError("oracle find failed")
     res = []
+    # what the parity checks need to question the oracle about one seed again
+    ctx = (cfg, t, lay, len(layers), int(layer.shape[0]), arrs, layer)
     for i in range(seeds.shape[0]):
         o = out[i]
         n = o.plan_len
         res.append({"seed_ok": bool(o.seed_ok), "n_hits": o.n_hits, "n_miss": o.n_miss,
                     "plan": np.array(o.plan[:n], np.int32), "hit": np.array(o.hit[:n], np.int32),
                     "par": np.array(o.par[:]), "cov": np.array(o.cov[:]).reshape(6, 6),
-                    "chi2": o.chi2, "fragile_step": o.fragile_step, "n_steps": o.n_steps})
+                    "chi2": o.chi2, "fragile_step": o.fragile_step, "n_steps": o.n_steps,
+                    "plan_fragile": bool(o.plan_fragile),
+                    "_orc": (ctx, seeds[i].copy())})
     return res
+
+
+def find_prefixes(trk, step, cap=4096):
+    """Histories (rows of the plan length) of the candidates the oracle's
+    find had alive at plan step `step` of the seed of find_event result
+    trk (kept at step - 1, then those retired before it; at step >= plan
+    length, the final and all retired ones)."""
+    (cfg, t, lay, nl, nh, arrs, layer), sh = trk["_orc"]
+    hist = np.zeros((cap, MAX_PLAN), np.int32)
+    sh = np.ascontiguousarray(sh, np.int32)
+    n = lib().orc_find_prefixes(C.byref(cfg), C.byref(t), lay, nl, nh,
+                                *[_p(a, _F) for a in arrs], _p(layer, _I), _p(sh, _I),
+                                int(step), cap, _p(hist, _I))
+    if n < 0 or n > cap:
+        raise ValueError("oracle prefixes failed")
+    return hist[:n, :len(trk["plan"])].copy()
+
+
+def follow_path(trk, hist):
+    """Follow the history `hist` (one entry per plan step) of the seed of
+    find_event result trk with the oracle's filter and check its decisions.
+    Returns (status: 0 valid, 1 invalid, -1 seed or plan mismatch, dict)."""
+    (cfg, t, lay, nl, nh, arrs, layer), sh = trk["_orc"]
+    plan = np.ascontiguousarray(trk["plan"], np.int32)
+    h = np.ascontiguousarray(hist, np.int32)
+    if h.shape[0] != plan.shape[0]:
+        raise ValueError("history and plan lengths differ")
+    sh = np.ascontiguousarray(sh, np.int32)
+    out = Path()
+    st = lib().orc_follow_path(C.byref(cfg), C.byref(t), lay, nl, nh, *[_p(a, _F) for a in arrs],
+                               _p(layer, _I), _p(sh, _I), int(plan.shape[0]),
+                               _p(plan, _I) if plan.size else None,
+                               _p(h, _I) if h.size else None, C.byref(out))
+    return int(st), {"bad_step": out.bad_step, "n_hits": out.n_hits, "n_miss": out.n_miss,
+                     "chi2": out.chi2, "max_chi2": out.max_chi2,
+                     "n_near_cut": out.n_near_cut, "n_edge": out.n_edge,
+                     "par": np.array(out.par[:]), "cov": np.array(out.cov[:]).reshape(6, 6)}
 
 
 def fit_track(fc, p0, C0, kinds, pos, hits, var_u, var_v, material=None, field=None):

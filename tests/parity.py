@@ -7,9 +7,13 @@ Tolerances (the arithmetic is FP32 on the GPU, FP64 in the oracle):
               rounding of positions near 100 cm, ~1e-3 of a 30 um hit error);
   indices:    equal, unless the oracle flagged a decision of that seed as
               lying within the chi2 tolerance of the cut or of a tie, or an
-              extent decision within 1e-3 cm of a widened edge.
+              extent decision within 1e-3 cm of a widened edge; then the
+              GPU's track must agree with the oracle up to the first such
+              decision and be a valid path beyond it (explain_mismatch).
 """
 import numpy as np
+
+from oracle import oracle as O
 
 PAR_REL = 1e-4
 CHI2_REL, CHI2_ABS = 1e-3, 1e-2
@@ -78,11 +82,47 @@ def chi2_ok(g, r):
     return abs(float(g) - float(r)) <= CHI2_REL * abs(float(r)) + CHI2_ABS
 
 
+def explain_mismatch(g, r):
+    """Whether the GPU's hit list g may differ from the oracle's result r.
+    Before the oracle's first fragile step f every
+    decision is clear, so the GPU's candidates there are the oracle's: its
+    track's first f entries must be the history of a candidate the oracle
+    had alive at step f (kept or retired).  From f on, its decisions must
+    each be valid (the oracle follows its history: hits below the cut
+    within tolerance, misses with a hole left, skips without a crossing,
+    retiring with nothing compatible), and its hit count and chi2 must be
+    the ones that path gives.  If only the final choice was fragile, the
+    two results must tie in (hits, chi2).  Returns (first differing step,
+    f) when excused, or a string saying what failed."""
+    n = len(r["plan"])
+    gh = [int(v) for v in g["hit"][:n]]
+    rh = [int(v) for v in r["hit"]]
+    d = next((k for k in range(n) if gh[k] != rh[k]), n)
+    f = int(r["fragile_step"])
+    if f < 0:
+        return f"no fragile decision (first difference at step {d})"
+    if f > 0:
+        pre = O.find_prefixes(r, f)
+        if not any(list(p[:f]) == gh[:f] for p in pre):
+            return f"differs before the first fragile step {f} (at step {d})"
+    st, path = O.follow_path(r, gh)
+    if st != 0:
+        return f"invalid decision at step {path['bad_step']} (status {st})"
+    if path["n_hits"] != int(g["n_hits"]) or not chi2_ok(g["chi2"], path["chi2"]):
+        return (f"path totals: GPU {int(g['n_hits'])} hits chi2 {float(g['chi2'])}, "
+                f"the path gives {path['n_hits']} hits chi2 {path['chi2']}")
+    if f >= n and (int(g["n_hits"]) != r["n_hits"] or not chi2_ok(g["chi2"], r["chi2"])):
+        return "only the final choice was fragile, but the results do not tie"
+    return (d, f)
+
+
 def compare_tracks(gpu, ref, full_cov, cov_rel=COV_REL_FOUND):
     """gpu: records (TRACK_DTYPE) of the sampled seeds; ref: oracle dicts.
-    Returns counts; 'fail' lists unexplained mismatches."""
+    Returns counts; 'fail' lists unexplained mismatches, 'diverged' the
+    (sample index, first differing step, first fragile step) of the
+    excused ones."""
     out = {"n": 0, "equal": 0, "tie_diverged": 0, "plan_diverged": 0, "fragile": 0,
-           "max_cov_err": 0.0, "fail": []}
+           "max_cov_err": 0.0, "fail": [], "diverged": []}
     for i, (g, r) in enumerate(zip(gpu, ref)):
         out["n"] += 1
         fragile = r["fragile_step"] >= 0
@@ -96,17 +136,19 @@ def compare_tracks(gpu, ref, full_cov, cov_rel=COV_REL_FOUND):
             continue
         n = len(r["plan"])
         if g["plan_len"] != n or list(g["plan"][:n]) != list(r["plan"]):
-            if r["fragile_step"] == 0:
+            if r["plan_fragile"]:
                 out["plan_diverged"] += 1
             else:
                 out["fail"].append((i, "plan", list(g["plan"][:g["plan_len"]]), list(r["plan"])))
             continue
         same = list(g["hit"][:n]) == list(r["hit"]) and g["n_hits"] == r["n_hits"]
         if not same:
-            if fragile:
+            why = explain_mismatch(g, r)
+            if isinstance(why, tuple):
                 out["tie_diverged"] += 1
+                out["diverged"].append((i,) + why)
             else:
-                out["fail"].append((i, "hits", list(g["hit"][:n]), list(r["hit"])))
+                out["fail"].append((i, "hits", why, list(g["hit"][:n]), list(r["hit"])))
             continue
         ok_p, rel = par_ok(g["par"], r["par"])
         ok_c = chi2_ok(g["chi2"], r["chi2"])
