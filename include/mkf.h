@@ -432,6 +432,8 @@ typedef struct {
   float lr;          /* Adam step size (cosine-decayed to lr/100) */
   uint64_t seed;     /* seed of the counter-based sampler */
   float loss_w[7];   /* per-output weights of the squared error */
+  int32_t first_step; /* first step of the schedule this call takes (see below) */
+  int32_t n_steps;    /* steps this call takes; 0: to the end of the schedule */
 } mkf_train_cfg;
 
 typedef struct {
@@ -447,14 +449,36 @@ typedef struct {
  * geometry with the plain propagator (tracks from the beam line, pT
  * 0.3-10 GeV/c log-uniform, |eta| < 2.4, from each barrel layer to the
  * next), then train with the library's forward/backward kernels and Adam
- * (fresh moments; batches taken in order, epochs repeat them).  Blocks until
- * done.  Errors: MKF_E_ORDER without geometry, MKF_E_GEOMETRY with fewer
- * than 2 barrel layers, MKF_E_ARG for bad settings. */
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  The schedule has S = (n_samples /
+ * batch) x epochs steps: step s (0-based) takes the samples [(s mod
+ * (n_samples / batch)) batch, + batch) and the step size lr_min + (lr -
+ * lr_min) (1 + cos(pi s / (S - 1))) / 2 with lr_min = lr / 100 (lr for
+ * S = 1).  This call takes steps first_step .. first_step + n_steps - 1
+ * (to S - 1 if n_steps = 0): with first_step = 0 from fresh moments, with
+ * first_step > 0 continuing the context's optimizer state, which must then
+ * be at step first_step (after an earlier call, or restored by
+ * mkf_surrogate_set_state; MKF_E_ORDER otherwise).  The samples are
+ * regenerated from seed, so a schedule taken in pieces gives the weights of
+ * one uninterrupted call bit for bit.  Blocks until done.  Errors:
+ * MKF_E_ORDER without geometry, MKF_E_GEOMETRY with fewer than 2 barrel
+ * layers, MKF_E_ARG for bad settings. */
 mkf_status mkf_surrogate_train(mkf_ctx *ctx, const mkf_train_cfg *cfg, mkf_train_report *rep);
 
-/* Read or replace the parameter vector (host, 5,191 floats). */
+/* Read or replace the parameter vector (host, 5,191 floats).  Replacing it
+ * resets the optimizer state (zero moments, step 0). */
 mkf_status mkf_surrogate_get(mkf_ctx *ctx, float *params);
 mkf_status mkf_surrogate_set(mkf_ctx *ctx, const float *params);
+
+/* Checkpoint of the training, all that resuming it needs: the parameters,
+ * Adam's first and
+ * second moments (host, 5,191 floats each) and the number of Adam steps
+ * taken.  get writes them; set restores them (finite values, second
+ * moments >= 0, step >= 0; MKF_E_ARG otherwise), after which
+ * mkf_surrogate_train with first_step = step continues the run. */
+mkf_status mkf_surrogate_get_state(mkf_ctx *ctx, float *params, float *m, float *v,
+                                   int32_t *step);
+mkf_status mkf_surrogate_set_state(mkf_ctx *ctx, const float *params, const float *m,
+                                   const float *v, int32_t step);
 
 /* Loss and its gradient for the current weights on n samples (n a positive
  * multiple of 64; x [n][8], t [n][7] device; loss_w host [7]); grad host

@@ -16,9 +16,14 @@
  * before each product, as the GPU's matrix cores consume them; everything
  * else stays FP64.
  */
+#define _USE_MATH_DEFINES
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 
 #define NI 8
 #define NH 64
@@ -135,4 +140,14 @@ void orc_adam(double *p, double *m, double *v, const double *g, int n, int t, do
     v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
     p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
   }
+}
+
+/* Step size of step s (0-based) of an n_steps-step training schedule: a
+ * half cosine from lr at the first step down to lr_min = lr / 100 at the
+ * last (lr for a one-step schedule).  The training recipe is a reading: the
+ * paper does not train a network. */
+double orc_lr_cosine(double lr, int n_steps, int s) {
+  const double lr_min = 0.01 * lr;
+  const double u = n_steps > 1 ? (double)s / (double)(n_steps - 1) : 0.0;
+  return lr_min + 0.5 * (lr - lr_min) * (1.0 + cos(M_PI * u));
 }

@@ -161,6 +161,8 @@ def lib():
         L.orc_mlp_forward.argtypes = [_D, C.c_int, _D, C.c_int, _D]
         L.orc_mlp_grad.argtypes = [_D, C.c_int, _D, _D, _D, C.c_int, _D]
         L.orc_mlp_grad.restype = C.c_double
+        L.orc_lr_cosine.argtypes = [C.c_double, C.c_int, C.c_int]
+        L.orc_lr_cosine.restype = C.c_double
         L.orc_adam.argtypes = [_D, _D, _D, _D, C.c_int, C.c_int, C.c_double, C.c_double,
                                C.c_double, C.c_double]
     return _lib
@@ -194,6 +196,12 @@ def adam(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     g = _d(g)
     lib().orc_adam(_p(p), _p(m), _p(v), _p(g), p.size, t, lr, b1, b2, eps)
     return p, m, v
+
+
+def lr_cosine(lr, n_steps, s):
+    """Step size of step s of an n_steps-step schedule (half cosine from lr
+    to lr / 100)."""
+    return float(lib().orc_lr_cosine(float(lr), int(n_steps), int(s)))
 
 
 def _d(a, n=None):

@@ -1265,6 +1265,17 @@ mkf_status mkf_surrogate_train(mkf_ctx *c, const mkf_train_cfg *cfg, mkf_train_r
   const int64_t steps64 = per_epoch * cfg->epochs;
   if (steps64 > (1 << 24)) return fail(c, MKF_E_ARG, "too many training steps");
   const int steps = (int)steps64;
+  if (cfg->first_step < 0 || cfg->first_step >= steps)
+    return fail(c, MKF_E_ARG, "first_step %d outside the schedule's %d steps", cfg->first_step,
+                steps);
+  if (cfg->n_steps < 0 || cfg->n_steps > steps - cfg->first_step)
+    return fail(c, MKF_E_ARG, "n_steps %d beyond the schedule's end", cfg->n_steps);
+  if (cfg->first_step > 0 && c->mlp_step != cfg->first_step)
+    return fail(c, MKF_E_ORDER, "the optimizer state is at step %d, not %d", c->mlp_step,
+                cfg->first_step);
+  const int s0 = cfg->first_step;
+  const int s1 = cfg->n_steps ? s0 + cfg->n_steps : steps;
+  const int run = s1 - s0;
   const int waves = cfg->batch / 64;
   HIP_TRY(c, c->d_tx.ensure(sizeof(float) * 8 * n));
   HIP_TRY(c, c->d_tt.ensure(sizeof(float) * 7 * n));
@@ -1272,19 +1283,20 @@ mkf_status mkf_surrogate_train(mkf_ctx *c, const mkf_train_cfg *cfg, mkf_train_r
   HIP_TRY(c, c->d_partial.ensure(sizeof(float) * (size_t)waves * (kNParam + 1)));
   HIP_TRY(c, c->d_partial2.ensure(sizeof(float) * (size_t)(waves / kReduceGroup + 1) *
                                   (kNParam + 1)));
-  HIP_TRY(c, c->d_loss.ensure(sizeof(float) * steps));
+  HIP_TRY(c, c->d_loss.ensure(sizeof(float) * run));
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   mkf_status st = gen_samples(c, n, cfg->seed, c->d_tx.as<float>(), c->d_tt.as<float>(),
                               c->d_tvalid.as<float>());
   if (st != MKF_OK) return st;
   HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
-  // a fresh Adam state for every training run
-  HIP_TRY(c, hipMemsetAsync(c->d_mlp_m.ptr, 0, sizeof(float) * kNParam, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_mlp_v.ptr, 0, sizeof(float) * kNParam, c->stream));
+  if (s0 == 0) {  // a run from its start has fresh moments
+    HIP_TRY(c, hipMemsetAsync(c->d_mlp_m.ptr, 0, sizeof(float) * kNParam, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_mlp_v.ptr, 0, sizeof(float) * kNParam, c->stream));
+  }
   HIP_TRY(c, hipEventRecord(c->ev_m0, c->stream));
   const MlpBuffers B = mlp_buffers(c);
   const float lr_min = cfg->lr * 0.01f;
-  for (int s = 0; s < steps; ++s) {
+  for (int s = s0; s < s1; ++s) {
     const double u = steps > 1 ? (double)s / (steps - 1) : 0.0;
     const float lr = lr_min + 0.5f * (cfg->lr - lr_min) * (float)(1.0 + std::cos(M_PI * u));
     const int64_t begin = (s % per_epoch) * cfg->batch;
@@ -1292,30 +1304,30 @@ mkf_status mkf_surrogate_train(mkf_ctx *c, const mkf_train_cfg *cfg, mkf_train_r
                     c->d_tvalid.as<float>(), n, begin, cfg->batch, cfg->loss_w,
                     c->d_partial.as<float>());
     launch_mlp_reduce(c->stream, B, c->d_partial.as<float>(), waves, s + 1, lr, 1, nullptr,
-                      c->d_loss.as<float>() + s, c->d_partial2.as<float>());
+                      c->d_loss.as<float>() + (s - s0), c->d_partial2.as<float>());
   }
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_m1, c->stream));
-  std::vector<float> loss(steps), valid(n);
-  HIP_TRY(c, hipMemcpyAsync(loss.data(), c->d_loss.ptr, sizeof(float) * steps,
+  std::vector<float> loss(run), valid(n);
+  HIP_TRY(c, hipMemcpyAsync(loss.data(), c->d_loss.ptr, sizeof(float) * run,
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(valid.data(), c->d_tvalid.ptr, sizeof(float) * n,
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->mlp_step = steps;
+  c->mlp_step = s1;
   if (rep) {
     float gen_ms = 0.f, train_ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&gen_ms, c->ev_a, c->ev_b));
     HIP_TRY(c, hipEventElapsedTime(&train_ms, c->ev_m0, c->ev_m1));
-    const int k = std::max(1, steps / 100);
+    const int k = std::max(1, run / 100);
     double first = 0.0, last = 0.0;
     for (int i = 0; i < k; ++i) {
       first += loss[i];
-      last += loss[steps - k + i];
+      last += loss[run - k + i];
     }
     int64_t nv = 0;
     for (float v : valid) nv += v != 0.f;
-    rep->steps = steps;
+    rep->steps = run;
     rep->loss_first = (float)(first / k);
     rep->loss_last = (float)(last / k);
     rep->datagen_ms = gen_ms;
@@ -1347,6 +1359,44 @@ mkf_status mkf_surrogate_set(mkf_ctx *c, const float *params) {
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->mlp_step = 0;
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_get_state(mkf_ctx *c, float *params, float *m, float *v,
+                                   int32_t *step) {
+  if (!c) return MKF_E_ARG;
+  if (!params || !m || !v || !step) return fail(c, MKF_E_ARG, "null state buffer");
+  HIP_TRY(c, hipMemcpyAsync(params, c->d_mlp_param.ptr, sizeof(float) * kNParam,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m, c->d_mlp_m.ptr, sizeof(float) * kNParam, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(v, c->d_mlp_v.ptr, sizeof(float) * kNParam, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *step = c->mlp_step;
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_set_state(mkf_ctx *c, const float *params, const float *m,
+                                   const float *v, int32_t step) {
+  if (!c) return MKF_E_ARG;
+  if (!params || !m || !v) return fail(c, MKF_E_ARG, "null state buffer");
+  if (step < 0) return fail(c, MKF_E_ARG, "step must be >= 0");
+  for (int i = 0; i < kNParam; ++i) {
+    if (!finite_f(params[i]) || !finite_f(m[i]) || !finite_f(v[i]))
+      return fail(c, MKF_E_ARG, "state entry %d is not finite", i);
+    if (v[i] < 0.f) return fail(c, MKF_E_ARG, "second moment %d is negative", i);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_mlp_param.ptr, params, sizeof(float) * kNParam,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_mlp_m.ptr, m, sizeof(float) * kNParam, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_mlp_v.ptr, v, sizeof(float) * kNParam, hipMemcpyHostToDevice,
+                            c->stream));
+  launch_mlp_images(c->stream, mlp_buffers(c));
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->mlp_step = step;
   return MKF_OK;
 }
 

@@ -30,7 +30,8 @@ EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry",
            "mkf_find_duplicates",
            "mkf_get_stats",
            "mkf_set_tuning",
-           "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set", "mkf_surrogate_grad",
+           "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set",
+           "mkf_surrogate_get_state", "mkf_surrogate_set_state", "mkf_surrogate_grad",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
 
 
@@ -122,7 +123,8 @@ class Stats(C.Structure):
 
 class TrainCfg(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32),
-                ("lr", C.c_float), ("seed", C.c_uint64), ("loss_w", C.c_float * 7)]
+                ("lr", C.c_float), ("seed", C.c_uint64), ("loss_w", C.c_float * 7),
+                ("first_step", C.c_int32), ("n_steps", C.c_int32)]
 
 
 class TrainReport(C.Structure):
@@ -166,6 +168,8 @@ def _load():
         "mkf_surrogate_train": ([P, C.POINTER(TrainCfg), C.POINTER(TrainReport)], I32),
         "mkf_surrogate_get": ([P, P], I32),
         "mkf_surrogate_set": ([P, P], I32),
+        "mkf_surrogate_get_state": ([P, P, P, P, C.POINTER(I32)], I32),
+        "mkf_surrogate_set_state": ([P, P, P, P, I32], I32),
         "mkf_surrogate_grad": ([P, I32, P, P, P, P, P], I32),
         "mkf_surrogate_infer": ([P, I64, P, P], I32),
         "mkf_surrogate_samples": ([P, I64, C.c_uint64, P, P, P], I32),
@@ -380,10 +384,12 @@ class Context:
 
     # ---- learned propagation surrogate
 
-    def surrogate_train(self, n_samples, epochs, batch, lr, seed, loss_w=(1, 0, 0, 0, 0, 0, 0)):
+    def surrogate_train(self, n_samples, epochs, batch, lr, seed, loss_w=(1, 0, 0, 0, 0, 0, 0),
+                        first_step=0, n_steps=0):
         cfg = TrainCfg(int(n_samples), int(epochs), int(batch), float(lr), int(seed))
         for j in range(7):
             cfg.loss_w[j] = float(loss_w[j])
+        cfg.first_step, cfg.n_steps = int(first_step), int(n_steps)
         rep = TrainReport()
         self._check(lib.mkf_surrogate_train(self.h, C.byref(cfg), C.byref(rep)))
         return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
@@ -397,6 +403,20 @@ class Context:
         params = np.ascontiguousarray(params, np.float32)
         assert params.shape == (MLP_NPARAM,)
         self._check(lib.mkf_surrogate_set(self.h, _ptr(params)))
+
+    def surrogate_get_state(self):
+        """(params, m, v, step): the weights and Adam's state."""
+        p, m, v = (np.zeros(MLP_NPARAM, np.float32) for _ in range(3))
+        step = C.c_int32(0)
+        self._check(lib.mkf_surrogate_get_state(self.h, _ptr(p), _ptr(m), _ptr(v),
+                                                C.byref(step)))
+        return p, m, v, int(step.value)
+
+    def surrogate_set_state(self, params, m, v, step):
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (params, m, v)]
+        for a in arrs:
+            assert a.shape == (MLP_NPARAM,)
+        self._check(lib.mkf_surrogate_set_state(self.h, *[_ptr(a) for a in arrs], int(step)))
 
     def surrogate_grad(self, x, t, loss_w):
         """x [n][8], t [n][7] device tensors; returns (grad, loss) on the host."""

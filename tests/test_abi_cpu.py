@@ -41,6 +41,9 @@ def test_struct_layouts_match_header():
     assert C.sizeof(mkf.Region) == 4 * 3 + 4 * 32
     assert C.sizeof(mkf.MaterialInfo) == 4 * 6
     assert C.sizeof(mkf.Field) == 4 * 5
+    # mkf_train_cfg: int64, 2 int32, float, padding, uint64, 7 floats, 2 int32
+    assert C.sizeof(mkf.TrainCfg) == 72
+    assert mkf.TrainCfg.first_step.offset == 60 and mkf.TrainCfg.n_steps.offset == 64
 
 
 def test_host_side_argument_errors():

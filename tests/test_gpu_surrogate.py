@@ -238,3 +238,87 @@ def test_find_with_surrogate_matches_oracle(mkf, trained, net):
     assert np.array_equal(tr["status"], plain["status"])
     for i in np.nonzero(same)[0]:
         assert PT.par_ok(tr["par"][i], plain["par"][i])[0], (i, tr["par"][i], plain["par"][i])
+
+
+def test_adam_step_and_schedule_match_oracle(mkf, geo_ctx):
+    """One training step at the start, middle and end of a 32-step
+    schedule, from a restored optimizer state: the step's gradient (read
+    back from the first moment) against the oracle's gradient of the same
+    batch (invalid samples weigh zero, the loss is averaged over the
+    batch), and the second moment and the parameters against the oracle's
+    Adam step with the oracle's cosine step size."""
+    _, ctx = geo_ctx
+    n, batch, epochs, lr, seed = 8192, 512, 2, 3e-3, 21
+    per_epoch = n // batch
+    S = per_epoch * epochs
+    lw = np.array([1.0, 0.01, 0.01, 0.01, 0.01, 0.01, 0.01], np.float32)
+    x, t, v = samples(mkf, ctx, n, seed)
+    xg, tg, vg = (a.cpu().numpy().astype(np.float64) for a in (x, t, v))
+    rng = np.random.default_rng(22)
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    for s in (0, 13, S - 1):
+        p0 = glorot(rng)
+        if s == 0:  # a schedule's first step starts from fresh moments
+            m0 = np.zeros_like(p0)
+            v0 = np.zeros_like(p0)
+        else:
+            m0 = (rng.normal(size=p0.size) * 1e-4).astype(np.float32)
+            v0 = (rng.uniform(0, 1e-6, size=p0.size)).astype(np.float32)
+        ctx.surrogate_set_state(p0, m0, v0, s)
+        ctx.surrogate_train(n_samples=n, epochs=epochs, batch=batch, lr=lr, seed=seed,
+                            loss_w=lw, first_step=s, n_steps=1)
+        p1, m1, v1, step = ctx.surrogate_get_state()
+        assert step == s + 1
+        g = (m1.astype(np.float64) - b1 * m0) / (1 - b1)
+        rows = np.arange((s % per_epoch) * batch, (s % per_epoch + 1) * batch)
+        ok = rows[vg[rows] != 0]
+        _, gr = O.mlp_grad(bf16_weights(p0), xg[ok], tg[ok], lw.astype(np.float64),
+                           round_bf16=True)
+        gr *= ok.size / batch
+        o = 0
+        for name, n_p in [("W1", NH * NI), ("b1", NH), ("W2", NH * NH), ("b2", NH),
+                          ("W3", NO * NH), ("b3", NO)]:
+            rel = np.linalg.norm(g[o:o + n_p] - gr[o:o + n_p]) / np.linalg.norm(gr[o:o + n_p])
+            assert rel <= 2e-2, (s, name, rel)
+            o += n_p
+        lr_s = O.lr_cosine(lr, S, s)
+        pe, me, ve = O.adam(p0.astype(np.float64), m0.astype(np.float64),
+                            v0.astype(np.float64), g, s + 1, lr_s, b1, b2, eps)
+        np.testing.assert_allclose(v1, ve, rtol=1e-5, atol=1e-30)
+        step_e = pe - p0
+        d = np.abs(p1.astype(np.float64) - pe)
+        bound = 1e-4 * np.abs(step_e) + 2.0 * np.spacing(np.abs(p0).astype(np.float32))
+        say("adam step", s, "lr", lr_s, "worst", float((d / bound).max()))
+        assert np.all(d <= bound), (s, float((d / bound).max()))
+
+
+def test_training_resumes_bitwise_from_a_checkpoint(mkf, geo_ctx):
+    """A 64-step schedule taken in one call, and taken as 40 steps, a
+    checkpoint (weights, moments, step) restored into another context, then
+    the remaining 24: the same weights and moments bit for bit."""
+    w, ctx = geo_ctx
+    cfg = dict(n_samples=16384, epochs=2, batch=512, lr=3e-3, seed=31,
+               loss_w=(1, 0.01, 0.01, 0.01, 0.01, 0.01, 0.01))
+    p0 = glorot(np.random.default_rng(23))
+    ctx.surrogate_set(p0)
+    rep = ctx.surrogate_train(**cfg)
+    assert rep["steps"] == 64
+    full = ctx.surrogate_get_state()
+    ctx.surrogate_set(p0)
+    ctx.surrogate_train(**cfg, n_steps=40)
+    ck = ctx.surrogate_get_state()
+    assert ck[3] == 40
+    ctx2 = mkf.Context(w.find)
+    try:
+        ctx2.load_geometry(w.layers)
+        with pytest.raises(mkf.MkfError):  # its optimizer is at step 0, not 40
+            ctx2.surrogate_train(**cfg, first_step=40)
+        ctx2.surrogate_set_state(*ck)
+        rep = ctx2.surrogate_train(**cfg, first_step=40)
+        assert rep["steps"] == 24
+        resumed = ctx2.surrogate_get_state()
+    finally:
+        ctx2.close()
+    for a, b in zip(full[:3], resumed[:3]):
+        assert np.array_equal(a, b)
+    assert full[3] == resumed[3] == 64

@@ -133,3 +133,17 @@ def test_bf16_rounding_mode_is_a_small_perturbation():
     p0 = join(np.zeros_like(W1), np.zeros_like(b1), W2, np.zeros_like(b2), W3, b3)
     # zero pre-activations: h1 = silu(0) = 0 and h2 = 0 exactly in both modes
     np.testing.assert_array_equal(O.mlp_forward(p0, x), O.mlp_forward(p0, x, round_bf16=True))
+
+
+def test_cosine_schedule_endpoints_midpoint_and_shape():
+    """The step size starts at lr, ends at lr / 100, is their mean half way
+    (cos(pi/2) = 0), falls monotonically, and its steps are symmetric about
+    the middle (cos(pi - a) = -cos(a)): lr(s) + lr(S-1-s) = lr + lr/100."""
+    lr, S = 3e-3, 101
+    lrs = np.array([O.lr_cosine(lr, S, s) for s in range(S)])
+    assert lrs[0] == pytest.approx(lr, rel=1e-15)
+    assert lrs[-1] == pytest.approx(lr / 100, rel=1e-13)
+    assert lrs[50] == pytest.approx((lr + lr / 100) / 2, rel=1e-13)
+    assert np.all(np.diff(lrs) < 0)
+    np.testing.assert_allclose(lrs + lrs[::-1], lr + lr / 100, rtol=1e-13)
+    assert O.lr_cosine(lr, 1, 0) == lr
