@@ -2,10 +2,15 @@
 
 A step is one pass of the find (propagate, hit search, chi2, per-seed
 selection, Kalman update over every plan layer of every seed) over the whole
-workload: 100 synthetic barrel+endcap events of 5,000 tracks (scattering,
-2% inefficiency, 30% noise hits).  Hits are indexed and seeds fitted before
-the timed region (the paper times core finding without this
-pre-processing, Section 4.1); inputs are resident in HBM.
+workload: 512 synthetic barrel+endcap events of uneven size, 500-20,000
+tracks each (log-uniform; scattering, 2% inefficiency, 30% noise hits), in
+one persistent launch captured as a HIP graph, with the learned propagation
+surrogate (trained on 10 M propagations before the timed region).  Beside it
+the same events are found without the surrogate, in the layer-synchronous
+form over all events, and one launch sequence per event (the plain
+comparison).  Hits are indexed and seeds fitted before the timed region (the
+paper times core finding without this pre-processing, Section 4.1); inputs
+are resident in HBM.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K]
 [--warmup W].
@@ -23,6 +28,7 @@ METRIC = "candidate-layer updates/s (propagate+chi2+update), surrogate+batched v
 UNIT = "candidate-layer updates/s"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 # Algorithmic cost of one candidate-layer step (counted from the kernel's
 # arithmetic; see the design notes): FP32 flops and the bytes the
 # layer-synchronous form must move through HBM.
@@ -40,14 +46,16 @@ SMOOTH_BYTES_PER_SURFACE = 4.0 * (91 + 91 + 27)
 # 19,200
 MLP_FWD_FLOPS = 10112.0
 MLP_FWD_BWD_FLOPS = 29312.0
-BF16_MFMA_PEAK_TFLOPS = 2500.0
+# the surrogate's training (the uniform-field network of the find)
+TRAIN = dict(n_samples=10_000_000, epochs=2, batch=512, lr=3e-3, seed=11,
+             loss_w=(1, .01, .01, .01, .01, .01, .01))
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter record
     (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or None if the
     kernel sources changed since the counters were taken."""
@@ -55,7 +63,7 @@ def profiled_traffic(kernel):
     import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         rec = json.load(open(path))
-        if not rec["kernel"].startswith(kernel):
+        if rec["kernel"] != kernel or rec["workload"] != workload:
             continue
         h = hashlib.sha256()
         for f in rec["sources"]:
@@ -63,6 +71,16 @@ def profiled_traffic(kernel):
         if h.hexdigest() == rec["source_sha256"]:
             return rec["hbm_bytes_per_launch"]
     return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _oracle_share(job):
@@ -82,13 +100,16 @@ def _oracle_share(job):
 
 
 def cpu_baseline(w, batch, seconds, workers):
-    """The FP64 oracle as it stands, one event per host thread (the paper's
-    events-in-flight pattern), each on its own process; throughput is the
-    summed steps over the longest worker's time."""
+    """The FP64 oracle as it stands on this machine's host CPUs: one thread
+    on event 0, then one event per process on events 0..workers-1 (the
+    paper's events-in-flight pattern, Section 4.2), each on the first seeds
+    of its event for `seconds`; throughput is the summed steps over the
+    longest worker's time."""
+    one = _oracle_share((w, batch.events[0], seconds))
     n = max(1, min(workers, len(batch.events)))
     jobs = [(w, batch.events[e], seconds) for e in range(n)]
     if n == 1:
-        out = [_oracle_share(jobs[0])]
+        out = [one]
     else:
         import multiprocessing as mp
         pool = mp.get_context("spawn").Pool(n)
@@ -101,20 +122,108 @@ def cpu_baseline(w, batch, seconds, workers):
     t = max(o[1] for o in out)
     seeds = sum(o[2] for o in out)
     return {"value": steps / t, "unit": UNIT, "cores": n, "kind": "oracle",
-            "sample": f"first seeds of events 0-{n - 1}, one event per process "
+            "sample": f"first seeds of events 0-{n - 1} of the workload, one event per process "
                       f"({seeds} seeds, {steps} candidate-layer steps, {t:.1f} s; FP64, "
-                      f"brute-force hit scan)"}
+                      f"brute-force hit scan)",
+            "one_thread": {"value": one[0] / one[1], "sample":
+                           f"first {one[2]} seeds of event 0 ({one[0]} steps, {one[1]:.1f} s)"},
+            "cpu_model": cpu_model(), "hardware_concurrency": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0))}
 
 
-def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
+def time_form(mkf, w, b, flags, stream, args, T, params=None, autotune=True):
+    """One context of the given flags over the whole workload: warm-up, then
+    K finds between device synchronisations.  Returns (result, tracks)."""
+    import numpy as np
+    import torch
+    with torch.cuda.stream(stream):
+        ctx = mkf.Context(w.find, flags=flags, stream=stream.cuda_stream)
+        ctx.load_geometry(w.layers)
+        if params is not None:
+            ctx.surrogate_set(params)
+        ctx.load_hits(b.ev_off, *[T(a) for a in (b.x, b.y, b.z, b.var_u, b.var_v, b.layer)])
+        ctx.seed(T(b.seed_event), T(b.seed_hits))
+        tuning = ctx.autotune(repeats=2) if (flags & mkf.F_BATCHED) and autotune else None
+        for _ in range(args.warmup):
+            ctx.find()
+        torch.cuda.synchronize()
+        find_ms, main_ms = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.find()
+            st = ctx.stats()
+            find_ms.append(st["find_ms"])
+            main_ms.append(st["main_ms"])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        tr = ctx.get_tracks(b.seed_hits.shape[0])
+        st = ctx.stats()
+        ctx.close()
+    res = {"ms_per_step": wall * 1e3, "find_ms": float(np.median(find_ms)),
+           "main_ms": float(np.median(main_ms)), "main_launches": st["main_launches"],
+           "n_steps": st["n_steps"], "value": st["n_steps"] / wall,
+           "device_value": st["n_steps"] / (float(np.median(find_ms)) * 1e-3),
+           "tuning": tuning}
+    if flags & mkf.F_SURROGATE:
+        res["surrogate"] = {"kept": st["sur_kept"], "rejected": st["sur_rejected"],
+                            "kept_frac": st["sur_kept"] / max(1, st["sur_kept"] + st["sur_rejected"])}
+    return res, tr
+
+
+def time_per_event(mkf, w, b, stream, args, T):
+    """The plain comparison: one context per event, each found by its own
+    layer-synchronous launch sequence; a step finds every event once.  The
+    find call returns after its event's work, so `value` counts the host's
+    waits between events too; `device_value` sums the finds' device times."""
+    import numpy as np
+    import torch
+    from synth import make_batch
+    ctxs = []
+    with torch.cuda.stream(stream):
+        for e in range(w.n_events):
+            one = make_batch([b.events[e]])
+            c = mkf.Context(w.find, flags=0, stream=stream.cuda_stream)
+            c.load_geometry(w.layers)
+            c.load_hits(one.ev_off, *[T(a) for a in (one.x, one.y, one.z, one.var_u,
+                                                    one.var_v, one.layer)])
+            c.seed(T(one.seed_event), T(one.seed_hits))
+            ctxs.append((c, one.seed_hits.shape[0]))
+        for _ in range(args.warmup):
+            for c, _ in ctxs:
+                c.find()
+        torch.cuda.synchronize()
+        dev_ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            tot = 0.0
+            for c, _ in ctxs:
+                c.find()
+                tot += c.stats()["find_ms"]
+            dev_ms.append(tot)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        steps = sum(c.stats()["n_steps"] for c, _ in ctxs)
+        launches = sum(c.stats()["n_launches"] for c, _ in ctxs)
+        tr = np.concatenate([c.get_tracks(n) for c, n in ctxs])
+        for c, _ in ctxs:
+            c.close()
+    off = np.concatenate([[0], np.cumsum([n for _, n in ctxs])[:-1]])
+    tr["seed_id"] += np.repeat(off, [n for _, n in ctxs]).astype(np.int32)
+    return ({"ms_per_step": wall * 1e3, "find_ms": float(np.median(dev_ms)), "n_steps": steps,
+             "launches_per_step": launches, "value": steps / wall,
+             "device_value": steps / (float(np.median(dev_ms)) * 1e-3)}, tr)
+
+
+def measure_kernels(mkf, w, stream, T, f, batch, extended):
     """Throughput of the other hot-path kernels, each from HIP events on the
     context stream around one launch after a warm-up: the search-free fit
     (131,072 tracks x 26 layers), the backward fit and the smoothing of the
-    benchmark workload's found tracks, triplet seeding with cleaning, find and
-    duplicate removal on it, the find with a material map and with region
-    steering, the find in a parameterised field (events simulated in it),
-    and the surrogate network's inference and gradient (2^20 samples from
-    its training sampler)."""
+    workload's found tracks, and the surrogate network's inference and
+    gradient (2^20 samples from its training sampler).  With `extended`:
+    triplet seeding with cleaning, find and duplicate removal, the find with
+    a material map and with region steering, and the find in a parameterised
+    field (100 events of 5,000 tracks simulated in it) with and without the
+    uniform field."""
     import numpy as np
     import torch
 
@@ -133,6 +242,8 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         return {"ms": ms, "throughput": unit_count / (ms * 1e-3), "unit": unit,
                 "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}
 
+    hits = [T(a) for a in (batch.x, batch.y, batch.z, batch.var_u, batch.var_v, batch.layer)]
+    seeds = (T(batch.seed_event), T(batch.seed_hits))
     out = {}
     with torch.cuda.stream(stream):
         ctx = mkf.Context(w.find, stream=stream.cuda_stream)
@@ -140,16 +251,17 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         k, n = f.x.shape
         ins = [T(a) for a in (f.kind, f.pos, f.x, f.y, f.z, f.var_u, f.var_v, f.length,
                               f.init_par, f.init_cov)]
-        outs = [torch.zeros((n, 6), device=ins[0].device), torch.zeros((n, 21), device=ins[0].device),
-                torch.zeros(n, device=ins[0].device),
-                torch.zeros(n, dtype=torch.int32, device=ins[0].device)]
+        dev = ins[0].device
+        outs = [torch.zeros((n, 6), device=dev), torch.zeros((n, 21), device=dev),
+                torch.zeros(n, device=dev), torch.zeros(n, dtype=torch.int32, device=dev)]
         ms = timed(lambda: ctx.fit(*ins, *outs))
         out["k_fit"] = dict(alu(FIT_FLOPS_PER_UPDATE * n * k, ms, FP32_VECTOR_PEAK_TFLOPS, n * k,
                                 "track-layer updates/s"), bound="alu",
                             workload=f"{n} tracks x {k} layers")
-        # backward fit of the tracks found in the benchmark workload,
-        # counted by its updates (one per hit, the seed hits included; the
-        # propagations through layers without a hit are not counted)
+        del ins, outs
+        # backward fit of the tracks found in the workload, counted by its
+        # updates (one per hit, the seed hits included; the propagations
+        # through layers without a hit are not counted)
         ctx2 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
         ctx2.load_geometry(w.layers)
         ctx2.load_hits(batch.ev_off, *hits)
@@ -157,7 +269,6 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         ctx2.find()
         ns = batch.seed_hits.shape[0]
         tr = ctx2.get_tracks(ns)
-        dev = ins[0].device
         bouts = [torch.zeros((ns, 6), device=dev), torch.zeros((ns, 21), device=dev),
                  torch.zeros(ns, device=dev), torch.zeros(ns, dtype=torch.int32, device=dev)]
         ms = timed(lambda: ctx2.backward_fit(*bouts))
@@ -166,6 +277,7 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         out["k_backfit"] = dict(alu(FIT_FLOPS_PER_UPDATE * upd, ms, FP32_VECTOR_PEAK_TFLOPS, upd,
                                     "track-hit updates/s"), bound="alu",
                                 workload=f"{int(ok.sum())} found tracks, {upd} hits")
+        del bouts
         sm = [torch.zeros((ns, 33, 6), device=dev), torch.zeros((ns, 33, 21), device=dev),
               torch.zeros(ns, dtype=torch.int32, device=dev)]
         ms = timed(lambda: ctx2.smooth(*sm))
@@ -179,105 +291,7 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
                                                f"{nsurf} surfaces"}
         del sm
         ctx2.close()
-        # combinatorial triplet seeding, seed cleaning, the find from all the
-        # triplet seeds and duplicate removal on the same workload (each call
-        # between HIP events on the context stream; the seeding and removal
-        # calls wait on the host for their counts inside that span)
-        from synth import CleaningConfig, SeedingConfig
-        ctx3 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
-        ctx3.load_geometry(w.layers)
-        ctx3.load_hits(batch.ev_off, *hits)
-        cap = 8 << 20
-        sev = torch.zeros(cap, dtype=torch.int32, device=dev)
-        shit = torch.zeros((cap, 3), dtype=torch.int32, device=dev)
-        nt = [0]
-
-        def mk():
-            nt[0] = ctx3.make_seeds(SeedingConfig(), cap, sev, shit)
-
-        ms_seed = timed(mk)
-        ctx3.seed(sev[:nt[0]], shit[:nt[0]])
-        keep = torch.zeros(nt[0], dtype=torch.int32, device=dev)
-        nk = [0]
-
-        def cl():
-            nk[0] = ctx3.clean_seeds(CleaningConfig(), keep)
-
-        ms_clean = timed(cl)
-        ctx3.find()
-        ctx3.find()
-        find_ms = ctx3.stats()["find_ms"]
-        dup = torch.zeros(nt[0], dtype=torch.int32, device=dev)
-        nd = [0]
-
-        def dd():
-            nd[0] = ctx3.find_duplicates(0.5, dup)
-
-        ms_dup = timed(dd)
-        out["triplet_seeding_pipeline"] = {
-            "workload": f"{w.name}, seeds from every triplet of layers 0-2",
-            "triplets": nt[0], "make_seeds_ms": ms_seed, "clean_seeds_ms": ms_clean,
-            "kept_after_cleaning": nk[0], "find_ms_all_triplet_seeds": find_ms,
-            "duplicates": nd[0], "find_duplicates_ms": ms_dup}
-        del sev, shit, keep, dup
-        ctx3.close()
-        # the batched find with a silicon-like material map (1.5% of a
-        # radiation length and 0.1 g/cm^2 per layer, 1.5x beyond |z| = 50 cm)
-        # and with five-region steering, from the same seeds (each autotuned;
-        # mkf_get_stats timing)
-        from synth import five_regions, material_map
-        variants = (("find_material_map",
-                     lambda c: c.load_material(material_map(120.0, 300.0, 24, 30, 0.015, 0.1))),
-                    ("find_five_region_steering", lambda c: c.load_steering(five_regions())))
-        for label, setup in variants:
-            c4 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
-            c4.load_geometry(w.layers)
-            setup(c4)
-            c4.load_hits(batch.ev_off, *hits)
-            c4.seed(*seeds)
-            tun4 = c4.autotune(repeats=2)
-            c4.find()
-            c4.find()
-            st = c4.stats()
-            c4.close()
-            out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
-                          "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
-                          "unit": "candidate-layer updates/s", "workload": w.name,
-                          "tuning": tun4}
-        # the batched find in the solenoid-like parameterised field (Runge-Kutta
-        # crossings) on events of the benchmark's sizes simulated in that field
-        # (generated here, in this process: ~1.6 s per event), against the
-        # uniform-field find on the same events
-        from synth import barrel_endcap_field, generate_event, make_batch
-        wf = barrel_endcap_field(w.n_events, w.n_tracks[0])
-        evs = []
-        for e in range(wf.n_events):
-            evs.append(generate_event(wf, e))
-            if e % 10 == 9:
-                log(f"field events generated: {e + 1}/{wf.n_events}")
-        bf = make_batch(evs)
-        del evs
-        fh = [T(a) for a in (bf.x, bf.y, bf.z, bf.var_u, bf.var_v, bf.layer)]
-        fs = (T(bf.seed_event), T(bf.seed_hits))
-        for label, fld in (("find_parameterised_field", wf.field),
-                           ("find_uniform_field_same_events", None)):
-            c5 = mkf.Context(wf.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
-            c5.load_geometry(wf.layers)
-            c5.load_field(fld)
-            c5.load_hits(bf.ev_off, *fh)
-            c5.seed(*fs)
-            tun5 = c5.autotune(repeats=2)
-            c5.find()
-            c5.find()
-            st = c5.stats()
-            n = int(bf.seed_hits.shape[0])
-            tr = c5.get_tracks(n)
-            c5.close()
-            out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
-                          "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
-                          "unit": "candidate-layer updates/s", "workload": wf.name,
-                          "mean_hits_per_track": float(tr["n_hits"].mean()), "tuning": tun5}
-        del fh, fs, bf
+        torch.cuda.empty_cache()
         m = 1 << 20
         x = torch.zeros((m, 8), device=dev)
         t = torch.zeros((m, 7), device=dev)
@@ -291,9 +305,110 @@ def measure_kernels(mkf, w, stream, T, f, batch, hits, seeds):
         ms = timed(lambda: ctx.surrogate_grad(x, t, lw))
         out["k_mlp_grad+reduce"] = dict(alu(MLP_FWD_BWD_FLOPS * m, ms, BF16_MFMA_PEAK_TFLOPS, m,
                                             "samples/s"), bound="mfma", workload=f"{m} samples")
+        del x, t, v, y
         ctx.close()
+        if extended:
+            out.update(measure_extended(mkf, w, stream, T, batch, hits, seeds, timed))
     log("kernels", json.dumps(out))
     return out
+
+
+def measure_extended(mkf, w, stream, T, batch, hits, seeds, timed):
+    """The extended finds: triplet seeding, cleaning and duplicate removal;
+    the find with a material map and with five-region steering; the find in
+    a parameterised field on events simulated in it."""
+    import torch
+    from synth import (CleaningConfig, SeedingConfig, barrel_endcap_field, five_regions,
+                       generate_event, make_batch, material_map)
+    out = {}
+    dev = hits[0].device
+    ctx3 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+    ctx3.load_geometry(w.layers)
+    ctx3.load_hits(batch.ev_off, *hits)
+    cap = 48 << 20
+    sev = torch.zeros(cap, dtype=torch.int32, device=dev)
+    shit = torch.zeros((cap, 3), dtype=torch.int32, device=dev)
+    nt = [0]
+
+    def mk():
+        nt[0] = ctx3.make_seeds(SeedingConfig(), cap, sev, shit)
+
+    ms_seed = timed(mk)
+    ctx3.seed(sev[:nt[0]], shit[:nt[0]])
+    keep = torch.zeros(nt[0], dtype=torch.int32, device=dev)
+    nk = [0]
+
+    def cl():
+        nk[0] = ctx3.clean_seeds(CleaningConfig(), keep)
+
+    ms_clean = timed(cl)
+    ctx3.find()
+    ctx3.find()
+    find_ms = ctx3.stats()["find_ms"]
+    dup = torch.zeros(nt[0], dtype=torch.int32, device=dev)
+    nd = [0]
+
+    def dd():
+        nd[0] = ctx3.find_duplicates(0.5, dup)
+
+    ms_dup = timed(dd)
+    out["triplet_seeding_pipeline"] = {
+        "workload": f"{w.name}, seeds from every triplet of layers 0-2",
+        "triplets": nt[0], "make_seeds_ms": ms_seed, "clean_seeds_ms": ms_clean,
+        "kept_after_cleaning": nk[0], "find_ms_all_triplet_seeds": find_ms,
+        "duplicates": nd[0], "find_duplicates_ms": ms_dup}
+    del sev, shit, keep, dup
+    ctx3.close()
+    variants = (("find_material_map",
+                 lambda c: c.load_material(material_map(120.0, 300.0, 24, 30, 0.015, 0.1))),
+                ("find_five_region_steering", lambda c: c.load_steering(five_regions())))
+    for label, setup in variants:
+        c4 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+        c4.load_geometry(w.layers)
+        setup(c4)
+        c4.load_hits(batch.ev_off, *hits)
+        c4.seed(*seeds)
+        tun4 = c4.autotune(repeats=2)
+        c4.find()
+        c4.find()
+        st = c4.stats()
+        c4.close()
+        out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
+                      "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
+                      "unit": UNIT, "workload": w.name, "tuning": tun4}
+    wf = barrel_endcap_field(100, 5000)
+    evs = []
+    for e in range(wf.n_events):
+        evs.append(generate_event(wf, e))
+        if e % 10 == 9:
+            log(f"field events generated: {e + 1}/{wf.n_events}")
+    bf = make_batch(evs)
+    del evs
+    fh = [T(a) for a in (bf.x, bf.y, bf.z, bf.var_u, bf.var_v, bf.layer)]
+    fs = (T(bf.seed_event), T(bf.seed_hits))
+    for label, fld in (("find_parameterised_field", wf.field),
+                       ("find_uniform_field_same_events", None)):
+        c5 = mkf.Context(wf.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
+        c5.load_geometry(wf.layers)
+        c5.load_field(fld)
+        c5.load_hits(bf.ev_off, *fh)
+        c5.seed(*fs)
+        tun5 = c5.autotune(repeats=2)
+        c5.find()
+        c5.find()
+        st = c5.stats()
+        n = int(bf.seed_hits.shape[0])
+        tr = c5.get_tracks(n)
+        c5.close()
+        out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
+                      "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
+                      "unit": UNIT, "workload": wf.name,
+                      "mean_hits_per_track": float(tr["n_hits"].mean()), "tuning": tun5}
+    return out
+
+
+FORMS = ("surrogate", "surrogate_eager", "graph", "batched", "plain_all_events",
+         "plain_per_event")
 
 
 def main():
@@ -301,15 +416,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--events", type=int, default=100)
-    ap.add_argument("--tracks", type=int, default=5000)
-    ap.add_argument("--forms", default="plain,batched,graph,surrogate")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="budget of the oracle CPU baseline (0 disables)")
-    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+    ap.add_argument("--events", type=int, default=512)
+    ap.add_argument("--forms", default=",".join(FORMS))
+    ap.add_argument("--gen-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
+                    help="host processes generating the events (1 under a profiler)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="budget of each leg of the oracle CPU baseline (0 disables)")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
                     help="host processes of the CPU baseline, one event each")
     ap.add_argument("--kernels", type=int, default=1,
-                    help="also time the fit and the surrogate network kernels (0 disables)")
+                    help="also time the fit, backward fit, smoothing and network kernels")
+    ap.add_argument("--extended", type=int, default=0,
+                    help="also time the seeding pipeline and the material, steering and "
+                         "field finds")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -318,13 +437,18 @@ def main():
               "event with no exchange, so more GPUs would run independent copies of this "
               "workload", file=sys.stderr)
         sys.exit(2)
+    forms = [f for f in args.forms.split(",") if f]
+    for f in forms:
+        if f not in FORMS:
+            sys.exit(f"unknown form {f}; known: {', '.join(FORMS)}")
 
     import numpy as np
-    from synth import barrel_endcap, generate
+    from synth import batched_uneven, generate
 
-    w = barrel_endcap(args.events, args.tracks)
+    w = batched_uneven(args.events)
     t0 = time.time()
-    batch = generate(w)
+    log(f"generating {w.name} with {args.gen_workers} processes")
+    batch = generate(w, workers=args.gen_workers)
     log(f"generated {w.name}: {batch.x.shape[0]} hits, {batch.seed_hits.shape[0]} seeds "
         f"in {time.time() - t0:.1f}s")
     fit_inputs = None
@@ -337,8 +461,6 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)  # default priority
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    hits = [T(a) for a in (batch.x, batch.y, batch.z, batch.var_u, batch.var_v, batch.layer)]
-    seeds = (T(batch.seed_event), T(batch.seed_hits))
     torch.cuda.synchronize()
 
     if args.copy_calib:
@@ -347,92 +469,83 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
         log("copy calibration: 3 x 1 GiB copies")
 
-    forms = {"plain": 0, "batched": mkf.F_BATCHED, "graph": mkf.F_BATCHED | mkf.F_GRAPH,
-             "surrogate": mkf.F_BATCHED | mkf.F_GRAPH | mkf.F_SURROGATE}
-    results = {}
-    tracks_ref = None
-    for name in args.forms.split(","):
-        flags = forms[name]
+    train, params = None, None
+    if any(f.startswith("surrogate") for f in forms):
         with torch.cuda.stream(stream):
-            ctx = mkf.Context(w.find, flags=flags, stream=stream.cuda_stream)
-            ctx.load_geometry(w.layers)
-            train = None
-            if flags & mkf.F_SURROGATE:  # trained on the GPU before the timed region
-                train = ctx.surrogate_train(n_samples=1 << 20, epochs=4, batch=512, lr=3e-3,
-                                            seed=11, loss_w=(1, .01, .01, .01, .01, .01, .01))
-            ctx.load_hits(batch.ev_off, *hits)
-            ctx.seed(*seeds)
-            tuning = ctx.autotune(repeats=2) if flags & mkf.F_BATCHED else None
-            for _ in range(args.warmup):
-                ctx.find()
-            torch.cuda.synchronize()
-            main_ms = []
-            find_ms = []
-            t_start = time.perf_counter()
-            for _ in range(args.steps):
-                ctx.find()
-                st = ctx.stats()
-                main_ms.append(st["main_ms"])
-                find_ms.append(st["find_ms"])
-            torch.cuda.synchronize()
-            t_end = time.perf_counter()
-            n_seeds = batch.seed_hits.shape[0]
-            tr = ctx.get_tracks(n_seeds)
-            if tracks_ref is None:
-                tracks_ref = tr
-            same = tr.tobytes() == tracks_ref.tobytes()
-            st = ctx.stats()
-            ctx.close()
-        wall = (t_end - t_start) / args.steps
-        results[name] = {
-            "ms_per_step": wall * 1e3,
-            "find_ms": float(np.mean(find_ms)),
-            "main_ms": float(np.mean(main_ms)),
-            "main_launches": st["main_launches"],
-            "n_steps": st["n_steps"],
-            "value": st["n_steps"] / wall,
-            "identical_to_first_form": bool(same),
-            "same_hits_as_first_form": float(np.mean(np.all(tr["hit"] == tracks_ref["hit"],
-                                                            axis=1))),
-            "tuning": tuning,
-        }
-        if train is not None:
-            results[name]["surrogate"] = {
-                "kept": st["sur_kept"], "rejected": st["sur_rejected"],
-                "kept_frac": st["sur_kept"] / max(1, st["sur_kept"] + st["sur_rejected"]),
-                "train": train}
-        log(name, json.dumps(results[name]))
+            c = mkf.Context(w.find, stream=stream.cuda_stream)
+            c.load_geometry(w.layers)
+            train = c.surrogate_train(**TRAIN)
+            params = c.surrogate_get()
+            c.close()
+        log("surrogate trained", json.dumps(train))
 
-    best = max(results, key=lambda k: results[k]["value"])
-    speedup = None
-    if "surrogate" in results and "plain" in results:
-        speedup = {k: results["surrogate"]["value"] / results[k]["value"]
-                   for k in ("plain", "batched", "graph") if k in results}
-    R = results[best]
-    # roofline of the dominant kernel, from HIP events on the context stream
-    # (a graph replay cannot bracket the kernel with events: take the same
-    # kernel's eager form, else the whole find of the best form)
-    timed = [k for k in (best, "batched", "plain") if k in results and results[k]["main_ms"] > 0]
-    kernel_form = timed[0] if timed else best
-    K = results[kernel_form]
-    kernel_ms = K["main_ms"] if K["main_ms"] > 0 else K["find_ms"]
-    per_launch_steps = K["n_steps"] / max(1, K["main_launches"])
-    per_launch_ms = kernel_ms / max(1, K["main_launches"])
-    if kernel_form == "plain":
-        achieved = PLAIN_BYTES_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_find_step", "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        achieved = FLOPS_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_find_persistent", "bound": "alu", "achieved": achieved,
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = profiled_traffic(roof["kernel"])
-    roof["avg_launch_ms"] = per_launch_ms
+    flag_of = {"surrogate": mkf.F_BATCHED | mkf.F_GRAPH | mkf.F_SURROGATE,
+               "surrogate_eager": mkf.F_BATCHED | mkf.F_SURROGATE,
+               "graph": mkf.F_BATCHED | mkf.F_GRAPH, "batched": mkf.F_BATCHED,
+               "plain_all_events": 0}
+    results, tracks_ref, ref_name = {}, None, None
+    for name in forms:
+        if name == "plain_per_event":
+            res, tr = time_per_event(mkf, w, batch, stream, args, T)
+        else:
+            res, tr = time_form(mkf, w, batch, flag_of[name], stream, args, T,
+                                params=params if name.startswith("surrogate") else None)
+        if tracks_ref is None:
+            tracks_ref, ref_name = tr, name
+        res["identical_to_" + ref_name] = bool(tr.tobytes() == tracks_ref.tobytes())
+        res["same_hits_as_" + ref_name] = float(np.mean(np.all(tr["hit"] == tracks_ref["hit"],
+                                                               axis=1)))
+        results[name] = res
+        log(name, json.dumps(res))
+        torch.cuda.empty_cache()
 
-    kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, hits, seeds)
+    head = "surrogate" if "surrogate" in results else forms[0]
+    R = results[head]
+    plain = next((k for k in ("plain_per_event", "plain_all_events") if k in results), None)
+    ratios = None
+    if plain:
+        ratios = {k: {"wall": results[k]["value"] / results[plain]["value"],
+                      "device": results[k]["device_value"] / results[plain]["device_value"]}
+                  for k in results if k != plain}
+        ratios["plain_form"] = plain
+    # roofline of the dominant kernel of the headline form, from HIP events on
+    # the context stream around its launch (a graph replay cannot bracket the
+    # kernel with events: the same kernel's eager form is timed instead)
+    eager = {"surrogate": "surrogate_eager", "graph": "batched"}.get(head, head)
+    K = results.get(eager, R)
+    roof = None
+    if K.get("main_ms", -1) > 0:
+        per_launch_steps = K["n_steps"] / max(1, K["main_launches"])
+        per_launch_ms = K["main_ms"] / max(1, K["main_launches"])
+        if eager.startswith("plain"):
+            kname = "k_find_step<false>"
+            achieved = PLAIN_BYTES_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e9
+            roof = {"kernel": kname, "bound": "hbm", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            t = K["tuning"] or {"waves_per_simd": 0}
+            kname = (f"k_find_persistent<{t['waves_per_simd']}, "
+                     f"{'true' if eager.startswith('surrogate') else 'false'}, 6>")
+            achieved = FLOPS_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e12
+            roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = profiled_traffic(kname, w.name)
+        roof["avg_launch_ms"] = per_launch_ms
+        roof["timed_form"] = eager
+    plain_roof = None
+    if "plain_all_events" in results and results["plain_all_events"]["main_ms"] > 0:
+        P = results["plain_all_events"]
+        gbs = PLAIN_BYTES_PER_STEP * P["n_steps"] / (P["main_ms"] * 1e-3) / 1e9
+        plain_roof = {"kernel": "k_find_step<false>", "bound": "hbm", "achieved": gbs,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                      "launches": P["main_launches"], "ms": P["main_ms"],
+                      "traffic": profiled_traffic("k_find_step<false>", w.name)}
+
+    kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, args.extended)
                if args.kernels else None)
 
     cpu = None
@@ -452,13 +565,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "events": args.events, "tracks_per_event": args.tracks,
+        "config": {"workload": w.name, "events": w.n_events,
+                   "tracks_per_event": "log-uniform 500-20000",
                    "seeds": int(batch.seed_hits.shape[0]), "hits": int(batch.x.shape[0]),
-                   "form": best, "candidates_per_seed": w.find.n_cand},
+                   "form": head + " (persistent launch, HIP graph, learned surrogate)"
+                   if head == "surrogate" else head,
+                   "candidates_per_seed": w.find.n_cand},
         "forms": results,
-        "surrogate_speedup": speedup,
+        "vs_plain": ratios,
+        "surrogate_training": train,
         "kernels": kernels,
         "roofline": roof,
+        "plain_roofline": plain_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

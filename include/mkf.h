@@ -385,23 +385,32 @@ mkf_status mkf_clean_seeds(mkf_ctx *ctx, const mkf_cleaning *cc, int32_t *out_ke
 /* Counters and timings of the last calls. */
 mkf_status mkf_get_stats(mkf_ctx *ctx, mkf_stats *out);
 
-/* Launch shape of the persistent find (MKF_F_BATCHED).  Results do not
- * depend on it. */
+/* Launch shape of the persistent find (MKF_F_BATCHED) and binning of the
+ * hit index.  Results do not depend on it (tested bit for bit). */
 typedef struct {
   int32_t waves_per_simd; /* register budget of the persistent kernel, 1..4
                              (more waves hide more latency, but spill) */
   int32_t blocks_per_cu;  /* persistent grid = blocks_per_cu x compute units, 1..32 */
+  int32_t lane_group;     /* lanes per seed: 6 (a wavefront tile of 10 seeds; candidate
+                             budgets up to 6) or 8 (8 seeds); 0: 6 when the budget allows */
+  int32_t phi_bin_shift;  /* hit-index bins per layer: the layer records' counts times */
+  int32_t q_bin_shift;    /*   2^shift (-2..2; clamped to 1..4096 in phi, 1..1024 in q) */
 } mkf_tuning;
 
+/* Set the tuning.  A change of the bin shifts rebuilds the hit index of
+ * loaded hits (seeds stay valid).  MKF_E_ARG for values out of range. */
 mkf_status mkf_set_tuning(mkf_ctx *ctx, const mkf_tuning *t);
 mkf_status mkf_get_tuning(mkf_ctx *ctx, mkf_tuning *t);
 
-/* Time the persistent find for each candidate launch shape on the loaded
- * seeds (best of `repeats` runs each, repeats >= 1) and keep the fastest
- * (written to *best if not NULL).  cache_path (may be NULL) names a text
- * file of earlier results keyed by GPU architecture, compute units and
- * workload size: a matching line is used without searching, a search
- * appends its result.  Blocks until done. */
+/* Autotuner of the persistent find on the loaded seeds: first the launch
+ * shape (lane group 6 or 8, waves per SIMD 1..4, 1 or 2 x waves blocks per
+ * CU), then at that shape the hit-index binning (phi and q bin shifts
+ * -1..1, the index rebuilt for each), each timed as the best of `repeats`
+ * runs (repeats >= 1); the fastest is kept (written to *best if not NULL).
+ * cache_path (may be NULL) names a text file of earlier results keyed by
+ * GPU architecture, compute units, kernel form and workload size: a
+ * matching line is used without searching, a search appends its result.
+ * Blocks until done. */
 mkf_status mkf_autotune(mkf_ctx *ctx, int32_t repeats, const char *cache_path,
                         mkf_tuning *best);
 

@@ -49,6 +49,7 @@ enum Stage { kCreated = 0, kGeometry = 1, kHits = 2, kSeeds = 3, kFound = 4 };
 
 }  // namespace
 
+
 struct mkf_ctx {
   mkf_config cfg{};
   hipStream_t stream = nullptr;
@@ -56,6 +57,7 @@ struct mkf_ctx {
   int stage = kCreated;
 
   int n_layers = 0;
+  mkf_layer user_layers[kMaxLayers]{};  // as loaded (bin counts before the tuning's shifts)
   DevLayer layers[kMaxLayers]{};
   int bins_per_event = 0;
   DevBuf d_layers;
@@ -95,8 +97,9 @@ struct mkf_ctx {
   int graph_launches = 0;
   mkf_stats stats{};
   int n_cu = 0;
+  int device = 0;  // the device current at mkf_create
   std::string arch;
-  mkf_tuning tuning{2, 8};
+  mkf_tuning tuning{2, 8, 0, 0, 0};
 
   // learned surrogate: master weights, Adam moments, BF16 images, counters
   DevBuf d_mlp_param, d_mlp_m, d_mlp_v, d_W1p, d_W2p, d_W3p, d_W2T, d_W3T, d_mb1, d_mb2, d_mb3;
@@ -334,6 +337,7 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   c->n_cu = std::max(1, n_cu);
+  c->device = dev;
   if (hipError_t em = mlp_setup(c)) {
     delete c;
     return fail(nullptr, MKF_E_HIP, "surrogate setup failed: %s", hipGetErrorString(em));
@@ -358,12 +362,91 @@ const char *mkf_last_error(const mkf_ctx *ctx) {
   return ctx ? ctx->err.c_str() : g_create_error.c_str();
 }
 
+}  // extern "C"
+
+namespace {
+
+int shifted_bins(int n, int shift, int max) {
+  const int64_t v = shift >= 0 ? (int64_t)n << shift : (int64_t)n >> -shift;
+  return (int)std::min<int64_t>(std::max<int64_t>(v, 1), max);
+}
+
+// Device layer records from the loaded layers and the tuning's bin shifts.
+mkf_status upload_layers(mkf_ctx *c) {
+  int base = 0;
+  DevLayer dl[kMaxLayers]{};
+  for (int i = 0; i < c->n_layers; ++i) {
+    const mkf_layer &L = c->user_layers[i];
+    const int nphi = shifted_bins(L.n_phi_bins, c->tuning.phi_bin_shift, 4096);
+    const int nq = shifted_bins(L.n_q_bins, c->tuning.q_bin_shift, 1024);
+    DevLayer &d = dl[i];
+    d.kind = L.kind;
+    d.pos = L.pos;
+    d.lo = L.ext_lo;
+    d.hi = L.ext_hi;
+    d.vu_max = L.var_u_max;
+    d.vv_max = L.var_v_max;
+    d.nphi = nphi;
+    d.nq = nq;
+    d.bin_base = base;
+    d.q_lo = L.ext_lo;
+    d.q_scale = (float)nq / (L.ext_hi - L.ext_lo);
+    d.phi_scale = (float)nphi / kTwoPi;
+    d.cs = L.stereo == 0.f ? 1.f : std::cos(L.stereo);
+    d.sn = L.stereo == 0.f ? 0.f : std::sin(L.stereo);
+    d.hole_lo = L.hole_lo < L.hole_hi ? L.hole_lo : 0.f;
+    d.hole_hi = L.hole_lo < L.hole_hi ? L.hole_hi : 0.f;
+    base += nphi * nq;
+  }
+  HIP_TRY(c, c->d_layers.ensure(sizeof(DevLayer) * kMaxLayers));
+  HIP_TRY(c, hipMemcpyAsync(c->d_layers.ptr, dl, sizeof(dl), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(c->layers, dl, sizeof(dl));
+  c->bins_per_event = base;
+  return MKF_OK;
+}
+
+// The binned hit index of the loaded hits (count, scan, scatter), for the
+// current layer records.
+mkf_status build_index(mkf_ctx *c) {
+  const int64_t n_hits = c->n_hits;
+  const int64_t total_bins = (int64_t)c->n_events * c->bins_per_event;
+  if (total_bins >= ((int64_t)1 << 31) - 1)
+    return fail(c, MKF_E_CAPACITY, "events x bins exceed the index size");
+  HIP_TRY(c, c->d_hit_bin.ensure(sizeof(int) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, c->d_counts.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
+  HIP_TRY(c, c->d_fill.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
+  HIP_TRY(c, c->d_bin_start.ensure(sizeof(int) * (size_t)(total_bins + 1)));
+  HIP_TRY(c, c->d_scan_tmp.ensure(sizeof(int) * (size_t)(4 * (total_bins / 2048 + 4) + 64)));
+  HIP_TRY(c, c->d_sorted.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, c->d_byorig.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
+  launch_fill_i32(c->stream, c->d_counts.as<int>(), total_bins, 0);
+  launch_fill_i32(c->stream, c->d_fill.as<int>(), total_bins, 0);
+  FindParams P = params(c);
+  launch_hit_bins(c->stream, P, n_hits, c->d_layer.as<int>(), c->d_hit_bin.as<int>(),
+                  c->d_counts.as<int>());
+  launch_scan(c->stream, c->d_counts.as<int>(), c->d_bin_start.as<int>(), total_bins,
+              c->d_scan_tmp.as<int>(), nullptr);
+  launch_scatter(c->stream, P, n_hits, c->d_hit_bin.as<int>(), c->d_fill.as<int>(),
+                 c->d_sorted.as<HitRec>(), c->d_byorig.as<HitRec>());
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev_b));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+  c->stats.index_ms = ms;
+  return MKF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_layers) {
   if (!c) return MKF_E_ARG;
   if (!layers || n_layers <= 0 || n_layers > MKF_MAX_LAYERS)
     return fail(c, MKF_E_ARG, "need 1..%d layers", MKF_MAX_LAYERS);
-  int base = 0;
-  DevLayer dl[kMaxLayers]{};
   for (int i = 0; i < n_layers; ++i) {
     const mkf_layer &L = layers[i];
     if (L.kind != MKF_BARREL && L.kind != MKF_DISK)
@@ -384,31 +467,11 @@ mkf_status mkf_load_geometry(mkf_ctx *c, const mkf_layer *layers, int32_t n_laye
       return fail(c, MKF_E_GEOMETRY, "layer %d: stereo angle must lie in (-pi/2, pi/2)", i);
     if (!finite_f(L.hole_lo) || !finite_f(L.hole_hi))
       return fail(c, MKF_E_GEOMETRY, "layer %d: bad hole", i);
-    DevLayer &d = dl[i];
-    d.kind = L.kind;
-    d.pos = L.pos;
-    d.lo = L.ext_lo;
-    d.hi = L.ext_hi;
-    d.vu_max = L.var_u_max;
-    d.vv_max = L.var_v_max;
-    d.nphi = L.n_phi_bins;
-    d.nq = L.n_q_bins;
-    d.bin_base = base;
-    d.q_lo = L.ext_lo;
-    d.q_scale = (float)L.n_q_bins / (L.ext_hi - L.ext_lo);
-    d.phi_scale = (float)L.n_phi_bins / kTwoPi;
-    d.cs = L.stereo == 0.f ? 1.f : std::cos(L.stereo);
-    d.sn = L.stereo == 0.f ? 0.f : std::sin(L.stereo);
-    d.hole_lo = L.hole_lo < L.hole_hi ? L.hole_lo : 0.f;
-    d.hole_hi = L.hole_lo < L.hole_hi ? L.hole_hi : 0.f;
-    base += L.n_phi_bins * L.n_q_bins;
   }
-  HIP_TRY(c, c->d_layers.ensure(sizeof(DevLayer) * kMaxLayers));
-  HIP_TRY(c, hipMemcpyAsync(c->d_layers.ptr, dl, sizeof(dl), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memcpy(c->layers, dl, sizeof(dl));
+  std::memcpy(c->user_layers, layers, sizeof(mkf_layer) * n_layers);
   c->n_layers = n_layers;
-  c->bins_per_event = base;
+  mkf_status st = upload_layers(c);
+  if (st != MKF_OK) return st;
   c->n_regions = 0;
   c->stage = kGeometry;
   return MKF_OK;
@@ -568,31 +631,7 @@ mkf_status mkf_load_hits(mkf_ctx *c, int32_t n_events, const int64_t *ev_off, co
   c->n_events = n_events;
   c->n_hits = n_hits;
   c->ev_off.assign(ev_off, ev_off + n_events + 1);
-
-  // binned index: count, scan, scatter
-  HIP_TRY(c, c->d_hit_bin.ensure(sizeof(int) * (size_t)std::max<int64_t>(n_hits, 1)));
-  HIP_TRY(c, c->d_counts.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
-  HIP_TRY(c, c->d_fill.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
-  HIP_TRY(c, c->d_bin_start.ensure(sizeof(int) * (size_t)(total_bins + 1)));
-  HIP_TRY(c, c->d_scan_tmp.ensure(sizeof(int) * (size_t)(4 * (total_bins / 2048 + 4) + 64)));
-  HIP_TRY(c, c->d_sorted.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
-  HIP_TRY(c, c->d_byorig.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
-  HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
-  launch_fill_i32(c->stream, c->d_counts.as<int>(), total_bins, 0);
-  launch_fill_i32(c->stream, c->d_fill.as<int>(), total_bins, 0);
-  FindParams P = params(c);
-  launch_hit_bins(c->stream, P, n_hits, c->d_layer.as<int>(), c->d_hit_bin.as<int>(),
-                  c->d_counts.as<int>());
-  launch_scan(c->stream, c->d_counts.as<int>(), c->d_bin_start.as<int>(), total_bins,
-              c->d_scan_tmp.as<int>(), nullptr);
-  launch_scatter(c->stream, P, n_hits, c->d_hit_bin.as<int>(), c->d_fill.as<int>(),
-                 c->d_sorted.as<HitRec>(), c->d_byorig.as<HitRec>());
-  HIP_TRY(c, hipGetLastError());
-  HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
-  HIP_TRY(c, hipEventSynchronize(c->ev_b));
-  float ms = 0.f;
-  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
-  c->stats.index_ms = ms;
+  if ((st = build_index(c))) return st;
   c->stage = kHits;
   c->n_seeds = 0;
   return MKF_OK;
@@ -790,7 +829,8 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
     ++launches;
     if (main_a) (void)hipEventRecord(main_a, c->stream);
     launch_find_persistent(c->stream, P, c->tuning.blocks_per_cu * c->n_cu,
-                           c->tuning.waves_per_simd, (c->cfg.flags & MKF_F_SURROGATE) != 0);
+                           c->tuning.waves_per_simd, (c->cfg.flags & MKF_F_SURROGATE) != 0,
+                           c->tuning.lane_group);
     ++launches;
     c->stats.main_launches = 1;
   } else {
@@ -1114,14 +1154,39 @@ mkf_status mkf_get_stats(mkf_ctx *c, mkf_stats *out) {
   return MKF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+bool tuning_ok(const mkf_ctx *c, const mkf_tuning &t) {
+  return t.waves_per_simd >= 1 && t.waves_per_simd <= 4 && t.blocks_per_cu >= 1 &&
+         t.blocks_per_cu <= 32 &&
+         (t.lane_group == 0 || t.lane_group == 8 || (t.lane_group == 6 && c->cfg.n_cand <= 6)) &&
+         t.phi_bin_shift >= -2 && t.phi_bin_shift <= 2 && t.q_bin_shift >= -2 &&
+         t.q_bin_shift <= 2;
+}
+
+// Apply a tuning; a change of the binning rebuilds the layer records and
+// the index of loaded hits.
+mkf_status apply_tuning(mkf_ctx *c, const mkf_tuning &t) {
+  const bool rebin =
+      t.phi_bin_shift != c->tuning.phi_bin_shift || t.q_bin_shift != c->tuning.q_bin_shift;
+  c->tuning = t;
+  drop_graph(c);
+  if (!rebin || c->n_layers == 0) return MKF_OK;
+  mkf_status st = upload_layers(c);
+  if (st == MKF_OK && c->stage >= kHits) st = build_index(c);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 mkf_status mkf_set_tuning(mkf_ctx *c, const mkf_tuning *t) {
   if (!c) return MKF_E_ARG;
-  if (!t || t->waves_per_simd < 1 || t->waves_per_simd > 4 || t->blocks_per_cu < 1 ||
-      t->blocks_per_cu > 32)
-    return fail(c, MKF_E_ARG, "tuning out of range");
-  c->tuning = *t;
-  drop_graph(c);
-  return MKF_OK;
+  if (!t || !tuning_ok(c, *t)) return fail(c, MKF_E_ARG, "tuning out of range");
+  return apply_tuning(c, *t);
 }
 
 mkf_status mkf_get_tuning(mkf_ctx *c, mkf_tuning *t) {
@@ -1148,53 +1213,78 @@ mkf_status mkf_autotune(mkf_ctx *c, int32_t repeats, const char *cache_path, mkf
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "r")) {
       char line[512];
-      mkf_tuning hit{0, 0};
+      mkf_tuning hit{0, 0, 0, 0, 0};
+      bool found = false;
       while (fgets(line, sizeof line, f)) {
         const size_t kl = strlen(key);
-        int w = 0, b = 0;
+        mkf_tuning t{};
         if (strncmp(line, key, kl) == 0 && line[kl] == '\t' &&
-            sscanf(line + kl + 1, "%d %d", &w, &b) == 2)
-          hit = mkf_tuning{w, b};
+            sscanf(line + kl + 1, "%d %d %d %d %d", &t.waves_per_simd, &t.blocks_per_cu,
+                   &t.lane_group, &t.phi_bin_shift, &t.q_bin_shift) == 5 &&
+            tuning_ok(c, t)) {
+          hit = t;
+          found = true;
+        }
       }
       fclose(f);
-      if (hit.waves_per_simd >= 1 && hit.waves_per_simd <= 4 && hit.blocks_per_cu >= 1 &&
-          hit.blocks_per_cu <= 32) {
-        c->tuning = hit;
-        drop_graph(c);
-        if (best) *best = hit;
-        return MKF_OK;
+      if (found) {
+        mkf_status st = apply_tuning(c, hit);
+        if (st == MKF_OK && best) *best = hit;
+        return st;
       }
     }
   }
   const uint32_t flags = c->cfg.flags;
   c->cfg.flags &= ~MKF_F_GRAPH;  // time eager launches
-  drop_graph(c);
-  mkf_tuning keep = c->tuning, win = c->tuning;
+  const mkf_tuning keep = c->tuning;
+  mkf_tuning win = c->tuning;
   float win_ms = 1e30f;
-  for (int w = 1; w <= 4; ++w)
-    for (int mult = 1; mult <= 2; ++mult) {
-      c->tuning = mkf_tuning{w, w * mult};
-      float ms = 1e30f;
-      for (int r = 0; r < repeats; ++r) {
-        mkf_status st = mkf_find(c);
-        if (st != MKF_OK) {
-          c->tuning = keep;
-          c->cfg.flags = flags;
-          return st;
-        }
-        ms = std::min(ms, c->stats.main_ms);
-      }
-      if (ms < win_ms) {
-        win_ms = ms;
-        win = c->tuning;
-      }
+  mkf_status st = MKF_OK;
+  auto time_shape = [&](const mkf_tuning &t) -> mkf_status {
+    mkf_status s2 = apply_tuning(c, t);
+    if (s2 != MKF_OK) return s2;
+    float ms = 1e30f;
+    for (int r = 0; r < repeats; ++r) {
+      s2 = mkf_find(c);
+      if (s2 != MKF_OK) return s2;
+      ms = std::min(ms, c->stats.main_ms);
     }
-  c->tuning = win;
+    if (ms < win_ms) {
+      win_ms = ms;
+      win = c->tuning;
+    }
+    return MKF_OK;
+  };
+  // launch shape at the current binning
+  const int groups[2] = {6, 8};
+  for (int gi = c->cfg.n_cand <= 6 ? 0 : 1; gi < 2 && st == MKF_OK; ++gi)
+    for (int w = 1; w <= 4 && st == MKF_OK; ++w)
+      for (int mult = 1; mult <= 2 && st == MKF_OK; ++mult)
+        st = time_shape(mkf_tuning{w, w * mult, groups[gi], keep.phi_bin_shift, keep.q_bin_shift});
+  // binning at that shape
+  const mkf_tuning shape = win;
+  for (int sp = -1; sp <= 1 && st == MKF_OK; ++sp)
+    for (int sq = -1; sq <= 1 && st == MKF_OK; ++sq) {
+      if (sp == shape.phi_bin_shift && sq == shape.q_bin_shift) continue;
+      mkf_tuning t = shape;
+      t.phi_bin_shift = sp;
+      t.q_bin_shift = sq;
+      st = time_shape(t);
+    }
   c->cfg.flags = flags;
+  if (st != MKF_OK) {
+    std::string e = c->err;
+    (void)apply_tuning(c, keep);
+    c->err = e;
+    return st;
+  }
+  st = apply_tuning(c, win);
+  if (st != MKF_OK) return st;
   if (best) *best = win;
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "a")) {
-      fprintf(f, "%s\t%d %d %.4f\n", key, win.waves_per_simd, win.blocks_per_cu, win_ms);
+      fprintf(f, "%s\t%d %d %d %d %d %.4f\n", key, win.waves_per_simd, win.blocks_per_cu,
+              win.lane_group, win.phi_bin_shift, win.q_bin_shift, win_ms);
       fclose(f);
     }
   }

@@ -2113,43 +2113,40 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
   else hipLaunchKernelGGL(k_find_step<false>, dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
-template <bool kSurr>
-static void launch_persistent_t(hipStream_t s, const FindParams &P, int grid, int waves) {
-  if (P.cfg.n_cand > 6) {  // 8-lane groups, one occupancy target
-    const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 8, Grp<8>::kSeeds);
-    hipLaunchKernelGGL((k_find_persistent<2, kSurr, 8>), dim3(grid), dim3(256), lds, s, P);
-    return;
-  }
-  const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 6, Grp<6>::kSeeds);
-  switch (waves) {
-    case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
-    case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
-    case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
-    default: hipLaunchKernelGGL((k_find_persistent<2, kSurr, 6>), dim3(grid), dim3(256), lds, s, P); break;
+template <int G, bool kSurr, bool kMat>
+static void launch_persistent_g(hipStream_t s, const FindParams &P, int grid, int waves) {
+  const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, G, Grp<G>::kSeeds);
+  if constexpr (kMat) {
+    switch (waves) {
+      case 1: hipLaunchKernelGGL((k_find_persistent_mat<1, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 3: hipLaunchKernelGGL((k_find_persistent_mat<3, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 4: hipLaunchKernelGGL((k_find_persistent_mat<4, G>), dim3(grid), dim3(256), lds, s, P); break;
+      default: hipLaunchKernelGGL((k_find_persistent_mat<2, G>), dim3(grid), dim3(256), lds, s, P); break;
+    }
+  } else {
+    switch (waves) {
+      case 1: hipLaunchKernelGGL((k_find_persistent<1, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 3: hipLaunchKernelGGL((k_find_persistent<3, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 4: hipLaunchKernelGGL((k_find_persistent<4, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+      default: hipLaunchKernelGGL((k_find_persistent<2, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+    }
   }
 }
 
-static void launch_persistent_mat(hipStream_t s, const FindParams &P, int grid, int waves) {
-  if (P.cfg.n_cand > 6) {
-    const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 8, Grp<8>::kSeeds);
-    hipLaunchKernelGGL((k_find_persistent_mat<2, 8>), dim3(grid), dim3(256), lds, s, P);
-    return;
-  }
-  const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, 6, Grp<6>::kSeeds);
-  switch (waves) {
-    case 1: hipLaunchKernelGGL((k_find_persistent_mat<1, 6>), dim3(grid), dim3(256), lds, s, P); break;
-    case 3: hipLaunchKernelGGL((k_find_persistent_mat<3, 6>), dim3(grid), dim3(256), lds, s, P); break;
-    case 4: hipLaunchKernelGGL((k_find_persistent_mat<4, 6>), dim3(grid), dim3(256), lds, s, P); break;
-    default: hipLaunchKernelGGL((k_find_persistent_mat<2, 6>), dim3(grid), dim3(256), lds, s, P); break;
-  }
+template <bool kSurr, bool kMat>
+static void launch_persistent_k(hipStream_t s, const FindParams &P, int grid, int waves,
+                                int group) {
+  // 6-lane groups only hold budgets up to 6 candidates
+  if (group == 8 || P.cfg.n_cand > 6) launch_persistent_g<8, kSurr, kMat>(s, P, grid, waves);
+  else launch_persistent_g<6, kSurr, kMat>(s, P, grid, waves);
 }
 
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
-                            bool surrogate) {
+                            bool surrogate, int group) {
   if (P.n_seeds == 0) return;
-  if (P.cfg.mat.tab || P.cfg.field.on) launch_persistent_mat(s, P, grid_blocks, waves);
-  else if (surrogate) launch_persistent_t<true>(s, P, grid_blocks, waves);
-  else launch_persistent_t<false>(s, P, grid_blocks, waves);
+  if (P.cfg.mat.tab || P.cfg.field.on) launch_persistent_k<false, true>(s, P, grid_blocks, waves, group);
+  else if (surrogate) launch_persistent_k<true, false>(s, P, grid_blocks, waves, group);
+  else launch_persistent_k<false, false>(s, P, grid_blocks, waves, group);
 }
 
 void launch_finalize(hipStream_t s, const FindParams &P) {

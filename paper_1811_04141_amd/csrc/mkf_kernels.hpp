@@ -143,8 +143,9 @@ void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int
                           int *pevent, int8_t *pplan);
 void launch_find_init(hipStream_t s, const FindParams &P);
 void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active_seeds);
+// group: lanes per seed (6 or 8; 8 whenever the candidate budget exceeds 6)
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
-                            bool surrogate);
+                            bool surrogate, int group);
 void launch_finalize(hipStream_t s, const FindParams &P);
 void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,
                       const float *cov, const int *layer, float *out_par, float *out_cov,

@@ -133,7 +133,9 @@ class TrainReport(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("waves_per_simd", C.c_int32), ("blocks_per_cu", C.c_int32)]
+    _fields_ = [("waves_per_simd", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("lane_group", C.c_int32), ("phi_bin_shift", C.c_int32),
+                ("q_bin_shift", C.c_int32)]
 
 
 def _load():
@@ -368,19 +370,22 @@ class Context:
         self._check(lib.mkf_find_duplicates(self.h, float(frac), _ptr(out_dup), C.byref(n)))
         return int(n.value)
 
-    def set_tuning(self, waves_per_simd, blocks_per_cu):
-        self._check(lib.mkf_set_tuning(self.h, C.byref(Tuning(waves_per_simd, blocks_per_cu))))
+    def set_tuning(self, waves_per_simd, blocks_per_cu, lane_group=0, phi_bin_shift=0,
+                   q_bin_shift=0):
+        self._check(lib.mkf_set_tuning(self.h, C.byref(Tuning(waves_per_simd, blocks_per_cu,
+                                                               lane_group, phi_bin_shift,
+                                                               q_bin_shift))))
 
     def get_tuning(self):
         t = Tuning()
         self._check(lib.mkf_get_tuning(self.h, C.byref(t)))
-        return {"waves_per_simd": t.waves_per_simd, "blocks_per_cu": t.blocks_per_cu}
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def autotune(self, repeats=2, cache_path=None):
         t = Tuning()
         self._check(lib.mkf_autotune(self.h, repeats,
                                      cache_path.encode() if cache_path else None, C.byref(t)))
-        return {"waves_per_simd": t.waves_per_simd, "blocks_per_cu": t.blocks_per_cu}
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     # ---- learned propagation surrogate
 

@@ -182,8 +182,10 @@ def test_batched_equals_layer_synchronous_bitwise(mkf, n_cand):
 
 
 def test_launch_shapes_do_not_change_results(mkf, tmp_path):
-    """Every persistent-kernel launch shape the autotuner may pick gives
-    bitwise the same tracks; the autotuner's cache round-trips."""
+    """Every persistent-kernel launch shape and hit-index binning the
+    autotuner may pick (waves per SIMD, blocks per CU, 6- or 8-lane seed
+    groups, bin counts halved to quadrupled) gives bitwise the same tracks,
+    in both find forms; the autotuner's cache round-trips."""
     w = barrel_endcap()
     b = generate(w, events=[5, 6])
     ctx = mkf.Context(w.find, flags=mkf.F_BATCHED)
@@ -193,18 +195,43 @@ def test_launch_shapes_do_not_change_results(mkf, tmp_path):
     ctx.seed(dev(b.seed_event), dev(b.seed_hits))
     n = b.seed_hits.shape[0]
     ref = None
-    for waves, bpc in [(2, 8), (1, 1), (3, 3), (4, 8)]:
-        ctx.set_tuning(waves, bpc)
+    shapes = [(2, 8, 0, 0, 0), (1, 1, 6, 0, 0), (3, 3, 6, 0, 0), (4, 8, 6, 0, 0),
+              (1, 2, 8, 0, 0), (2, 4, 8, 0, 0), (3, 6, 8, 0, 0), (4, 4, 8, 0, 0),
+              (3, 3, 6, -1, 1), (3, 3, 6, 1, -1), (2, 2, 8, 2, 2), (3, 3, 6, -2, -2)]
+    for shape in shapes:
+        print("shape", shape, flush=True)
+        ctx.set_tuning(*shape)
+        assert ctx.get_tuning() == dict(zip(("waves_per_simd", "blocks_per_cu", "lane_group",
+                                             "phi_bin_shift", "q_bin_shift"), shape))
         ctx.find()
         tr = ctx.get_tracks(n)
         ref = tr if ref is None else ref
-        assert tr.tobytes() == ref.tobytes(), (waves, bpc)
+        assert tr.tobytes() == ref.tobytes(), shape
+    # the layer-synchronous form on a rebinned index
+    c2 = mkf.Context(w.find)
+    c2.load_geometry(w.layers)
+    c2.set_tuning(2, 8, 0, 1, -1)
+    c2.load_hits(b.ev_off, dev(b.x), dev(b.y), dev(b.z), dev(b.var_u), dev(b.var_v),
+                 dev(b.layer))
+    c2.seed(dev(b.seed_event), dev(b.seed_hits))
+    c2.find()
+    assert c2.get_tracks(n).tobytes() == ref.tobytes()
+    c2.set_tuning(2, 8, 0, -1, 2)  # rebuilt with the hits loaded
+    c2.find()
+    assert c2.get_tracks(n).tobytes() == ref.tobytes()
+    c2.close()
     cache = str(tmp_path / "tune.txt")
     t1 = ctx.autotune(repeats=1, cache_path=cache)
+    print("autotuned", t1, flush=True)
     t2 = ctx.autotune(repeats=1, cache_path=cache)
     assert t1 == t2 and open(cache).read().count("\n") == 1
+    assert ctx.get_tuning() == t1
     ctx.find()
     assert ctx.get_tracks(n).tobytes() == ref.tobytes()
+    with pytest.raises(mkf.MkfError):
+        ctx.set_tuning(2, 8, 7, 0, 0)
+    with pytest.raises(mkf.MkfError):
+        ctx.set_tuning(2, 8, 0, 3, 0)
     ctx.close()
 
 

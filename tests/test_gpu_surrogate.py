@@ -255,7 +255,9 @@ def test_adam_step_and_schedule_match_oracle(mkf, geo_ctx):
     x, t, v = samples(mkf, ctx, n, seed)
     xg, tg, vg = (a.cpu().numpy().astype(np.float64) for a in (x, t, v))
     rng = np.random.default_rng(22)
-    b1, b2, eps = 0.9, 0.999, 1e-8
+    # the library's hyperparameters are FP32 numbers (1 - 0.999f differs
+    # from 0.001 by 1.3e-5 relative): the oracle takes them at those values
+    b1, b2, eps = (float(np.float32(v)) for v in (0.9, 0.999, 1e-8))
     for s in (0, 13, S - 1):
         p0 = glorot(rng)
         if s == 0:  # a schedule's first step starts from fresh moments
