@@ -495,6 +495,20 @@ mkf_status mkf_surrogate_set_state(mkf_ctx *ctx, const float *params, const floa
 mkf_status mkf_surrogate_grad(mkf_ctx *ctx, int32_t n, const float *x, const float *t,
                               const float *loss_w, float *grad, float *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the loss
+ * and gradient of mkf_surrogate_grad, with device outputs grad [5,191] and
+ * loss [1], queued on the context's stream without waiting (x, t device;
+ * loss_w host [7], read before the call returns).  n is a positive multiple
+ * of 64 up to MKF_NOALLOC_MAX_SAMPLES (MKF_E_CAPACITY above).  It allocates
+ * nothing: its scratch is one fixed 5.5 MB array per GPU, held until the
+ * process ends and shared by every context on that GPU, so calls that
+ * overlap on one GPU (other streams or host threads) race and must be
+ * ordered by the caller. */
+#define MKF_NOALLOC_MAX_SAMPLES 16384
+mkf_status mkf_surrogate_grad_noalloc(mkf_ctx *ctx, int32_t n, const float *x, const float *t,
+                                      const float *loss_w, float *grad, float *loss);
+
 /* Outputs y [n][7] (device) for inputs x [n][8] (device). */
 mkf_status mkf_surrogate_infer(mkf_ctx *ctx, int64_t n, const float *x, float *y);
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -46,6 +47,43 @@ struct DevBuf {
 };
 
 enum Stage { kCreated = 0, kGeometry = 1, kHits = 2, kSeeds = 3, kFound = 4 };
+
+}  // namespace
+
+// Scratch of mkf_surrogate_grad_noalloc, for callers that cannot allocate:
+// the per-wave partial gradient rows of up to kNoAllocMaxSamples samples,
+// their first-level sums and the per-sample weights.  Each GPU holds one
+// copy (5.5 MB) for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress gives on that device.
+constexpr int kNoAllocMaxSamples = MKF_NOALLOC_MAX_SAMPLES;
+constexpr int kNoAllocMaxWaves = kNoAllocMaxSamples / 64;
+constexpr size_t kNoAllocPartial = (size_t)kNoAllocMaxWaves * (kNParam + 1);
+constexpr size_t kNoAllocPartial2 = (size_t)(kNoAllocMaxWaves / kReduceGroup + 1) * (kNParam + 1);
+constexpr size_t kNoAllocFloats = kNoAllocPartial + kNoAllocPartial2 + kNoAllocMaxSamples;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices] = {};  // device address of scratch, per device
+
+// Resolves scratch's device address on the current device, once per device.
+hipError_t resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[dev] = static_cast<float *>(ptr);
+  return hipSuccess;
+}
+
+float *scratch_on(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev >= 0 && dev < kMaxDevices ? g_scratch[dev] : nullptr;
+}
 
 }  // namespace
 
@@ -338,6 +376,11 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   c->n_cu = std::max(1, n_cu);
   c->device = dev;
+  if (hipError_t es = resolve_scratch(dev)) {
+    delete c;
+    return fail(nullptr, MKF_E_HIP, "scratch address on device %d: %s", dev,
+                hipGetErrorString(es));
+  }
   if (hipError_t em = mlp_setup(c)) {
     delete c;
     return fail(nullptr, MKF_E_HIP, "surrogate setup failed: %s", hipGetErrorString(em));
@@ -1516,6 +1559,29 @@ mkf_status mkf_surrogate_grad(mkf_ctx *c, int32_t n, const float *x, const float
   HIP_TRY(c, hipMemcpyAsync(loss, c->d_grad.as<float>() + kNParam, sizeof(float),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_grad_noalloc(mkf_ctx *c, int32_t n, const float *x, const float *t,
+                                      const float *loss_w, float *grad, float *loss) {
+  if (!c) return MKF_E_ARG;
+  if (n < 64 || n % 64 != 0)
+    return fail(c, MKF_E_ARG, "n must be a positive multiple of 64");
+  if (n > kNoAllocMaxSamples)
+    return fail(c, MKF_E_CAPACITY, "n = %d exceeds the %d samples the fixed scratch holds", n,
+                kNoAllocMaxSamples);
+  if (!x || !t || !loss_w || !grad || !loss) return fail(c, MKF_E_ARG, "null argument");
+  for (int j = 0; j < kNO; ++j)
+    if (!finite_f(loss_w[j])) return fail(c, MKF_E_ARG, "loss weights must be finite");
+  float *base = scratch_on(c->device);
+  if (!base) return fail(c, MKF_E_HIP, "no scratch on device %d", c->device);
+  float *partial = base, *partial2 = base + kNoAllocPartial;
+  float *weight = partial2 + kNoAllocPartial2;
+  const int waves = n / 64;
+  launch_fill_i32(c->stream, reinterpret_cast<int *>(weight), n, 0x3F800000);  // 1.0f
+  launch_mlp_grad(c->stream, mlp_buffers(c).weights(), x, t, weight, n, 0, n, loss_w, partial);
+  launch_mlp_reduce(c->stream, mlp_buffers(c), partial, waves, 1, 0.f, 0, grad, loss, partial2);
+  HIP_TRY(c, hipGetLastError());
   return MKF_OK;
 }
 

@@ -18,6 +18,7 @@ MKF_OK, MKF_E_ARG, MKF_E_ORDER, MKF_E_CAPACITY, MKF_E_HIP, MKF_E_GEOMETRY, MKF_E
 MEM_HOST, MEM_DEVICE = 0, 1
 F_BATCHED, F_GRAPH, F_SURROGATE = 1, 2, 4
 MLP_NPARAM = 5191  # W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]
+NOALLOC_MAX_SAMPLES = 16384  # MKF_NOALLOC_MAX_SAMPLES
 MAX_LAYERS = MAX_PLAN = 32
 MAX_CAND = 8
 MAX_REGIONS = 8
@@ -32,6 +33,7 @@ EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry",
            "mkf_set_tuning",
            "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set",
            "mkf_surrogate_get_state", "mkf_surrogate_set_state", "mkf_surrogate_grad",
+           "mkf_surrogate_grad_noalloc",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
 
 
@@ -173,6 +175,7 @@ def _load():
         "mkf_surrogate_get_state": ([P, P, P, P, C.POINTER(I32)], I32),
         "mkf_surrogate_set_state": ([P, P, P, P, I32], I32),
         "mkf_surrogate_grad": ([P, I32, P, P, P, P, P], I32),
+        "mkf_surrogate_grad_noalloc": ([P, I32, P, P, P, P, P], I32),
         "mkf_surrogate_infer": ([P, I64, P, P], I32),
         "mkf_surrogate_samples": ([P, I64, C.c_uint64, P, P, P], I32),
     }
@@ -431,6 +434,13 @@ class Context:
         self._check(lib.mkf_surrogate_grad(self.h, int(x.shape[0]), _ptr(x), _ptr(t), _ptr(lw),
                                            _ptr(grad), _ptr(loss)))
         return grad, float(loss[0])
+
+    def surrogate_grad_noalloc(self, x, t, loss_w, grad, loss):
+        """Loss and gradient into device tensors grad [5191] and loss [1]
+        without any device allocation (queued on the context's stream)."""
+        lw = np.ascontiguousarray(loss_w, np.float32)
+        self._check(lib.mkf_surrogate_grad_noalloc(self.h, int(x.shape[0]), _ptr(x), _ptr(t),
+                                                   _ptr(lw), _ptr(grad), _ptr(loss)))
 
     def surrogate_infer(self, x, y):
         self._check(lib.mkf_surrogate_infer(self.h, int(x.shape[0]), _ptr(x), _ptr(y)))
