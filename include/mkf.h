@@ -128,6 +128,15 @@ typedef struct {
   int32_t main_launches;   /* number of those launches */
   int64_t sur_kept;        /* surrogate path lengths kept after their Newton step */
   int64_t sur_rejected;    /* ... rejected (the closed-form crossing was used) */
+  /* Decisions of the last find that rounding may take either way: window
+   * hits whose chi2 lies within 1e-3 chi2_cut + 0.01 of the cut (the
+   * band in which the FP32 result may differ from an exact evaluation). */
+  int64_t n_near_cut;
+  /* Work of the field crossings of the last find (parameterised field
+   * only, else 0): Runge-Kutta steps (the Newton iterations' included) and
+   * Newton iterations. */
+  int64_t n_rk_steps;
+  int64_t n_newton;
 } mkf_stats;
 
 /* Cuts of the combinatorial triplet seeding (mkf_make_seeds). */
@@ -197,8 +206,12 @@ typedef struct {
 
 typedef struct mkf_ctx mkf_ctx;
 
-/* Create a context.  cfg is copied.  stream: a hipStream_t (NULL = the
- * default stream), e.g. torch.cuda.current_stream().cuda_stream. */
+/* Create a context holding the method's settings (the find's parameters,
+ * which the paper keeps in its steering and configuration, Section 2.1) and
+ * every device buffer of the work it runs.  cfg is copied.  stream: a
+ * hipStream_t (NULL = the default stream), e.g.
+ * torch.cuda.current_stream().cuda_stream.  MKF_E_ARG for bad settings,
+ * MKF_E_HIP if the device set-up fails. */
 mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out);
 
 /* Release all device memory of ctx.  NULL is accepted. */
@@ -216,18 +229,23 @@ mkf_status mkf_load_geometry(mkf_ctx *ctx, const mkf_layer *layers, int32_t n_la
  * xi [n_z][n_r] (0..100 g/cm^2), copied.  info == NULL returns to the
  * constant angle ms_sigma.  Used by every later call that fits: mkf_seed,
  * mkf_find, mkf_fit, mkf_backward_fit, mkf_smooth (seed states already made
- * keep the material they were fitted with).  MKF_E_ARG for bad values.
- * The surrogate form (MKF_F_SURROGATE) has no material variant: mkf_find
- * returns MKF_E_ARG while a map is loaded. */
+ * keep the material they were fitted with).  The surrogate form
+ * (MKF_F_SURROGATE) runs with a map too: the network's path only starts the
+ * barrel crossing, the material update follows it as without the network.
+ * MKF_E_ARG for bad values. */
 mkf_status mkf_load_material(mkf_ctx *ctx, const mkf_material_info *info, const float *x_x0,
                              const float *xi);
 
 /* Parameterised field: f copied; NULL returns to the uniform cfg.bz.  Used
  * by every later call that propagates: mkf_seed (the seed momentum takes the
  * field at the middle hit; plans), mkf_find, mkf_fit, mkf_backward_fit,
- * mkf_smooth, mkf_propagate.  Not by mkf_make_seeds (its cuts take the
- * uniform cfg.bz) nor the surrogate, whose form mkf_find refuses while a
- * field is loaded.  MKF_E_ARG for bad values. */
+ * mkf_smooth, mkf_propagate, and the surrogate's sampler (mkf_surrogate_train
+ * and mkf_surrogate_samples then produce the field's stepped crossings).  Not
+ * by mkf_make_seeds (its cuts take the uniform cfg.bz).  In the field the
+ * surrogate form (MKF_F_SURROGATE) starts each barrel crossing from the
+ * network's path: equal Runge-Kutta steps to it and one Newton step taken as
+ * one more Runge-Kutta step, kept under the same checks as in the uniform
+ * field, else the full stepped search.  MKF_E_ARG for bad values. */
 mkf_status mkf_load_field(mkf_ctx *ctx, const mkf_field *f);
 
 /* Region steering (Section 2.1): n_regions (0..MKF_MAX_REGIONS) records,
@@ -267,9 +285,13 @@ mkf_status mkf_get_seed_states(mkf_ctx *ctx, float *par, float *cov, int32_t *ok
 /* Clone-engine track finding over all seeds (the timed hot path). */
 mkf_status mkf_find(mkf_ctx *ctx);
 
-/* Copy the found tracks (one per seed, in seed order) to host memory.
- * Writes min(capacity, n_seeds) records; *n_total = n_seeds; returns
- * MKF_E_CAPACITY if capacity < n_seeds.  Blocks until done. */
+/* Copy the found tracks (one per seed, in seed order) to host memory: the
+ * step that hands the result back to the caller, as the paper's framework
+ * integration copies the found tracks back into the host framework's format
+ * (Section 2.2).  Writes the records of seeds 0 .. min(capacity, n_seeds) - 1
+ * and nothing beyond; *n_total = n_seeds; returns MKF_E_CAPACITY if
+ * capacity < n_seeds, MKF_E_ARG for capacity < 0, MKF_E_ORDER before a find.
+ * Blocks until done. */
 mkf_status mkf_get_tracks(mkf_ctx *ctx, mkf_track *out, int64_t capacity, int64_t *n_total);
 
 /* Propagate n states to layers of the loaded geometry (unit access to the
@@ -289,7 +311,10 @@ mkf_status mkf_propagate(mkf_ctx *ctx, int64_t n, const float *par, const float 
  * [n_tracks] (hits used, <= n_steps); init_par [n_tracks][6], init_cov
  * [n_tracks][21]; outputs out_par, out_cov, out_chi2 [n_tracks],
  * out_status [n_tracks] (0 ok, k > 0: propagation to hit k-1 failed).
- * Scattering uses cfg.ms_sigma; no extent test. */
+ * Material effects are those of the find: the loaded material map
+ * (mkf_load_material), else the constant angle cfg.ms_sigma; propagation
+ * takes the loaded parameterised field (mkf_load_field), else cfg.bz.  No
+ * extent test. */
 mkf_status mkf_fit(mkf_ctx *ctx, int64_t n_tracks, int32_t n_steps, const int8_t *kind,
                    const float *pos, const float *x, const float *y, const float *z,
                    const float *var_u, const float *var_v, const int32_t *len,

@@ -87,7 +87,6 @@ float *scratch_on(int dev) {
 
 }  // namespace
 
-
 struct mkf_ctx {
   mkf_config cfg{};
   hipStream_t stream = nullptr;
@@ -141,7 +140,7 @@ struct mkf_ctx {
 
   // learned surrogate: master weights, Adam moments, BF16 images, counters
   DevBuf d_mlp_param, d_mlp_m, d_mlp_v, d_W1p, d_W2p, d_W3p, d_W2T, d_W3T, d_mb1, d_mb2, d_mb3;
-  DevBuf d_sur, d_radii, d_tx, d_tt, d_tvalid, d_partial, d_partial2, d_loss, d_grad;
+  DevBuf d_cnt, d_radii, d_tx, d_tt, d_tvalid, d_partial, d_partial2, d_loss, d_grad;
   int mlp_step = 0;  // Adam steps taken
 
   // fit scratch (host-side inputs are staged here)
@@ -152,7 +151,7 @@ struct mkf_ctx {
                      &d_plan_len, &d_plan, &d_plan_l, &d_order, &d_pstate, &d_pinfo,
                      &d_pevent, &d_pplan, &d_cand, &d_fin_key, &d_fin_rec, &d_fin_meta,
                      &d_bp, &d_steps, &d_tiles, &d_qoff, &d_out, &d_mlp_param, &d_mlp_m, &d_mlp_v, &d_W1p,
-                     &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_sur, &d_radii,
+                     &d_W2p, &d_W3p, &d_W2T, &d_W3T, &d_mb1, &d_mb2, &d_mb3, &d_cnt, &d_radii,
                      &d_tx, &d_tt, &d_tvalid, &d_partial, &d_partial2, &d_loss, &d_grad, &d_bf_tmp, &d_sm_wk, &d_sm_n, &d_tr_cnt, &d_tr_off, &d_tr_tmp, &d_dup_h, &d_dup_n, &d_dup_cnt, &d_dup_off,
                      &d_dup_fill, &d_dup_list, &d_dup_tmp, &d_dup_total, &d_seed_chi2};
     for (DevBuf *b : all) b->release();
@@ -231,6 +230,8 @@ FindParams params(mkf_ctx *c) {
   P.pevent = c->d_pevent.as<int>();
   P.pplan = c->d_pplan.as<int8_t>();
   P.out = c->d_out.as<float>();
+  // the layer-synchronous form's lane groups: 6 lanes hold budgets up to 6
+  P.slots = c->cfg.n_cand <= 6 ? 6 : 8;
   P.cand = c->d_cand.as<float>();
   P.fin_key = c->d_fin_key.as<unsigned long long>();
   P.fin_rec = c->d_fin_rec.as<float>();
@@ -243,7 +244,7 @@ FindParams params(mkf_ctx *c) {
   P.mlp = MlpWeights{c->d_W1p.as<__bf16>(), c->d_W2p.as<__bf16>(), c->d_W3p.as<__bf16>(),
                      c->d_W2T.as<__bf16>(), c->d_W3T.as<__bf16>(), c->d_mb1.as<float>(),
                      c->d_mb2.as<float>(), c->d_mb3.as<float>()};
-  P.sur_stats = c->d_sur.as<unsigned long long>();
+  P.counters = c->d_cnt.as<unsigned long long>();
   return P;
 }
 
@@ -281,10 +282,10 @@ hipError_t mlp_setup(mkf_ctx *c) {
   if (e == hipSuccess) e = c->d_mb1.ensure(sizeof(float) * 64);
   if (e == hipSuccess) e = c->d_mb2.ensure(sizeof(float) * 64);
   if (e == hipSuccess) e = c->d_mb3.ensure(sizeof(float) * 32);
-  if (e == hipSuccess) e = c->d_sur.ensure(sizeof(unsigned long long) * 2);
+  if (e == hipSuccess) e = c->d_cnt.ensure(sizeof(unsigned long long) * kCounters * kCounterSlots);
   if (e != hipSuccess) return e;
   DevBuf *zero[] = {&c->d_mlp_m, &c->d_mlp_v, &c->d_W1p, &c->d_W2p, &c->d_W3p, &c->d_W2T,
-                    &c->d_W3T, &c->d_mb1, &c->d_mb2, &c->d_mb3, &c->d_sur};
+                    &c->d_W3T, &c->d_mb1, &c->d_mb2, &c->d_mb3, &c->d_cnt};
   for (DevBuf *b : zero)
     if (e == hipSuccess) e = hipMemsetAsync(b->ptr, 0, b->bytes, c->stream);
   std::vector<float> p(kNParam, 0.f);
@@ -865,7 +866,7 @@ mkf_status mkf_get_seed_states(mkf_ctx *c, float *par, float *cov, int32_t *ok,
 static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipEvent_t main_b) {
   int launches = 0;
   launch_fill_u64(c->stream, c->d_steps.as<unsigned long long>(), 1, 0ull);
-  launch_fill_u64(c->stream, c->d_sur.as<unsigned long long>(), 2, 0ull);
+  launch_fill_u64(c->stream, c->d_cnt.as<unsigned long long>(), kCounters * kCounterSlots, 0ull);
   ++launches;
   if (c->cfg.flags & MKF_F_BATCHED) {
     launch_fill_i32(c->stream, c->d_tiles.as<int>(), kQueues, 0);
@@ -899,8 +900,6 @@ static int enqueue_find(mkf_ctx *c, const FindParams &P, hipEvent_t main_a, hipE
 mkf_status mkf_find(mkf_ctx *c) {
   if (!c) return MKF_E_ARG;
   if (c->stage < kSeeds) return fail(c, MKF_E_ORDER, "seed first");
-  if ((c->cfg.flags & MKF_F_SURROGATE) && (c->mat.tab || c->field.on))
-    return fail(c, MKF_E_ARG, "the surrogate form has no material-map or field variant");
   FindParams P = params(c);
   int launches = 0;
   const bool graph = (c->cfg.flags & MKF_F_GRAPH) != 0;
@@ -930,12 +929,18 @@ mkf_status mkf_find(mkf_ctx *c) {
   float ms = 0.f, mms = -1.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
   if (!graph) HIP_TRY(c, hipEventElapsedTime(&mms, c->ev_m0, c->ev_m1));
-  unsigned long long steps = 0, sur[2] = {0, 0};
+  unsigned long long steps = 0, cnt[kCounters * kCounterSlots];
   HIP_TRY(c, hipMemcpyAsync(&steps, c->d_steps.ptr, sizeof steps, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(sur, c->d_sur.ptr, sizeof sur, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(cnt, c->d_cnt.ptr, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->stats.sur_kept = (int64_t)sur[0];
-  c->stats.sur_rejected = (int64_t)sur[1];
+  int64_t tot[kCounters] = {};
+  for (int k = 0; k < kCounters; ++k)
+    for (int j = 0; j < kCounterSlots; ++j) tot[k] += (int64_t)cnt[k * kCounterSlots + j];
+  c->stats.sur_kept = tot[kCntSurKept];
+  c->stats.sur_rejected = tot[kCntSurRejected];
+  c->stats.n_near_cut = tot[kCntNearCut];
+  c->stats.n_rk_steps = tot[kCntRk];
+  c->stats.n_newton = tot[kCntNewton];
   c->stats.find_ms = ms;
   c->stats.main_ms = mms;
   c->stats.n_steps = (int64_t)steps;
@@ -1247,8 +1252,9 @@ mkf_status mkf_autotune(mkf_ctx *c, int32_t repeats, const char *cache_path, mkf
   // budget, sizes
   int lg = 0;
   while (((int64_t)1 << (lg + 1)) <= c->n_seeds) ++lg;
-  const char *form = (c->mat.tab || c->field.on) ? "extended"
-                     : (c->cfg.flags & MKF_F_SURROGATE) ? "surrogate" : "plain";
+  const bool ext = c->mat.tab || c->field.on, sur = (c->cfg.flags & MKF_F_SURROGATE) != 0;
+  const char *form = ext ? (sur ? "extended-surrogate" : "extended")
+                         : (sur ? "surrogate" : "plain");
   char key[256];
   snprintf(key, sizeof key, "%s cu%d %s cand%d seeds2^%d events%d layers%d",
            c->arch.empty() ? "unknown" : c->arch.c_str(), c->n_cu, form, c->cfg.n_cand, lg,

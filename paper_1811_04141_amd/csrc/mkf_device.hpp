@@ -156,7 +156,10 @@ __device__ __forceinline__ T tau_to_l(T tau, T w) {
 // the helix reaches the cylinder r = R.  Closed form: with
 // a = x cos phi + y sin phi, c = y cos phi - x sin phi, g0 = x^2 + y^2 - R^2,
 // tau = (2/w) tan(w l / 2) solves (1 + c w + g0 w^2/4) tau^2 + 2 a tau + g0 = 0;
-// every real root is a crossing with |w l| < pi.
+// every real root is a crossing with |w l| < pi.  l grows with tau (dl/dtau
+// = 1 / (1 + (w tau / 2)^2)), so the smaller root is converted first and the
+// larger one only if the smaller lies below l_min: one arctangent per
+// crossing in the usual case.
 template <typename T>
 __device__ __forceinline__ bool path_barrel(T x, T y, T cphi, T sphi, T w, T R, T l_min,
                                             T &l_out) {
@@ -168,17 +171,19 @@ __device__ __forceinline__ bool path_barrel(T x, T y, T cphi, T sphi, T w, T R, 
   if (!(disc >= T(0))) return false;
   const T sq = sqrt_t(disc);
   const T qq = -(a + copysign_t(sq, a));
-  T best = T(INFINITY);
-  if (qq != T(0)) {
-    const T l1 = tau_to_l(g0 / qq, w);
-    if (l1 > l_min) best = l1;
-    if (alpha != T(0)) {
-      const T l2 = tau_to_l(qq / alpha, w);
-      if (l2 > l_min && l2 < best) best = l2;
-    }
-  }  // qq == 0: a == 0 and disc == 0, a double root at tau = 0 <= l_min
-  if (!(best < T(INFINITY))) return false;
-  l_out = best;
+  // qq == 0: a == 0 and disc == 0, a double root at tau = 0 <= l_min
+  if (qq == T(0)) return false;
+  const T t1 = g0 / qq;
+  const bool two = alpha != T(0);
+  const T t2 = two ? qq / alpha : t1;
+  const T ta = two && t2 < t1 ? t2 : t1, tb = two && t2 < t1 ? t1 : t2;
+  T l = tau_to_l(ta, w);
+  if (!(l > l_min)) {
+    if (!two) return false;
+    l = tau_to_l(tb, w);
+    if (!(l > l_min)) return false;
+  }
+  l_out = l;
   return true;
 }
 
@@ -249,9 +254,12 @@ constexpr float kFieldMaxPath = 1000.f;  // cm of transverse path searched
 // r^2 - R^2 changes sign, then three Newton iterations on the last step's length.
 // The turning stays below half a turn, the path below kFieldMaxPath.
 // y: the end point (x, y, z, phi unwrapped).
+// cnt (if given): cnt[0] += Runge-Kutta steps taken, cnt[1] += Newton
+// iterations.
 template <typename T>
 __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T sth, T cth,
-                                               const DevLayer &L, T l_min, T &l, T *y) {
+                                               const DevLayer &L, T l_min, T &l, T *y,
+                                               int *cnt = nullptr) {
 #pragma clang fp contract(on)
   const T cot = cth / sth;
   y[0] = p[0];
@@ -266,6 +274,7 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
     if (!(lt > l_min) || lt > T(kFieldMaxPath)) return false;
     const int n = (int)ceil(lt / h_max);
     const T h = lt / T(n);
+    if (cnt) cnt[0] += n;
     T cmp[4] = {T(0), T(0), T(0), T(0)}, d[4];
     for (int k = 0; k < n; ++k) {
       rk4_field(f, p[3], cot, y, h, d);
@@ -284,6 +293,7 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
   int nstep = 0;
   for (;;) {
     T yn[4], cn[4];
+    if (cnt) ++cnt[0];
     rk4_field(f, p[3], cot, y, h_max, d);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -295,6 +305,10 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
     if ((g < T(0)) != (gn < T(0)) || gn == T(0)) {
       T s = g == gn ? h_max : h_max * g / (g - gn), ys[4];
       for (int it = 0; it < 3; ++it) {
+        if (cnt) {
+          ++cnt[0];
+          ++cnt[1];
+        }
         rk4_field(f, p[3], cot, y, s, d);
 #pragma unroll
         for (int i = 0; i < 4; ++i) ys[i] = y[i] + (d[i] - cmp[i]);
@@ -305,6 +319,7 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
         if (gp == T(0)) break;
         s -= gs / gp;
       }
+      if (cnt) ++cnt[0];
       rk4_field(f, p[3], cot, y, s, d);
 #pragma unroll
       for (int i = 0; i < 4; ++i) ys[i] = y[i] + (d[i] - cmp[i]);
@@ -325,6 +340,62 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
     lacc = T(++nstep) * h_max;  // the path so far, without accumulated rounding
     if (lacc > T(kFieldMaxPath)) return false;
   }
+}
+
+// Barrel crossing in the parameterised field from a predicted path l_hint
+// (the learned surrogate's): equal Runge-Kutta steps of at most h_max to
+// l_hint, then one Newton step on g = r^2 - R^2 there, taken as one
+// Runge-Kutta step of the correction's length.  Kept under the checks of
+// the uniform-field hint (correction at most 1e-4 l1, the Newton error bound
+// 3 dl^2 / |g'| at most 1e-7 l1, g' of the sign that marks the first
+// crossing, l1 > l_min, turning below half a turn); otherwise false, and the
+// caller takes field_crossing.  y: the end point (x, y, z, phi unwrapped).
+template <typename T>
+__device__ __forceinline__ bool field_crossing_hinted(const DevField &f, const T *p, T sth, T cth,
+                                                      const DevLayer &L, T l_min, T l_hint, T &l,
+                                                      T *y, int *cnt = nullptr) {
+#pragma clang fp contract(on)
+  const T cot = cth / sth;
+  const T pos = T(L.pos);
+  const T h_max = T(f.h_max);
+  if (!(l_hint > l_min) || !(l_hint <= T(kFieldMaxPath))) return false;
+  const int n = max(1, (int)ceil(l_hint / h_max));
+  const T h = l_hint / T(n);
+  if (cnt) cnt[0] += n;
+  y[0] = p[0];
+  y[1] = p[1];
+  y[2] = p[2];
+  y[3] = p[4];
+  T cmp[4] = {T(0), T(0), T(0), T(0)}, d[4];
+  for (int k = 0; k < n; ++k) {
+    rk4_field(f, p[3], cot, y, h, d);
+    rk_accumulate(y, cmp, d);
+    if (abs_t(y[3] - p[4]) >= Consts<T>::pi()) return false;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[i] -= cmp[i];
+  T sp, cp;
+  sincos_t(y[3], &sp, &cp);
+  const T R2 = pos * pos;
+  const T g = y[0] * y[0] + y[1] * y[1] - R2;
+  const T gp = T(2) * (y[0] * cp + y[1] * sp);
+  const T g0 = p[0] * p[0] + p[1] * p[1] - R2;
+  if (!(gp * g0 < T(0))) return false;
+  const T dl = -g / gp;
+  const T l1 = l_hint + dl;
+  if (!(l1 > l_min) || !(abs_t(dl) <= T(1e-4) * l1) ||
+      !(T(3) * dl * dl <= T(1e-7) * l1 * abs_t(gp)))
+    return false;
+  if (cnt) {
+    ++cnt[0];
+    ++cnt[1];
+  }
+  rk4_field(f, p[3], cot, y, dl, d);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[i] += d[i];
+  if (abs_t(y[3] - p[4]) >= Consts<T>::pi()) return false;
+  l = l1;
+  return true;
 }
 
 // Exact helix transport by l, surface polish, extent test, and the
@@ -350,17 +421,30 @@ __device__ __forceinline__ bool field_crossing(const DevField &f, const T *p, T 
 // point come from Runge-Kutta steps (field_crossing); the Jacobian is the
 // helix's with the path's mean curvature (the turning over the path), whose
 // end direction is the stepped one.
+//
+// trig (if given): sin phi, cos phi, sin theta, cos theta of p, computed by
+// the caller (the same values the propagation would compute).
+//
+// cnt (if given): the field crossing's Runge-Kutta steps and Newton
+// iterations are added to cnt[0] and cnt[1].
 template <bool kWantCov, typename T, bool kWantFC = false>
 __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__restrict__ c,
                                          const DevLayer &L, T mkb, T l_min, bool check_extent,
                                          T edge_margin, PropT<T> &o, T l_hint = T(0),
                                          int *sur = nullptr, T *fc = nullptr,
-                                         const DevField *fld = nullptr) {
+                                         const DevField *fld = nullptr,
+                                         const T *trig = nullptr, int *cnt = nullptr) {
   T w = mkb * p[3];
-  T sphi, cphi;
-  sincos_t(p[4], &sphi, &cphi);
-  T sth, cth;
-  sincos_t(p[5], &sth, &cth);
+  T sphi, cphi, sth, cth;
+  if (trig) {
+    sphi = trig[0];
+    cphi = trig[1];
+    sth = trig[2];
+    cth = trig[3];
+  } else {
+    sincos_t(p[4], &sphi, &cphi);
+    sincos_t(p[5], &sth, &cth);
+  }
   const T cot = cth / sth;
   const T pos = T(L.pos);
   T l;
@@ -368,7 +452,11 @@ __device__ __forceinline__ int propagate(const T *__restrict__ p, const T *__res
   const bool stepped = fld != nullptr && fld->on;
   T yf[4];
   if (stepped) {
-    if (!field_crossing(*fld, p, sth, cth, L, l_min, l, yf)) return kNoCrossing;
+    if (L.kind == 0 && l_hint > T(0)) {
+      hinted = field_crossing_hinted(*fld, p, sth, cth, L, l_min, l_hint, l, yf, cnt);
+      if (sur) *sur = hinted ? 1 : 2;
+    }
+    if (!hinted && !field_crossing(*fld, p, sth, cth, L, l_min, l, yf, cnt)) return kNoCrossing;
     w = (yf[3] - p[4]) / l;
     mkb = p[3] != T(0) ? w / p[3] : mkb;
   } else if (L.kind == 0) {

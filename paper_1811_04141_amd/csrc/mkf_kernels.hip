@@ -7,7 +7,8 @@
 //                is propagated to the next plan layer, all its window hits
 //                are scored by chi2, the seed's best extensions are chosen
 //                across its lane group, and only the kept ones are updated.
-//                One lane per candidate slot, kGroup = 8 lanes per seed.
+//                One lane per candidate slot, a group of 6 lanes per seed
+//                (10 seeds per wavefront) for budgets up to 6, else 8.
 //                Two forms share the step code: one launch per layer step
 //                with the state in HBM, or one persistent launch that keeps
 //                the state in VGPRs across all steps of a seed tile.
@@ -123,6 +124,18 @@ __device__ __forceinline__ void stage_layers(const FindParams &P, DevLayer *sl) 
   for (int i = threadIdx.x; i < P.n_layers; i += blockDim.x) sl[i] = P.layers[i];
 }
 
+// Adds a wavefront's value of find counter k (every lane of the wave must
+// call this; lanes with nothing to count pass 0).  Skipped when the whole
+// wave has nothing.
+__device__ __forceinline__ void add_counter(const FindParams &P, int k, int v) {
+  if (__ballot(v != 0) == 0ull) return;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+  if ((threadIdx.x & 63) == 0)
+    atomicAdd(&P.counters[k * kCounterSlots + blockIdx.x % kCounterSlots],
+              (unsigned long long)v);
+}
+
 struct Cand {
   float p[6];
   float c[21];
@@ -143,10 +156,10 @@ struct GlobalRec {
   const FindParams *P;
   int64_t pos;
   __device__ void put_bp(int step, int slot, int v) const {
-    P->bp[((size_t)step * (size_t)P->n_seeds + pos) * kGroup + slot] = v;
+    P->bp[((size_t)step * (size_t)P->n_seeds + pos) * P->slots + slot] = v;
   }
   __device__ int get_bp(int step, int slot) const {
-    return P->bp[((size_t)step * (size_t)P->n_seeds + pos) * kGroup + slot];
+    return P->bp[((size_t)step * (size_t)P->n_seeds + pos) * P->slots + slot];
   }
   __device__ void put_fin(const Cand &cd) const {
     const size_t N = (size_t)P->n_seeds;
@@ -233,10 +246,12 @@ __device__ __forceinline__ float chi2_hit(const Frame &f, float vu, float vv, fl
   return (svv * u * u - 2.f * suv * u * v + suu * v * v) * __builtin_amdgcn_rcpf(det);
 }
 
-template <int N>
-__device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer &L, int ev,
-                                            const Prop &pr, const Frame &f, float chi2_base,
-                                            int nh, int slot, u64 (&lst)[N], int &n_ext) {
+// The window's bins: q rows qlo..qhi of the event's layer (base: the index
+// of its first bin) and up to two azimuth segments per row, [seg[0],
+// seg[1]] and [seg[2], seg[3]] (the second empty unless the window wraps).
+__device__ __forceinline__ void window_bins(const FindParams &P, const DevLayer &L, int ev,
+                                            const Prop &pr, const Frame &f, int &base, int &qlo,
+                                            int &qhi, int (&seg)[4]) {
   const float cut = P.cfg.chi2_cut;
   // (hardware square roots, 1 ulp: the 0.1% widening covers them)
   const float du = __builtin_amdgcn_sqrtf(cut * (f.suu + L.vu_max)) * 1.001f + 1e-5f;
@@ -259,34 +274,61 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
   qmin -= 1e-4f;
   qmax += 1e-4f;
   const int nphi = L.nphi;
-  const int qlo = clampi((int)floorf((qmin - L.q_lo) * L.q_scale), 0, L.nq - 1);
-  const int qhi = clampi((int)floorf((qmax - L.q_lo) * L.q_scale), 0, L.nq - 1);
-  int s0lo = 0, s0hi = nphi - 1, s1lo = 1, s1hi = 0;
+  qlo = clampi((int)floorf((qmin - L.q_lo) * L.q_scale), 0, L.nq - 1);
+  qhi = clampi((int)floorf((qmax - L.q_lo) * L.q_scale), 0, L.nq - 1);
+  seg[0] = 0;
+  seg[1] = nphi - 1;
+  seg[2] = 1;
+  seg[3] = 0;
   if (dphi < kPi) {
     const int blo = (int)floorf((phic - dphi + kPi) * L.phi_scale);
     const int bhi = (int)floorf((phic + dphi + kPi) * L.phi_scale);
     if (bhi - blo + 1 < nphi) {
       if (blo < 0) {
-        s0lo = blo + nphi; s0hi = nphi - 1; s1lo = 0; s1hi = bhi;
+        seg[0] = blo + nphi; seg[1] = nphi - 1; seg[2] = 0; seg[3] = bhi;
       } else if (bhi >= nphi) {
-        s0lo = blo; s0hi = nphi - 1; s1lo = 0; s1hi = bhi - nphi;
+        seg[0] = blo; seg[1] = nphi - 1; seg[2] = 0; seg[3] = bhi - nphi;
       } else {
-        s0lo = blo; s0hi = bhi;
+        seg[0] = blo; seg[1] = bhi;
       }
     }
   }
-  const int base = ev * P.bins_per_event + L.bin_base;
+  base = ev * P.bins_per_event + L.bin_base;
+}
+
+// One window hit against a candidate's prediction (point p, frame f): its
+// chi2 (>= 0), or a negative value for a hit on the other half of a barrel.
+__device__ __forceinline__ float hit_chi2(const float *p, const Frame &f, int kind,
+                                          const float4 &a, const float4 &b) {
+  float u, v;
+  if (!residual(p, f, kind, a.x, a.y, a.z, u, v)) return -1.f;
+  return fmaxf(chi2_hit(f, a.w, b.x, b.z, u, v), 0.f);
+}
+
+// A hit's chi2 within this band of the cut is a decision that rounding may
+// take either way (the band of the parity checks: 1e-3 relative + 1e-2).
+__device__ __forceinline__ float near_cut_band(float cut) { return fmaf(1e-3f, cut, 1e-2f); }
+
+// One lane's window scan: every hit of the window's bins, four at a time.
+// n_near counts the hits whose chi2 lies within near_cut_band of the cut.
+template <int N>
+__device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer &L, int ev,
+                                            const Prop &pr, const Frame &f, float chi2_base,
+                                            int nh, int slot, u64 (&lst)[N], int &n_ext,
+                                            int &n_near) {
+  const float cut = P.cfg.chi2_cut;
+  const float band = near_cut_band(cut);
+  int base, qlo, qhi, seg[4];
+  window_bins(P, L, ev, pr, f, base, qlo, qhi, seg);
   for (int qb = qlo; qb <= qhi; ++qb) {
-    const int row = base + qb * nphi;
+    const int row = base + qb * L.nphi;
 #pragma unroll
     for (int sg = 0; sg < 2; ++sg) {
-      const int lo = sg == 0 ? s0lo : s1lo;
-      const int hi = sg == 0 ? s0hi : s1hi;
+      const int lo = seg[2 * sg], hi = seg[2 * sg + 1];
       if (lo > hi) continue;
       const int h0 = P.bin_start[row + lo];
       const int h1 = P.bin_start[row + hi + 1];
       const float4 *hits = reinterpret_cast<const float4 *>(P.sorted);
-      const float4 *hits2 = reinterpret_cast<const float4 *>(P.sorted);
       for (int k = h0; k < h1; k += 4) {
         float4 a[4];
         float4 b[4];  // (var_v, index, covariance uv, -)
@@ -294,15 +336,14 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
         for (int j = 0; j < 4; ++j) {
           const int kk = min(k + j, h1 - 1);
           a[j] = hits[2 * kk];
-          b[j] = hits2[2 * kk + 1];
+          b[j] = hits[2 * kk + 1];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (k + j >= h1) break;
-          float u, v;
-          if (!residual(pr.p, f, L.kind, a[j].x, a[j].y, a[j].z, u, v)) continue;
-          const float c2 = fmaxf(chi2_hit(f, a[j].w, b[j].x, b[j].z, u, v), 0.f);
-          if (c2 < cut) {
+          const float c2 = hit_chi2(pr.p, f, L.kind, a[j], b[j]);
+          n_near += fabsf(c2 - cut) <= band ? 1 : 0;
+          if (c2 >= 0.f && c2 < cut) {
             insert_sorted(lst, ext_key(nh + 1, chi2_base + c2, slot,
                                        (unsigned)__float_as_int(b[j].y)));
             ++n_ext;
@@ -317,20 +358,23 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
 //
 // One layer step of one seed, executed by its G-lane group.  On entry each
 // lane holds one candidate (or none); on exit it holds the candidate of its
-// rank among the kept extensions.  pos indexes the seed's find buffers
-// (back-pointers keep kGroup = 8 slots per seed for either G).
+// rank among the kept extensions.  pos indexes the seed's find buffers.
+// cnt: the lane's counters, cnt[0] near-cut chi2 decisions, and with kMat
+// cnt[1] Runge-Kutta steps and cnt[2] Newton iterations of field crossings.
 template <int G, bool kMat, class Rec>
 __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *sl, Cand &cd,
                                            int lane, int slot, const Rec &rec, int ev,
                                            int64_t ev_base, int step, int lid, u64 &fin_key,
-                                           float l_hint = 0.f, int *sur = nullptr,
-                                           const float2 *mtab = nullptr) {
+                                           int *cnt, float l_hint = 0.f,
+                                           int *sur = nullptr, const float2 *mtab = nullptr,
+                                           const float *trig = nullptr) {
   const DevLayer &L = sl[lid];
   Prop pr;
   int st = kNoCrossing;
   if (cd.active)
     st = propagate<true, float>(cd.p, cd.c, L, P.cfg.mkb, P.cfg.l_min, true, P.cfg.edge_margin, pr,
-                         l_hint, sur, nullptr, kMat ? &P.cfg.field : nullptr);
+                                l_hint, sur, nullptr, kMat ? &P.cfg.field : nullptr, trig,
+                                kMat ? cnt + 1 : nullptr);
   const bool ok = cd.active && st == kOk;
   // kMat: the material map's effects and the parameterised field (a separate
   // instantiation, so that the constant-angle uniform-field form keeps its
@@ -351,7 +395,7 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
     } else {
       Frame f;
       make_frame(pr.p, pr.c, L.kind, f);
-      scan_window(P, L, ev, pr, f, cd.chi2, cd.nh, slot, lst, n_ext);
+      scan_window(P, L, ev, pr, f, cd.chi2, cd.nh, slot, lst, n_ext, cnt[0]);
       if (cd.nm < P.cfg.max_holes) {
         insert_sorted(lst, ext_key(cd.nh, cd.chi2, slot, kOrderNone));  // miss
         ++n_ext;
@@ -463,7 +507,7 @@ __device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand
 }
 
 __device__ __forceinline__ void load_cand(const FindParams &P, size_t idx, Cand &cd) {
-  const size_t NS = (size_t)P.n_seeds * kGroup;
+  const size_t NS = (size_t)P.n_seeds * P.slots;
   const int meta = __float_as_int(P.cand[28 * NS + idx]);
   cd.active = (meta >> 16) & 1;
   cd.nh = meta & 0xFF;
@@ -478,7 +522,7 @@ __device__ __forceinline__ void load_cand(const FindParams &P, size_t idx, Cand 
 }
 
 __device__ __forceinline__ void store_cand(const FindParams &P, size_t idx, const Cand &cd) {
-  const size_t NS = (size_t)P.n_seeds * kGroup;
+  const size_t NS = (size_t)P.n_seeds * P.slots;
   const int meta = cd.nh | (cd.nm << 8) | (cd.active ? (1 << 16) : 0);
   P.cand[28 * NS + idx] = __int_as_float(meta);
   if (cd.active) {
@@ -540,8 +584,8 @@ __device__ __forceinline__ void write_empty(const FindParams &P, int64_t pos, co
 
 __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t pos = gid / kGroup;
-  const int slot = (int)(gid % kGroup);
+  const int64_t pos = gid / P.slots;
+  const int slot = (int)(gid % P.slots);
   if (pos >= P.n_seeds) return;
   Cand cd;
   cd.active = slot == 0 && ((P.pinfo[pos] >> 8) & 1);
@@ -549,11 +593,13 @@ __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
   cd.nm = 0;
   cd.chi2 = 0.f;
   if (cd.active) load_seed(P, pos, cd);
-  store_cand(P, (size_t)pos * kGroup + slot, cd);
+  store_cand(P, (size_t)pos * P.slots + slot, cd);
   if (slot == 0) P.fin_key[pos] = kKeyMax;
 }
 
-template <bool kMat>
+// One layer step of the layer-synchronous form: G-lane seed groups,
+// Grp<G>::kSeeds seeds per wavefront (lanes 60-63 idle for G = 6).
+template <bool kMat, int G>
 __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64_t n_active) {
   __shared__ DevLayer sl[kMaxLayers];
   stage_layers(P, sl);
@@ -563,22 +609,33 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   // (the grid is a multiple of kQueues blocks, so this is a permutation)
   const int64_t per = gridDim.x / kQueues;
   const int64_t b = (int64_t)(blockIdx.x % kQueues) * per + blockIdx.x / kQueues;
-  const int64_t gid = b * blockDim.x + threadIdx.x;
-  const int64_t pos = gid / kGroup;
-  const int slot = (int)(gid % kGroup);
   const int lane = threadIdx.x & 63;
-  if (pos >= n_active) return;
-  if (step >= (P.pinfo[pos] & 0xFF)) return;  // whole group leaves together
-  const int lid = P.pplan[(size_t)pos * kMaxPlan + step];
-  const int ev = P.pevent[pos];
-  Cand cd;
-  load_cand(P, (size_t)pos * kGroup + slot, cd);
-  u64 fin_key = P.fin_key[pos];
-  const u64 fk0 = fin_key;
-  group_step<kGroup, kMat>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, P.ev_off[ev], step, lid,
-                     fin_key);
-  store_cand(P, (size_t)pos * kGroup + slot, cd);
-  if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
+  const int grp = lane / G;
+  const int64_t pos = (b * 4 + (threadIdx.x >> 6)) * Grp<G>::kSeeds + grp;
+  const int slot = Grp<G>::slot(lane);
+  // a seed group takes part while the step is in its plan (the whole group
+  // leaves together); the wave stays to add its counters
+  const bool in_range = grp < Grp<G>::kSeeds && pos < n_active;
+  const bool live = in_range && step < (P.pinfo[pos] & 0xFF);
+  if (__ballot(live) == 0ull) return;
+  int cnt[3] = {0, 0, 0};
+  if (live) {
+    const int lid = P.pplan[(size_t)pos * kMaxPlan + step];
+    const int ev = P.pevent[pos];
+    Cand cd;
+    load_cand(P, (size_t)pos * G + slot, cd);
+    u64 fin_key = P.fin_key[pos];
+    const u64 fk0 = fin_key;
+    group_step<G, kMat>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, P.ev_off[ev], step, lid,
+                        fin_key, cnt);
+    store_cand(P, (size_t)pos * G + slot, cd);
+    if (slot == 0 && fin_key != fk0) P.fin_key[pos] = fin_key;
+  }
+  add_counter(P, kCntNearCut, cnt[0]);
+  if constexpr (kMat) {
+    add_counter(P, kCntRk, cnt[1]);
+    add_counter(P, kCntNewton, cnt[2]);
+  }
 }
 
 // Best of the final and the retired candidates of each seed (more hits,
@@ -595,18 +652,19 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
     const int plen = info & 0xFF;
     const bool ok = (info >> 8) & 1;
     const size_t N = (size_t)P.n_seeds;
-    const size_t NS = N * kGroup;
+    const int G = P.slots;
+    const size_t NS = N * G;
     int cnt = (ok && plen > 0) ? 1 : 0;
     for (int s = 0; s + 1 < plen; ++s)
-      for (int j = 0; j < kGroup; ++j) cnt += P.bp[((size_t)s * N + pos) * kGroup + j] >= 0;
+      for (int j = 0; j < G; ++j) cnt += P.bp[((size_t)s * N + pos) * G + j] >= 0;
     if (cnt) atomicAdd(&block_steps, (unsigned long long)cnt);
     u64 m = kKeyMax;
     int best = 0;
     if (ok)
-      for (int j = 0; j < kGroup; ++j) {
-        const int meta = __float_as_int(P.cand[28 * NS + pos * kGroup + j]);
+      for (int j = 0; j < G; ++j) {
+        const int meta = __float_as_int(P.cand[28 * NS + pos * G + j]);
         if (!((meta >> 16) & 1)) continue;
-        const u64 fk = final_key(meta & 0xFF, P.cand[27 * NS + pos * kGroup + j], 0, 0, j);
+        const u64 fk = final_key(meta & 0xFF, P.cand[27 * NS + pos * G + j], 0, 0, j);
         if (fk < m) {
           m = fk;
           best = j;
@@ -616,7 +674,7 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
     const GlobalRec rec{&P, pos};
     if (m != kKeyMax && m < fin) {
       Cand cd;
-      load_cand(P, (size_t)pos * kGroup + best, cd);
+      load_cand(P, (size_t)pos * G + best, cd);
       write_result(P, pos, rec, cd.p, cd.c, cd.chi2, cd.nh, cd.nm, plen - 1, best, plen);
     } else if (fin != kKeyMax) {
       write_retired(P, pos, rec, fin, plen);
@@ -647,13 +705,14 @@ __global__ __launch_bounds__(256) void k_finalize(FindParams P) {
 template <int kWaves, bool kSurr, int G, bool kMat>
 __device__ __forceinline__ void find_persistent(const FindParams &P) {
   __shared__ DevLayer sl[kMaxLayers];
-  __shared__ unsigned long long block_steps, block_sur[2];
+  __shared__ unsigned long long block_steps;
   // surrogate: the network's BF16 weight images and biases, shared by the
   // block, and one activation tile per wave (the input tile overlays it)
   constexpr int kW1n = 64 * kLdW1, kW2n = 64 * kLdW2, kW3n = 32 * kLdW3;
   __shared__ __attribute__((aligned(16))) __bf16 sMW[kSurr ? kW1n + kW2n + kW3n : 8];
   __shared__ __attribute__((aligned(16))) float sMB[kSurr ? 64 + 64 + 32 : 4];
-  __shared__ __attribute__((aligned(16))) __bf16 sMH[kSurr ? 4 * 64 * kLdH : 8];
+  // (one sample row per seed: at most 10 rows, one 16-sample tile per wave)
+  __shared__ __attribute__((aligned(16))) __bf16 sMH[kSurr ? 4 * 16 * kLdH : 8];
   // material: a table of up to kMatLds bins is read from LDS
   constexpr int kMatLds = 1024;
   __shared__ float2 sMat[kMat ? kMatLds : 1];
@@ -684,7 +743,6 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
   }
   if (threadIdx.x == 0) {
     block_steps = 0;
-    block_sur[0] = block_sur[1] = 0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -700,6 +758,7 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
   const LdsRec rec{wrec + gi * G, kS * G,
                    reinterpret_cast<float *>(wrec + P.max_plan * kS * G) + gi * kFinWords};
   int my_steps = 0, my_acc = 0, my_fb = 0;
+  int cnt[3] = {0, 0, 0};  // near-cut decisions, field Runge-Kutta steps, Newton iterations
   int q = blockIdx.x % kQueues;  // this block's XCD
   int tried = 0;
   // the next tile of queue q is claimed one tile ahead, so that the atomic's
@@ -747,56 +806,57 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
       }
       const int lid = in_plan ? (w_cur >> (8 * (step & 3))) & 0xFF : 0;
       float l_hint = 0.f;
+      float trig[4];  // sin, cos of phi and theta, shared by the inputs and the propagation
       if constexpr (kSurr) {
-        // every lane of the wave takes part in the matrix-core inference
+        // The candidates of a seed all head to the same layer from nearby
+        // states: the network predicts the path of the seed's leading
+        // candidate (slot 0), one sample row per seed, and every candidate
+        // applies that relative correction to its own straight-line path
+        // and checks it with its own Newton step (falling back to the
+        // closed form when the check fails).
         const bool want = in_plan && cd.active && sl[lid].kind == 0;
+        const bool lead = want && slot == 0;
         float xin[kNI];
         if (want) {
-          mlp_inputs(cd.p, sl[lid].pos, P.cfg.mkb, xin);
+          sincosf(cd.p[4], &trig[0], &trig[1]);
+          sincosf(cd.p[5], &trig[2], &trig[3]);
+        }
+        if (lead) {
+          mlp_inputs(cd.p, trig, sl[lid].pos, P.cfg.mkb, xin);
         } else {
 #pragma unroll
           for (int k = 0; k < kNI; ++k) xin[k] = 0.f;
         }
-        // The lanes that head to a barrel layer write their inputs to
-        // consecutive sample rows; one 32-sample tile suffices when at most
-        // 32 of them do (no inference at all when none does).
-        const unsigned long long m = __ballot(want);
+        // the leading candidates write their inputs to consecutive sample
+        // rows (at most 10 per wavefront: one 16-sample tile); no inference
+        // at all when none heads to a barrel layer
+        const unsigned long long m = __ballot(lead);
         if (m != 0ull) {
-          const int cnt = __popcll(m);
-          const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-          __bf16 *H = sMH + wv * 64 * kLdH;
+          const int base = Grp<G>::base(lane);
+          const unsigned long long below = base ? (m & ((1ull << base) - 1ull)) : 0ull;
+          const int row = __popcll(below);  // this seed's sample row
+          __bf16 *H = sMH + wv * 16 * kLdH;
           __bf16 *X = H;  // the input tile overlays the activation tile
-          if (want) {
-            bf16x8 xv, zv;
+          if (lead) {
+            bf16x8 xv;
 #pragma unroll
-            for (int k = 0; k < kNI; ++k) {
-              xv[k] = (__bf16)xin[k];
-              zv[k] = (__bf16)0.f;
-            }
-            reinterpret_cast<bf16x8 *>(X + rank * kLdX)[0] = xv;
-            reinterpret_cast<bf16x8 *>(X + rank * kLdX)[1] = zv;
+            for (int k = 0; k < kNI; ++k) xv[k] = (__bf16)xin[k];
+            *reinterpret_cast<bf16x8 *>(X + row * kLdX) = xv;
           }
           wave_sync();
-          float y0;
-          if (cnt <= 32) {
-            f32x16 y[1][1];
-            mlp_forward_tiles<1>(mw, X, H, y);
-            y0 = mlp_output<1>(y, rank & 31, 0);
-          } else {
-            f32x16 y[1][2];
-            mlp_forward_tiles<2>(mw, X, H, y);
-            y0 = mlp_output<2>(y, rank, 0);
-          }
+          f32x4 y;
+          mlp_forward16(mw, X, H, y);
+          const float y0 = mlp_output16(y, row, 0);
           wave_sync();  // the tiles are rewritten at the next step
-          if (want) l_hint = surrogate_path(cd.p, sl[lid].pos, P.cfg.mkb, y0);
+          if (want) l_hint = surrogate_path(cd.p, trig, sl[lid].pos, P.cfg.mkb, y0);
         }
       }
       if (in_plan) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
-        group_step<G, kMat>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, l_hint,
-                            &sur, mtab);
+        group_step<G, kMat>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, cnt,
+                            l_hint, &sur, mtab,
+                            kSurr && cd.active && sl[lid].kind == 0 ? trig : nullptr);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
@@ -816,22 +876,19 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
     wave_sync();  // read before the next tile overwrites them
   }
 #pragma unroll
-  for (int m = 1; m < 64; m <<= 1) {
-    my_steps += __shfl_xor(my_steps, m);
-    my_acc += __shfl_xor(my_acc, m);
-    my_fb += __shfl_xor(my_fb, m);
-  }
+  for (int m = 1; m < 64; m <<= 1) my_steps += __shfl_xor(my_steps, m);
   if (lane == 0 && my_steps) atomicAdd(&block_steps, (unsigned long long)my_steps);
-  if (kSurr && lane == 0) {
-    atomicAdd(&block_sur[0], (unsigned long long)my_acc);
-    atomicAdd(&block_sur[1], (unsigned long long)my_fb);
+  if constexpr (kSurr) {
+    add_counter(P, kCntSurKept, my_acc);
+    add_counter(P, kCntSurRejected, my_fb);
+  }
+  add_counter(P, kCntNearCut, cnt[0]);
+  if constexpr (kMat) {
+    add_counter(P, kCntRk, cnt[1]);
+    add_counter(P, kCntNewton, cnt[2]);
   }
   __syncthreads();
   if (threadIdx.x == 0 && block_steps) atomicAdd(P.n_steps, block_steps);
-  if (kSurr && threadIdx.x == 0) {
-    atomicAdd(&P.sur_stats[0], block_sur[0]);
-    atomicAdd(&P.sur_stats[1], block_sur[1]);
-  }
 }
 
 template <int kWaves, bool kSurr, int G>
@@ -839,9 +896,9 @@ __global__ __launch_bounds__(256, kWaves) void k_find_persistent(FindParams P) {
   find_persistent<kWaves, kSurr, G, false>(P);
 }
 
-template <int kWaves, int G>
+template <int kWaves, bool kSurr, int G>
 __global__ __launch_bounds__(256, kWaves) void k_find_persistent_mat(FindParams P) {
-  find_persistent<kWaves, false, G, true>(P);
+  find_persistent<kWaves, kSurr, G, true>(P);
 }
 
 // Gather the seed results into processing order (untimed preparation), so
@@ -2101,16 +2158,22 @@ void launch_seed(hipStream_t s, const FindParams &P, const int *seed_hits, float
 
 void launch_find_init(hipStream_t s, const FindParams &P) {
   if (P.n_seeds == 0) return;
-  hipLaunchKernelGGL(k_find_init, dim3(blocks_for(P.n_seeds * kGroup, 256)), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_find_init, dim3(blocks_for(P.n_seeds * P.slots, 256)), dim3(256), 0, s, P);
+}
+
+template <int G>
+static void launch_find_step_g(hipStream_t s, const FindParams &P, int step, int64_t n_active) {
+  const unsigned nb = blocks_for(n_active, 4 * Grp<G>::kSeeds);
+  const unsigned grid = (nb + kQueues - 1) / kQueues * kQueues;  // whole XCD shares
+  if (P.cfg.mat.tab || P.cfg.field.on)
+    hipLaunchKernelGGL((k_find_step<true, G>), dim3(grid), dim3(256), 0, s, P, step, n_active);
+  else hipLaunchKernelGGL((k_find_step<false, G>), dim3(grid), dim3(256), 0, s, P, step, n_active);
 }
 
 void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_active) {
   if (n_active == 0) return;
-  const unsigned nb = blocks_for(n_active * kGroup, 256);
-  const unsigned grid = (nb + kQueues - 1) / kQueues * kQueues;  // whole XCD shares
-  if (P.cfg.mat.tab || P.cfg.field.on)
-    hipLaunchKernelGGL(k_find_step<true>, dim3(grid), dim3(256), 0, s, P, step, n_active);
-  else hipLaunchKernelGGL(k_find_step<false>, dim3(grid), dim3(256), 0, s, P, step, n_active);
+  if (P.slots == 6) launch_find_step_g<6>(s, P, step, n_active);
+  else launch_find_step_g<8>(s, P, step, n_active);
 }
 
 template <int G, bool kSurr, bool kMat>
@@ -2118,10 +2181,10 @@ static void launch_persistent_g(hipStream_t s, const FindParams &P, int grid, in
   const size_t lds = 4 * sizeof(int) * persistent_rec_words(P.max_plan, G, Grp<G>::kSeeds);
   if constexpr (kMat) {
     switch (waves) {
-      case 1: hipLaunchKernelGGL((k_find_persistent_mat<1, G>), dim3(grid), dim3(256), lds, s, P); break;
-      case 3: hipLaunchKernelGGL((k_find_persistent_mat<3, G>), dim3(grid), dim3(256), lds, s, P); break;
-      case 4: hipLaunchKernelGGL((k_find_persistent_mat<4, G>), dim3(grid), dim3(256), lds, s, P); break;
-      default: hipLaunchKernelGGL((k_find_persistent_mat<2, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 1: hipLaunchKernelGGL((k_find_persistent_mat<1, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 3: hipLaunchKernelGGL((k_find_persistent_mat<3, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+      case 4: hipLaunchKernelGGL((k_find_persistent_mat<4, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
+      default: hipLaunchKernelGGL((k_find_persistent_mat<2, kSurr, G>), dim3(grid), dim3(256), lds, s, P); break;
     }
   } else {
     switch (waves) {
@@ -2144,8 +2207,10 @@ static void launch_persistent_k(hipStream_t s, const FindParams &P, int grid, in
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
                             bool surrogate, int group) {
   if (P.n_seeds == 0) return;
-  if (P.cfg.mat.tab || P.cfg.field.on) launch_persistent_k<false, true>(s, P, grid_blocks, waves, group);
-  else if (surrogate) launch_persistent_k<true, false>(s, P, grid_blocks, waves, group);
+  if (P.cfg.mat.tab || P.cfg.field.on) {
+    if (surrogate) launch_persistent_k<true, true>(s, P, grid_blocks, waves, group);
+    else launch_persistent_k<false, true>(s, P, grid_blocks, waves, group);
+  } else if (surrogate) launch_persistent_k<true, false>(s, P, grid_blocks, waves, group);
   else launch_persistent_k<false, false>(s, P, grid_blocks, waves, group);
 }
 

@@ -32,8 +32,8 @@ struct DevRegion {
 };
 
 // Candidate buffers between layer steps (layer-synchronous form), SoA by
-// field over n_seeds * kGroup slots so that a wavefront reads 64
-// consecutive floats per field.
+// field over n_seeds * slots (slots = the lane group, 6 or 8) so that a
+// wavefront reads consecutive floats per field.
 constexpr int kCandFields = 29;  // 6 par + 21 cov + chi2 + meta (bit cast)
 constexpr int kSeedWords = 28;   // a seed's state in processing order (112 bytes)
 // one result record per seed (processing order), kOutWords words: par[6],
@@ -74,11 +74,12 @@ struct FindParams {
   // results, by processing position: one kOutWords record per seed
   float *out;
   // find state
-  float *cand;              // [kCandFields][n_seeds * kGroup]
+  int slots;                // candidate slots per seed of the layer-synchronous form (6 or 8)
+  float *cand;              // [kCandFields][n_seeds * slots]
   unsigned long long *fin_key;  // [n_seeds]
   float *fin_rec;           // [28][n_seeds] state + chi2 of the best retired candidate
   int *fin_meta;            // [n_seeds] n_hits | n_miss << 8
-  int *bp;                  // [kMaxPlan][n_seeds][kGroup] back-pointers
+  int *bp;                  // [kMaxPlan][n_seeds][slots] back-pointers
   // persistent form: kQueues tile queues, queue q owning positions
   // [q_off[q], q_off[q+1]) (whole events); the blocks of XCD x start on
   // queue x and move on to the others when it is empty
@@ -88,8 +89,16 @@ struct FindParams {
   unsigned long long *n_steps;
   // learned surrogate (persistent form)
   MlpWeights mlp;
-  unsigned long long *sur_stats;  // [2]: hints kept, hints rejected
+  // find counters [kCounters][kCounterSlots]: surrogate hints kept, hints
+  // rejected, near-cut chi2 decisions, Runge-Kutta steps and Newton
+  // iterations of field crossings; each counter is spread over
+  // kCounterSlots words (by block index) so that the waves' atomic adds do
+  // not queue on one address; the host sums the slots
+  unsigned long long *counters;
 };
+constexpr int kCounters = 5;
+constexpr int kCounterSlots = 64;
+enum { kCntSurKept = 0, kCntSurRejected = 1, kCntNearCut = 2, kCntRk = 3, kCntNewton = 4 };
 
 // 32-bit words of one wavefront's LDS records in the persistent form:
 // back-pointers [max_plan][seeds][G] and retired candidates [seeds][kFinWords]

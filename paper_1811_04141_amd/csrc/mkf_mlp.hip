@@ -72,7 +72,10 @@ __global__ __launch_bounds__(256) void k_mlp_datagen(FindParams P, int64_t n, ui
     L.kind = 0;
     L.pos = R1;
     PropT<float> pr;
-    if (propagate<false, float>(p, nullptr, L, P.cfg.mkb, P.cfg.l_min, false, 0.f, pr) != kOk)
+    // in the loaded parameterised field, if any: the network then predicts
+    // the stepped crossings the find makes there
+    if (propagate<false, float>(p, nullptr, L, P.cfg.mkb, P.cfg.l_min, false, 0.f, pr, 0.f,
+                                nullptr, nullptr, P.cfg.field.on ? &P.cfg.field : nullptr) != kOk)
       continue;
     if (fabsf(pr.p[2]) > 100.f) continue;
     const float ll = line_path(p, R1);
@@ -377,18 +380,28 @@ __global__ __launch_bounds__(256) void k_mlp_images(AdamParams A) {
 
 // ------------------------------------------------------------ inference
 
+// One sample per lane, evaluated as four 16-sample tiles (the find's
+// inference code, so that this entry point tests it).
 __global__ __launch_bounds__(256) void k_mlp_infer(MlpWeights w, int64_t n, const float *x,
                                                    float *y) {
   __shared__ __attribute__((aligned(16))) __bf16 sX[4][64 * kLdX];
-  __shared__ __attribute__((aligned(16))) __bf16 sH[4][64 * kLdH];
+  __shared__ __attribute__((aligned(16))) __bf16 sH[4][16 * kLdH];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool valid = s < n;
-  for (int k = 0; k < 16; ++k)
-    sX[wv][lane * kLdX + k] = (__bf16)((valid && k < 8) ? x[s * 8 + k] : 0.f);
+  for (int k = 0; k < 8; ++k) sX[wv][lane * kLdX + k] = (__bf16)(valid ? x[s * 8 + k] : 0.f);
   wave_sync();
   float out[kNO];
-  mlp_forward_wave(w, sX[wv], sH[wv], out);
+  for (int g = 0; g < 4; ++g) {
+    f32x4 yt;
+    mlp_forward16(w, sX[wv] + 16 * g * kLdX, sH[wv], yt);
+#pragma unroll
+    for (int j = 0; j < kNO; ++j) {
+      const float v = mlp_output16(yt, lane, j);
+      if ((lane >> 4) == g) out[j] = v;
+    }
+    wave_sync();  // the tile's last reads of H precede the next tile's stores
+  }
   if (valid)
     for (int j = 0; j < kNO; ++j) y[s * 7 + j] = out[j];
 }

@@ -2,13 +2,20 @@
 // propagation surrogate: a multilayer perceptron 8 -> 64 -> 64 -> 7 with
 // SiLU activations, BF16 weights and activations, FP32 accumulation.
 //
-// A wavefront evaluates 64 samples at once.  Activations are staged in the
-// wave's own LDS tile, sample-major ([sample][unit], rows padded by 8
-// elements); each layer is a chain of v_mfma_f32_32x32x16_bf16 over
+// Activations are staged in the wave's own LDS tile, sample-major
+// ([sample][unit], rows padded by 8 elements).
+//
+// Training (64 samples per wavefront) chains v_mfma_f32_32x32x16_bf16 over
 // 32 x 32 output tiles.  Operand layout of that instruction (lane l,
 // r = l % 32, h = l / 32): A holds row r, k = 8h .. 8h + 7 of the 32 x 16 tile;
 // B holds column r, k = 8h .. 8h + 7 of the 16 x 32 tile; accumulator
 // register i holds row 8 (i / 4) + 4 h + i % 4, column r of the 32 x 32 tile.
+//
+// Inference runs on 16-sample tiles of v_mfma_f32_16x16x32_bf16 (lane l,
+// r = l % 16, h = l / 16): A holds row r, k = 8h .. 8h + 7 of the 16 x 32
+// tile; B holds column r, the same k; accumulator register i holds row
+// 4h + i, column r.  The find asks for at most 10 samples per wavefront at
+// a time, so the narrower tile halves the activations each lane evaluates.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +26,7 @@ namespace mkf {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int kNI = 8, kNH = 64, kNO = 7;
 constexpr int kNParam = kNH * kNI + kNH + kNH * kNH + kNH + kNO * kNH + kNO;  // 5191
@@ -54,11 +62,10 @@ constexpr float kOutL = 10.f;       // y0 = 10 (l / l_line - 1) / (omega R)
 // angle alpha between the direction and the radial direction at the start
 // (cos, sin) and omega R (omega = the signed curvature); R, cot(theta), z
 // and q/pT complete the state for the longitudinal outputs.
-__device__ __forceinline__ void mlp_inputs(const float *p, float R, float mkb, float *x) {
-  float sphi, cphi;
-  sincosf(p[4], &sphi, &cphi);
-  float sth, cth;
-  sincosf(p[5], &sth, &cth);
+// trig: sin phi, cos phi, sin theta, cos theta of p, already at hand.
+__device__ __forceinline__ void mlp_inputs(const float *p, const float *trig, float R, float mkb,
+                                           float *x) {
+  const float sphi = trig[0], cphi = trig[1], sth = trig[2], cth = trig[3];
   const float r0 = sqrtf(fmaf(p[0], p[0], p[1] * p[1]));
   const float ir0 = r0 > 0.f ? 1.f / r0 : 0.f;
   x[0] = r0 / R;
@@ -71,21 +78,33 @@ __device__ __forceinline__ void mlp_inputs(const float *p, float R, float mkb, f
   x[7] = p[3] * kInIpt;
 }
 
+__device__ __forceinline__ void mlp_inputs(const float *p, float R, float mkb, float *x) {
+  float trig[4];
+  sincosf(p[4], &trig[0], &trig[1]);
+  sincosf(p[5], &trig[2], &trig[3]);
+  mlp_inputs(p, trig, R, mkb, x);
+}
+
 // straight-line transverse path from (x, y) along phi to the cylinder R
 // (the baseline of the surrogate's relative correction)
-__device__ __forceinline__ float line_path(const float *p, float R) {
-  float sphi, cphi;
-  sincosf(p[4], &sphi, &cphi);
+__device__ __forceinline__ float line_path(const float *p, float sphi, float cphi, float R) {
   const float a = fmaf(p[0], cphi, p[1] * sphi);
   const float g0 = fmaf(p[0], p[0], fmaf(p[1], p[1], -R * R));
   return -a + sqrtf(fmaxf(fmaf(a, a, -g0), 0.f));
 }
+__device__ __forceinline__ float line_path(const float *p, float R) {
+  float sphi, cphi;
+  sincosf(p[4], &sphi, &cphi);
+  return line_path(p, sphi, cphi, R);
+}
 
 // path length predicted from the surrogate's first output: the helix path
 // differs from the straight line by a relative amount of first order in
-// omega R, which the network predicts divided by omega R
-__device__ __forceinline__ float surrogate_path(const float *p, float R, float mkb, float y0) {
-  return line_path(p, R) * fmaf(y0 * (1.f / kOutL), mkb * p[3] * R, 1.f);
+// omega R, which the network predicts divided by omega R (trig as in
+// mlp_inputs)
+__device__ __forceinline__ float surrogate_path(const float *p, const float *trig, float R,
+                                                float mkb, float y0) {
+  return line_path(p, trig[0], trig[1], R) * fmaf(y0 * (1.f / kOutL), mkb * p[3] * R, 1.f);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -107,10 +126,11 @@ __device__ __forceinline__ float dsilu(float z) {
 __device__ __forceinline__ int acc_row(int i, int h) { return 8 * (i / 4) + 4 * h + (i % 4); }
 
 // acc[mt][nt] = bias + W (MT*32 x KC*16, row-major, ld) . act^T, where act is
-// the sample-major LDS tile [32 NT][lda] (columns = units, k).
-template <int MT, int KC, int NT = 2>
+// the sample-major LDS tile [64][lda] (columns = units, k).
+template <int MT, int KC>
 __device__ __forceinline__ void gemm_w_act(const __bf16 *W, int ldw, const __bf16 *act, int lda,
-                                           const float *bias, f32x16 (&acc)[MT][NT]) {
+                                           const float *bias, f32x16 (&acc)[MT][2]) {
+  constexpr int NT = 2;
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -138,8 +158,9 @@ __device__ __forceinline__ void gemm_w_act(const __bf16 *W, int ldw, const __bf1
 // Store silu(acc) (or acc itself) as BF16 into a sample-major LDS tile.
 // Accumulator registers 4q .. 4q + 3 hold four consecutive units of one
 // sample, written as one 8-byte store.
-template <int MT, bool kSilu, int NT = 2>
-__device__ __forceinline__ void store_act(const f32x16 (&acc)[MT][NT], __bf16 *out, int ldo) {
+template <int MT, bool kSilu>
+__device__ __forceinline__ void store_act(const f32x16 (&acc)[MT][2], __bf16 *out, int ldo) {
+  constexpr int NT = 2;
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -157,59 +178,87 @@ __device__ __forceinline__ void store_act(const f32x16 (&acc)[MT][NT], __bf16 *o
       }
 }
 
-// Forward pass of the first 32 NT samples of the wave's tiles; X is the
-// sample-major input tile (k 0..7 inputs, 8..15 zero), H a [64][kLdH]
-// scratch tile (X may lie inside H).  y receives the output layer's accumulators: output j of
-// sample s is column s % 32 of tile s / 32, row j (see mlp_output).
-template <int NT>
-__device__ __forceinline__ void mlp_forward_tiles(const MlpWeights &w, const __bf16 *X, __bf16 *H,
-                                                  f32x16 (&y)[1][NT]) {
+// bias + W . act^T for the four 16-unit row tiles of a 64-unit layer with
+// K = 32 KC (16-sample tile, layout above).
+template <int KC>
+__device__ __forceinline__ void gemm16(const __bf16 *W, int ldw, const __bf16 *act, int lda,
+                                       const float *bias, f32x4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, h = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[mt][i] = bias[16 * mt + 4 * h + i];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(act + r * lda + 32 * kc + 8 * h);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W + (16 * mt + r) * ldw + 32 * kc + 8 * h);
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mt], 0, 0, 0);
+    }
+  }
+}
+
+// silu(acc) as BF16 into the sample-major tile: registers 0..3 of a lane
+// are four consecutive units of one sample, one 8-byte store per row tile.
+__device__ __forceinline__ void store16_silu(const f32x4 (&acc)[4], __bf16 *out, int ldo) {
+  const int lane = threadIdx.x & 63, r = lane & 15, h = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    bf16x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (__bf16)silu(acc[mt][e]);
+    *reinterpret_cast<bf16x4 *>(out + r * ldo + 16 * mt + 4 * h) = v;
+  }
+}
+
+// Forward pass of 16 samples: X is the sample-major input tile [16][kLdX]
+// (k 0..7 the inputs), H a [16][kLdH] scratch tile (X may lie inside H).
+// Sample columns are independent, so rows of X that hold no sample may hold
+// anything.  y: output j of sample s is register j % 4 of lane s + 16 (j / 4)
+// (mlp_output16).
+__device__ __forceinline__ void mlp_forward16(const MlpWeights &w, const __bf16 *X, __bf16 *H,
+                                              f32x4 &y) {
+  const int lane = threadIdx.x & 63, r = lane & 15, h = lane >> 4;
   {
-    f32x16 acc[2][NT];
-    gemm_w_act<2, 1, NT>(w.W1p, kLdW1, X, kLdX, w.b1, acc);
+    // first layer: K = 8 inputs, padded to the instruction's 32 with zeros
+    // in the lanes of k >= 8 (both operands, so padding cannot meet a NaN)
+    f32x4 acc[4];
+    const bf16x8 zero = {};
+    const bf16x8 b = h == 0 ? *reinterpret_cast<const bf16x8 *>(X + r * kLdX) : zero;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[mt][i] = w.b1[16 * mt + 4 * h + i];
+      const bf16x8 a =
+          h == 0 ? *reinterpret_cast<const bf16x8 *>(w.W1p + (16 * mt + r) * kLdW1) : zero;
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mt], 0, 0, 0);
+    }
     wave_sync();  // X may overlay H: every lane has read it before h1 is stored
-    store_act<2, true, NT>(acc, H, kLdH);
+    store16_silu(acc, H, kLdH);
   }
   wave_sync();
   {
-    f32x16 acc[2][NT];
-    gemm_w_act<2, 4, NT>(w.W2p, kLdW2, H, kLdH, w.b2, acc);
+    f32x4 acc[4];
+    gemm16<2>(w.W2p, kLdW2, H, kLdH, w.b2, acc);
     wave_sync();  // every lane has read h1 before h2 overwrites it
-    store_act<2, true, NT>(acc, H, kLdH);
+    store16_silu(acc, H, kLdH);
   }
   wave_sync();
-  gemm_w_act<1, 4, NT>(w.W3p, kLdW3, H, kLdH, w.b3, y);
-}
-
-// Output j of sample s (any lane may ask for any sample): row j < 4 is in
-// half 0, register j; rows 4..6 in half 1, register j - 4.
-template <int NT>
-__device__ __forceinline__ float mlp_output(const f32x16 (&y)[1][NT], int s, int j) {
-  const int reg = j & 3;
-  const int src = (s & 31) + (j < 4 ? 0 : 32);
-  float v = __shfl(y[0][0][reg], src);
-  if (NT == 2) {
-    const float v1 = __shfl(y[0][NT - 1][reg], src);
-    v = s >= 32 ? v1 : v;
+  // output layer: rows 0..15 of the padded W3p (7 outputs, the rest zero)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[i] = w.b3[4 * h + i];
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(H + r * kLdH + 32 * kc + 8 * h);
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(w.W3p + r * kLdW3 + 32 * kc + 8 * h);
+    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, y, 0, 0, 0);
   }
-  return v;
 }
 
-// Forward pass of the wave's 64 samples (sample = lane); returns the first
-// output (y0) of the lane's own sample; all 7 outputs go to y_all[7] if not
-// null.
-__device__ __forceinline__ float mlp_forward_wave(const MlpWeights &w, const __bf16 *X, __bf16 *H,
-                                                  float *y_all) {
-  const int lane = threadIdx.x & 63;
-  f32x16 y[1][2];
-  mlp_forward_tiles<2>(w, X, H, y);
-  float own[kNO];
-#pragma unroll
-  for (int j = 0; j < kNO; ++j) own[j] = mlp_output<2>(y, lane, j);
-  if (y_all)
-#pragma unroll
-    for (int j = 0; j < kNO; ++j) y_all[j] = own[j];
-  return own[0];
+// Output j of sample s of mlp_forward16 (any lane may ask for any sample).
+__device__ __forceinline__ float mlp_output16(const f32x4 &y, int s, int j) {
+  return __shfl(y[j & 3], (s & 15) + 16 * (j >> 2));
 }
 
 }  // namespace mkf

@@ -120,7 +120,8 @@ class Stats(C.Structure):
                 ("max_plan_len", C.c_int32), ("n_launches", C.c_int32), ("find_ms", C.c_float),
                 ("index_ms", C.c_float), ("seed_ms", C.c_float), ("main_ms", C.c_float),
                 ("main_launches", C.c_int32), ("sur_kept", C.c_int64),
-                ("sur_rejected", C.c_int64)]
+                ("sur_rejected", C.c_int64), ("n_near_cut", C.c_int64),
+                ("n_rk_steps", C.c_int64), ("n_newton", C.c_int64)]
 
 
 class TrainCfg(C.Structure):

@@ -198,9 +198,104 @@ def test_bad_field_is_an_argument_error(mkf):
             ctx.load_field(bad)
         assert ei.value.status == mkf.MKF_E_ARG
     ctx.close()
-    b = generate(w, events=[0])
-    ctx = context(mkf, w, b, flags=mkf.F_BATCHED | mkf.F_SURROGATE)
-    with pytest.raises(mkf.MkfError) as ei:
-        ctx.find()
-    assert ei.value.status == mkf.MKF_E_ARG
+
+
+@pytest.fixture(scope="module")
+def field_weights(mkf):
+    """The surrogate trained on the field's own stepped crossings (its
+    sampler propagates in the loaded field)."""
+    w = barrel_endcap_field()
+    ctx = mkf.Context(w.find)
+    ctx.load_geometry(w.layers)
+    ctx.load_field(w.field)
+    rep = ctx.surrogate_train(n_samples=1 << 20, epochs=2, batch=512, lr=3e-3, seed=17,
+                              loss_w=(1, .01, .01, .01, .01, .01, .01))
+    say("field training", rep)
+    p = ctx.surrogate_get()
     ctx.close()
+    assert rep["loss_last"] < 0.05 * rep["loss_first"]
+    return p
+
+
+def test_field_surrogate_matches_oracle_and_the_stepped_search(mkf, field_weights):
+    """In the solenoid-like field the surrogate form starts the barrel
+    crossings from the network's path (equal steps to it, one Newton step
+    as one more Runge-Kutta step).  With the field-trained weights most
+    hints are kept and the hit lists are those of the full stepped search
+    for at least 99.5% of seeds, with the oracle's tracks on sampled seeds;
+    with large random weights every hint is refused and the tracks are bit
+    for bit those of the form without the surrogate (zero weights would
+    predict the straight line, which passes the check for stiff tracks)."""
+    w = barrel_endcap_field()
+    b = generate(w, events=[0, 1])
+    n = b.seed_hits.shape[0]
+    plain = context(mkf, w, b, mkf.F_BATCHED)
+    plain.find()
+    tp = plain.get_tracks(n)
+    plain.close()
+    garbage = (np.random.default_rng(95).normal(size=field_weights.size) * 8.0).astype(np.float32)
+    for label, params in (("trained", field_weights), ("garbage", garbage)):
+        ctx = mkf.Context(w.find, flags=mkf.F_BATCHED | mkf.F_SURROGATE)
+        ctx.load_geometry(w.layers)
+        ctx.load_field(w.field)
+        ctx.surrogate_set(params)
+        ctx.load_hits(b.ev_off, dev(b.x), dev(b.y), dev(b.z), dev(b.var_u), dev(b.var_v),
+                      dev(b.layer))
+        ctx.seed(dev(b.seed_event), dev(b.seed_hits))
+        ctx.find()
+        ts = ctx.get_tracks(n)
+        st = ctx.stats()
+        ctx.close()
+        kept, rej = st["sur_kept"], st["sur_rejected"]
+        same = np.all(ts["hit"] == tp["hit"], axis=1).mean()
+        say(label, "kept", kept, "rejected", rej, "same hit lists", same)
+        if label == "garbage":
+            assert kept == 0 and rej > 0
+            assert ts.tobytes() == tp.tobytes()
+            continue
+        assert kept >= 0.4 * (kept + rej)
+        assert same >= 0.995
+        rng = np.random.default_rng(94)
+        for e in range(2):
+            E = b.events[e]
+            sel = np.nonzero(b.seed_event == e)[0]
+            pick = np.sort(rng.choice(sel, 100, replace=False))
+            ref = O.find_event(w.find, w.layers, E, seeds=E.seeds[pick - sel[0]],
+                               field=w.field)
+            out = PT.compare_tracks(ts[pick], ref, mkf.unpack_cov)
+            say(e, {k: (v if k != "fail" else len(v)) for k, v in out.items()})
+            assert not out["fail"], out["fail"][:5]
+            assert out["equal"] >= 0.9 * out["n"]
+
+
+def test_find_counters_agree_between_forms(mkf, field_weights):
+    """mkf_stats' decision and work counters: both find forms evaluate the
+    same candidates with the same arithmetic, so they count the same
+    near-cut chi2 decisions, Runge-Kutta steps and Newton iterations; the
+    uniform field takes no steps; every Newton iteration is one Runge-Kutta
+    step.  The surrogate form's counts are reported beside them."""
+    w = barrel_endcap_field()
+    b = generate(w, events=[0, 1])
+    rows = {}
+    for field in (True, False):
+        for flags in (0, mkf.F_BATCHED):
+            ctx = context(mkf, w, b, flags, field=field)
+            ctx.find()
+            st = ctx.stats()
+            ctx.close()
+            rows[(field, flags)] = (st["n_near_cut"], st["n_rk_steps"], st["n_newton"])
+            say("field" if field else "uniform", "batched" if flags else "plain",
+                rows[(field, flags)], "steps", st["n_steps"])
+    ctx = context(mkf, w, b, mkf.F_BATCHED | mkf.F_SURROGATE)
+    ctx.surrogate_set(field_weights)
+    ctx.find()
+    st = ctx.stats()
+    ctx.close()
+    say("field surrogate", (st["n_near_cut"], st["n_rk_steps"], st["n_newton"]),
+        "hints kept", st["sur_kept"], "rejected", st["sur_rejected"])
+    assert rows[(True, 0)] == rows[(True, mkf.F_BATCHED)]
+    assert rows[(False, 0)] == rows[(False, mkf.F_BATCHED)]
+    nc, rk, nw = rows[(True, 0)]
+    assert nc > 0 and rk > 0 and 0 < nw < rk
+    assert rows[(False, 0)][0] > 0 and rows[(False, 0)][1:] == (0, 0)
+    assert st["n_rk_steps"] > 0 and st["n_newton"] > 0

@@ -207,10 +207,32 @@ def test_bad_material_is_an_argument_error(mkf):
         if isinstance(ei.value, mkf.MkfError):
             assert ei.value.status == mkf.MKF_E_ARG
     ctx.close()
-    # the surrogate form has no material variant
-    b = generate(w, events=[0])
+
+
+def test_surrogate_with_material_map_keeps_the_hit_lists(mkf):
+    """The surrogate form with a material map: the network only starts the
+    barrel crossings (one Newton step checks each hint), the material update
+    follows as without it, so the hit lists are those of the form without
+    the surrogate and most hints are kept."""
+    w = cms_like_material()
+    b = generate(w, events=[0, 1])
+    n = b.seed_hits.shape[0]
+    ref = context(mkf, w, b, flags=mkf.F_BATCHED)
+    ref.find()
+    tp = ref.get_tracks(n)
+    ref.close()
     ctx = context(mkf, w, b, flags=mkf.F_BATCHED | mkf.F_SURROGATE)
-    with pytest.raises(mkf.MkfError) as ei:
+    try:
+        rep = ctx.surrogate_train(n_samples=1 << 20, epochs=4, batch=512, lr=3e-3, seed=23,
+                                  loss_w=(1, .01, .01, .01, .01, .01, .01))
+        say("training", rep)
         ctx.find()
-    assert ei.value.status == mkf.MKF_E_ARG
-    ctx.close()
+        ts = ctx.get_tracks(n)
+        st = ctx.stats()
+    finally:
+        ctx.close()
+    kept, rej = st["sur_kept"], st["sur_rejected"]
+    same = np.all(ts["hit"] == tp["hit"], axis=1).mean()
+    say("kept", kept, "rejected", rej, "same hit lists", same)
+    assert kept >= 0.5 * (kept + rej)
+    assert same >= 0.995
