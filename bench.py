@@ -221,9 +221,7 @@ def measure_kernels(mkf, w, stream, T, f, batch, extended):
     workload's found tracks, and the surrogate network's inference and
     gradient (2^20 samples from its training sampler).  With `extended`:
     triplet seeding with cleaning, find and duplicate removal, the find with
-    a material map and with region steering, and the find in a parameterised
-    field (100 events of 5,000 tracks simulated in it) with and without the
-    uniform field."""
+    a material map and with region steering."""
     import numpy as np
     import torch
 
@@ -315,11 +313,9 @@ def measure_kernels(mkf, w, stream, T, f, batch, extended):
 
 def measure_extended(mkf, w, stream, T, batch, hits, seeds, timed):
     """The extended finds: triplet seeding, cleaning and duplicate removal;
-    the find with a material map and with five-region steering; the find in
-    a parameterised field on events simulated in it."""
+    the find with a material map and with five-region steering."""
     import torch
-    from synth import (CleaningConfig, SeedingConfig, barrel_endcap_field, five_regions,
-                       generate_event, make_batch, material_map)
+    from synth import CleaningConfig, SeedingConfig, five_regions, material_map
     out = {}
     dev = hits[0].device
     ctx3 = mkf.Context(w.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
@@ -376,34 +372,69 @@ def measure_extended(mkf, w, stream, T, batch, hits, seeds, timed):
         out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
                       "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
                       "unit": UNIT, "workload": w.name, "tuning": tun4}
-    wf = barrel_endcap_field(100, 5000)
-    evs = []
-    for e in range(wf.n_events):
-        evs.append(generate_event(wf, e))
-        if e % 10 == 9:
-            log(f"field events generated: {e + 1}/{wf.n_events}")
-    bf = make_batch(evs)
-    del evs
+    return out
+
+
+FIELD_TRAIN = dict(n_samples=10_000_000, epochs=2, batch=512, lr=3e-3, seed=17,
+                   loss_w=(1, .01, .01, .01, .01, .01, .01))
+
+
+def measure_field(mkf, stream, T, n_events, gen_workers, repeats=5):
+    """The find in the parameterised solenoid-like field, on events of the
+    barrel + endcap workload simulated in it (n_events x 5,000 tracks), with
+    and without the learned surrogate.  Without it every barrel crossing is
+    found by Runge-Kutta stepping and Newton iteration; with it the crossing
+    starts from the network's path (equal steps to it and one Newton step,
+    kept under the same checks, else the full stepped search).  The network
+    is trained on 10 M stepped crossings of the field's own sampler.  Each
+    form is autotuned, then timed as the median device time of `repeats`
+    finds; the hit lists of the two forms are compared track by track."""
+    import numpy as np
+    import torch
+    from synth import barrel_endcap_field, generate
+    wf = barrel_endcap_field(n_events, 5000)
+    t0 = time.time()
+    bf = generate(wf, workers=gen_workers)
+    log(f"{wf.name}: {bf.x.shape[0]} hits, {bf.seed_hits.shape[0]} seeds in "
+        f"{time.time() - t0:.1f}s")
     fh = [T(a) for a in (bf.x, bf.y, bf.z, bf.var_u, bf.var_v, bf.layer)]
     fs = (T(bf.seed_event), T(bf.seed_hits))
-    for label, fld in (("find_parameterised_field", wf.field),
-                       ("find_uniform_field_same_events", None)):
-        c5 = mkf.Context(wf.find, flags=mkf.F_BATCHED, stream=stream.cuda_stream)
-        c5.load_geometry(wf.layers)
-        c5.load_field(fld)
-        c5.load_hits(bf.ev_off, *fh)
-        c5.seed(*fs)
-        tun5 = c5.autotune(repeats=2)
-        c5.find()
-        c5.find()
-        st = c5.stats()
-        n = int(bf.seed_hits.shape[0])
-        tr = c5.get_tracks(n)
-        c5.close()
-        out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
-                      "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
-                      "unit": UNIT, "workload": wf.name,
-                      "mean_hits_per_track": float(tr["n_hits"].mean()), "tuning": tun5}
+    n = int(bf.seed_hits.shape[0])
+    out = {"workload": wf.name, "events": n_events, "seeds": n}
+    tracks = {}
+    with torch.cuda.stream(stream):
+        for label, flags in (("stepped", mkf.F_BATCHED),
+                             ("surrogate", mkf.F_BATCHED | mkf.F_SURROGATE)):
+            c = mkf.Context(wf.find, flags=flags, stream=stream.cuda_stream)
+            c.load_geometry(wf.layers)
+            c.load_field(wf.field)
+            if label == "surrogate":
+                out["training"] = c.surrogate_train(**FIELD_TRAIN)
+                log("field surrogate trained", json.dumps(out["training"]))
+            c.load_hits(bf.ev_off, *fh)
+            c.seed(*fs)
+            tun = c.autotune(repeats=2)
+            ms, main = [], []
+            for _ in range(repeats):
+                c.find()
+                st = c.stats()
+                ms.append(st["find_ms"])
+                main.append(st["main_ms"])
+            tracks[label] = c.get_tracks(n)
+            c.close()
+            f_ms = float(np.median(ms))
+            res = {"find_ms": f_ms, "main_ms": float(np.median(main)), "n_steps": st["n_steps"],
+                   "throughput": st["n_steps"] / (f_ms * 1e-3), "unit": UNIT, "tuning": tun}
+            if label == "surrogate":
+                kept, rej = st["sur_kept"], st["sur_rejected"]
+                res["hints_kept"] = kept
+                res["hints_rejected"] = rej
+                res["kept_fraction"] = kept / max(1, kept + rej)
+            out[label] = res
+            log("field", label, json.dumps(res))
+    out["same_hits"] = float(np.mean(np.all(tracks["surrogate"]["hit"] ==
+                                            tracks["stepped"]["hit"], axis=1)))
+    out["speedup"] = out["stepped"]["find_ms"] / out["surrogate"]["find_ms"]
     return out
 
 
@@ -420,6 +451,12 @@ def main():
     ap.add_argument("--forms", default=",".join(FORMS))
     ap.add_argument("--gen-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
                     help="host processes generating the events (1 under a profiler)")
+    ap.add_argument("--workload-cache", default=None,
+                    help="file holding the generated events: read if present, else written "
+                         "(lets profiled runs skip the generation)")
+    ap.add_argument("--surrogate-params", default=None,
+                    help="file of the trained surrogate weights (.npy): read if present, else "
+                         "written after training (lets profiled runs skip the training)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="budget of each leg of the oracle CPU baseline (0 disables)")
     ap.add_argument("--cpu-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
@@ -427,8 +464,10 @@ def main():
     ap.add_argument("--kernels", type=int, default=1,
                     help="also time the fit, backward fit, smoothing and network kernels")
     ap.add_argument("--extended", type=int, default=0,
-                    help="also time the seeding pipeline and the material, steering and "
-                         "field finds")
+                    help="also time the seeding pipeline and the material and steering finds")
+    ap.add_argument("--field-events", type=int, default=100,
+                    help="events of 5,000 tracks for the find in the parameterised field "
+                         "with and without the surrogate (0 disables)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -447,9 +486,21 @@ def main():
 
     w = batched_uneven(args.events)
     t0 = time.time()
-    log(f"generating {w.name} with {args.gen_workers} processes")
-    batch = generate(w, workers=args.gen_workers)
-    log(f"generated {w.name}: {batch.x.shape[0]} hits, {batch.seed_hits.shape[0]} seeds "
+    if args.workload_cache and os.path.exists(args.workload_cache):
+        import pickle  # a file this program wrote itself
+        with open(args.workload_cache, "rb") as f:
+            name, batch = pickle.load(f)
+        if name != w.name:
+            sys.exit(f"{args.workload_cache} holds {name}, not {w.name}")
+        log(f"read {w.name} from {args.workload_cache}")
+    else:
+        log(f"generating {w.name} with {args.gen_workers} processes")
+        batch = generate(w, workers=args.gen_workers)
+        if args.workload_cache:
+            import pickle
+            with open(args.workload_cache, "wb") as f:
+                pickle.dump((w.name, batch), f, protocol=pickle.HIGHEST_PROTOCOL)
+    log(f"{w.name}: {batch.x.shape[0]} hits, {batch.seed_hits.shape[0]} seeds "
         f"in {time.time() - t0:.1f}s")
     fit_inputs = None
     if args.kernels:  # (in this process: no children under a profiler)
@@ -474,13 +525,21 @@ def main():
 
     train, params = None, None
     if any(f.startswith("surrogate") for f in forms):
-        with torch.cuda.stream(stream):
-            c = mkf.Context(w.find, stream=stream.cuda_stream)
-            c.load_geometry(w.layers)
-            train = c.surrogate_train(**TRAIN)
-            params = c.surrogate_get()
-            c.close()
-        log("surrogate trained", json.dumps(train))
+        sp = args.surrogate_params
+        if sp and os.path.exists(sp):
+            params = np.load(sp)  # a plain float32 array this program saved
+            train = {"loaded_from": sp}
+            log(f"surrogate weights read from {sp}")
+        else:
+            with torch.cuda.stream(stream):
+                c = mkf.Context(w.find, stream=stream.cuda_stream)
+                c.load_geometry(w.layers)
+                train = c.surrogate_train(**TRAIN)
+                params = c.surrogate_get()
+                c.close()
+            log("surrogate trained", json.dumps(train))
+            if sp:
+                np.save(sp, params)
 
     flag_of = {"surrogate": mkf.F_BATCHED | mkf.F_GRAPH | mkf.F_SURROGATE,
                "surrogate_eager": mkf.F_BATCHED | mkf.F_SURROGATE,
@@ -517,18 +576,21 @@ def main():
     eager = {"surrogate": "surrogate_eager", "graph": "batched"}.get(head, head)
     K = results.get(eager, R)
     roof = None
+    # the layer-synchronous form's kernel: 6-lane seed groups for budgets up to 6
+    plain_kernel = f"k_find_step<false, {6 if w.find.n_cand <= 6 else 8}>"
     if K.get("main_ms", -1) > 0:
         per_launch_steps = K["n_steps"] / max(1, K["main_launches"])
         per_launch_ms = K["main_ms"] / max(1, K["main_launches"])
         if eager.startswith("plain"):
-            kname = "k_find_step<false>"
+            kname = plain_kernel
             achieved = PLAIN_BYTES_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e9
             roof = {"kernel": kname, "bound": "hbm", "achieved": achieved,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         else:
             t = K["tuning"] or {"waves_per_simd": 0}
             kname = (f"k_find_persistent<{t['waves_per_simd']}, "
-                     f"{'true' if eager.startswith('surrogate') else 'false'}, 6>")
+                     f"{'true' if eager.startswith('surrogate') else 'false'}, "
+                     f"{t.get('lane_group', 6)}>")
             achieved = FLOPS_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e12
             roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
@@ -540,13 +602,22 @@ def main():
     if "plain_all_events" in results and results["plain_all_events"]["main_ms"] > 0:
         P = results["plain_all_events"]
         gbs = PLAIN_BYTES_PER_STEP * P["n_steps"] / (P["main_ms"] * 1e-3) / 1e9
-        plain_roof = {"kernel": "k_find_step<false>", "bound": "hbm", "achieved": gbs,
+        per_launch = profiled_traffic(plain_kernel, w.name)
+        plain_roof = {"kernel": plain_kernel, "bound": "hbm", "achieved": gbs,
                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                       "launches": P["main_launches"], "ms": P["main_ms"],
-                      "traffic": profiled_traffic("k_find_step<false>", w.name)}
+                      "algorithmic_bytes": PLAIN_BYTES_PER_STEP * P["n_steps"],
+                      # all launches of the find, from the profiled per-launch mean
+                      "traffic": (per_launch * P["main_launches"]
+                                  if per_launch is not None else None)}
 
     kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, args.extended)
                if args.kernels else None)
+
+    field = None
+    if args.field_events > 0:
+        field = measure_field(mkf, stream, T, args.field_events, args.gen_workers)
+        torch.cuda.empty_cache()
 
     cpu = None
     if args.cpu_seconds > 0:
@@ -575,6 +646,7 @@ def main():
         "vs_plain": ratios,
         "surrogate_training": train,
         "kernels": kernels,
+        "field_surrogate": field,
         "roofline": roof,
         "plain_roofline": plain_roof,
         "cpu_baseline": cpu,
