@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "candidate-layer updates/s (propagate+chi2+update), surrogate+batched vs plain, 1 GPU"
 UNIT = "candidate-layer updates/s"
+FIT_TRACKS = 2_000_000  # the fit stress workload: 2 M tracks x 26 layers
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
@@ -214,12 +215,14 @@ def time_per_event(mkf, w, b, stream, args, T):
              "device_value": steps / (float(np.median(dev_ms)) * 1e-3)}, tr)
 
 
-def measure_kernels(mkf, w, stream, T, f, batch, extended):
+def measure_kernels(mkf, w, stream, T, f, batch, extended, params, gen_workers):
     """Throughput of the other hot-path kernels, each from HIP events on the
     context stream around one launch after a warm-up: the search-free fit
-    (131,072 tracks x 26 layers), the backward fit and the smoothing of the
-    workload's found tracks, and the surrogate network's inference and
-    gradient (2^20 samples from its training sampler).  With `extended`:
+    (2 M tracks x 26 layers), the backward fit and the smoothing of the
+    workload's found tracks, the surrogate network's inference and gradient
+    (2^20 samples from its training sampler), and the find on dense events
+    (4 x 25,000 tracks, 50% noise) with and without the surrogate (its
+    weights: params, trained on the same geometry).  With `extended`:
     triplet seeding with cleaning, find and duplicate removal, the find with
     a material map and with region steering."""
     import numpy as np
@@ -305,6 +308,8 @@ def measure_kernels(mkf, w, stream, T, f, batch, extended):
                                             "samples/s"), bound="mfma", workload=f"{m} samples")
         del x, t, v, y
         ctx.close()
+        torch.cuda.empty_cache()
+        out["find_dense"] = measure_dense(mkf, stream, T, params, gen_workers)
         if extended:
             out.update(measure_extended(mkf, w, stream, T, batch, hits, seeds, timed))
     log("kernels", json.dumps(out))
@@ -372,6 +377,50 @@ def measure_extended(mkf, w, stream, T, batch, hits, seeds, timed):
         out[label] = {"find_ms": st["find_ms"], "n_steps": st["n_steps"],
                       "throughput": st["n_steps"] / (st["find_ms"] * 1e-3),
                       "unit": UNIT, "workload": w.name, "tuning": tun4}
+    return out
+
+
+def measure_dense(mkf, stream, T, params, gen_workers, repeats=5):
+    """The find on dense events (4 x 25,000 tracks, 50% noise hits), in the
+    persistent form with and without the surrogate: median device time of
+    `repeats` finds after autotuning, and the fraction of identical hit
+    lists."""
+    import numpy as np
+    from synth import dense, generate
+    wd = dense(4)
+    bd = generate(wd, workers=gen_workers)
+    hits = [T(a) for a in (bd.x, bd.y, bd.z, bd.var_u, bd.var_v, bd.layer)]
+    seeds = (T(bd.seed_event), T(bd.seed_hits))
+    n = int(bd.seed_hits.shape[0])
+    out = {"workload": wd.name, "seeds": n, "hits": int(bd.x.shape[0])}
+    tracks = {}
+    forms = [("batched", mkf.F_BATCHED)]
+    if params is not None:
+        forms.append(("surrogate", mkf.F_BATCHED | mkf.F_SURROGATE))
+    for label, flags in forms:
+        c = mkf.Context(wd.find, flags=flags, stream=stream.cuda_stream)
+        c.load_geometry(wd.layers)
+        if label == "surrogate":
+            c.surrogate_set(params)
+        c.load_hits(bd.ev_off, *hits)
+        c.seed(*seeds)
+        tun = c.autotune(repeats=2)
+        ms = []
+        for _ in range(repeats):
+            c.find()
+            st = c.stats()
+            ms.append(st["find_ms"])
+        tracks[label] = c.get_tracks(n)
+        c.close()
+        f_ms = float(np.median(ms))
+        out[label] = {"find_ms": f_ms, "n_steps": st["n_steps"],
+                      "throughput": st["n_steps"] / (f_ms * 1e-3), "unit": UNIT, "tuning": tun,
+                      "near_cut_decisions": st["n_near_cut"]}
+        if label == "surrogate":
+            out[label]["kept_fraction"] = st["sur_kept"] / max(1, st["sur_kept"] + st["sur_rejected"])
+    if "surrogate" in tracks:
+        out["same_hits"] = float(np.mean(np.all(tracks["surrogate"]["hit"] ==
+                                                tracks["batched"]["hit"], axis=1)))
     return out
 
 
@@ -505,7 +554,7 @@ def main():
     fit_inputs = None
     if args.kernels:  # (in this process: no children under a profiler)
         from synth.fitstress import fit_stress
-        fit_inputs = fit_stress(131072, 26)
+        fit_inputs = fit_stress(FIT_TRACKS, 26, workers=args.gen_workers)
 
     import torch
     from paper_1811_04141_amd import mkf
@@ -611,7 +660,8 @@ def main():
                       "traffic": (per_launch * P["main_launches"]
                                   if per_launch is not None else None)}
 
-    kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, args.extended)
+    kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, args.extended, params,
+                               args.gen_workers)
                if args.kernels else None)
 
     field = None

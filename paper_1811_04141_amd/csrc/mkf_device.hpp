@@ -672,10 +672,11 @@ __device__ __forceinline__ void surface_prior(const DevCfg &cfg, const T *p, int
 template <typename T>
 __device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c, T sth, T cth) {
   if (ms_var == T(0)) return;
-  const T a = p[3] * cth / sth;
+  const T is = T(1) / sth;
+  const T a = p[3] * cth * is;
   c[tri(3, 3)] += a * a * ms_var;
   c[tri(3, 5)] -= a * ms_var;
-  c[tri(4, 4)] += ms_var / (sth * sth);
+  c[tri(4, 4)] += ms_var * (is * is);
   c[tri(5, 5)] += ms_var;
 }
 
@@ -684,11 +685,7 @@ __device__ __forceinline__ void add_ms(const T *p, T ms_var, T *c) {
   if (ms_var == T(0)) return;
   T sth, cth;
   sincos_t(p[5], &sth, &cth);
-  const T a = p[3] * cth / sth;
-  c[tri(3, 3)] += a * a * ms_var;
-  c[tri(3, 5)] -= a * ms_var;
-  c[tri(4, 4)] += ms_var / (sth * sth);
-  c[tri(5, 5)] += ms_var;
+  add_ms(p, ms_var, c, sth, cth);
 }
 
 // Mean ionisation loss rate in silicon (Bethe, no density or shell

@@ -259,7 +259,8 @@ __device__ __forceinline__ void window_bins(const FindParams &P, const DevLayer 
   const float phic = window_azimuth(pr.p[1], pr.p[0]);
   float dphi, qmin, qmax;
   if (L.kind == 0) {
-    const float s = du / (L.pos * 0.99999f);
+    // (hardware reciprocals below: the 1e-5 and 1e-4 widenings cover their ulp)
+    const float s = du * __builtin_amdgcn_rcpf(L.pos * 0.99999f);
     dphi = s >= 0.99f ? kPi : s * rsqrtf(fmaf(-s, s, 1.f)) * 1.0001f;
     qmin = pr.p[2] - dv;
     qmax = pr.p[2] + dv;
@@ -268,7 +269,7 @@ __device__ __forceinline__ void window_bins(const FindParams &P, const DevLayer 
     const float rl = r - dv;
     qmin = rl;
     qmax = __builtin_amdgcn_sqrtf(fmaf(r + dv, r + dv, du * du));
-    dphi = rl > 0.f ? fminf(du / rl * 1.0001f, kPi) : kPi;
+    dphi = rl > 0.f ? fminf(du * __builtin_amdgcn_rcpf(rl) * 1.0001f, kPi) : kPi;
   }
   dphi += 6e-6f;
   qmin -= 1e-4f;
@@ -437,11 +438,20 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
 
   // children read their parent's propagated state (or, for a skip, its
   // unpropagated state) across the group
+  // (a candidate whose propagation failed hands on its unpropagated state;
+  // the selects are skipped, wave-uniformly, when no lane has one: lanes
+  // without a candidate are never chosen as parents)
   float src[27];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) src[i] = ok ? pr.p[i] : cd.p[i];
+  for (int i = 0; i < 6; ++i) src[i] = pr.p[i];
 #pragma unroll
-  for (int i = 0; i < 21; ++i) src[6 + i] = ok ? pr.c[i] : cd.c[i];
+  for (int i = 0; i < 21; ++i) src[6 + i] = pr.c[i];
+  if (__ballot(cd.active && !ok) != 0ull) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) src[i] = ok ? pr.p[i] : cd.p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) src[6 + i] = ok ? pr.c[i] : cd.c[i];
+  }
   const int src_meta = cd.nh | (cd.nm << 8) | (ok ? (1 << 16) : 0);
   const int parent = mine == kKeyMax ? slot : (int)((mine >> 23) & 7);
   const int src_lane = Grp<G>::base(lane) + parent;
