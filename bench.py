@@ -122,12 +122,20 @@ def cpu_baseline(w, batch, seconds, workers):
     steps = sum(o[0] for o in out)
     t = max(o[1] for o in out)
     seeds = sum(o[2] for o in out)
+    # one thread on the other workloads' shapes: the 200-track barrel event
+    # (whole) and a dense 25,000-track event with 50% noise (first seeds)
+    from synth import dense, generate_event, small_barrel
+    others = {}
+    for wo in (small_barrel(), dense(1)):
+        so, to, no = _oracle_share((wo, generate_event(wo, 0), min(seconds, 3.0)))
+        others[wo.name] = {"value": so / to, "seeds": no, "steps": so, "seconds": round(to, 2)}
     return {"value": steps / t, "unit": UNIT, "cores": n, "kind": "oracle",
             "sample": f"first seeds of events 0-{n - 1} of the workload, one event per process "
                       f"({seeds} seeds, {steps} candidate-layer steps, {t:.1f} s; FP64, "
                       f"brute-force hit scan)",
             "one_thread": {"value": one[0] / one[1], "sample":
                            f"first {one[2]} seeds of event 0 ({one[0]} steps, {one[1]:.1f} s)"},
+            "other_workloads_one_thread": others,
             "cpu_model": cpu_model(), "hardware_concurrency": os.cpu_count(),
             "cpus_available": len(os.sched_getaffinity(0))}
 
@@ -424,6 +432,54 @@ def measure_dense(mkf, stream, T, params, gen_workers, repeats=5):
     return out
 
 
+def validation(batch, tracks, plen, plan, ok):
+    """Hit-selection accuracy and efficiency of found tracks against the
+    generator's truth.  Accuracy: over the plan layers of every seed whose
+    fit succeeded, the fraction where the selected hit is the seed's truth
+    track's hit on that layer (a layer where the truth track left no hit
+    counts as correct).  Efficiency: the fraction of those seeds whose track
+    (its three seed hits and the found ones) has at least 75% hits of the
+    seed's truth track.  Purity: found hits from the seed's truth track over
+    all found hits."""
+    import numpy as np
+    evs = batch.events
+    truth = np.concatenate([e.track for e in evs]).astype(np.int64)
+    layer = np.asarray(batch.layer, np.int64)
+    nl = int(layer.max()) + 1 if layer.size else 1
+    ntrk = max(int(truth.max()) + 1, 1)
+    ev_of_hit = np.repeat(np.arange(len(evs), dtype=np.int64), np.diff(batch.ev_off))
+    real = truth >= 0
+    keys = ((ev_of_hit[real] * ntrk + truth[real]) * nl + layer[real])
+    gidx = np.nonzero(real)[0]
+    order = np.argsort(keys, kind="stable")
+    keys, gidx = keys[order], gidx[order]
+    seed_track = np.concatenate([e.seed_track for e in evs]).astype(np.int64)
+    sev = np.asarray(batch.seed_event, np.int64)
+    base = batch.ev_off[sev]
+    sel = np.asarray(tracks["hit"], np.int64)
+    m = sel.shape[1]
+    steps = np.arange(m)[None, :]
+    valid = (steps < plen[:, None]) & (ok[:, None] != 0)
+    qkey = ((sev * ntrk + seed_track)[:, None] * nl + plan[:, :m].astype(np.int64))
+    pos = np.searchsorted(keys, qkey)
+    posc = np.minimum(pos, max(keys.size - 1, 0))
+    has_truth = (keys.size > 0) & (keys[posc] == qkey)
+    truth_hit = np.where(has_truth, gidx[posc], -1)
+    sel_g = np.where(sel >= 0, sel + base[:, None], -1)
+    correct = (~has_truth) | (sel_g == truth_hit)
+    found = (sel >= 0) & valid
+    match = found & (truth[np.maximum(sel_g, 0)] == seed_track[:, None])
+    n_found = found.sum(axis=1)
+    n_match = match.sum(axis=1)
+    good = ok != 0
+    eff = ((3 + n_match) >= 0.75 * (3 + n_found)) & good
+    return {"seeds": int(good.sum()),
+            "hit_selection_accuracy": float(correct[valid].mean()) if valid.any() else None,
+            "efficiency_75pct": float(eff.sum() / max(1, good.sum())),
+            "hit_purity": float(n_match[good].sum() / max(1, n_found[good].sum())),
+            "found_hits_per_track": float(n_found[good].mean()) if good.any() else None}
+
+
 FIELD_TRAIN = dict(n_samples=10_000_000, epochs=2, batch=512, lr=3e-3, seed=17,
                    loss_w=(1, .01, .01, .01, .01, .01, .01))
 
@@ -517,6 +573,9 @@ def main():
     ap.add_argument("--field-events", type=int, default=100,
                     help="events of 5,000 tracks for the find in the parameterised field "
                          "with and without the surrogate (0 disables)")
+    ap.add_argument("--run-record", default=None,
+                    help="append the run record (throughput, roofline fraction, hit-selection "
+                         "accuracy, efficiency) as one JSON line to this file")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -660,6 +719,20 @@ def main():
                       "traffic": (per_launch * P["main_launches"]
                                   if per_launch is not None else None)}
 
+    # the found tracks against the generator's truth (hit lists are the same
+    # in every form; the plans come from the seeding)
+    with torch.cuda.stream(stream):
+        cv = mkf.Context(w.find, stream=stream.cuda_stream)
+        cv.load_geometry(w.layers)
+        cv.load_hits(batch.ev_off, *[T(a) for a in (batch.x, batch.y, batch.z, batch.var_u,
+                                                    batch.var_v, batch.layer)])
+        cv.seed(T(batch.seed_event), T(batch.seed_hits))
+        _, _, s_ok, s_plen, s_plan, _ = cv.get_seed_states(batch.seed_hits.shape[0])
+        cv.close()
+    val = validation(batch, tracks_ref, s_plen, s_plan, s_ok)
+    log("validation", json.dumps(val))
+    torch.cuda.empty_cache()
+
     kernels = (measure_kernels(mkf, w, stream, T, fit_inputs, batch, args.extended, params,
                                args.gen_workers)
                if args.kernels else None)
@@ -697,11 +770,20 @@ def main():
         "surrogate_training": train,
         "kernels": kernels,
         "field_surrogate": field,
+        "validation": val,
         "roofline": roof,
         "plain_roofline": plain_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.run_record:
+        rec = {"time": time.strftime("%Y-%m-%dT%H:%M:%S"), "workload": w.name,
+               "value": line["value"], "unit": UNIT,
+               "roofline_frac": roof["frac"] if roof else None,
+               "plain_hbm_frac": plain_roof["frac"] if plain_roof else None,
+               **val}
+        with open(args.run_record, "a") as f:
+            f.write(json.dumps(rec) + "\n")
 
 
 if __name__ == "__main__":

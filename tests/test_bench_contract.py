@@ -53,3 +53,40 @@ def test_committed_traffic_records_name_existing_sources():
             assert os.path.exists(os.path.join(ROOT, s)), (f, s)
         assert rec["hbm_bytes_per_launch"] > 0
         assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
+
+
+def test_validation_scores_truth_and_planted_mistakes():
+    """The run record's hit-selection accuracy, purity and efficiency: 1 for
+    tracks that select exactly their truth hits; a planted wrong hit and a
+    planted miss lower them by the expected amounts."""
+    import numpy as np
+    from synth import generate, small_barrel
+    bench = load_bench()
+    w = small_barrel()
+    b = generate(w)
+    E = b.events[0]
+    n = E.seed_track.shape[0]
+    tr = np.zeros(n, dtype=[("hit", np.int32, (32,))])
+    tr["hit"][:] = -1
+    plan = np.zeros((n, 32), np.int8)
+    plen = np.zeros(n, np.int32)
+    for s, t in enumerate(E.seed_track):
+        th = E.track_hits[t][3:]
+        plen[s] = th.shape[0]
+        plan[s, :th.shape[0]] = E.layer[th]
+        tr["hit"][s, :th.shape[0]] = th
+    ok = np.ones(n, np.int32)
+    v = bench.validation(b, tr, plen, plan, ok)
+    assert v["hit_selection_accuracy"] == 1.0 and v["hit_purity"] == 1.0
+    assert v["efficiency_75pct"] == 1.0 and v["seeds"] == n
+    total = int(plen.sum())
+    # seed 0's first found hit replaced by another track's hit on that layer
+    s0, t0 = 0, int(E.seed_track[0])
+    lay = plan[s0, 0]
+    other = np.nonzero((E.layer == lay) & (E.track != t0) & (E.track >= 0))[0][0]
+    tr["hit"][s0, 0] = other
+    # seed 1's last found hit dropped (a miss where the truth track has a hit)
+    tr["hit"][1, plen[1] - 1] = -1
+    v = bench.validation(b, tr, plen, plan, ok)
+    assert abs(v["hit_selection_accuracy"] - (total - 2) / total) < 1e-12
+    assert abs(v["hit_purity"] - (total - 2) / (total - 1)) < 1e-12
