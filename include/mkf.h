@@ -452,11 +452,16 @@ mkf_status mkf_autotune(mkf_ctx *ctx, int32_t repeats, const char *cache_path,
  * offsets from the straight line along and across the initial direction and
  * in z; then 10 (cos, sin) of the turning angle minus (10, 0); then 0.  Only
  * the first output is used by the find; the rest are trained and reported.
- * In the find (MKF_F_SURROGATE) every prediction gets one exact Newton step
- * and is kept only if that step moves it by at most 1e-4 relative, the
- * Newton error bound left after it is at most 1e-7 relative and it is the
- * first crossing; otherwise the closed-form crossing is used, so the tracks
- * do not depend on the weights beyond FP32 rounding.  Parameters (5,191 FP32,
+ * In the find (MKF_F_SURROGATE) the network predicts, per layer step, the
+ * path of each seed's leading candidate; every candidate applies that
+ * relative correction to its own straight-line path and takes one exact
+ * Newton step from there (in the parameterised field: Runge-Kutta steps to
+ * the predicted path and the correction as one more step).  The result is
+ * kept only if that step moves it by at most 1e-4 relative, the Newton error
+ * bound left after it is at most 1e-7 relative and it is the first crossing;
+ * otherwise the closed-form crossing (in the field, the full stepped search)
+ * is used, so the tracks do not depend on the weights beyond FP32 rounding.
+ * Parameters (5,191 FP32,
  * in this order): W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]. */
 
 typedef struct {
@@ -534,7 +539,9 @@ mkf_status mkf_surrogate_grad(mkf_ctx *ctx, int32_t n, const float *x, const flo
 mkf_status mkf_surrogate_grad_noalloc(mkf_ctx *ctx, int32_t n, const float *x, const float *t,
                                       const float *loss_w, float *grad, float *loss);
 
-/* Outputs y [n][7] (device) for inputs x [n][8] (device). */
+/* Outputs y [n][7] (device) for inputs x [n][8] (device).  Calls of up to
+ * 16,384 samples run on the find's 16-sample tiles, larger ones on 64-sample
+ * tiles; the two may differ in the last bits (accumulation order). */
 mkf_status mkf_surrogate_infer(mkf_ctx *ctx, int64_t n, const float *x, float *y);
 
 /* The training sampler: n inputs x [n][8], targets t [n][7] and validity

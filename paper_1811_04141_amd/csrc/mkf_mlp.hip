@@ -380,28 +380,89 @@ __global__ __launch_bounds__(256) void k_mlp_images(AdamParams A) {
 
 // ------------------------------------------------------------ inference
 
-// One sample per lane, evaluated as four 16-sample tiles (the find's
-// inference code, so that this entry point tests it).
-__global__ __launch_bounds__(256) void k_mlp_infer(MlpWeights w, int64_t n, const float *x,
-                                                   float *y) {
-  __shared__ __attribute__((aligned(16))) __bf16 sX[4][64 * kLdX];
+// Forward pass of the wave's 64 samples on 32 x 32 tiles (the training
+// layout): X is the sample-major input tile [64][kLdX] (k 0..7 inputs,
+// 8..15 zero), H a separate [64][kLdH] scratch tile (not overlaying X).
+// out[j] receives output j of the lane's own sample.
+__device__ __forceinline__ void mlp_forward64(const MlpWeights &w, const __bf16 *X, __bf16 *H,
+                                              float *out) {
+  const int lane = threadIdx.x & 63;
+  f32x16 y[1][2];
+  {
+    f32x16 acc[2][2];
+    gemm_w_act<2, 1>(w.W1p, kLdW1, X, kLdX, w.b1, acc);
+    store_act<2, true>(acc, H, kLdH);
+  }
+  wave_sync();
+  {
+    f32x16 acc[2][2];
+    gemm_w_act<2, 4>(w.W2p, kLdW2, H, kLdH, w.b2, acc);
+    wave_sync();  // every lane has read h1 before h2 overwrites it
+    store_act<2, true>(acc, H, kLdH);
+  }
+  wave_sync();
+  gemm_w_act<1, 4>(w.W3p, kLdW3, H, kLdH, w.b3, y);
+  // output j of sample s: column s % 32 of tile s / 32, row j (rows 0..3 in
+  // the lower half of the lanes, 4..6 in the upper)
+#pragma unroll
+  for (int j = 0; j < kNO; ++j) {
+    const int src = (lane & 31) + (j < 4 ? 0 : 32);
+    const float v0 = __shfl(y[0][0][j & 3], src);
+    const float v1 = __shfl(y[0][1][j & 3], src);
+    out[j] = lane >= 32 ? v1 : v0;
+  }
+}
+
+
+// Inference of n samples.  Calls of at most kInferNarrow samples run 16
+// samples per wavefront, four wavefronts per block, on the find's own
+// inference code (mlp_forward16): less padding for small calls, and the
+// entry point's tests check that code.  Larger calls run 64 samples per
+// wavefront on the training layout (mlp_forward64), which loads each weight
+// operand once per 64 samples.  The two accumulate in different orders, so
+// their outputs may differ in the last bits.
+constexpr int64_t kInferNarrow = 16384;
+
+__global__ __launch_bounds__(256) void k_mlp_infer16(MlpWeights w, int64_t n, const float *x,
+                                                     float *y) {
   __shared__ __attribute__((aligned(16))) __bf16 sH[4][16 * kLdH];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * 16;  // the wave's first sample
+  __bf16 *H = sH[wv];
+  __bf16 *X = H;  // the input tile overlays the activation tile
+  {
+    // 16 samples x 8 inputs, two consecutive inputs per lane
+    const int r = lane >> 2, k = 2 * (lane & 3);
+    const int64_t s = s0 + r;
+    const float a = s < n ? x[s * 8 + k] : 0.f;
+    const float b = s < n ? x[s * 8 + k + 1] : 0.f;
+    X[r * kLdX + k] = (__bf16)a;
+    X[r * kLdX + k + 1] = (__bf16)b;
+  }
+  wave_sync();
+  f32x4 yt;
+  mlp_forward16(w, X, H, yt);
+  // lane (h, r) holds outputs 4h .. 4h + 3 of sample r
+  const int r = lane & 15, h = lane >> 4;
+  const int64_t s = s0 + r;
+  if (h < 2 && s < n)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * h + i < kNO) y[s * 7 + 4 * h + i] = yt[i];
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer64(MlpWeights w, int64_t n, const float *x,
+                                                     float *y) {
+  __shared__ __attribute__((aligned(16))) __bf16 sX[4][64 * kLdX];
+  __shared__ __attribute__((aligned(16))) __bf16 sH[4][64 * kLdH];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool valid = s < n;
-  for (int k = 0; k < 8; ++k) sX[wv][lane * kLdX + k] = (__bf16)(valid ? x[s * 8 + k] : 0.f);
+  for (int k = 0; k < 16; ++k)
+    sX[wv][lane * kLdX + k] = (__bf16)((valid && k < 8) ? x[s * 8 + k] : 0.f);
   wave_sync();
   float out[kNO];
-  for (int g = 0; g < 4; ++g) {
-    f32x4 yt;
-    mlp_forward16(w, sX[wv] + 16 * g * kLdX, sH[wv], yt);
-#pragma unroll
-    for (int j = 0; j < kNO; ++j) {
-      const float v = mlp_output16(yt, lane, j);
-      if ((lane >> 4) == g) out[j] = v;
-    }
-    wave_sync();  // the tile's last reads of H precede the next tile's stores
-  }
+  mlp_forward64(w, sX[wv], sH[wv], out);
   if (valid)
     for (int j = 0; j < kNO; ++j) y[s * 7 + j] = out[j];
 }
@@ -482,7 +543,12 @@ void launch_mlp_images(hipStream_t s, const MlpBuffers &B) {
 
 void launch_mlp_infer(hipStream_t s, const MlpWeights &w, int64_t n, const float *x, float *y) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n, x, y);
+  if (n <= kInferNarrow)
+    hipLaunchKernelGGL(k_mlp_infer16, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, w, n, x,
+                       y);
+  else
+    hipLaunchKernelGGL(k_mlp_infer64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n,
+                       x, y);
 }
 
 }  // namespace mkf

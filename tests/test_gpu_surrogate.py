@@ -78,13 +78,16 @@ def trained(mkf, geo_ctx):
     return rep, ctx.surrogate_get()
 
 
-def test_infer_matches_oracle(mkf, geo_ctx):
+@pytest.mark.parametrize("n", [1000, 20000])
+def test_infer_matches_oracle(mkf, geo_ctx, n):
+    """Both inference layouts (16-sample tiles, the find's own code, for
+    calls of up to 16,384 samples; 64-sample tiles above), each on a count
+    that is not a multiple of its tile."""
     _, ctx = geo_ctx
     rng = np.random.default_rng(1)
     p = glorot(rng)
     ctx.surrogate_set(p)
     assert np.array_equal(ctx.surrogate_get(), p)
-    n = 1000  # not a multiple of the 64-sample tile
     x, _, _ = samples(mkf, ctx, n, 3)
     y = torch.full((n, NO), np.nan, device="cuda")
     ctx.surrogate_infer(x, y)
