@@ -529,7 +529,9 @@ def measure_field(mkf, stream, T, n_events, gen_workers, repeats=5):
             c.close()
             f_ms = float(np.median(ms))
             res = {"find_ms": f_ms, "main_ms": float(np.median(main)), "n_steps": st["n_steps"],
-                   "throughput": st["n_steps"] / (f_ms * 1e-3), "unit": UNIT, "tuning": tun}
+                   "throughput": st["n_steps"] / (f_ms * 1e-3), "unit": UNIT, "tuning": tun,
+                   "rk_steps": st["n_rk_steps"], "newton_iterations": st["n_newton"],
+                   "near_cut_decisions": st["n_near_cut"]}
             if label == "surrogate":
                 kept, rej = st["sur_kept"], st["sur_rejected"]
                 res["hints_kept"] = kept
