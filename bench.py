@@ -704,8 +704,8 @@ def main():
             achieved = FLOPS_PER_STEP * per_launch_steps / (per_launch_ms * 1e-3) / 1e12
             roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    # the issue limit without packed FP32, which this build does
-                    # not generate: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+                    # the issue limit without packed FP32, which the library is
+                    # compiled without: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
                     "peak_unpacked": FP32_VECTOR_PEAK_TFLOPS / 2,
                     "frac_unpacked": achieved / (FP32_VECTOR_PEAK_TFLOPS / 2)}
         roof["frac"] = roof["achieved"] / roof["peak"]
