@@ -58,6 +58,15 @@ enum { MKF_MEM_HOST = 0, MKF_MEM_DEVICE = 1 };
 #define MKF_F_GRAPH 2u    /* replay the find as a captured HIP graph */
 #define MKF_F_SURROGATE 4u /* with MKF_F_BATCHED: barrel propagations start from the
                               learned surrogate's path length (see mkf_surrogate_*) */
+#define MKF_F_CHECKED 8u  /* after each find (outside its timed region), every result
+                             record is checked on the device: hits of the seed's event
+                             on the plan's layers, misses, skips, then none once the
+                             candidate stopped; hit and miss counts that match the
+                             list; finite parameters and chi2, positive variances
+                             (the position's, pinned along the last surface's normal,
+                             down to -1e-5 of their sum).
+                             Failures are counted in mkf_stats.n_check_failed and make
+                             mkf_find return MKF_E_NUMERIC (the records stay readable). */
 
 /* History codes in mkf_track.hit. */
 #define MKF_HIT_MISS (-1) /* layer crossed, no hit taken */
@@ -137,6 +146,7 @@ typedef struct {
    * Newton iterations. */
   int64_t n_rk_steps;
   int64_t n_newton;
+  int64_t n_check_failed;  /* MKF_F_CHECKED: records failing the checks (else 0) */
 } mkf_stats;
 
 /* Cuts of the combinatorial triplet seeding (mkf_make_seeds). */

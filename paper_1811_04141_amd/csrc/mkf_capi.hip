@@ -357,6 +357,8 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   for (int i = 0; i < 6; ++i)
     if (!(cfg->init_var[i] > 0.f) || !finite_f(cfg->init_var[i]))
       return fail(nullptr, MKF_E_ARG, "init_var must be finite and > 0");
+  if (cfg->flags & ~(MKF_F_BATCHED | MKF_F_GRAPH | MKF_F_SURROGATE | MKF_F_CHECKED))
+    return fail(nullptr, MKF_E_ARG, "unknown flag bits 0x%x", (unsigned)cfg->flags);
   mkf_ctx *c = new (std::nothrow) mkf_ctx();
   if (!c) return fail(nullptr, MKF_E_CAPACITY, "out of host memory");
   c->cfg = *cfg;
@@ -925,6 +927,11 @@ mkf_status mkf_find(mkf_ctx *c) {
   }
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipEventRecord(c->ev_b, c->stream));
+  // (after the timed region: the checked find's record invariants)
+  if (c->cfg.flags & MKF_F_CHECKED) {
+    launch_check_results(c->stream, P);
+    HIP_TRY(c, hipGetLastError());
+  }
   HIP_TRY(c, hipEventSynchronize(c->ev_b));
   float ms = 0.f, mms = -1.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
@@ -941,11 +948,15 @@ mkf_status mkf_find(mkf_ctx *c) {
   c->stats.n_near_cut = tot[kCntNearCut];
   c->stats.n_rk_steps = tot[kCntRk];
   c->stats.n_newton = tot[kCntNewton];
+  c->stats.n_check_failed = tot[kCntCheckFailed];
   c->stats.find_ms = ms;
   c->stats.main_ms = mms;
   c->stats.n_steps = (int64_t)steps;
   c->stats.n_launches = launches;
   c->stage = kFound;
+  if (c->stats.n_check_failed > 0)
+    return fail(c, MKF_E_NUMERIC, "checked find: %lld result records violate the find's invariants",
+                (long long)c->stats.n_check_failed);
   return MKF_OK;
 }
 

@@ -2118,6 +2118,67 @@ __global__ void k_fill_i32(int *p, int64_t n, int v) {
   if (i < n) p[i] = v;
 }
 
+// The checked find's invariants of one seed's result record: a seed whose
+// fit failed has no hits; otherwise each plan step holds a hit of the
+// seed's event on that step's layer, a miss, a skip, or (once the candidate
+// stopped, and from then on) none; the hit count is the three seed hits
+// plus the hits taken, the miss count the misses; chi2 and the parameters
+// are finite; the variances of q/pT, phi and theta are positive, those of
+// the position at least -1e-5 of their (positive) sum.
+__global__ __launch_bounds__(256) void k_check_results(FindParams P) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int bad = 0;
+  if (pos < P.n_seeds) {
+    const float *rec = P.out + (size_t)pos * kOutWords;
+    const int *hit = reinterpret_cast<const int *>(rec + kOutHit);
+    const int meta = __float_as_int(rec[kOutMeta]);
+    const int nh = meta & 0xFF, nm = (meta >> 8) & 0xFF;
+    const int info = P.pinfo[pos];
+    const int plen = info & 0xFF;
+    if (!((info >> 8) & 1)) {
+      bad = nh != 0 || nm != 0;
+    } else {
+      const int ev = P.pevent[pos];
+      const int64_t base = P.ev_off[ev], nev = P.ev_off[ev + 1] - base;
+      int found = 0, miss = 0;
+      bool stopped = false;
+      for (int s = 0; s < plen; ++s) {
+        const int h = hit[s];
+        const int lid = P.pplan[(size_t)pos * kMaxPlan + s];
+        if (h >= 0) {
+          if (stopped || h >= nev) bad = 1;
+          else if (P.hlayer[base + h] != lid) bad = 1;
+          ++found;
+        } else if (h == MKF_HIT_MISS) {
+          bad |= stopped;
+          ++miss;
+        } else if (h == MKF_HIT_SKIP) {
+          bad |= stopped;
+        } else if (h == MKF_HIT_NONE) {
+          stopped = true;
+        } else {
+          bad = 1;
+        }
+      }
+      bad |= nh != 3 + found || nm != miss;
+      const float c2 = rec[kOutChi2];
+      bad |= !(c2 >= 0.f) || !isfinite(c2);
+      // (the state lies on its last surface: the variance along the
+      // surface's normal is zero up to rounding, so a position variance
+      // may be a rounding below zero; their sum must be positive)
+      const float tp = rec[kOutCov + tri(0, 0)] + rec[kOutCov + tri(1, 1)] +
+                       rec[kOutCov + tri(2, 2)];
+      bad |= !(tp > 0.f) || !isfinite(tp);
+      for (int i = 0; i < 6; ++i) {
+        bad |= !isfinite(rec[kOutPar + i]);
+        const float d = rec[kOutCov + tri(i, i)];
+        bad |= !isfinite(d) || (i < 3 ? d < -1e-5f * tp : !(d > 0.f));
+      }
+    }
+  }
+  add_counter(P, kCntCheckFailed, bad);
+}
+
 // ------------------------------------------------------------- launchers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -2227,6 +2288,10 @@ void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks,
 void launch_finalize(hipStream_t s, const FindParams &P) {
   if (P.n_seeds == 0) return;
   hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P);
+}
+void launch_check_results(hipStream_t s, const FindParams &P) {
+  if (P.n_seeds == 0) return;
+  hipLaunchKernelGGL(k_check_results, dim3(blocks_for(P.n_seeds, 256)), dim3(256), 0, s, P);
 }
 
 void launch_permute_seeds(hipStream_t s, const FindParams &P, float *pstate, int *pinfo,

@@ -91,14 +91,18 @@ struct FindParams {
   MlpWeights mlp;
   // find counters [kCounters][kCounterSlots]: surrogate hints kept, hints
   // rejected, near-cut chi2 decisions, Runge-Kutta steps and Newton
-  // iterations of field crossings; each counter is spread over
+  // iterations of field crossings, failed result checks; each counter is
+  // spread over
   // kCounterSlots words (by block index) so that the waves' atomic adds do
   // not queue on one address; the host sums the slots
   unsigned long long *counters;
 };
-constexpr int kCounters = 5;
+constexpr int kCounters = 6;
 constexpr int kCounterSlots = 64;
-enum { kCntSurKept = 0, kCntSurRejected = 1, kCntNearCut = 2, kCntRk = 3, kCntNewton = 4 };
+enum {
+  kCntSurKept = 0, kCntSurRejected = 1, kCntNearCut = 2, kCntRk = 3, kCntNewton = 4,
+  kCntCheckFailed = 5  // result records that fail the checked find's invariants
+};
 
 // 32-bit words of one wavefront's LDS records in the persistent form:
 // back-pointers [max_plan][seeds][G] and retired candidates [seeds][kFinWords]
@@ -156,6 +160,9 @@ void launch_find_step(hipStream_t s, const FindParams &P, int step, int64_t n_ac
 void launch_find_persistent(hipStream_t s, const FindParams &P, int grid_blocks, int waves,
                             bool surrogate, int group);
 void launch_finalize(hipStream_t s, const FindParams &P);
+// MKF_F_CHECKED: every result record against the find's invariants; the
+// failures are added to counter kCntCheckFailed
+void launch_check_results(hipStream_t s, const FindParams &P);
 void launch_propagate(hipStream_t s, const FindParams &P, int64_t n, const float *par,
                       const float *cov, const int *layer, float *out_par, float *out_cov,
                       float *out_l, int *out_status);

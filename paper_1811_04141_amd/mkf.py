@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libmkf.so")
 MKF_OK, MKF_E_ARG, MKF_E_ORDER, MKF_E_CAPACITY, MKF_E_HIP, MKF_E_GEOMETRY, MKF_E_NUMERIC = (
     0, -1, -2, -3, -4, -5, -6)
 MEM_HOST, MEM_DEVICE = 0, 1
-F_BATCHED, F_GRAPH, F_SURROGATE = 1, 2, 4
+F_BATCHED, F_GRAPH, F_SURROGATE, F_CHECKED = 1, 2, 4, 8
 MLP_NPARAM = 5191  # W1[64][8], b1[64], W2[64][64], b2[64], W3[7][64], b3[7]
 NOALLOC_MAX_SAMPLES = 16384  # MKF_NOALLOC_MAX_SAMPLES
 MAX_LAYERS = MAX_PLAN = 32
@@ -121,7 +121,8 @@ class Stats(C.Structure):
                 ("index_ms", C.c_float), ("seed_ms", C.c_float), ("main_ms", C.c_float),
                 ("main_launches", C.c_int32), ("sur_kept", C.c_int64),
                 ("sur_rejected", C.c_int64), ("n_near_cut", C.c_int64),
-                ("n_rk_steps", C.c_int64), ("n_newton", C.c_int64)]
+                ("n_rk_steps", C.c_int64), ("n_newton", C.c_int64),
+                ("n_check_failed", C.c_int64)]
 
 
 class TrainCfg(C.Structure):

@@ -60,6 +60,9 @@ def test_host_side_argument_errors():
     bad = mkf.make_config(FindConfig(init_var=(1, 1, 1, 0, 1, 1)))
     assert lib.mkf_create(C.byref(bad), None, C.byref(h)) == mkf.MKF_E_ARG
     assert lib.mkf_create(C.byref(mkf.make_config(FindConfig())), None, None) == mkf.MKF_E_ARG
+    bad = mkf.make_config(FindConfig(), flags=16)  # no such flag
+    assert lib.mkf_create(C.byref(bad), None, C.byref(h)) == mkf.MKF_E_ARG
+    assert b"flag" in lib.mkf_last_error(None)
     lib.mkf_destroy(None)  # NULL is accepted
     assert lib.mkf_find(None) == mkf.MKF_E_ARG
     assert lib.mkf_load_geometry(None, None, 0) == mkf.MKF_E_ARG
