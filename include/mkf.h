@@ -529,6 +529,16 @@ mkf_status mkf_surrogate_get_state(mkf_ctx *ctx, float *params, float *m, float 
 mkf_status mkf_surrogate_set_state(mkf_ctx *ctx, const float *params, const float *m,
                                    const float *v, int32_t step);
 
+/* The same checkpoint as one byte blob, for files: "MKFS", uint32 version
+ * (1), uint32 parameter count (5,191), int32 Adam step, then the
+ * parameters, first and second moments (FP32), 62,308 bytes in all.  save
+ * sets *n to the size and writes the blob if cap is large enough
+ * (MKF_E_CAPACITY otherwise, with *n set, so buf = NULL asks for the size);
+ * load takes a blob of exactly that size and header (MKF_E_ARG otherwise)
+ * and restores it as mkf_surrogate_set_state does. */
+mkf_status mkf_surrogate_save(mkf_ctx *ctx, void *buf, size_t cap, size_t *n);
+mkf_status mkf_surrogate_load(mkf_ctx *ctx, const void *buf, size_t n);
+
 /* Loss and its gradient for the current weights on n samples (n a positive
  * multiple of 64; x [n][8], t [n][7] device; loss_w host [7]); grad host
  * [5,191], loss host.  Blocks until done. */

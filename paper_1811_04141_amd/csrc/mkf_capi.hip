@@ -1550,6 +1550,54 @@ mkf_status mkf_surrogate_set_state(mkf_ctx *c, const float *params, const float 
   return MKF_OK;
 }
 
+// Blob layout: the 4 bytes "MKFS", then uint32 version, uint32 parameter
+// count, int32 Adam step, then the parameters, the first and the second
+// moments (FP32, little-endian as in memory).
+namespace {
+constexpr uint32_t kBlobVersion = 1;
+constexpr size_t kBlobHeader = 16;
+constexpr size_t kBlobBytes = kBlobHeader + 3 * sizeof(float) * kNParam;
+}  // namespace
+
+mkf_status mkf_surrogate_save(mkf_ctx *c, void *buf, size_t cap, size_t *n) {
+  if (!c) return MKF_E_ARG;
+  if (!n) return fail(c, MKF_E_ARG, "n is NULL");
+  *n = kBlobBytes;
+  if (!buf || cap < kBlobBytes)
+    return fail(c, MKF_E_CAPACITY, "the blob takes %zu bytes", kBlobBytes);
+  std::vector<float> st(3 * (size_t)kNParam);
+  int32_t step = 0;
+  const mkf_status r = mkf_surrogate_get_state(c, st.data(), st.data() + kNParam,
+                                               st.data() + 2 * kNParam, &step);
+  if (r != MKF_OK) return r;
+  unsigned char *b = static_cast<unsigned char *>(buf);
+  const uint32_t ver = kBlobVersion, np = kNParam;
+  memcpy(b, "MKFS", 4);
+  memcpy(b + 4, &ver, 4);
+  memcpy(b + 8, &np, 4);
+  memcpy(b + 12, &step, 4);
+  memcpy(b + kBlobHeader, st.data(), 3 * sizeof(float) * kNParam);
+  return MKF_OK;
+}
+
+mkf_status mkf_surrogate_load(mkf_ctx *c, const void *buf, size_t n) {
+  if (!c) return MKF_E_ARG;
+  if (!buf) return fail(c, MKF_E_ARG, "buf is NULL");
+  if (n != kBlobBytes) return fail(c, MKF_E_ARG, "a blob has %zu bytes, not %zu", kBlobBytes, n);
+  const unsigned char *b = static_cast<const unsigned char *>(buf);
+  uint32_t ver = 0, np = 0;
+  int32_t step = 0;
+  memcpy(&ver, b + 4, 4);
+  memcpy(&np, b + 8, 4);
+  memcpy(&step, b + 12, 4);
+  if (memcmp(b, "MKFS", 4) != 0 || ver != kBlobVersion || np != (uint32_t)kNParam)
+    return fail(c, MKF_E_ARG, "not a surrogate blob of this version and size");
+  std::vector<float> st(3 * (size_t)kNParam);
+  memcpy(st.data(), b + kBlobHeader, 3 * sizeof(float) * kNParam);
+  return mkf_surrogate_set_state(c, st.data(), st.data() + kNParam, st.data() + 2 * kNParam,
+                                 step);
+}
+
 mkf_status mkf_surrogate_grad(mkf_ctx *c, int32_t n, const float *x, const float *t,
                               const float *loss_w, float *grad, float *loss) {
   if (!c) return MKF_E_ARG;

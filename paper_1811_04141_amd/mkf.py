@@ -32,7 +32,7 @@ EXPORTS = ("mkf_create", "mkf_destroy", "mkf_last_error", "mkf_load_geometry",
            "mkf_get_stats",
            "mkf_set_tuning",
            "mkf_get_tuning", "mkf_autotune", "mkf_surrogate_train", "mkf_surrogate_get", "mkf_surrogate_set",
-           "mkf_surrogate_get_state", "mkf_surrogate_set_state", "mkf_surrogate_grad",
+           "mkf_surrogate_get_state", "mkf_surrogate_set_state", "mkf_surrogate_save", "mkf_surrogate_load", "mkf_surrogate_grad",
            "mkf_surrogate_grad_noalloc",
            "mkf_surrogate_infer", "mkf_surrogate_samples")
 
@@ -176,6 +176,8 @@ def _load():
         "mkf_surrogate_set": ([P, P], I32),
         "mkf_surrogate_get_state": ([P, P, P, P, C.POINTER(I32)], I32),
         "mkf_surrogate_set_state": ([P, P, P, P, I32], I32),
+        "mkf_surrogate_save": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], I32),
+        "mkf_surrogate_load": ([P, P, C.c_size_t], I32),
         "mkf_surrogate_grad": ([P, I32, P, P, P, P, P], I32),
         "mkf_surrogate_grad_noalloc": ([P, I32, P, P, P, P, P], I32),
         "mkf_surrogate_infer": ([P, I64, P, P], I32),
@@ -413,6 +415,20 @@ class Context:
         params = np.ascontiguousarray(params, np.float32)
         assert params.shape == (MLP_NPARAM,)
         self._check(lib.mkf_surrogate_set(self.h, _ptr(params)))
+
+    def surrogate_save(self):
+        """The training checkpoint as a byte blob (mkf_surrogate_save)."""
+        n = C.c_size_t(0)
+        st = lib.mkf_surrogate_save(self.h, None, 0, C.byref(n))
+        assert st == MKF_E_CAPACITY, st
+        buf = (C.c_ubyte * n.value)()
+        self._check(lib.mkf_surrogate_save(self.h, buf, n.value, C.byref(n)))
+        return bytes(buf)
+
+    def surrogate_load(self, blob):
+        blob = bytes(blob)
+        buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+        self._check(lib.mkf_surrogate_load(self.h, buf, len(blob)))
 
     def surrogate_get_state(self):
         """(params, m, v, step): the weights and Adam's state."""

@@ -327,3 +327,43 @@ def test_training_resumes_bitwise_from_a_checkpoint(mkf, geo_ctx):
     for a, b in zip(full[:3], resumed[:3]):
         assert np.array_equal(a, b)
     assert full[3] == resumed[3] == 64
+
+
+def test_checkpoint_blob_round_trips_and_resumes(mkf, geo_ctx):
+    """mkf_surrogate_save/_load: the blob of a 40-step checkpoint restored
+    into another context resumes the schedule to the uninterrupted run's
+    weights and moments bit for bit; a short buffer reports the size with
+    MKF_E_CAPACITY, and a blob of the wrong size or header is refused."""
+    import ctypes as C
+    w, ctx = geo_ctx
+    cfg = dict(n_samples=16384, epochs=2, batch=512, lr=3e-3, seed=37,
+               loss_w=(1, 0.01, 0.01, 0.01, 0.01, 0.01, 0.01))
+    p0 = glorot(np.random.default_rng(29))
+    ctx.surrogate_set(p0)
+    ctx.surrogate_train(**cfg)
+    full = ctx.surrogate_get_state()
+    ctx.surrogate_set(p0)
+    ctx.surrogate_train(**cfg, n_steps=40)
+    blob = ctx.surrogate_save()
+    assert len(blob) == 16 + 3 * 4 * mkf.MLP_NPARAM and blob[:4] == b"MKFS"
+    n = C.c_size_t(0)
+    small = (C.c_ubyte * 100)()
+    assert mkf.lib.mkf_surrogate_save(ctx.h, small, 100, C.byref(n)) == mkf.MKF_E_CAPACITY
+    assert n.value == len(blob)
+    ctx2 = mkf.Context(w.find)
+    try:
+        ctx2.load_geometry(w.layers)
+        for bad in (blob[:-4], b"MKFX" + blob[4:], blob[:4] + b"\x02" + blob[5:]):
+            with pytest.raises(mkf.MkfError) as e:
+                ctx2.surrogate_load(bad)
+            assert e.value.status == mkf.MKF_E_ARG
+        ctx2.surrogate_load(blob)
+        ck = ctx2.surrogate_get_state()
+        assert ck[3] == 40
+        ctx2.surrogate_train(**cfg, first_step=40)
+        resumed = ctx2.surrogate_get_state()
+    finally:
+        ctx2.close()
+    for a, b in zip(full[:3], resumed[:3]):
+        assert np.array_equal(a, b)
+    assert full[3] == resumed[3]
