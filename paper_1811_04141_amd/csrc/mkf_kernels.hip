@@ -516,19 +516,28 @@ __device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand
   cd.nm = 0;
 }
 
-__device__ __forceinline__ void load_cand(const FindParams &P, size_t idx, Cand &cd) {
+// A candidate slot's state and its meta word (hits, misses, active) as
+// stored by store_cand.  The state words are requested together with the
+// meta word, not after it, so that their latencies overlap (an empty
+// slot's words are read and not used); the meta word is returned raw and
+// unpacked by set_meta where it is first needed.
+__device__ __forceinline__ int load_cand_raw(const FindParams &P, size_t idx, Cand &cd) {
   const size_t NS = (size_t)P.n_seeds * P.slots;
   const int meta = __float_as_int(P.cand[28 * NS + idx]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) cd.p[i] = P.cand[i * NS + idx];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) cd.c[i] = P.cand[(6 + i) * NS + idx];
+  cd.chi2 = P.cand[27 * NS + idx];
+  return meta;
+}
+__device__ __forceinline__ void set_meta(Cand &cd, int meta) {
   cd.active = (meta >> 16) & 1;
   cd.nh = meta & 0xFF;
   cd.nm = (meta >> 8) & 0xFF;
-  if (cd.active) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) cd.p[i] = P.cand[i * NS + idx];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) cd.c[i] = P.cand[(6 + i) * NS + idx];
-    cd.chi2 = P.cand[27 * NS + idx];
-  }
+}
+__device__ __forceinline__ void load_cand(const FindParams &P, size_t idx, Cand &cd) {
+  set_meta(cd, load_cand_raw(P, idx, cd));
 }
 
 __device__ __forceinline__ void store_cand(const FindParams &P, size_t idx, const Cand &cd) {
@@ -612,8 +621,6 @@ __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
 template <bool kMat, int G>
 __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64_t n_active) {
   __shared__ DevLayer sl[kMaxLayers];
-  stage_layers(P, sl);
-  __syncthreads();
   // XCD x (blocks x, x + 8, ...) takes the x-th contiguous share of the
   // positions, so that an XCD's L2 serves a few events' hits
   // (the grid is a multiple of kQueues blocks, so this is a permutation)
@@ -624,17 +631,31 @@ __global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64
   const int64_t pos = (b * 4 + (threadIdx.x >> 6)) * Grp<G>::kSeeds + grp;
   const int slot = Grp<G>::slot(lane);
   // a seed group takes part while the step is in its plan (the whole group
-  // leaves together); the wave stays to add its counters
+  // leaves together); the wave stays to add its counters.  The positions
+  // below n_active are the seeds whose plans are longer than step (the
+  // host orders the seeds longest plan first), so every word the step
+  // starts from is requested at once, without waiting for the plan length,
+  // and before the block stages the layer table.
   const bool in_range = grp < Grp<G>::kSeeds && pos < n_active;
-  const bool live = in_range && step < (P.pinfo[pos] & 0xFF);
-  if (__ballot(live) == 0ull) return;
+  // (the plan length is the low byte of the seed's info word, read as a
+  // byte so that nothing waits on it before the barrier)
+  int meta = 0, plen = 0, lid = 0, ev = 0;
+  u64 fin_key = kKeyMax;
+  Cand cd;
+  if (in_range) {
+    meta = load_cand_raw(P, (size_t)pos * G + slot, cd);
+    fin_key = P.fin_key[pos];
+    plen = reinterpret_cast<const unsigned char *>(P.pinfo)[4 * pos];
+    lid = P.pplan[(size_t)pos * kMaxPlan + step];
+    ev = P.pevent[pos];
+  }
+  stage_layers(P, sl);
+  __syncthreads();
+  if (__ballot(in_range) == 0ull) return;
+  set_meta(cd, meta);
+  const bool live = in_range && step < plen;
   int cnt[3] = {0, 0, 0};
   if (live) {
-    const int lid = P.pplan[(size_t)pos * kMaxPlan + step];
-    const int ev = P.pevent[pos];
-    Cand cd;
-    load_cand(P, (size_t)pos * G + slot, cd);
-    u64 fin_key = P.fin_key[pos];
     const u64 fk0 = fin_key;
     group_step<G, kMat>(P, sl, cd, lane, slot, GlobalRec{&P, pos}, ev, P.ev_off[ev], step, lid,
                         fin_key, cnt);
