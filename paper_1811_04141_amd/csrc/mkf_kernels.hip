@@ -495,8 +495,10 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   rec.put_bp(step, slot, bpv);
 }
 
-__device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand &cd) {
-  // one seed's 27 words are contiguous: seven 16-byte loads
+// A seed's state; its record's last word, the index of its event's first
+// hit, is returned.
+__device__ __forceinline__ int load_seed(const FindParams &P, int64_t pos, Cand &cd) {
+  // one seed's 28 words are contiguous: seven 16-byte loads
   const float4 *src = reinterpret_cast<const float4 *>(P.pstate + (size_t)pos * kSeedWords);
   float w[28];
 #pragma unroll
@@ -514,6 +516,7 @@ __device__ __forceinline__ void load_seed(const FindParams &P, int64_t pos, Cand
   cd.chi2 = 0.f;
   cd.nh = 3;
   cd.nm = 0;
+  return __float_as_int(w[27]);
 }
 
 // A candidate slot's state and its meta word (hits, misses, active) as
@@ -791,44 +794,71 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
   int my_steps = 0, my_acc = 0, my_fb = 0;
   int cnt[3] = {0, 0, 0};  // near-cut decisions, field Runge-Kutta steps, Newton iterations
   int q = blockIdx.x % kQueues;  // this block's XCD
+  int64_t q_lo = P.q_off[q], q_hi = P.q_off[q + 1];  // queue q's positions
   int tried = 0;
   // the next tile of queue q is claimed one tile ahead, so that the atomic's
   // latency overlaps the current tile's work (lane 0 holds it; -1: none)
   int ahead = -1;
   for (;;) {
-    int tile = 0;
-    if (lane == 0) tile = ahead >= 0 ? ahead : atomicAdd(&P.tile_counter[q], 1);
-    tile = __shfl(tile, 0);
+    // (ahead is wave-uniform: a tile claimed ahead needs no wait here, so
+    // the previous tile's result stores drain while this one starts)
+    int tile;
+    if (ahead >= 0) {
+      tile = ahead;
+    } else {
+      int t = 0;
+      if (lane == 0) t = atomicAdd(&P.tile_counter[q], 1);
+      tile = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+    }
     ahead = -1;
-    const int64_t start = P.q_off[q] + (int64_t)tile * Grp<G>::kSeeds;
-    const int64_t end = P.q_off[q + 1];
+    const int64_t start = q_lo + (int64_t)tile * Grp<G>::kSeeds;
+    const int64_t end = q_hi;
     if (start >= end) {
       // queue exhausted: help the next one; stop after all were tried
       if (++tried >= kQueues) break;
       q = (q + 1) % kQueues;
+      q_lo = P.q_off[q];
+      q_hi = P.q_off[q + 1];
       continue;
     }
     if (lane == 0 && start + Grp<G>::kSeeds < end) ahead = atomicAdd(&P.tile_counter[q], 1);
     const int64_t pos = start + grp;
     const bool valid = grp < Grp<G>::kSeeds && pos < end;
-    const int info = valid ? P.pinfo[pos] : 0;
-    const int plen = info & 0xFF;
-    const int ev = valid ? P.pevent[pos] : 0;
-    const int64_t ev_base = valid ? P.ev_off[ev] : 0;
+    // Every lane reads the words of an existing seed (lanes past the tile
+    // read its last one and use none of it), without branches, so that the
+    // seed's info word, event, state and first plan words are all requested
+    // before the first wait; a seed without a fit has its state read and
+    // not used.
+    const int64_t pc = valid ? pos : end - 1;
+    const int info_w = P.pinfo[pc];
+    const int ev_w = P.pevent[pc];
     Cand cd;
+    const int ev_base_w = load_seed(P, pc, cd);
+    // the plan is read four layer ids at a time, one word ahead
+    const int *plan_w = reinterpret_cast<const int *>(P.pplan) + (size_t)pc * (kMaxPlan / 4);
+    int w_cur = plan_w[0];
+    int w_next = plan_w[1];
+    const int info = valid ? info_w : 0;
+    const int ev = valid ? ev_w : 0;
+    const int64_t ev_base = valid ? (int64_t)ev_base_w : 0;
+    const int plen = info & 0xFF;
     cd.active = valid && slot == 0 && ((info >> 8) & 1);
     cd.nh = 3;
     cd.nm = 0;
     cd.chi2 = 0.f;
-    if (cd.active) load_seed(P, pos, cd);
     u64 fin_key = kKeyMax;
-    int maxlen = plen;
+    // the tile's longest plan (at most kMaxPlan = 32 steps), by a binary
+    // search over ballots: no round trips through the LDS crossbar.  At
+    // least one step is taken (a step beyond every plan does nothing), so
+    // that the loads above are not deferred behind a test for an empty
+    // tile.
+    int maxlen = 1;
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, m));
-    // the plan is read four layer ids at a time, one word ahead
-    const int *plan_w = reinterpret_cast<const int *>(P.pplan) + (size_t)pos * (kMaxPlan / 4);
-    int w_cur = plen > 0 ? plan_w[0] : 0;
-    int w_next = plen > 4 ? plan_w[1] : 0;
+    for (int b = 32; b >= 1; b >>= 1)
+      if (__ballot(plen >= maxlen + b) != 0ull) maxlen += b;
+    // the tile claimed ahead is read now: its atomic was issued before this
+    // tile's loads, so it has returned with the info word
+    ahead = __builtin_amdgcn_readfirstlane(__shfl(ahead, 0));
     for (int step = 0; step < maxlen; ++step) {
       const bool in_plan = step < plen;
       if (step > 0 && (step & 3) == 0) {
@@ -941,7 +971,9 @@ __global__ __launch_bounds__(256) void k_permute_seeds(FindParams P, float *psta
   const size_t N = (size_t)P.n_seeds;
   const int seed = P.order[pos];
   for (int i = 0; i < 27; ++i) pstate[(size_t)pos * kSeedWords + i] = P.seed_state[i * N + seed];
-  pstate[(size_t)pos * kSeedWords + 27] = 0.f;
+  // the last word: the index of the event's first hit (below 2^31), read
+  // with the state so that the find need not look it up
+  pstate[(size_t)pos * kSeedWords + 27] = __int_as_float((int)P.ev_off[P.seed_event[seed]]);
   pinfo[pos] = P.plan_len[seed] | (P.seed_ok[seed] << 8);
   pevent[pos] = P.seed_event[seed];
   for (int s = 0; s < kMaxPlan; ++s)

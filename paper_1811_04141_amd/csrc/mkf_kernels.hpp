@@ -67,7 +67,7 @@ struct FindParams {
   const int8_t *plan;       // [n_seeds][kMaxPlan]
   const int *order;         // processing position -> seed id
   // the same, gathered once into processing order (read by the find)
-  const float *pstate;      // [n_seeds][kSeedWords]: 6 par, 21 cov, pad
+  const float *pstate;      // [n_seeds][kSeedWords]: 6 par, 21 cov, event's first hit (int bits)
   const int *pinfo;         // [n_seeds] plan_len | ok << 8
   const int *pevent;        // [n_seeds]
   const int8_t *pplan;      // [n_seeds][kMaxPlan]
