@@ -875,10 +875,13 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
         // applies that relative correction to its own straight-line path
         // and checks it with its own Newton step (falling back to the
         // closed form when the check fails).
+        // (the sines and cosines are taken for every candidate that steps,
+        // barrel or disk, and always handed to the propagation: a pointer
+        // chosen per lane would keep the array in scratch memory)
         const bool want = in_plan && cd.active && sl[lid].kind == 0;
         const bool lead = want && slot == 0;
         float xin[kNI];
-        if (want) {
+        if (in_plan && cd.active) {
           sincosf(cd.p[4], &trig[0], &trig[1]);
           sincosf(cd.p[5], &trig[2], &trig[3]);
         }
@@ -916,8 +919,7 @@ __device__ __forceinline__ void find_persistent(const FindParams &P) {
         my_steps += cd.active ? 1 : 0;
         int sur = 0;
         group_step<G, kMat>(P, sl, cd, lane, slot, rec, ev, ev_base, step, lid, fin_key, cnt,
-                            l_hint, &sur, mtab,
-                            kSurr && cd.active && sl[lid].kind == 0 ? trig : nullptr);
+                            l_hint, &sur, mtab, kSurr ? trig : nullptr);
         my_acc += sur == 1;
         my_fb += sur == 2;
       }
