@@ -113,6 +113,14 @@ __device__ __forceinline__ void insert_sorted(u64 (&lst)[N], u64 k) {
     k = lt ? a : k;
   }
 }
+// k into position n of a sorted list whose first n entries are all smaller
+// than k and whose others are empty (nothing when n >= N): the insertion of
+// a key that ranks after every key in the list, without comparisons
+template <int N>
+__device__ __forceinline__ void put_at(u64 (&lst)[N], int n, u64 k) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) lst[i] = i == n ? k : lst[i];
+}
 template <int N>
 __device__ __forceinline__ void pop_front(u64 (&lst)[N]) {
 #pragma unroll
@@ -391,14 +399,16 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
   int n_ext = 0;
   if (cd.active) {
     if (!ok) {
-      insert_sorted(lst, ext_key(cd.nh, cd.chi2, slot, kOrderNone));  // skip
+      lst[0] = ext_key(cd.nh, cd.chi2, slot, kOrderNone);  // skip (the list is empty)
       n_ext = 1;
     } else {
       Frame f;
       make_frame(pr.p, pr.c, L.kind, f);
       scan_window(P, L, ev, pr, f, cd.chi2, cd.nh, slot, lst, n_ext, cnt[0]);
       if (cd.nm < P.cfg.max_holes) {
-        insert_sorted(lst, ext_key(cd.nh, cd.chi2, slot, kOrderNone));  // miss
+        // a miss has one hit fewer than each of the n_ext hit extensions, so
+        // it ranks after all of them
+        put_at(lst, n_ext, ext_key(cd.nh, cd.chi2, slot, kOrderNone));
         ++n_ext;
       }
     }
