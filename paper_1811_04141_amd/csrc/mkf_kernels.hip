@@ -427,13 +427,16 @@ __device__ __forceinline__ void group_step(const FindParams &P, const DevLayer *
     }
   }
 
-  // the seed's best n_cand extensions, rank r goes to slot r
+  // the seed's best n_cand extensions, rank r goes to slot r (the last
+  // round's winner stays on its list, which is not read again)
   u64 mine = kKeyMax;
-  for (int r = 0; r < P.cfg.n_cand; ++r) {
+  const int n_cand = P.cfg.n_cand;
+  for (int r = 0; r < n_cand; ++r) {
     if (__ballot(lst[0] != kKeyMax) == 0ull) break;
     const u64 m = Grp<G>::min(lst[0], lane);
-    if (m != kKeyMax && lst[0] == m) pop_front(lst);
     if (slot == r) mine = m;
+    if (r + 1 == n_cand) break;
+    if (m != kKeyMax && lst[0] == m) pop_front(lst);
   }
 
   // the kept hit's record is requested first, so that its latency overlaps
