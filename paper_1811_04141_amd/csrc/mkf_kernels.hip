@@ -102,16 +102,24 @@ template <> struct Grp<6> {
   }
 };
 
-// sorted insertion into a register list (compile-time indices only)
+// Sorted insertion into a register list (compile-time indices only; keys
+// are distinct, empty entries hold kKeyMax).  All comparisons with k come
+// first; then entry i keeps its key if that is smaller than k, else takes k
+// (where entry i - 1 is smaller) or entry i - 1's key (shifted up).  One
+// compare per entry, none of them next to the selects that read it.
 template <int N>
 __device__ __forceinline__ void insert_sorted(u64 (&lst)[N], u64 k) {
+  // the comparisons read a copy of k that the compiler cannot see through
+  // (an empty statement, no instruction), so that it keeps one compare per
+  // entry for both selects instead of forming a minimum and a maximum
+  u64 kc = k;
+  asm("" : "+v"(kc));
+  bool below[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const u64 a = lst[i];
-    const bool lt = k < a;
-    lst[i] = lt ? k : a;
-    k = lt ? a : k;
-  }
+  for (int i = 0; i < N; ++i) below[i] = lst[i] < kc;
+#pragma unroll
+  for (int i = N - 1; i > 0; --i) lst[i] = below[i] ? lst[i] : (below[i - 1] ? k : lst[i - 1]);
+  lst[0] = below[0] ? lst[0] : k;
 }
 // k into position n of a sorted list whose first n entries are all smaller
 // than k and whose others are empty (nothing when n >= N): the insertion of
