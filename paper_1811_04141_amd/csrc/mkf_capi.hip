@@ -133,6 +133,9 @@ struct mkf_ctx {
   hipGraphExec_t graph_exec = nullptr;
   int graph_launches = 0;
   mkf_stats stats{};
+  // pinned host words the find's step count and counters are read back
+  // into: [0] steps, then kCounters x kCounterSlots
+  unsigned long long *h_cnt = nullptr;
   int n_cu = 0;
   int device = 0;  // the device current at mkf_create
   std::string arch;
@@ -161,6 +164,7 @@ struct mkf_ctx {
     if (ev_b) (void)hipEventDestroy(ev_b);
     if (ev_m0) (void)hipEventDestroy(ev_m0);
     if (ev_m1) (void)hipEventDestroy(ev_m1);
+    if (h_cnt) (void)hipHostFree(h_cnt);
   }
 };
 
@@ -370,6 +374,10 @@ mkf_status mkf_create(const mkf_config *cfg, void *stream, mkf_ctx **out) {
   if (e == hipSuccess) e = c->d_steps.ensure(sizeof(unsigned long long));
   if (e == hipSuccess) e = c->d_tiles.ensure(sizeof(int) * kQueues);
   if (e == hipSuccess) e = c->d_bad.ensure(sizeof(int));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&c->h_cnt),
+                      sizeof(unsigned long long) * (1 + kCounters * kCounterSlots),
+                      hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
     return fail(nullptr, MKF_E_HIP, "HIP setup failed: %s", hipGetErrorString(e));
@@ -932,14 +940,19 @@ mkf_status mkf_find(mkf_ctx *c) {
     launch_check_results(c->stream, P);
     HIP_TRY(c, hipGetLastError());
   }
-  HIP_TRY(c, hipEventSynchronize(c->ev_b));
+  // the step count and counters: two copies into pinned memory behind the
+  // find on its stream, then one wait, which also completes the events
+  unsigned long long *cnt = c->h_cnt + 1;
+  HIP_TRY(c, hipMemcpyAsync(c->h_cnt, c->d_steps.ptr, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(cnt, c->d_cnt.ptr,
+                            sizeof(unsigned long long) * kCounters * kCounterSlots,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   float ms = 0.f, mms = -1.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
   if (!graph) HIP_TRY(c, hipEventElapsedTime(&mms, c->ev_m0, c->ev_m1));
-  unsigned long long steps = 0, cnt[kCounters * kCounterSlots];
-  HIP_TRY(c, hipMemcpyAsync(&steps, c->d_steps.ptr, sizeof steps, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(cnt, c->d_cnt.ptr, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const unsigned long long steps = c->h_cnt[0];
   int64_t tot[kCounters] = {};
   for (int k = 0; k < kCounters; ++k)
     for (int j = 0; j < kCounterSlots; ++j) tot[k] += (int64_t)cnt[k * kCounterSlots + j];
