@@ -472,7 +472,7 @@ mkf_status build_index(mkf_ctx *c) {
   HIP_TRY(c, c->d_fill.ensure(sizeof(int) * (size_t)std::max<int64_t>(total_bins, 1)));
   HIP_TRY(c, c->d_bin_start.ensure(sizeof(int) * (size_t)(total_bins + 1)));
   HIP_TRY(c, c->d_scan_tmp.ensure(sizeof(int) * (size_t)(4 * (total_bins / 2048 + 4) + 64)));
-  HIP_TRY(c, c->d_sorted.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
+  HIP_TRY(c, c->d_sorted.ensure(sizeof(HitRec) * (size_t)(std::max<int64_t>(n_hits, 1) + kHitPad)));
   HIP_TRY(c, c->d_byorig.ensure(sizeof(HitRec) * (size_t)std::max<int64_t>(n_hits, 1)));
   HIP_TRY(c, hipEventRecord(c->ev_a, c->stream));
   launch_fill_i32(c->stream, c->d_counts.as<int>(), total_bins, 0);

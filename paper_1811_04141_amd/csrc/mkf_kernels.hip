@@ -227,8 +227,9 @@ struct LdsRec {
 // du^2)] and its azimuth within atan(du / (r' - dv)) <= du / (r' - dv).  The
 // box only has to contain the ellipse (the chi2 test decides), so these
 // cheaper upper bounds replace asin and atan; a small margin absorbs FP32
-// rounding of the bin assignment.  Hits are read four at a time (indices
-// clamped into the bin range) so that their loads overlap.
+// rounding of the bin assignment.  Hits are read four at a time from one
+// base address (the sorted array is padded past its end) so that their
+// loads overlap.
 // Azimuth of (x, y) for the window centre only, within 1e-6 rad (the
 // window adds that to its margin): octant reduction, then atan(a) = a P(a^2)
 // on [0, 1] with a degree-7 polynomial fitted to atan (largest error 1.3e-7
@@ -347,13 +348,16 @@ __device__ __forceinline__ void scan_window(const FindParams &P, const DevLayer 
       const int h1 = P.bin_start[row + hi + 1];
       const float4 *hits = reinterpret_cast<const float4 *>(P.sorted);
       for (int k = h0; k < h1; k += 4) {
+        // records k .. k + 3 from one base address: past the bin's last
+        // hit they are the next bin's hits or the array's padding records
+        // (kHitPad), read and not used
+        const float4 *hk = hits + 2 * (size_t)k;
         float4 a[4];
         float4 b[4];  // (var_v, index, covariance uv, -)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int kk = min(k + j, h1 - 1);
-          a[j] = hits[2 * kk];
-          b[j] = hits[2 * kk + 1];
+          a[j] = hk[2 * j];
+          b[j] = hk[2 * j + 1];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {

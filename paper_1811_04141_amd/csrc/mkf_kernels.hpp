@@ -106,6 +106,9 @@ enum {
 
 // 32-bit words of one wavefront's LDS records in the persistent form:
 // back-pointers [max_plan][seeds][G] and retired candidates [seeds][kFinWords]
+// records allocated past the end of the sorted hits: a window scan reads
+// four records from one base address without clamping them to the bin
+constexpr int kHitPad = 3;
 constexpr int kFinWords = 29;  // 6 + 21 state, chi2, counts
 constexpr __host__ __device__ int persistent_rec_words(int max_plan, int g, int seeds) {
   return (max_plan > 0 ? max_plan : 1) * seeds * g + seeds * kFinWords;
