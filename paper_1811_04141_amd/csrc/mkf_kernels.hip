@@ -1632,13 +1632,30 @@ __global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
   float chi2 = 0.f;
   int status = 0;
   const int m = min(len[i], n_steps);
-  for (int s = 0; s < m; ++s) {
+  // a step's surface and hit are requested one step ahead, while the step
+  // before computes (the last step's words are requested twice, so that
+  // every step issues the same loads)
+  int nk = 0;
+  float npos = 0.f, nx = 0.f, ny = 0.f, nz = 0.f, nvu = 0.f, nvv = 0.f;
+  auto fetch = [&](int s) {
     const size_t j = (size_t)s * (size_t)n + i;
+    nk = kind[j];
+    npos = pos[j];
+    nx = x[j];
+    ny = y[j];
+    nz = z[j];
+    nvu = vu[j];
+    nvv = vv[j];
+  };
+  if (m > 0) fetch(0);
+  for (int s = 0; s < m; ++s) {
     DevLayer L;
-    L.kind = kind[j];
-    L.pos = pos[j];
+    L.kind = nk;
+    L.pos = npos;
     L.lo = 0.f;
     L.hi = 0.f;
+    const float hx = nx, hy = ny, hz = nz, hvu = nvu, hvv = nvv;
+    fetch(min(s + 1, m - 1));
     Prop pr;
     if (propagate<true, float>(p, c, L, cfg.mkb, cfg.l_min, false, 0.f, pr, 0.f, nullptr, nullptr,
                         &cfg.field) != kOk) {
@@ -1649,11 +1666,10 @@ __global__ __launch_bounds__(256) void k_fit(DevCfg cfg, int64_t n, int n_steps,
     Frame f;
     make_frame(pr.p, pr.c, L.kind, f);
     float u, v;
-    if (!residual(pr.p, f, L.kind, x[j], y[j], z[j], u, v)) {
+    if (!residual(pr.p, f, L.kind, hx, hy, hz, u, v)) {
       status = s + 1;
       break;
     }
-    const float hvu = vu[j], hvv = vv[j];
     chi2 += fmaxf(chi2_of(f, hvu, hvv, 0.f, u, v), 0.f);
     kf_update(pr.p, pr.c, f, L.kind, hvu, hvv, 0.f, u, v);
 #pragma unroll
