@@ -646,8 +646,11 @@ __global__ __launch_bounds__(256) void k_find_init(FindParams P) {
 
 // One layer step of the layer-synchronous form: G-lane seed groups,
 // Grp<G>::kSeeds seeds per wavefront (lanes 60-63 idle for G = 6).
+// (the uniform-field form is compiled for four waves per SIMD, which its
+// load latency needs; the extended form would spill far more there)
 template <bool kMat, int G>
-__global__ __launch_bounds__(256) void k_find_step(FindParams P, int step, int64_t n_active) {
+__global__ __launch_bounds__(256, kMat ? 1 : 4) void k_find_step(FindParams P, int step,
+                                                                 int64_t n_active) {
   __shared__ DevLayer sl[kMaxLayers];
   // XCD x (blocks x, x + 8, ...) takes the x-th contiguous share of the
   // positions, so that an XCD's L2 serves a few events' hits
