@@ -440,7 +440,7 @@ mkf_status mkf_get_tuning(mkf_ctx *ctx, mkf_tuning *t);
 /* Autotuner of the persistent find on the loaded seeds: first the launch
  * shape (lane group 6 or 8, waves per SIMD 1..4, 1 or 2 x waves blocks per
  * CU), then at that shape the hit-index binning (phi and q bin shifts
- * -1..1, the index rebuilt for each), each timed as the best of `repeats`
+ * -1..2, the index rebuilt for each), each timed as the best of `repeats`
  * runs (repeats >= 1); the fastest is kept (written to *best if not NULL).
  * cache_path (may be NULL) names a text file of earlier results keyed by
  * GPU architecture, compute units, kernel form and workload size: a

@@ -1334,10 +1334,10 @@ mkf_status mkf_autotune(mkf_ctx *c, int32_t repeats, const char *cache_path, mkf
     for (int w = 1; w <= 4 && st == MKF_OK; ++w)
       for (int mult = 1; mult <= 2 && st == MKF_OK; ++mult)
         st = time_shape(mkf_tuning{w, w * mult, groups[gi], keep.phi_bin_shift, keep.q_bin_shift});
-  // binning at that shape
+  // binning at that shape: phi and q bin counts x 2^s, s in -1..2 each
   const mkf_tuning shape = win;
-  for (int sp = -1; sp <= 1 && st == MKF_OK; ++sp)
-    for (int sq = -1; sq <= 1 && st == MKF_OK; ++sq) {
+  for (int sp = -1; sp <= 2 && st == MKF_OK; ++sp)
+    for (int sq = -1; sq <= 2 && st == MKF_OK; ++sq) {
       if (sp == shape.phi_bin_shift && sq == shape.q_bin_shift) continue;
       mkf_tuning t = shape;
       t.phi_bin_shift = sp;
